@@ -1,0 +1,192 @@
+"""CPU FP64 oracle for the PSD-cone projection -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg
+of ``bench.py`` may import this package.  It shares no code with the GPU
+library in ``paper_2606_20519_amd`` and never imports it.
+
+Contents (each function cites the passage it follows):
+
+* ``unpack`` / ``pack`` -- the paper's real encoding vec_R / mat_R of a
+  Hermitian matrix (App. D.1): diagonal entries, then sqrt(2) Re X_ij and
+  sqrt(2) Im X_ij for i<j.  Ordering (open in the paper): row-major over the
+  upper triangle, Re/Im interleaved; row i starts at offset i(2n-i).
+* ``eigh`` -- cyclic complex Jacobi eigendecomposition (C, ``psd_oracle.c``).
+* ``project`` -- Pi(X) = V diag(max(lam,0)) V^H, the Euclidean projection onto
+  the PSD cone (App. D.1, Pi_S), implemented as in App. D.2: eigendecompose,
+  set the negative eigenvalues to zero.  Reconstruction in long double.
+* ``vjp`` -- Daleckii-Krein derivative DPi(X)[G] = V (Gamma o V^H G V) V^H,
+  which is what back-propagation through the projection needs (App. E).
+* ``constructed_projection`` -- the closed form U diag(max(lam,0)) U^H for an
+  input built as U diag(lam) U^H (matmul as a library step).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "psd_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+def build(force: bool = True, src: str = _SRC, out: str = _LIB) -> str:
+    """Compile ``psd_oracle.c`` (or a variant source) into a shared library
+    with gcc + OpenMP."""
+    if force or not os.path.exists(out):
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11",
+               "-o", out + ".tmp", src, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(out + ".tmp", out)
+    return out
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(x) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+def _check(st: int, what: str):
+    if st != 0:
+        raise OracleError(f"{what} failed with status {st}")
+
+
+class Oracle:
+    """ctypes front end of one compiled oracle library."""
+
+    def __init__(self, path: str):
+        lib = ctypes.CDLL(path)
+        dp = ctypes.POINTER(ctypes.c_double)
+        ip = ctypes.POINTER(ctypes.c_int)
+        lp = ctypes.POINTER(ctypes.c_long)
+        lib.or_unpack.argtypes = [ctypes.c_int, dp, dp]
+        lib.or_pack.argtypes = [ctypes.c_int, dp, dp]
+        lib.or_eigh_svec.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_int, ctypes.c_int, ip, lp]
+        lib.or_project.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, ip, dp, dp]
+        lib.or_reconstruct.argtypes = [ctypes.c_int, dp, dp, dp]
+        lib.or_vjp.argtypes = [ctypes.c_int, dp, dp, dp, ctypes.c_int]
+        lib.or_svec_row_offset.argtypes = [ctypes.c_int, ctypes.c_int]
+        lib.or_svec_row_offset.restype = ctypes.c_long
+        lib.or_svec_offdiag_offset.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        lib.or_svec_offdiag_offset.restype = ctypes.c_long
+        lib.or_num_threads.restype = ctypes.c_int
+        self.lib = lib
+        self.path = path
+
+    def row_offset(self, n: int, i: int) -> int:
+        return int(self.lib.or_svec_row_offset(n, i))
+
+    def offdiag_offset(self, n: int, i: int, j: int) -> int:
+        return int(self.lib.or_svec_offdiag_offset(n, i, j))
+
+    def unpack(self, s, n: int) -> np.ndarray:
+        """mat_R: svec (n*n reals) -> Hermitian complex128 (n, n)."""
+        s = _f64(s)
+        assert s.size == n * n
+        a = np.empty((n, n), dtype=np.complex128)
+        _check(self.lib.or_unpack(n, _dp(s), _dp(a.view(np.float64))), "unpack")
+        return a
+
+    def pack(self, a) -> np.ndarray:
+        """vec_R: Hermitian (n, n) -> svec (upper triangle read)."""
+        a = np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+        n = a.shape[0]
+        s = np.empty(n * n, dtype=np.float64)
+        _check(self.lib.or_pack(n, _dp(a.view(np.float64)), _dp(s)), "pack")
+        return s
+
+    def eigh(self, s, n: int, mode: int = 1, max_sweeps: int = 0, return_stats: bool = False):
+        """Jacobi eigendecomposition of mat_R(s).  Returns (lam, V) with lam
+        ascending and V[:, k] the eigenvector of lam[k].
+
+        mode 0: row-cyclic serial sweeps; mode 1: round-robin parallel sweeps.
+        """
+        s = _f64(s)
+        lam = np.empty(n, dtype=np.float64)
+        v = np.empty((n, n), dtype=np.complex128)
+        sw = ctypes.c_int(0)
+        rot = ctypes.c_long(0)
+        st = self.lib.or_eigh_svec(n, _dp(s), _dp(lam), _dp(v.view(np.float64)), mode,
+                                   max_sweeps, ctypes.byref(sw), ctypes.byref(rot))
+        _check(st, "eigh")
+        order = np.argsort(lam, kind="stable")
+        lam, v = lam[order], v[:, order]
+        if return_stats:
+            return lam, v, {"sweeps": sw.value, "rotations": rot.value}
+        return lam, v
+
+    def project(self, s, n: int, mode: int = 1) -> np.ndarray:
+        """svec(Pi(mat_R(s))): eigendecompose, clamp negative eigenvalues to
+        0, reconstruct (App. D.2)."""
+        s = _f64(s)
+        y = np.empty(n * n, dtype=np.float64)
+        sw = ctypes.c_int(0)
+        _check(self.lib.or_project(n, _dp(s), _dp(y), mode, ctypes.byref(sw), None, None), "project")
+        return y
+
+    def reconstruct(self, lam, v) -> np.ndarray:
+        """svec(V diag(max(lam,0)) V^H) with long-double accumulation."""
+        lam = _f64(lam)
+        v = np.ascontiguousarray(np.asarray(v, dtype=np.complex128))
+        n = lam.size
+        y = np.empty(n * n, dtype=np.float64)
+        _check(self.lib.or_reconstruct(n, _dp(lam), _dp(v.view(np.float64)), _dp(y)), "reconstruct")
+        return y
+
+    def vjp(self, s, gy, n: int, mode: int = 1) -> np.ndarray:
+        """svec(DPi(X)[mat_R(gy)]) by the Daleckii-Krein formula; equal to the
+        vector-Jacobian product since DPi(X) is self-adjoint in svec space."""
+        s, gy = _f64(s), _f64(gy)
+        gx = np.empty(n * n, dtype=np.float64)
+        _check(self.lib.or_vjp(n, _dp(s), _dp(gy), _dp(gx), mode), "vjp")
+        return gx
+
+    def constructed_projection(self, u, lam) -> np.ndarray:
+        """Closed form for X = U diag(lam) U^H with U unitary:
+        Pi(X) = U diag(max(lam,0)) U^H, returned as svec."""
+        u = np.asarray(u, dtype=np.complex128)
+        lp = np.maximum(np.asarray(lam, dtype=np.float64), 0.0)
+        p = (u * lp[None, :]) @ u.conj().T
+        return self.pack(p)
+
+    def num_threads(self) -> int:
+        return int(self.lib.or_num_threads())
+
+
+_default = None
+
+
+def default() -> Oracle:
+    global _default
+    if _default is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        _default = Oracle(_LIB)
+    return _default
+
+
+def svec_len(n: int) -> int:
+    return n * n
+
+
+def row_offset(n, i): return default().row_offset(n, i)
+def offdiag_offset(n, i, j): return default().offdiag_offset(n, i, j)
+def unpack(s, n): return default().unpack(s, n)
+def pack(a): return default().pack(a)
+def eigh(s, n, mode=1, max_sweeps=0, return_stats=False): return default().eigh(s, n, mode, max_sweeps, return_stats)
+def project(s, n, mode=1): return default().project(s, n, mode)
+def reconstruct(lam, v): return default().reconstruct(lam, v)
+def vjp(s, gy, n, mode=1): return default().vjp(s, gy, n, mode)
+def constructed_projection(u, lam): return default().constructed_projection(u, lam)
+
+
+def num_threads() -> int:
+    return default().num_threads()

@@ -1,0 +1,332 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: each check is a value printed
+or derived by hand from the definitions (golden files), a closed form, an
+invariant of the Euclidean projection onto the PSD cone, a special case that
+reduces to a library routine (LAPACK through NumPy), or a brute-force count.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2606_20519_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+EPS = np.finfo(np.float64).eps
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / (nb if nb > 0 else 1.0)
+
+
+def read_golden(name):
+    out = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            k, *vals = line.split()
+            out[k] = np.array([float(v) for v in vals])
+    return out
+
+
+def herm(n, rng):
+    return W.gue_matrix(n, rng)
+
+
+# --------------------------------------------------------------------------
+# vec_R / mat_R  (App. D.1)
+# --------------------------------------------------------------------------
+
+def test_svec_golden_n2(orc):
+    g = read_golden("svec_n2.txt")
+    x = (g["matrix_re"] + 1j * g["matrix_im"]).reshape(2, 2)
+    np.testing.assert_allclose(orc.pack(x), g["svec"], rtol=0, atol=4 * EPS)
+    np.testing.assert_allclose(orc.unpack(g["svec"], 2), x, rtol=0, atol=8 * EPS)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 16, 31])
+def test_svec_offsets_bruteforce(orc, n):
+    # Enumerate the upper triangle row by row: X_ii then (Re, Im) of X_ij.
+    pos = 0
+    for i in range(n):
+        assert orc.row_offset(n, i) == pos
+        pos += 1
+        for j in range(i + 1, n):
+            assert orc.offdiag_offset(n, i, j) == pos
+            pos += 2
+    assert pos == n * n
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 17, 64])
+def test_svec_isometry_and_roundtrip(orc, n):
+    rng = np.random.default_rng(10 + n)
+    x, y = herm(n, rng), herm(n, rng)
+    sx, sy = orc.pack(x), orc.pack(y)
+    # <svec X, svec Y> = tr[X^H Y]  (App. D.1)
+    assert abs(sx @ sy - np.trace(x.conj().T @ y).real) <= 64 * EPS * np.linalg.norm(x) * np.linalg.norm(y)
+    ux = orc.unpack(sx, n)
+    np.testing.assert_allclose(ux, x, rtol=0, atol=4 * EPS * np.abs(x).max())
+    assert np.array_equal(ux, ux.conj().T)  # Hermitian by construction
+    np.testing.assert_allclose(orc.pack(orc.unpack(sx, n)), sx, rtol=0, atol=4 * EPS * np.abs(sx).max())
+    # The input generator's independent packer agrees with the oracle's.
+    np.testing.assert_allclose(W.upper_pack(x), sx, rtol=0, atol=0)
+
+
+# --------------------------------------------------------------------------
+# Jacobi eigendecomposition
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_jacobi_n1(orc, mode):
+    lam, v = orc.eigh(np.array([-2.5]), 1, mode)
+    assert lam[0] == -2.5 and v[0, 0] == 1.0
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_jacobi_diagonal_needs_no_rotation(orc, mode):
+    d = np.array([3.0, -1.0, 0.0, 2.5, -7.25, 1e-300])
+    n = d.size
+    s = orc.pack(np.diag(d).astype(complex))
+    lam, v, st = orc.eigh(s, n, mode, return_stats=True)
+    assert st["rotations"] == 0
+    assert np.array_equal(np.sort(d), lam)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_jacobi_2x2_closed_form(orc, mode):
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        a, b = rng.standard_normal(2)
+        c = complex(*rng.standard_normal(2))
+        x = np.array([[a, c], [np.conj(c), b]])
+        lam, v, st = orc.eigh(orc.pack(x), 2, mode, return_stats=True)
+        m, r = (a + b) / 2, np.hypot((a - b) / 2, abs(c))
+        np.testing.assert_allclose(lam, [m - r, m + r], rtol=0, atol=8 * EPS * (abs(m) + r))
+        # a single rotation zeroes the pivot
+        assert st["rotations"] == 1
+        np.testing.assert_allclose(x @ v, v * lam, rtol=0, atol=16 * EPS * (abs(m) + r))
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("n", [3, 8, 25, 64, 97])
+def test_jacobi_residual_orthogonality_lapack(orc, n, mode):
+    s = W.gue(n, 100 + n)
+    x = orc.unpack(s, n)
+    lam, v = orc.eigh(s, n, mode)
+    nx = np.linalg.norm(x)
+    assert np.linalg.norm(x @ v - v * lam) <= 8 * n * EPS * nx
+    assert np.linalg.norm(v.conj().T @ v - np.eye(n)) <= 8 * n * EPS
+    # eigenvalues agree with LAPACK (run as a library routine)
+    ref = np.linalg.eigvalsh(x)
+    assert np.max(np.abs(lam - ref)) <= 8 * n * EPS * np.abs(ref).max()
+
+
+def test_jacobi_sweep_cap_reports_noconv(orc):
+    import oracle
+    s = W.gue(24, 3)
+    with pytest.raises(oracle.OracleError):
+        orc.eigh(s, 24, 0, max_sweeps=1)
+
+
+# --------------------------------------------------------------------------
+# Pi(X) = V diag(max(lam,0)) V^H  (App. D.2)
+# --------------------------------------------------------------------------
+
+def test_projection_golden_2x2(orc):
+    g = read_golden("projection_2x2.txt")
+    for c in ("case1", "case2"):
+        np.testing.assert_allclose(orc.project(g[c + "_x"], 2), g[c + "_y"], rtol=0, atol=16 * EPS)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_projection_diagonal_bitwise(orc, mode):
+    d = np.array([3.0, -1.0, 0.0, 2.5, -7.25, 1e-300, -0.0])
+    s = orc.pack(np.diag(d).astype(complex))
+    y = orc.project(s, d.size, mode)
+    assert np.array_equal(y, orc.pack(np.diag(np.maximum(d, 0.0)).astype(complex)))
+
+
+def test_projection_2x2_closed_form(orc):
+    rng = np.random.default_rng(7)
+    for _ in range(50):
+        a, b = rng.standard_normal(2)
+        c = complex(*rng.standard_normal(2))
+        x = np.array([[a, c], [np.conj(c), b]])
+        m, r = (a + b) / 2, np.hypot((a - b) / 2, abs(c))
+        lp, lm = m + r, m - r
+        if lm >= 0:
+            ref = x
+        elif lp <= 0:
+            ref = np.zeros_like(x)
+        else:
+            ref = lp * (x - lm * np.eye(2)) / (lp - lm)
+        np.testing.assert_allclose(orc.project(orc.pack(x), 2), orc.pack(ref), rtol=0,
+                                   atol=32 * EPS * (abs(m) + r))
+
+
+@pytest.mark.parametrize("n", [5, 20, 48])
+def test_projection_psd_nsd_rank1(orc, n):
+    rng = np.random.default_rng(n)
+    g = W.cn01(rng, (n, n))
+    p = g @ g.conj().T  # PSD
+    sp = orc.pack(p)
+    assert rel(orc.project(sp, n), sp) <= 64 * n * EPS
+    assert np.abs(orc.project(-sp, n)).max() <= 64 * n * EPS * np.abs(sp).max()
+    v = W.cn01(rng, n)
+    mu = 2.75
+    r1 = mu * np.outer(v, v.conj())
+    assert rel(orc.project(orc.pack(r1), n), orc.pack(r1)) <= 64 * n * EPS
+    assert np.abs(orc.project(orc.pack(-r1), n)).max() <= 64 * n * EPS * np.abs(r1).max()
+
+
+@pytest.mark.parametrize("n", [16, 41, 80])
+def test_projection_constructed_spectrum(orc, n):
+    sx, u, lam = W.constructed(n, 1003 + n)
+    y = orc.project(sx, n)
+    ref = orc.constructed_projection(u, lam)
+    # ||Pi(X_fp64) - U Lam+ U^H|| <= ||X_fp64 - U Lam U^H|| by non-expansiveness
+    assert rel(y, ref) <= 1e-13
+
+
+@pytest.mark.parametrize("n", [10, 37, 64])
+def test_projection_vs_lapack(orc, n):
+    s = W.gue(n, 1001 + n)
+    x = orc.unpack(s, n)
+    w, u = np.linalg.eigh(x)
+    ref = (u * np.maximum(w, 0)) @ u.conj().T
+    assert rel(orc.project(s, n, 0), orc.pack(ref)) <= 1e-13
+    assert rel(orc.project(s, n, 1), orc.pack(ref)) <= 1e-13
+
+
+@pytest.mark.parametrize("n", [12, 50])
+def test_projection_invariants(orc, n):
+    rng = np.random.default_rng(77 + n)
+    s = W.gue(n, 200 + n)
+    x = orc.unpack(s, n)
+    y = orc.project(s, n)
+    p = orc.unpack(y, n)
+    nx2 = np.linalg.norm(x, 2)
+    tol = 64 * n * EPS * nx2
+    assert np.linalg.eigvalsh(p).min() >= -tol           # Pi >= 0
+    assert np.linalg.eigvalsh(p - x).min() >= -tol       # Pi - X >= 0
+    assert abs(y @ (y - s)) <= 64 * n * EPS * np.linalg.norm(s) ** 2  # <Pi, Pi - X> = 0
+    assert rel(orc.project(y, n), y) <= 64 * n * EPS     # idempotent
+    # Moreau: Pi(X) - Pi(-X) = X  (App. D.1, Pi_{C*}(x) = x + Pi_C(-x), C = C*)
+    assert rel(y - orc.project(-s, n), s) <= 64 * n * EPS
+    # conjugation: Pi(conj X) = conj Pi(X)
+    assert rel(orc.project(orc.pack(x.conj()), n), orc.pack(p.conj())) <= 64 * n * EPS
+    # unitary equivariance
+    u = W.haar_unitary(n, rng)
+    assert rel(orc.project(orc.pack(u @ x @ u.conj().T), n), orc.pack(u @ p @ u.conj().T)) <= 1e-13
+    # positive homogeneity, bitwise for powers of two
+    assert np.array_equal(orc.project(8.0 * s, n), 8.0 * y)
+    assert np.array_equal(orc.project(s / 1024.0, n), y / 1024.0)
+    # non-expansive
+    s2 = s + 0.3 * W.gue(n, 300 + n)
+    assert np.linalg.norm(orc.project(s2, n) - y) <= np.linalg.norm(s2 - s) * (1 + 1e-12)
+
+
+def test_projection_block_diagonal(orc):
+    a, b = 9, 14
+    xa = W.gue_matrix(a, np.random.default_rng(1))
+    xb = W.gue_matrix(b, np.random.default_rng(2))
+    x = np.zeros((a + b, a + b), complex)
+    x[:a, :a], x[a:, a:] = xa, xb
+    p = orc.unpack(orc.project(orc.pack(x), a + b), a + b)
+    assert np.abs(p[:a, a:]).max() <= 1e-14
+    assert rel(orc.pack(p[:a, :a]), orc.project(orc.pack(xa), a)) <= 1e-13
+    assert rel(orc.pack(p[a:, a:]), orc.project(orc.pack(xb), b)) <= 1e-13
+
+
+def test_modes_agree(orc):
+    n = 70
+    s = W.gue(n, 9)
+    assert rel(orc.project(s, n, 0), orc.project(s, n, 1)) <= 1e-13
+
+
+# --------------------------------------------------------------------------
+# Daleckii-Krein derivative (back-propagation through Pi, App. E)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [4, 16, 30])
+def test_vjp_finite_differences(orc, n):
+    s = W.gue(n, 500 + n)
+    rng = np.random.default_rng(600 + n)
+    h = 1e-6
+    for _ in range(3):
+        e = orc.pack(herm(n, rng))
+        fd = (orc.project(s + h * e, n) - orc.project(s - h * e, n)) / (2 * h)
+        jv = orc.vjp(s, e, n)
+        assert rel(jv, fd) <= 1e-7
+
+
+def test_vjp_full_jacobian_small(orc):
+    # all n^2 directions of a 6x6 problem against central differences
+    n = 6
+    s = W.gue(n, 42)
+    h = 1e-6
+    for k in range(n * n):
+        e = np.zeros(n * n); e[k] = 1.0
+        fd = (orc.project(s + h * e, n) - orc.project(s - h * e, n)) / (2 * h)
+        assert np.linalg.norm(orc.vjp(s, e, n) - fd) <= 1e-7
+
+
+@pytest.mark.parametrize("n", [7, 33])
+def test_vjp_structure(orc, n):
+    s = W.gue(n, 700 + n)
+    y = orc.project(s, n)
+    rng = np.random.default_rng(n)
+    a, b = orc.pack(herm(n, rng)), orc.pack(herm(n, rng))
+    tol = 64 * n * EPS
+    # self-adjoint in svec space
+    assert abs(a @ orc.vjp(s, b, n) - b @ orc.vjp(s, a, n)) <= tol * np.linalg.norm(a) * np.linalg.norm(b)
+    # Euler identity for the 1-homogeneous Pi: DPi(X)[X] = Pi(X)
+    assert rel(orc.vjp(s, s, n), y) <= tol
+    # X > 0 => identity;  X < 0 => zero
+    g = W.cn01(rng, (n, n))
+    spd = orc.pack(g @ g.conj().T + 0.5 * np.eye(n))
+    assert rel(orc.vjp(spd, a, n), a) <= tol
+    assert np.abs(orc.vjp(-spd, a, n)).max() <= tol * np.abs(a).max()
+    # 0 <= Gamma <= 1  =>  ||DPi[E]|| <= ||E||
+    assert np.linalg.norm(orc.vjp(s, a, n)) <= np.linalg.norm(a) * (1 + tol)
+
+
+def test_vjp_diagonal_input_is_hadamard(orc):
+    d = np.array([2.0, -1.0, 0.5, -3.0, 4.0])
+    n = d.size
+    e = herm(n, np.random.default_rng(3))
+    gam = np.empty((n, n))
+    for i in range(n):
+        for j in range(n):
+            a, b = d[i], d[j]
+            if a > 0 and b > 0:
+                gam[i, j] = 1.0
+            elif a <= 0 and b <= 0:
+                gam[i, j] = 0.0
+            else:
+                gam[i, j] = max(a, b) / (max(a, b) - min(a, b))
+    ref = orc.pack(gam * e)
+    got = orc.vjp(orc.pack(np.diag(d).astype(complex)), orc.pack(e), n)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=8 * EPS * np.abs(e).max())
+
+
+def test_vjp_constructed_spectrum(orc):
+    n = 24
+    sx, u, lam = W.constructed(n, 1234, gap=1e-2)
+    e = herm(n, np.random.default_rng(8))
+    gam = np.empty((n, n))
+    for i in range(n):
+        for j in range(n):
+            a, b = lam[i], lam[j]
+            if a > 0 and b > 0:
+                gam[i, j] = 1.0
+            elif a <= 0 and b <= 0:
+                gam[i, j] = 0.0
+            else:
+                gam[i, j] = max(a, b) / (max(a, b) - min(a, b))
+    ref = u @ (gam * (u.conj().T @ e @ u)) @ u.conj().T
+    assert rel(orc.vjp(sx, orc.pack(e), n), orc.pack(ref)) <= 1e-12
