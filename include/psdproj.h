@@ -1,0 +1,129 @@
+/*
+ * psdproj.h -- C ABI of the MI355X (gfx950) PSD-cone projection library.
+ *
+ * The library computes the Euclidean projection onto the cone of complex
+ * Hermitian positive-semidefinite matrices,
+ *
+ *     Pi(X) = argmin_{Y >= 0} ||Y - X||_F = V diag(max(lambda, 0)) V^H,
+ *
+ * which is the cone step u = Pi_C(u~ - v) of the SCS iteration (App. D.1,
+ * eq. final_iterates2; Pi_S is the Euclidean projection onto S) and which the
+ * paper evaluates by an eigendecomposition with the negative eigenvalues set
+ * to zero (App. D.2).  It also computes the derivative of Pi, needed to
+ * back-propagate through the projection (App. E).
+ *
+ * Matrix encoding ("svec"): the paper's real vectorisation vec_R of a
+ * Hermitian matrix (App. D.1): the diagonal entries X_ii and, for i < j,
+ * sqrt(2) Re X_ij and sqrt(2) Im X_ij, so that <svec X, svec Y> = tr[X^H Y].
+ * The paper leaves the order open; here it is row-major over the upper
+ * triangle with Re/Im interleaved:
+ *     row i starts at offset i*(2n - i) and holds
+ *     X_ii, sqrt2 Re X_i,i+1, sqrt2 Im X_i,i+1, ..., sqrt2 Im X_i,n-1.
+ * A block of order n has exactly n*n doubles.  Batched blocks are
+ * concatenated in the order given; block b starts at sum_{c<b} n_c^2.
+ *
+ * Memory: every double* below is HIP device memory owned by the caller
+ * (8-byte aligned; 16-byte aligned recommended), unless marked "host".
+ * The library never allocates in a call: the caller passes a device
+ * workspace of at least psd_workspace_size() bytes (256-byte aligned).
+ *
+ * Asynchrony: all device work is enqueued on `stream` (0 = the null stream).
+ * Errors found on the host (bad sizes, null pointers, misalignment, too small
+ * a workspace, partially overlapping x/y) are returned synchronously and
+ * nothing is enqueued.  Conditions found on the device (non-finite input,
+ * non-convergence) are written to `info` asynchronously; synchronise the
+ * stream before reading it.  No call prints, throws or allocates.  Calls on
+ * different streams with different workspaces may run concurrently.
+ */
+#ifndef PSDPROJ_H
+#define PSDPROJ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PSD_OK = 0,
+    PSD_EINVAL = 1,       /* invalid argument (size, pointer, alignment, mode, aliasing) */
+    PSD_EWORKSPACE = 2,   /* workspace too small */
+    PSD_ENOMEM = 3,       /* (reserved: the library does not allocate) */
+    PSD_ENONFINITE = 4,   /* device: the input held a NaN or an infinity */
+    PSD_ENOCONV = 5,      /* device: an iteration did not converge */
+    PSD_EDEVICE = 6,      /* a HIP runtime call failed (launch, no device) */
+    PSD_EUNSUPPORTED = 7  /* valid request this build does not serve */
+} psd_status;
+
+typedef enum {
+    PSD_FP64_EIG = 0,     /* FP64 eigendecomposition path (exact up to rounding) */
+    PSD_MIXED_BF16 = 1,   /* Newton-Schulz sign iteration, BF16 MFMA + FP64 correction */
+    PSD_MIXED_FP32 = 2    /* Newton-Schulz sign iteration, FP32 MFMA + FP64 correction */
+} psd_mode;
+
+/* Per-block result record, written by the device (device or pinned host
+ * memory; read it only after synchronising the stream). */
+typedef struct {
+    int32_t status;       /* psd_status of this block */
+    int32_t n_pos;        /* number of eigenvalues > 0 */
+    int32_t n_neg;        /* number of eigenvalues <= 0 */
+    int32_t iters;        /* NS iterations (mixed) or 0 */
+    int32_t fallback;     /* 1 if a mixed request fell back to the FP64 path */
+    int32_t reserved;
+    double est_rel_err;   /* mixed: estimated relative error; FP64: 0 */
+} psd_info;
+
+/* Workspace bytes needed to serve `nblocks` blocks of orders n[0..nblocks)
+ * (host array) in `mode` by psd_project / psd_project_batched /
+ * psd_project_vjp.  flags: bit 0 = also return the eigen-pair for a later VJP
+ * (PSD_FLAG_SAVE).  Returns PSD_EINVAL for n < 1, nblocks < 1 or a bad mode. */
+#define PSD_FLAG_SAVE 1
+psd_status psd_workspace_size(int32_t nblocks, const int32_t *n, psd_mode mode,
+                              int32_t flags, size_t *bytes);
+
+/* Bytes of the `saved` record of one block of order n: lambda (n doubles,
+ * ascending) followed by V (n x n complex, column-major, interleaved re/im)
+ * with V[:,k] the unit eigenvector of lambda[k] -- of the conjugate matrix
+ * mat(x)^T, in the svec convention above (Pi commutes with conjugation). */
+size_t psd_saved_size(int32_t n);
+
+/* y <- svec(Pi(mat(x))) for one block of order n >= 1.
+ * x, y: n*n doubles; y == x (in place) is allowed, partial overlap is not.
+ * info: nullable (device or pinned).  saved: nullable; if given (size
+ * psd_saved_size(n)), receives lambda and V for psd_project_vjp.
+ * mode PSD_FP64_EIG: relative Frobenius error ~ n * 2^-53.  */
+psd_status psd_project(int32_t n, const double *x, double *y, psd_mode mode,
+                       void *ws, size_t ws_bytes, void *stream, psd_info *info,
+                       double *saved);
+
+/* Projects nblocks independent blocks (orders n[0..nblocks), host array)
+ * stored back to back in x into y (same layout).  infos: nullable array of
+ * nblocks records. */
+psd_status psd_project_batched(int32_t nblocks, const int32_t *n, const double *x,
+                               double *y, psd_mode mode, void *ws, size_t ws_bytes,
+                               void *stream, psd_info *infos);
+
+/* gx <- svec(DPi(X)[mat(gy)]) with X = mat(x): the Daleckii-Krein formula
+ *   DPi(X)[G] = V (Gamma o (V^H G V)) V^H,
+ *   Gamma_ij = 1 (lambda_i, lambda_j > 0), 0 (both <= 0),
+ *              lambda_i / (lambda_i - lambda_j) (lambda_i > 0 >= lambda_j).
+ * DPi(X) is self-adjoint in svec coordinates, so this is both the JVP and
+ * the vector-Jacobian product.  Give either x (the eigen-pair is recomputed)
+ * or saved (from psd_project); if both are non-null, saved is used.
+ * gy, gx: n*n doubles; gx may alias gy. */
+psd_status psd_project_vjp(int32_t n, const double *x, const double *saved,
+                           const double *gy, double *gx, psd_mode mode, void *ws,
+                           size_t ws_bytes, void *stream);
+
+/* Static description of a status code. */
+const char *psd_status_string(psd_status status);
+
+/* Library version string. */
+const char *psd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSDPROJ_H */

@@ -1,1 +1,143 @@
-"""MI355X-native PSD-cone projection (placeholder; binding added with the C ABI)."""
+"""MI355X (gfx950) projection onto the complex Hermitian PSD cone.
+
+Python binding of libpsdproj.so (include/psdproj.h).  PyTorch supplies device
+memory and the stream; every step of the projection runs in the library's
+HIP kernels.  Inputs and outputs are float64 device tensors in the svec
+encoding (App. D.1 vec_R): per row i of the upper triangle, X_ii followed by
+sqrt(2) Re X_ij, sqrt(2) Im X_ij for j > i; a block of order n has n*n reals.
+
+    project(x, n, mode="fp64")            -> svec(Pi(mat(x)))
+    project_batched(x, sizes, mode)       -> blocks projected independently
+    vjp(gy, n, x=None, saved=None)        -> svec(DPi(X)[mat(gy)])
+    PSDProject.apply(x, n, mode)          -> differentiable projection
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import MODES, PSD_FLAG_SAVE, PsdError, PsdInfo, check  # noqa: F401
+
+__all__ = ["project", "project_batched", "vjp", "PSDProject", "workspace", "PsdError", "MODES"]
+
+_ws_cache: dict = {}
+
+
+def _mode(mode) -> int:
+    if isinstance(mode, str):
+        return MODES[mode]
+    return int(mode)
+
+
+def _stream_ptr(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def workspace(sizes, mode, device, flags: int = 0) -> torch.Tensor:
+    """A cached device workspace large enough for `sizes` in `mode`."""
+    nbytes = _lib.workspace_size(list(sizes), _mode(mode), flags)
+    key = (str(device), torch.cuda.current_stream(device).cuda_stream)
+    ws = _ws_cache.get(key)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _ws_cache[key] = ws
+    return ws
+
+
+def _check_vec(x: torch.Tensor, numel: int, what: str):
+    if not x.is_cuda or x.dtype != torch.float64:
+        raise TypeError(f"{what} must be a float64 HIP tensor")
+    if x.numel() != numel or not x.is_contiguous():
+        raise ValueError(f"{what} must be contiguous with {numel} elements")
+
+
+def project(x: torch.Tensor, n: int, mode="fp64", out: torch.Tensor = None, info: bool = False,
+            saved: torch.Tensor = None):
+    """svec(Pi(mat(x))) for one block of order n.  With info=True also
+    returns the device record (status, n_pos, n_neg, ...) as a dict (this
+    synchronises).  `saved` (float64, psd_saved_size(n)/8 elements) receives
+    the eigen-pair for a later vjp."""
+    _check_vec(x, n * n, "x")
+    y = torch.empty_like(x) if out is None else out
+    _check_vec(y, n * n, "out")
+    m = _mode(mode)
+    ws = workspace([n], m, x.device, PSD_FLAG_SAVE if saved is not None else 0)
+    inf_t = torch.zeros(8, dtype=torch.int32, device=x.device) if info else None
+    st = _lib.lib().psd_project(n, _ptr(x), _ptr(y), m, _ptr(ws), ws.numel(), ctypes.c_void_p(_stream_ptr(x.device)),
+                                _ptr(inf_t), _ptr(saved))
+    check(st, "psd_project")
+    if info:
+        return y, _info_dict(inf_t)
+    return y
+
+
+def _info_dict(t: torch.Tensor) -> dict:
+    raw = t.cpu().numpy().tobytes()
+    rec = PsdInfo.from_buffer_copy(raw[:ctypes.sizeof(PsdInfo)])
+    return {f: getattr(rec, f) for f, _ in PsdInfo._fields_}
+
+
+def project_batched(x: torch.Tensor, sizes, mode="fp64", out: torch.Tensor = None, info: bool = False):
+    """Projects consecutive svec blocks of orders `sizes` independently."""
+    sizes = [int(s) for s in sizes]
+    total = sum(s * s for s in sizes)
+    _check_vec(x, total, "x")
+    y = torch.empty_like(x) if out is None else out
+    _check_vec(y, total, "out")
+    m = _mode(mode)
+    ws = workspace(sizes, m, x.device)
+    inf_t = torch.zeros(8 * len(sizes), dtype=torch.int32, device=x.device) if info else None
+    st = _lib.lib().psd_project_batched(len(sizes), _lib.int_array(sizes), _ptr(x), _ptr(y), m, _ptr(ws),
+                                        ws.numel(), ctypes.c_void_p(_stream_ptr(x.device)), _ptr(inf_t))
+    check(st, "psd_project_batched")
+    if info:
+        raw = inf_t.cpu().numpy().tobytes()
+        k = ctypes.sizeof(PsdInfo)
+        recs = [PsdInfo.from_buffer_copy(raw[i * k:(i + 1) * k]) for i in range(len(sizes))]
+        return y, [{f: getattr(r, f) for f, _ in PsdInfo._fields_} for r in recs]
+    return y
+
+
+def saved_numel(n: int) -> int:
+    return _lib.saved_size(n) // 8
+
+
+def vjp(gy: torch.Tensor, n: int, x: torch.Tensor = None, saved: torch.Tensor = None, mode="fp64",
+        out: torch.Tensor = None):
+    """svec(DPi(X)[mat(gy)]) (Daleckii-Krein); DPi is self-adjoint, so this is
+    the vector-Jacobian product.  Pass x or the `saved` eigen-pair."""
+    _check_vec(gy, n * n, "gy")
+    if x is None and saved is None:
+        raise ValueError("vjp needs x or saved")
+    gx = torch.empty_like(gy) if out is None else out
+    m = _mode(mode)
+    ws = workspace([n], m, gy.device, PSD_FLAG_SAVE)
+    st = _lib.lib().psd_project_vjp(n, _ptr(x), _ptr(saved), _ptr(gy), _ptr(gx), m, _ptr(ws), ws.numel(),
+                                    ctypes.c_void_p(_stream_ptr(gy.device)))
+    check(st, "psd_project_vjp")
+    return gx
+
+
+class PSDProject(torch.autograd.Function):
+    """y = svec(Pi(mat(x))) with backward gx = svec(DPi(X)[mat(gy)])."""
+
+    @staticmethod
+    def forward(ctx, x, n, mode="fp64"):
+        saved = torch.empty(saved_numel(n), dtype=torch.float64, device=x.device)
+        y = project(x.detach().contiguous(), n, mode, saved=saved)
+        ctx.save_for_backward(saved)
+        ctx.n = n
+        ctx.mode = mode
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        (saved,) = ctx.saved_tensors
+        gx = vjp(gy.contiguous(), ctx.n, saved=saved, mode=ctx.mode)
+        return gx, None, None

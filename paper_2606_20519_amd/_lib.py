@@ -1,0 +1,92 @@
+"""ctypes front end of libpsdproj.so (the C ABI in include/psdproj.h).
+
+Argument marshalling only: every step of the projection runs in the HIP
+kernels behind the ABI.  Loading fails loudly if the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpsdproj.so")
+
+PSD_OK = 0
+STATUS_NAMES = {0: "PSD_OK", 1: "PSD_EINVAL", 2: "PSD_EWORKSPACE", 3: "PSD_ENOMEM",
+                4: "PSD_ENONFINITE", 5: "PSD_ENOCONV", 6: "PSD_EDEVICE", 7: "PSD_EUNSUPPORTED"}
+MODES = {"fp64": 0, "mixed_bf16": 1, "mixed_fp32": 2}
+PSD_FLAG_SAVE = 1
+
+# Every symbol include/psdproj.h declares.
+EXPORTS = ("psd_workspace_size", "psd_saved_size", "psd_project", "psd_project_batched",
+           "psd_project_vjp", "psd_status_string", "psd_version")
+
+
+class PsdError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {STATUS_NAMES.get(status, status)} ({status_string(status)})")
+
+
+class PsdInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_pos", ctypes.c_int32), ("n_neg", ctypes.c_int32),
+                ("iters", ctypes.c_int32), ("fallback", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("est_rel_err", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2606_20519_amd.build` "
+                           "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32
+    L.psd_workspace_size.argtypes = [i32, ctypes.POINTER(i32), i32, i32, ctypes.POINTER(sz)]
+    L.psd_workspace_size.restype = i32
+    L.psd_saved_size.argtypes = [i32]
+    L.psd_saved_size.restype = sz
+    L.psd_project.argtypes = [i32, vp, vp, i32, vp, sz, vp, vp, vp]
+    L.psd_project.restype = i32
+    L.psd_project_batched.argtypes = [i32, ctypes.POINTER(i32), vp, vp, i32, vp, sz, vp, vp]
+    L.psd_project_batched.restype = i32
+    L.psd_project_vjp.argtypes = [i32, vp, vp, vp, vp, i32, vp, sz, vp]
+    L.psd_project_vjp.restype = i32
+    L.psd_status_string.argtypes = [i32]
+    L.psd_status_string.restype = ctypes.c_char_p
+    L.psd_version.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def status_string(st: int) -> str:
+    try:
+        return lib().psd_status_string(st).decode()
+    except RuntimeError:
+        return STATUS_NAMES.get(st, "?")
+
+
+def check(st: int, what: str):
+    if st != PSD_OK:
+        raise PsdError(st, what)
+
+
+def int_array(vals):
+    arr = (ctypes.c_int32 * len(vals))(*[int(v) for v in vals])
+    return arr
+
+
+def workspace_size(sizes, mode: int, flags: int = 0) -> int:
+    out = ctypes.c_size_t(0)
+    arr = int_array(sizes)
+    check(lib().psd_workspace_size(len(sizes), arr, mode, flags, ctypes.byref(out)), "psd_workspace_size")
+    return int(out.value)
+
+
+def saved_size(n: int) -> int:
+    return int(lib().psd_saved_size(n))

@@ -1,0 +1,160 @@
+// Host runtime behind the C ABI declared in include/psdproj.h: argument
+// validation, workspace layout and kernel dispatch.  No call allocates,
+// prints or synchronises; all device work goes on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "../../include/psdproj.h"
+#include "kernels.h"
+
+using namespace psd;
+
+static_assert(sizeof(psd_info) == sizeof(psd_dev_info), "psd_info layout");
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+
+bool valid_mode(int m) { return m == PSD_FP64_EIG || m == PSD_MIXED_BF16 || m == PSD_MIXED_FP32; }
+
+bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
+
+// Partial overlap of [a, a+na) and [b, b+nb) (identical ranges are allowed).
+bool partial_overlap(const void *a, size_t na, const void *b, size_t nb) {
+    const char *pa = static_cast<const char *>(a), *pb = static_cast<const char *>(b);
+    if (pa == pb && na == nb) return false;
+    return pa < pb + nb && pb < pa + na;
+}
+
+// Bump allocator over the caller's workspace.
+struct Carve {
+    char *base;
+    size_t used = 0;
+    explicit Carve(void *b) : base(static_cast<char *>(b)) {}
+    template <class T>
+    T *take(size_t count) {
+        T *p = base ? reinterpret_cast<T *>(base + used) : nullptr;
+        used = align_up(used + count * sizeof(T));
+        return p;
+    }
+};
+
+// Workspace of one large (n > 64) FP64 projection; defined with the
+// large-block path.
+size_t large_ws_bytes(int n, int mode, int flags) {
+    (void)n; (void)mode; (void)flags;
+    return 0;
+}
+
+psd_status status_of(hipError_t e) { return e == hipSuccess ? PSD_OK : PSD_EDEVICE; }
+
+}  // namespace
+
+extern "C" {
+
+const char *psd_version(void) { return "psdproj 0.1 (gfx950)"; }
+
+const char *psd_status_string(psd_status s) {
+    switch (s) {
+        case PSD_OK: return "ok";
+        case PSD_EINVAL: return "invalid argument";
+        case PSD_EWORKSPACE: return "workspace too small";
+        case PSD_ENOMEM: return "out of memory";
+        case PSD_ENONFINITE: return "non-finite input";
+        case PSD_ENOCONV: return "iteration did not converge";
+        case PSD_EDEVICE: return "HIP runtime error";
+        case PSD_EUNSUPPORTED: return "unsupported request";
+    }
+    return "unknown status";
+}
+
+size_t psd_saved_size(int32_t n) {
+    if (n < 1) return 0;
+    return sizeof(double) * ((size_t)n + 2 * (size_t)n * (size_t)n);
+}
+
+psd_status psd_workspace_size(int32_t nblocks, const int32_t *n, psd_mode mode, int32_t flags,
+                              size_t *bytes) {
+    if (nblocks < 1 || !n || !bytes || !valid_mode(mode)) return PSD_EINVAL;
+    size_t small = 0, large = 0;
+    for (int b = 0; b < nblocks; ++b) {
+        if (n[b] < 1) return PSD_EINVAL;
+        if (n[b] <= 64) ++small;
+        else large = std::max(large, large_ws_bytes(n[b], mode, flags));
+    }
+    *bytes = align_up(small * sizeof(SmallJob)) + large + kAlign;
+    return PSD_OK;
+}
+
+psd_status psd_project(int32_t n, const double *x, double *y, psd_mode mode, void *ws,
+                       size_t ws_bytes, void *stream, psd_info *info, double *saved) {
+    if (n < 1 || !x || !y || !valid_mode(mode)) return PSD_EINVAL;
+    if (!aligned8(x) || !aligned8(y) || (saved && !aligned8(saved))) return PSD_EINVAL;
+    const size_t nb = sizeof(double) * (size_t)n * (size_t)n;
+    if (partial_overlap(x, nb, y, nb)) return PSD_EINVAL;
+    size_t need = 0;
+    psd_status st = psd_workspace_size(1, &n, mode, saved ? PSD_FLAG_SAVE : 0, &need);
+    if (st != PSD_OK) return st;
+    if (ws_bytes < need || (need && !ws)) return PSD_EWORKSPACE;
+    if (ws && (reinterpret_cast<uintptr_t>(ws) % kAlign)) return PSD_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (n <= 64) {
+        SmallJob job{0, 0, n, 0};
+        return status_of(launch_small_one(job, x, y, reinterpret_cast<psd_dev_info *>(info), saved, s));
+    }
+    return PSD_EUNSUPPORTED;
+}
+
+psd_status psd_project_batched(int32_t nblocks, const int32_t *n, const double *x, double *y,
+                               psd_mode mode, void *ws, size_t ws_bytes, void *stream,
+                               psd_info *infos) {
+    if (nblocks < 1 || !n || !x || !y || !valid_mode(mode)) return PSD_EINVAL;
+    if (!aligned8(x) || !aligned8(y)) return PSD_EINVAL;
+    size_t total = 0;
+    for (int b = 0; b < nblocks; ++b) {
+        if (n[b] < 1) return PSD_EINVAL;
+        total += (size_t)n[b] * (size_t)n[b];
+    }
+    if (partial_overlap(x, total * sizeof(double), y, total * sizeof(double))) return PSD_EINVAL;
+    size_t need = 0;
+    psd_status st = psd_workspace_size(nblocks, n, mode, 0, &need);
+    if (st != PSD_OK) return st;
+    if (ws_bytes < need || !ws) return PSD_EWORKSPACE;
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign) return PSD_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    std::vector<SmallJob> small;
+    std::vector<int> large;
+    int64_t off = 0;
+    for (int b = 0; b < nblocks; ++b) {
+        if (n[b] <= 64) small.push_back(SmallJob{off, 0, n[b], b});
+        else large.push_back(b);
+        off += (int64_t)n[b] * n[b];
+    }
+    if (!large.empty()) return PSD_EUNSUPPORTED;
+    Carve cv(ws);
+    SmallJob *djobs = cv.take<SmallJob>(small.size());
+    if (!small.empty()) {
+        // Pageable source: the copy is staged before hipMemcpyAsync returns.
+        hipError_t e = hipMemcpyAsync(djobs, small.data(), small.size() * sizeof(SmallJob),
+                                      hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return PSD_EDEVICE;
+        e = launch_small(djobs, (int)small.size(), x, y, reinterpret_cast<psd_dev_info *>(infos), nullptr, s);
+        if (e != hipSuccess) return PSD_EDEVICE;
+    }
+    return PSD_OK;
+}
+
+psd_status psd_project_vjp(int32_t n, const double *x, const double *saved, const double *gy,
+                           double *gx, psd_mode mode, void *ws, size_t ws_bytes, void *stream) {
+    if (n < 1 || (!x && !saved) || !gy || !gx || !valid_mode(mode)) return PSD_EINVAL;
+    (void)ws; (void)ws_bytes; (void)stream;
+    return PSD_EUNSUPPORTED;
+}
+
+}  // extern "C"

@@ -1,0 +1,76 @@
+// Internal device helpers of the gfx950 PSD-projection library.
+//
+// Conventions used by every kernel:
+//  * A svec block (the paper's vec_R, App. D.1) holds, per row i of the upper
+//    triangle of X, X_ii followed by sqrt2 (Re, Im) of X_ij, j > i.  Read as
+//    column i of a lower triangle this is the matrix M = X^T = conj(X):
+//    M(j,i) = X_ij for j >= i.  Every kernel works on M, column-major.
+//    Pi(conj X) = conj Pi(X) and DPi commutes with conjugation, so packing
+//    the result with the same rule gives exactly svec(Pi(X)).
+//  * Complex values are double2 {re, im}; matrices are column-major with a
+//    leading dimension `ld` (elements).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace psd {
+
+typedef double2 cd;
+
+__host__ __device__ inline long svec_col_start(int n, int j) { return (long)j * (2L * n - j); }
+// Offset of sqrt2*Re M(i,j), i > j (Im follows).
+__host__ __device__ inline long svec_off(int n, int i, int j) {
+    return svec_col_start(n, j) + 1 + 2L * (i - j - 1);
+}
+
+__device__ __forceinline__ cd cmk(double r, double i) { return make_double2(r, i); }
+__device__ __forceinline__ cd cadd(cd a, cd b) { return cmk(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ cd csub(cd a, cd b) { return cmk(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ cd cmul(cd a, cd b) { return cmk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+// conj(a) * b
+__device__ __forceinline__ cd cmulc(cd a, cd b) { return cmk(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x); }
+__device__ __forceinline__ cd cconj(cd a) { return cmk(a.x, -a.y); }
+__device__ __forceinline__ cd cscale(cd a, double s) { return cmk(a.x * s, a.y * s); }
+__device__ __forceinline__ double cabs2(cd a) { return a.x * a.x + a.y * a.y; }
+// acc + a*b
+__device__ __forceinline__ cd cfma(cd a, cd b, cd acc) {
+    return cmk(fma(a.x, b.x, fma(-a.y, b.y, acc.x)), fma(a.x, b.y, fma(a.y, b.x, acc.y)));
+}
+// acc + conj(a)*b
+__device__ __forceinline__ cd cfmac(cd a, cd b, cd acc) {
+    return cmk(fma(a.x, b.x, fma(a.y, b.y, acc.x)), fma(a.x, b.y, fma(-a.y, b.x, acc.y)));
+}
+__device__ __forceinline__ cd cdiv(cd a, cd b) {
+    // Smith's algorithm
+    if (fabs(b.x) >= fabs(b.y)) {
+        double r = b.y / b.x, den = b.x + b.y * r;
+        return cmk((a.x + a.y * r) / den, (a.y - a.x * r) / den);
+    } else {
+        double r = b.x / b.y, den = b.x * r + b.y;
+        return cmk((a.x * r + a.y) / den, (a.y * r - a.x) / den);
+    }
+}
+
+__device__ __forceinline__ double warp_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Block-wide sum of one double; `red` is LDS scratch of >= blockDim/64 doubles.
+// All threads receive the total.  Contains two barriers.
+__device__ inline double block_sum(double v, double *red) {
+    v = warp_sum(v);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int k = 0; k < nw; ++k) t += red[k];
+    return t;
+}
+
+// Device-side status codes (mirror psd_status).
+enum { ST_OK = 0, ST_ENONFINITE = 4, ST_ENOCONV = 5 };
+
+}  // namespace psd

@@ -1,0 +1,55 @@
+// FP64 MFMA GEMM used by every dense stage of the large-block path:
+//   C = alpha * op(A) op(B) + beta * C      (complex or real, column-major)
+// with op in {N, C (conjugate transpose; plain transpose for real data)}.
+//
+// Operands may be split along K into two parts (p0 for k < ksplit, p1 for
+// k >= ksplit): the Hermitian rank-2k update  A -= V W^H + W V^H  is one
+// GEMM with A = [V W], B = [W V]^H.  An operand may also carry a per-k real
+// scale (columns of op(A) scaled by s[k]), which builds V diag(lambda) on
+// the fly for the reconstruction.
+//
+// Epilogues: plain store; svec pack of the lower triangle (the output is the
+// projection, written straight into the caller's svec); Daleckii-Krein
+// weights Gamma(lambda_i, lambda_j) applied to the product before the store.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace psd {
+
+enum : int { OP_N = 0, OP_C = 1 };
+enum : int { EPI_STORE = 0, EPI_SVEC = 1, EPI_GAMMA = 2 };
+
+struct GemmOperand {
+    const void *p0;   // part used for k < ksplit
+    const void *p1;   // part used for k >= ksplit (may equal p0 with ksplit = K)
+    int64_t ld0, ld1; // leading dimensions (elements)
+    int ksplit;
+    int op;           // OP_N or OP_C
+    const double *kscale;  // optional per-k scale (A only)
+};
+
+struct GemmDesc {
+    int M, N, K;
+    int lower_only;   // skip tiles strictly above the diagonal
+    GemmOperand A, B;
+    void *C;
+    int64_t ldc;
+    double alpha, beta;
+    // EPI_SVEC: y (svec of order N == M), x base (nullable), sign
+    double *y;
+    const double *xbase;
+    int64_t svec_n;
+    double sign;
+    // EPI_GAMMA: eigenvalues for rows / columns
+    const double *lam;
+};
+
+// Launch one GEMM described by `d` (grid sized from d) on stream st.
+hipError_t gemm_launch(const GemmDesc &d, bool complex_data, int epilogue, hipStream_t st);
+// Launch `count` GEMMs whose descriptors live in device memory; every one
+// has M <= maxM, N <= maxN (grid sized from those bounds).
+hipError_t gemm_launch_batched(const GemmDesc *ddesc, int count, int maxM, int maxN, bool complex_data,
+                               hipStream_t st);
+
+}  // namespace psd

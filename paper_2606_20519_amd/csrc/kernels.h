@@ -1,0 +1,30 @@
+// Internal launch interface between the host runtime (abi.hip) and the
+// kernels.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace psd {
+
+// Same layout as the public psd_info.
+struct psd_dev_info {
+    int32_t status, n_pos, n_neg, iters, fallback, reserved;
+    double est_rel_err;
+};
+
+// One small block (order <= 64) for the whole-block LDS kernel.
+struct SmallJob {
+    int64_t offset;        // svec offset of the block in x / y
+    int64_t saved_offset;  // offset of its saved record (doubles), if saving
+    int32_t n;
+    int32_t info_index;
+};
+
+size_t small_lds_bytes();
+hipError_t launch_small(const SmallJob *jobs, int njobs, const double *x, double *y,
+                        psd_dev_info *infos, double *saved, hipStream_t st);
+hipError_t launch_small_one(const SmallJob &job, const double *x, double *y, psd_dev_info *info,
+                            double *saved, hipStream_t st);
+
+}  // namespace psd

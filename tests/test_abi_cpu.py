@@ -1,0 +1,87 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol
+include/psdproj.h declares, and rejects bad arguments before touching the
+device (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2606_20519_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2606_20519_amd import build
+        build.build()
+    return _lib
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "psdproj.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(psd_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = header_functions()
+    assert set(names) == set(L.EXPORTS), names
+    lib = L.lib()
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(L):
+    lib = L.lib()
+    for st in range(8):
+        assert lib.psd_status_string(st)
+    assert lib.psd_version().startswith(b"psdproj")
+
+
+def test_workspace_size_validation(L):
+    lib = L.lib()
+    out = ctypes.c_size_t(0)
+    n = L.int_array([16])
+    assert lib.psd_workspace_size(1, n, 0, 0, ctypes.byref(out)) == 0 and out.value > 0
+    assert lib.psd_workspace_size(0, n, 0, 0, ctypes.byref(out)) == 1
+    assert lib.psd_workspace_size(1, L.int_array([0]), 0, 0, ctypes.byref(out)) == 1
+    assert lib.psd_workspace_size(1, n, 9, 0, ctypes.byref(out)) == 1
+    assert lib.psd_workspace_size(1, None, 0, 0, ctypes.byref(out)) == 1
+    # monotone in n for the large path
+    sizes = []
+    for k in (65, 100, 625, 1296):
+        assert lib.psd_workspace_size(1, L.int_array([k]), 0, 0, ctypes.byref(out)) == 0
+        sizes.append(out.value)
+    assert sizes == sorted(sizes)
+
+
+def test_saved_size(L):
+    assert L.saved_size(1) == 8 * (1 + 2)
+    assert L.saved_size(16) == 8 * (16 + 2 * 256)
+    assert L.saved_size(0) == 0
+
+
+def test_project_rejects_bad_arguments_on_host(L):
+    lib = L.lib()
+    fake = ctypes.c_void_p(0x10000)   # never dereferenced: validation fails first
+    fake2 = ctypes.c_void_p(0x10000 + 8 * 256)
+    ws = ctypes.c_void_p(0x100000)
+    # n < 1, null pointers, bad mode
+    assert lib.psd_project(0, fake, fake2, 0, ws, 1 << 20, None, None, None) == 1
+    assert lib.psd_project(16, None, fake2, 0, ws, 1 << 20, None, None, None) == 1
+    assert lib.psd_project(16, fake, None, 0, ws, 1 << 20, None, None, None) == 1
+    assert lib.psd_project(16, fake, fake2, 5, ws, 1 << 20, None, None, None) == 1
+    # misaligned pointer
+    assert lib.psd_project(16, ctypes.c_void_p(0x10004), fake2, 0, ws, 1 << 20, None, None, None) == 1
+    # partial overlap of x and y
+    assert lib.psd_project(16, fake, ctypes.c_void_p(0x10000 + 8), 0, ws, 1 << 20, None, None, None) == 1
+    # workspace too small
+    assert lib.psd_project(16, fake, fake2, 0, ws, 0, None, None, None) == 2
+    # batched: bad sizes
+    assert lib.psd_project_batched(2, L.int_array([4, 0]), fake, fake2, 0, ws, 1 << 20, None, None) == 1
+    assert lib.psd_project_batched(0, L.int_array([4]), fake, fake2, 0, ws, 1 << 20, None, None) == 1
+    # vjp: needs x or saved
+    assert lib.psd_project_vjp(16, None, None, fake, fake2, 0, ws, 1 << 20, None) == 1
+    assert lib.psd_project_vjp(0, fake, None, fake, fake2, 0, ws, 1 << 20, None) == 1
