@@ -10,6 +10,7 @@
 
 #include "../../include/psdproj.h"
 #include "kernels.h"
+#include "large.h"
 
 using namespace psd;
 
@@ -44,11 +45,39 @@ struct Carve {
     }
 };
 
-// Workspace of one large (n > 64) FP64 projection; defined with the
-// large-block path.
+// Workspace of one FP64 large-block computation of order n.
 size_t large_ws_bytes(int n, int mode, int flags) {
-    (void)n; (void)mode; (void)flags;
-    return 0;
+    (void)mode;
+    return large_layout(n, flags, nullptr, nullptr);
+}
+
+// Full FP64 eigen pipeline on one block: unpack, tridiagonalise, block
+// reflectors, divide and conquer.  Leaves w.lam / w.Zfinal set.
+hipError_t large_eigen(LargeWs &w, const double *x, hipStream_t s) {
+    hipError_t e;
+    if ((e = large_init(w, s)) != hipSuccess) return e;
+    if ((e = large_unpack(w, x, s)) != hipSuccess) return e;
+    if ((e = large_tridiag(w, s)) != hipSuccess) return e;
+    if ((e = large_compute_T(w, s)) != hipSuccess) return e;
+    return large_dc(w, s);
+}
+
+// y = Pi(x) for one block of order n through the large-block path.
+hipError_t large_project(int n, const double *x, double *y, void *ws, hipStream_t s, psd_dev_info *info,
+                         double *saved) {
+    LargeWs w;
+    large_layout(n, saved ? PSD_FLAG_SAVE : 0, ws, &w);
+    hipError_t e = large_eigen(w, x, s);
+    if (e != hipSuccess) return e;
+    if (saved) {
+        if ((e = large_select(w, info, s, true)) != hipSuccess) return e;
+        if ((e = large_backtransform(w, n, s)) != hipSuccess) return e;
+        if ((e = large_save(w, saved, s)) != hipSuccess) return e;
+        return large_reconstruct(w, x, y, n, s);
+    }
+    if ((e = large_select(w, info, s, false)) != hipSuccess) return e;
+    if ((e = large_backtransform(w, w.kmax, s)) != hipSuccess) return e;
+    return large_reconstruct(w, x, y, w.kmax, s);
 }
 
 psd_status status_of(hipError_t e) { return e == hipSuccess ? PSD_OK : PSD_EDEVICE; }
@@ -84,7 +113,7 @@ psd_status psd_workspace_size(int32_t nblocks, const int32_t *n, psd_mode mode, 
     size_t small = 0, large = 0;
     for (int b = 0; b < nblocks; ++b) {
         if (n[b] < 1) return PSD_EINVAL;
-        if (n[b] <= 64) ++small;
+        if (n[b] <= 64 && !(flags & PSD_FLAG_SAVE)) ++small;
         else large = std::max(large, large_ws_bytes(n[b], mode, flags));
     }
     *bytes = align_up(small * sizeof(SmallJob)) + large + kAlign;
@@ -102,12 +131,14 @@ psd_status psd_project(int32_t n, const double *x, double *y, psd_mode mode, voi
     if (st != PSD_OK) return st;
     if (ws_bytes < need || (need && !ws)) return PSD_EWORKSPACE;
     if (ws && (reinterpret_cast<uintptr_t>(ws) % kAlign)) return PSD_EINVAL;
+    if (mode != PSD_FP64_EIG) return PSD_EUNSUPPORTED;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    psd_dev_info *dinfo = reinterpret_cast<psd_dev_info *>(info);
     if (n <= 64) {
         SmallJob job{0, 0, n, 0};
-        return status_of(launch_small_one(job, x, y, reinterpret_cast<psd_dev_info *>(info), saved, s));
+        return status_of(launch_small_one(job, x, y, dinfo, saved, s));
     }
-    return PSD_EUNSUPPORTED;
+    return status_of(large_project(n, x, y, ws, s, dinfo, saved));
 }
 
 psd_status psd_project_batched(int32_t nblocks, const int32_t *n, const double *x, double *y,
@@ -136,9 +167,24 @@ psd_status psd_project_batched(int32_t nblocks, const int32_t *n, const double *
         else large.push_back(b);
         off += (int64_t)n[b] * n[b];
     }
-    if (!large.empty()) return PSD_EUNSUPPORTED;
+    if (mode != PSD_FP64_EIG) return PSD_EUNSUPPORTED;
     Carve cv(ws);
     SmallJob *djobs = cv.take<SmallJob>(small.size());
+    void *lws = cv.base + cv.used;
+    {
+        // large blocks one after another on the stream, sharing one workspace
+        int64_t o = 0;
+        int li = 0;
+        for (int b = 0; b < nblocks; ++b) {
+            if (li < (int)large.size() && large[li] == b) {
+                psd_dev_info *inf = infos ? reinterpret_cast<psd_dev_info *>(infos) + b : nullptr;
+                hipError_t e = large_project(n[b], x + o, y + o, lws, s, inf, nullptr);
+                if (e != hipSuccess) return PSD_EDEVICE;
+                ++li;
+            }
+            o += (int64_t)n[b] * n[b];
+        }
+    }
     if (!small.empty()) {
         // Pageable source: the copy is staged before hipMemcpyAsync returns.
         hipError_t e = hipMemcpyAsync(djobs, small.data(), small.size() * sizeof(SmallJob),
@@ -153,8 +199,29 @@ psd_status psd_project_batched(int32_t nblocks, const int32_t *n, const double *
 psd_status psd_project_vjp(int32_t n, const double *x, const double *saved, const double *gy,
                            double *gx, psd_mode mode, void *ws, size_t ws_bytes, void *stream) {
     if (n < 1 || (!x && !saved) || !gy || !gx || !valid_mode(mode)) return PSD_EINVAL;
-    (void)ws; (void)ws_bytes; (void)stream;
-    return PSD_EUNSUPPORTED;
+    if ((x && !aligned8(x)) || (saved && !aligned8(saved)) || !aligned8(gy) || !aligned8(gx)) return PSD_EINVAL;
+    const size_t nb = sizeof(double) * (size_t)n * (size_t)n;
+    if (partial_overlap(gy, nb, gx, nb)) return PSD_EINVAL;
+    size_t need = 0;
+    psd_status st = psd_workspace_size(1, &n, mode, PSD_FLAG_SAVE, &need);
+    if (st != PSD_OK) return st;
+    if (ws_bytes < need || !ws) return PSD_EWORKSPACE;
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign) return PSD_EINVAL;
+    if (mode != PSD_FP64_EIG) return PSD_EUNSUPPORTED;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    LargeWs w;
+    large_layout(n, PSD_FLAG_SAVE, ws, &w);
+    hipError_t e;
+    if (saved) {
+        if ((e = large_init(w, s)) != hipSuccess) return PSD_EDEVICE;
+        if ((e = large_load_saved(w, saved, s)) != hipSuccess) return PSD_EDEVICE;
+        w.lam = w.D0;
+    } else {
+        if ((e = large_eigen(w, x, s)) != hipSuccess) return PSD_EDEVICE;
+        if ((e = large_select(w, nullptr, s, true)) != hipSuccess) return PSD_EDEVICE;
+        if ((e = large_backtransform(w, n, s)) != hipSuccess) return PSD_EDEVICE;
+    }
+    return status_of(large_vjp_from_v(w, gy, gx, s));
 }
 
 }  // extern "C"

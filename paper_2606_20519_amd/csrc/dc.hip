@@ -1,0 +1,399 @@
+// Divide-and-conquer eigensolver for the real symmetric tridiagonal T
+// (Cuppen's method with the Gu-Eisenstat eigenvector formula), bottom-up:
+//
+//  * T is cut into nl = 2^L leaves of <= DC_LEAF rows.  At every cut
+//    between rows m-1 and m, T = diag(T1, T2) + |beta| u u^T with
+//    beta = e[m-1], u = e_{m-1} + sgn(beta) e_m, T1/T2 having their touching
+//    diagonal entries reduced by |beta|.
+//  * Leaves: implicit QL in LDS (one workgroup each).
+//  * Merge of two solved halves (D1, Q1), (D2, Q2):
+//      T = diag(Q1,Q2) (D + rho z z^T) diag(Q1,Q2)^T,
+//      z = [last row of Q1, sgn(beta) first row of Q2] / sqrt2, rho = 2|beta|.
+//    Deflation: components with rho|z_i| <= tol are eigenpairs already; two
+//    close poles are combined by a plane rotation that zeroes one z entry.
+//    The k remaining roots of 1 + rho sum z_i^2/(d_i - lambda) = 0 are found
+//    one per thread in shifted coordinates lambda = d_o + tau (o the nearer
+//    pole) by a safeguarded two-pole rational iteration; z is then recomputed
+//    from the roots (Loewner), which makes the computed vectors
+//    u_j = (zhat_i / (d_i - lambda_j))_i numerically orthogonal.
+//    Q_new = diag(Q1, Q2) U is two FP64 MFMA GEMMs per merge, batched over
+//    the merges of a level.
+#include <algorithm>
+#include <utility>
+
+#include "common.h"
+#include "large.h"
+#include "ql.h"
+
+namespace psd {
+
+namespace {
+
+constexpr double EPS = 2.220446049250313e-16;
+constexpr int LEAF_MAX = 64;
+
+__host__ __device__ inline int leaf_bound(int i, int n, int nl) { return (int)(((int64_t)i * n) / nl); }
+
+// Vectors of the merge workspace (offsets in units of n; a merge [a,b) uses
+// indices a..b-1 of each).
+enum { DZ = 0, DDM, DDD, DDH, DZH, DTAU, DLAM, DZHAT, DRC, DRS, DRHO, DCOUNT };
+enum { IPERM = 0, IKEEP, IDEFL, IRP, IRN, IORG, ICOL, ICOUNT };
+enum { SK = 0, SND, SNR, SCOUNT };
+
+__global__ void __launch_bounds__(256) dc_leaf_kernel(const double *__restrict__ d, const double *__restrict__ e,
+                                                      int n, int nl, double *D, double *Q, int64_t ldq,
+                                                      int *status) {
+    __shared__ double dl[LEAF_MAX], el[LEAF_MAX], Z[LEAF_MAX * LEAF_MAX];
+    __shared__ double rc[LEAF_MAX], rs[LEAF_MAX];
+    __shared__ int ri[LEAF_MAX], rankv[LEAF_MAX];
+    __shared__ int nrot_s, done_s;
+    const int q = blockIdx.x, t = threadIdx.x;
+    const int a = leaf_bound(q, n, nl), b = leaf_bound(q + 1, n, nl), sz = b - a;
+    if (t < sz) {
+        double dv = d[a + t];
+        if (t == 0 && a > 0) dv -= fabs(e[a - 1]);
+        if (t == sz - 1 && b < n) dv -= fabs(e[b - 1]);
+        dl[t] = dv;
+        el[t] = (t < sz - 1) ? e[a + t] : 0.0;
+    }
+    for (int idx = t; idx < sz * sz; idx += blockDim.x) Z[idx] = (idx % sz == idx / sz) ? 1.0 : 0.0;
+    __syncthreads();
+    const int st = ql_implicit(dl, el, Z, sz, sz, rc, rs, ri, &nrot_s, &done_s);
+    if (t == 0 && st != ST_OK && status[2] == ST_OK) status[2] = st;
+    if (t < sz) {
+        const double v = dl[t];
+        int rank = 0;
+        for (int k = 0; k < sz; ++k) rank += (dl[k] < v) || (dl[k] == v && k < t);
+        rankv[t] = rank;
+        D[a + rank] = v;
+    }
+    __syncthreads();
+    for (int idx = t; idx < sz * sz; idx += blockDim.x) {
+        const int r = idx % sz, c = idx / sz;
+        Q[(a + r) + (int64_t)(a + rankv[c]) * ldq] = Z[r + c * sz];
+    }
+}
+
+struct MergeGeo {
+    int a, m, b;
+};
+__device__ inline MergeGeo merge_geo(int level, int q, int n, int nl) {
+    MergeGeo g;
+    g.a = leaf_bound(q << level, n, nl);
+    g.m = leaf_bound((q << level) + (1 << (level - 1)), n, nl);
+    g.b = leaf_bound((q + 1) << level, n, nl);
+    return g;
+}
+
+__global__ void __launch_bounds__(256) dc_prep_kernel(int level, int n, int nl, const double *__restrict__ e,
+                                                      const double *__restrict__ Dcur, const double *Qcur,
+                                                      double *Qnext, int64_t ldq, double *U, double *dv,
+                                                      int *iv, int *sv, GemmDesc *gd) {
+    __shared__ double red[8];
+    const int q = blockIdx.x, t = threadIdx.x;
+    const MergeGeo g = merge_geo(level, q, n, nl);
+    const int a = g.a, n1 = g.m - g.a, n2 = g.b - g.m, nm = g.b - g.a;
+    const double beta = e[g.m - 1];
+    const double rho = 2.0 * fabs(beta);
+    const double sgn = beta < 0.0 ? -1.0 : 1.0;
+    const double rs2 = 0.70710678118654752440;
+    double *z = dv + (int64_t)DZ * n + a, *Dm = dv + (int64_t)DDM * n + a, *dd = dv + (int64_t)DDD * n + a;
+    double *dh = dv + (int64_t)DDH * n + a, *zh = dv + (int64_t)DZH * n + a;
+    double *rcs = dv + (int64_t)DRC * n + a, *rsn = dv + (int64_t)DRS * n + a;
+    int *perm = iv + (int64_t)IPERM * n + a, *keep = iv + (int64_t)IKEEP * n + a;
+    int *defl = iv + (int64_t)IDEFL * n + a, *rp = iv + (int64_t)IRP * n + a, *rn = iv + (int64_t)IRN * n + a;
+    double zmax = 0.0, dmax = 0.0;
+    for (int i = t; i < nm; i += blockDim.x) {
+        const double zi = (i < n1) ? Qcur[(g.m - 1) + (int64_t)(a + i) * ldq] * rs2
+                                   : sgn * Qcur[g.m + (int64_t)(g.m + i - n1) * ldq] * rs2;
+        z[i] = zi;
+        const double di = Dcur[a + i];
+        Dm[i] = di;
+        dd[i] = di;
+        zmax = fmax(zmax, fabs(zi));
+        dmax = fmax(dmax, fabs(di));
+    }
+    // block max via the sum helper on a two-pass scheme
+    {
+        __shared__ double mx[2][4];
+        double v1 = zmax, v2 = dmax;
+        for (int o = 32; o > 0; o >>= 1) {
+            v1 = fmax(v1, __shfl_xor(v1, o, 64));
+            v2 = fmax(v2, __shfl_xor(v2, o, 64));
+        }
+        if ((t & 63) == 0) { mx[0][t >> 6] = v1; mx[1][t >> 6] = v2; }
+        __syncthreads();
+        zmax = fmax(fmax(mx[0][0], mx[0][1]), fmax(mx[0][2], mx[0][3]));
+        dmax = fmax(fmax(mx[1][0], mx[1][1]), fmax(mx[1][2], mx[1][3]));
+    }
+    (void)red;
+    __syncthreads();
+    if (t == 0) {
+        // merge the two ascending halves into one ascending order
+        int i1 = 0, i2 = n1, o = 0;
+        while (i1 < n1 && i2 < nm) perm[o++] = (Dm[i2] < Dm[i1]) ? i2++ : i1++;
+        while (i1 < n1) perm[o++] = i1++;
+        while (i2 < nm) perm[o++] = i2++;
+        // deflation
+        const double tol = 8.0 * EPS * fmax(dmax, rho * zmax);
+        int k = 0, nd = 0, nr = 0, prev = -1;
+        for (int idx = 0; idx < nm; ++idx) {
+            const int p = perm[idx];
+            if (rho * fabs(z[p]) <= tol) { defl[nd++] = p; continue; }
+            if (prev >= 0) {
+                const double tz = hypot(z[prev], z[p]);
+                const double c = z[p] / tz, s = -z[prev] / tz;
+                const double tt = dd[p] - dd[prev];
+                if (fabs(tt * c * s) <= tol) {
+                    z[p] = tz;
+                    z[prev] = 0.0;
+                    const double dp = dd[prev] * c * c + dd[p] * s * s;
+                    const double dn = dd[prev] * s * s + dd[p] * c * c;
+                    dd[prev] = dp;
+                    dd[p] = dn;
+                    rp[nr] = prev; rn[nr] = p; rcs[nr] = c; rsn[nr] = s; ++nr;
+                    defl[nd++] = prev;
+                    --k;
+                }
+            }
+            keep[k++] = p;
+            prev = p;
+        }
+        for (int i = 0; i < k; ++i) { dh[i] = dd[keep[i]]; zh[i] = z[keep[i]]; }
+        sv[q * SCOUNT + SK] = k;
+        sv[q * SCOUNT + SND] = nd;
+        sv[q * SCOUNT + SNR] = nr;
+        dv[(int64_t)DRHO * n + q] = rho;
+        // merge GEMMs: Qnext[a:m, a:b] = Q1 U[0:n1, :], Qnext[m:b, a:b] = Q2 U[n1:, :]
+        GemmDesc top{}, bot{};
+        top.M = n1; top.N = nm; top.K = n1;
+        top.A = GemmOperand{Qcur + a + (int64_t)a * ldq, Qcur + a + (int64_t)a * ldq, ldq, ldq, n1, OP_N, nullptr};
+        top.B = GemmOperand{U + (int64_t)a * n + a, U + (int64_t)a * n + a, n, n, n1, OP_C, nullptr};
+        top.C = Qnext + a + (int64_t)a * ldq; top.ldc = ldq; top.alpha = 1.0; top.beta = 0.0;
+        bot.M = n2; bot.N = nm; bot.K = n2;
+        bot.A = GemmOperand{Qcur + g.m + (int64_t)g.m * ldq, Qcur + g.m + (int64_t)g.m * ldq, ldq, ldq, n2, OP_N, nullptr};
+        bot.B = GemmOperand{U + (int64_t)g.m * n + a, U + (int64_t)g.m * n + a, n, n, n2, OP_C, nullptr};
+        bot.C = Qnext + g.m + (int64_t)a * ldq; bot.ldc = ldq; bot.alpha = 1.0; bot.beta = 0.0;
+        gd[2 * q] = top;
+        gd[2 * q + 1] = bot;
+    }
+}
+
+// Root j of 1 + rho sum_i zh_i^2 / (dh_i - lambda) = 0 (dh ascending, gaps > 0).
+// Returns the origin pole o and tau with lambda = dh[o] + tau.
+__device__ void secular_root(const double *dh, const double *zh, int k, double rho, int j, int *o_out,
+                             double *tau_out) {
+    int o;
+    double lo, hi;
+    if (j < k - 1) {
+        const double gap = dh[j + 1] - dh[j];
+        double f = 1.0;
+        for (int i = 0; i < k; ++i) f += rho * zh[i] * zh[i] / ((dh[i] - dh[j]) - 0.5 * gap);
+        if (f > 0.0) { o = j; lo = 0.0; hi = 0.5 * gap; }
+        else { o = j + 1; lo = -0.5 * gap; hi = 0.0; }
+    } else {
+        double zz = 0.0;
+        for (int i = 0; i < k; ++i) zz += zh[i] * zh[i];
+        o = j; lo = 0.0; hi = rho * zz;
+    }
+    const double dO = dh[o];
+    double tau = 0.5 * (lo + hi);
+    for (int it = 0; it < 100; ++it) {
+        double psi = 0.0, phi = 0.0, dpsi = 0.0, dphi = 0.0, sabs = 0.0;
+        for (int i = 0; i < k; ++i) {
+            const double diff = (dh[i] - dO) - tau;
+            const double w = rho * zh[i] * zh[i];
+            const double term = w / diff;
+            sabs += fabs(term);
+            if (i <= j) { psi += term; dpsi += term / diff; }
+            else { phi += term; dphi += term / diff; }
+        }
+        const double f = 1.0 + psi + phi;
+        if (f < 0.0) lo = tau; else hi = tau;
+        if (f == 0.0 || fabs(f) <= 8.0 * EPS * (1.0 + sabs)) break;
+        if (hi - lo <= 2.0 * EPS * fmax(fabs(lo), fabs(hi))) break;
+        const double a_ = (dh[j] - dO) - tau;
+        double tn;
+        bool ok = false;
+        if (j < k - 1) {
+            const double b_ = (dh[j + 1] - dO) - tau;
+            const double s = dpsi * a_ * a_, S = dphi * b_ * b_;
+            const double c = f - s / a_ - S / b_;
+            const double B = c * (a_ + b_) + s + S;
+            const double disc = B * B - 4.0 * c * f * a_ * b_;
+            double eta = 0.0;
+            if (disc >= 0.0) {
+                const double sq = sqrt(disc);
+                if (c == 0.0) { if (B != 0.0) { eta = f * a_ * b_ / B; ok = true; } }
+                else if (B > 0.0) { eta = 2.0 * f * a_ * b_ / (B + sq); ok = true; }
+                else { eta = (B - sq) / (2.0 * c); ok = true; }
+            }
+            tn = tau + eta;
+        } else {
+            const double s = dpsi * a_ * a_;
+            const double c = 1.0 + phi + psi - s / a_;
+            tn = tau + a_ + s / c;
+            ok = c > 0.0;
+        }
+        if (!ok || !(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
+        if (fabs(tn - tau) <= 2.0 * EPS * fabs(tn)) { tau = tn; break; }
+        tau = tn;
+    }
+    *o_out = o;
+    *tau_out = tau;
+}
+
+__global__ void __launch_bounds__(256) dc_secular_kernel(int level, int n, int nl, double *dv, int *iv,
+                                                         const int *sv) {
+    const int q = blockIdx.y;
+    const MergeGeo g = merge_geo(level, q, n, nl);
+    const int a = g.a;
+    const int k = sv[q * SCOUNT + SK];
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= k) return;
+    const double rho = dv[(int64_t)DRHO * n + q];
+    const double *dh = dv + (int64_t)DDH * n + a, *zh = dv + (int64_t)DZH * n + a;
+    int o;
+    double tau;
+    secular_root(dh, zh, k, rho, j, &o, &tau);
+    iv[(int64_t)IORG * n + a + j] = o;
+    dv[(int64_t)DTAU * n + a + j] = tau;
+    dv[(int64_t)DLAM * n + a + j] = dh[o] + tau;
+}
+
+// zhat_i^2 = prod_j (lambda_j - d_i) / (rho prod_{l != i} (d_l - d_i)), paired
+// so that every factor is a ratio in (0, 1] (interlacing).
+__global__ void __launch_bounds__(256) dc_lowner_kernel(int level, int n, int nl, double *dv, const int *iv,
+                                                        const int *sv) {
+    const int q = blockIdx.y;
+    const MergeGeo g = merge_geo(level, q, n, nl);
+    const int a = g.a;
+    const int k = sv[q * SCOUNT + SK];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= k) return;
+    const double rho = dv[(int64_t)DRHO * n + q];
+    const double *dh = dv + (int64_t)DDH * n + a, *zh = dv + (int64_t)DZH * n + a;
+    const double *tau = dv + (int64_t)DTAU * n + a;
+    const int *org = iv + (int64_t)IORG * n + a;
+    const double di = dh[i];
+    double prod = ((dh[org[k - 1]] - di) + tau[k - 1]) / rho;
+    for (int jj = 0; jj < k - 1; ++jj) {
+        const double num = (dh[org[jj]] - di) + tau[jj];
+        const double den = (jj < i) ? (dh[jj] - di) : (dh[jj + 1] - di);
+        prod *= num / den;
+    }
+    dv[(int64_t)DZHAT * n + a + i] = copysign(sqrt(fmax(prod, 0.0)), zh[i]);
+}
+
+// Final ascending order of the merged eigenvalues (secular roots + deflated
+// values); ties broken by element id.  Writes the eigenvalues and, per final
+// column, its source (j >= 0: root j; -(1+p): deflated local index p).
+__global__ void __launch_bounds__(256) dc_order_kernel(int level, int n, int nl, const double *dv, int *iv,
+                                                       const int *sv, double *Dnext) {
+    const int q = blockIdx.y;
+    const MergeGeo g = merge_geo(level, q, n, nl);
+    const int a = g.a, nm = g.b - g.a;
+    const int k = sv[q * SCOUNT + SK], nd = sv[q * SCOUNT + SND];
+    const int el = blockIdx.x * blockDim.x + threadIdx.x;
+    if (el >= nm) return;
+    const double *lam = dv + (int64_t)DLAM * n + a, *dd = dv + (int64_t)DDD * n + a;
+    const int *defl = iv + (int64_t)IDEFL * n + a;
+    const double v = el < k ? lam[el] : dd[defl[el - k]];
+    // roots (value, id) are lexicographically ascending: binary search
+    int lo = 0, hi = k;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const bool less = lam[mid] < v || (lam[mid] == v && mid < el);
+        if (less) lo = mid + 1; else hi = mid;
+    }
+    int rank = lo;
+    for (int p = 0; p < nd; ++p) {
+        const double u = dd[defl[p]];
+        rank += (u < v) || (u == v && k + p < el);
+    }
+    iv[(int64_t)ICOL * n + a + rank] = el < k ? el : -(1 + defl[el - k]);
+    Dnext[a + rank] = v;
+}
+
+// Column `col` of the merge matrix U (row-major, ld n, block at (a, a)).
+__global__ void __launch_bounds__(256) dc_vectors_kernel(int level, int n, int nl, const double *dv,
+                                                         const int *iv, const int *sv, double *U) {
+    const int q = blockIdx.y;
+    const MergeGeo g = merge_geo(level, q, n, nl);
+    const int a = g.a, nm = g.b - g.a;
+    const int k = sv[q * SCOUNT + SK], nr = sv[q * SCOUNT + SNR];
+    const int col = blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= nm) return;
+    const double *dh = dv + (int64_t)DDH * n + a, *zhat = dv + (int64_t)DZHAT * n + a;
+    const double *tau = dv + (int64_t)DTAU * n + a;
+    const double *rcs = dv + (int64_t)DRC * n + a, *rsn = dv + (int64_t)DRS * n + a;
+    const int *keep = iv + (int64_t)IKEEP * n + a, *org = iv + (int64_t)IORG * n + a;
+    const int *rp = iv + (int64_t)IRP * n + a, *rn = iv + (int64_t)IRN * n + a;
+    int src = iv[(int64_t)ICOL * n + a + col];
+    if (src >= k || src < -nm) src = -nm - 1;  // only reachable with non-finite input
+    double *Uc = U + (int64_t)a * n + a + col;  // U[r][col] = Uc[r * n]
+    for (int r = 0; r < nm; ++r) Uc[(int64_t)r * n] = 0.0;
+    if (src >= 0) {
+        const int j = src, o = org[j];
+        const double tj = tau[j], dO = dh[o];
+        double nrm = 0.0;
+        for (int i = 0; i < k; ++i) {
+            const double u = zhat[i] / ((dh[i] - dO) - tj);
+            nrm += u * u;
+        }
+        const double inv = 1.0 / sqrt(nrm);
+        for (int i = 0; i < k; ++i) Uc[(int64_t)keep[i] * n] = zhat[i] / ((dh[i] - dO) - tj) * inv;
+    } else if (src >= -nm) {
+        Uc[(int64_t)(-1 - src) * n] = 1.0;
+    }
+    // undo the deflating rotations, last first
+    for (int r = nr - 1; r >= 0; --r) {
+        const int pp = rp[r], pn = rn[r];
+        const double c = rcs[r], s = rsn[r];
+        const double up = Uc[(int64_t)pp * n], un = Uc[(int64_t)pn * n];
+        Uc[(int64_t)pp * n] = c * up - s * un;
+        Uc[(int64_t)pn * n] = s * up + c * un;
+    }
+}
+
+int dc_num_leaves(int n) {
+    int nl = 1;
+    while ((n + nl - 1) / nl > DC_LEAF) nl <<= 1;
+    return nl;
+}
+
+}  // namespace
+
+hipError_t large_dc(LargeWs &w, hipStream_t st) {
+    const int n = w.n;
+    const int nl = dc_num_leaves(n);
+    int64_t ldq = n;
+    double *Qc = w.Q0, *Qn = w.Q1, *Dc = w.D0, *Dn = w.D1;
+    hipLaunchKernelGGL(dc_leaf_kernel, dim3(nl), dim3(256), 0, st, w.d, w.e, n, nl, Dc, Qc, ldq, w.ksel);
+    for (int level = 1; (1 << level) <= nl; ++level) {
+        const int nmerge = nl >> level;
+        int maxnm = 0, maxhalf = 0;
+        for (int q = 0; q < nmerge; ++q) {
+            const int a = leaf_bound(q << level, n, nl), m = leaf_bound((q << level) + (1 << (level - 1)), n, nl),
+                      b = leaf_bound((q + 1) << level, n, nl);
+            maxnm = std::max(maxnm, b - a);
+            maxhalf = std::max(maxhalf, std::max(m - a, b - m));
+        }
+        hipLaunchKernelGGL(dc_prep_kernel, dim3(nmerge), dim3(256), 0, st, level, n, nl, w.e, Dc, Qc, Qn, ldq, w.U,
+                           w.dcd, w.dci, w.dcs, w.gdesc);
+        dim3 grid((maxnm + 255) / 256, nmerge);
+        hipLaunchKernelGGL(dc_secular_kernel, grid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs);
+        hipLaunchKernelGGL(dc_lowner_kernel, grid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs);
+        hipLaunchKernelGGL(dc_order_kernel, grid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs, Dn);
+        hipLaunchKernelGGL(dc_vectors_kernel, grid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs, w.U);
+        hipError_t e = gemm_launch_batched(w.gdesc, 2 * nmerge, maxhalf, maxnm, false, st);
+        if (e != hipSuccess) return e;
+        std::swap(Qc, Qn);
+        std::swap(Dc, Dn);
+    }
+    w.lam = Dc;
+    w.Zfinal = Qc;
+    return hipGetLastError();
+}
+
+}  // namespace psd

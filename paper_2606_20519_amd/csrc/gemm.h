@@ -43,10 +43,21 @@ struct GemmDesc {
     double sign;
     // EPI_GAMMA: eigenvalues for rows / columns
     const double *lam;
+    // Sizes known only on the device: N = min(N, *dN), K = min(K, *dK).
+    const int *dN;
+    const int *dK;
+    // EPI_SVEC: sign read from the device (base x used iff sign < 0).
+    const double *dsign;
+    // Split-K: blockIdx.z handles K range [z*kchunk, (z+1)*kchunk) and
+    // writes its partial product to C + z*c_zstride (beta must be 0).
+    int kchunk;
+    int64_t c_zstride;
 };
 
 // Launch one GEMM described by `d` (grid sized from d) on stream st.
 hipError_t gemm_launch(const GemmDesc &d, bool complex_data, int epilogue, hipStream_t st);
+// Number of split-K slices gemm_launch uses for `d` (1 without kchunk).
+inline int gemm_kslices(const GemmDesc &d) { return d.kchunk > 0 ? (d.K + d.kchunk - 1) / d.kchunk : 1; }
 // Launch `count` GEMMs whose descriptors live in device memory; every one
 // has M <= maxM, N <= maxN (grid sized from those bounds).
 hipError_t gemm_launch_batched(const GemmDesc *ddesc, int count, int maxM, int maxN, bool complex_data,

@@ -47,12 +47,21 @@ __device__ __forceinline__ double gamma_dk(double a, double b) {
 }
 
 template <typename T, int OPA, int OPB, int EPI>
-__device__ void gemm_tile(const GemmDesc &d, int ti, int tj) {
+__device__ void gemm_tile(const GemmDesc &dd, int ti, int tj, int tz) {
     __shared__ T As[BK][BM + PAD];
     __shared__ T Bs[BK][BN + PAD];
+    GemmDesc d = dd;
+    if (d.dN) d.N = min(d.N, *d.dN);
+    if (d.dK) d.K = min(d.K, *d.dK);
     const int i0 = ti * BM, j0 = tj * BN;
     if (i0 >= d.M || j0 >= d.N) return;
     if (d.lower_only && i0 + BM - 1 < j0) return;
+    int kbeg = 0;
+    if (d.kchunk > 0) {
+        kbeg = tz * d.kchunk;
+        d.K = min(d.K, kbeg + d.kchunk);
+        d.C = static_cast<void *>(static_cast<char *>(d.C) + (int64_t)tz * d.c_zstride * sizeof(T));
+    }
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wm = w & 1, wn = w >> 1;
     constexpr bool CPLX = sizeof(T) == 16;
@@ -66,7 +75,7 @@ __device__ void gemm_tile(const GemmDesc &d, int ti, int tj) {
             acc_i[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
         }
 
-    for (int k0 = 0; k0 < d.K; k0 += BK) {
+    for (int k0 = kbeg; k0 < d.K; k0 += BK) {
         // ---- A tile: op(A)[i0 + i][k0 + k]
         if (OPA == OP_N) {
             const int i = t & 63;
@@ -158,15 +167,17 @@ __device__ void gemm_tile(const GemmDesc &d, int ti, int tj) {
                 if (EPI == EPI_SVEC) {
                     if (i < j) continue;
                     const int64_t n = d.svec_n;
+                    const double sgn = d.dsign ? *d.dsign : d.sign;
+                    const double *xb = (d.dsign && sgn > 0.0) ? nullptr : d.xbase;
                     if (i == j) {
                         const int64_t o = svec_col_start((int)n, j);
-                        const double base = d.xbase ? d.xbase[o] : 0.0;
-                        d.y[o] = base + d.sign * re;
+                        const double base = xb ? xb[o] : 0.0;
+                        d.y[o] = base + sgn * re;
                     } else {
                         const int64_t o = svec_off((int)n, i, j);
-                        const double b0 = d.xbase ? d.xbase[o] : 0.0, b1 = d.xbase ? d.xbase[o + 1] : 0.0;
-                        d.y[o] = b0 + d.sign * rt2 * re;
-                        d.y[o + 1] = b1 + d.sign * rt2 * im;
+                        const double b0 = xb ? xb[o] : 0.0, b1 = xb ? xb[o + 1] : 0.0;
+                        d.y[o] = b0 + sgn * rt2 * re;
+                        d.y[o + 1] = b1 + sgn * rt2 * im;
                     }
                     continue;
                 }
@@ -193,18 +204,18 @@ __device__ void gemm_tile(const GemmDesc &d, int ti, int tj) {
 
 template <typename T, int OPA, int OPB, int EPI>
 __global__ void __launch_bounds__(NT) gemm_kernel(GemmDesc d) {
-    gemm_tile<T, OPA, OPB, EPI>(d, blockIdx.x, blockIdx.y);
+    gemm_tile<T, OPA, OPB, EPI>(d, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 template <typename T, int OPA, int OPB>
 __global__ void __launch_bounds__(NT) gemm_kernel_batched(const GemmDesc *ds) {
     const GemmDesc d = ds[blockIdx.z];
-    gemm_tile<T, OPA, OPB, EPI_STORE>(d, blockIdx.x, blockIdx.y);
+    gemm_tile<T, OPA, OPB, EPI_STORE>(d, blockIdx.x, blockIdx.y, 0);
 }
 
 template <typename T, int EPI>
 hipError_t launch_ops(const GemmDesc &d, hipStream_t st) {
-    dim3 grid((d.M + BM - 1) / BM, (d.N + BN - 1) / BN);
+    dim3 grid((d.M + BM - 1) / BM, (d.N + BN - 1) / BN, gemm_kslices(d));
     const int key = d.A.op * 2 + d.B.op;
     switch (key) {
         case 0: hipLaunchKernelGGL((gemm_kernel<T, OP_N, OP_N, EPI>), grid, dim3(NT), 0, st, d); break;

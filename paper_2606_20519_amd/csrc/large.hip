@@ -1,0 +1,300 @@
+// Large-block FP64 path, stages after the tridiagonal eigensolver:
+//  * select: count the eigenvalues > 0 (lambda ascending) and pick the side
+//    with fewer columns, k = min(k+, k-);
+//  * back-transform: V = Q Z for those k columns, block reflector by block
+//    reflector (last panel first): Z <- Z - V_b (T_b (V_b^H Z)), with V_b^H Z
+//    as a split-K MFMA GEMM, the T_b product in LDS, and the update as an
+//    MFMA GEMM;
+//  * reconstruction: Pi = V+ diag(lambda+) V+^H   (k+ <= k-), or
+//    Pi = X - V- diag(lambda-) V-^H (otherwise), one MFMA GEMM over the
+//    lower tiles whose epilogue writes the svec directly (App. D.2: zero the
+//    negative eigenvalues of the eigendecomposition);
+//  * the Daleckii-Krein derivative V (Gamma o (V^H G V)) V^H as four MFMA
+//    GEMMs, Gamma applied in the epilogue of the second.
+#include <algorithm>
+
+#include "common.h"
+#include "large.h"
+
+namespace psd {
+
+namespace {
+
+constexpr int NB = LG_NB;
+constexpr int KCHUNK = 256;
+
+inline size_t aup(size_t v) { return (v + 255) / 256 * 256; }
+
+__global__ void init_status_kernel(int *ksel) {
+    if (threadIdx.x < 4) ksel[threadIdx.x] = 0;
+}
+
+// k, sign, selected eigenvalues and the selected columns of Z (as complex).
+__global__ void __launch_bounds__(256) select_kernel(const double *__restrict__ lam, const double *__restrict__ Z,
+                                                     int n, int all_columns, double2 *Zc, int64_t lda,
+                                                     double *lamsel, int *ksel, double *sgn,
+                                                     psd_dev_info *info) {
+    // first index with lambda > 0
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (lam[mid] > 0.0) hi = mid; else lo = mid + 1;
+    }
+    const int npos = n - lo, nneg = lo;
+    int k, start;
+    double s;
+    if (all_columns) { k = n; start = 0; s = 1.0; }
+    else if (npos <= nneg) { k = npos; start = n - npos; s = 1.0; }
+    else { k = nneg; start = 0; s = -1.0; }
+    const int c = blockIdx.y;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c == 0 && r == 0) {
+        ksel[0] = k;
+        ksel[1] = npos;
+        *sgn = s;
+        if (info) {
+            info->status = ksel[2];
+            info->n_pos = npos;
+            info->n_neg = nneg;
+            info->iters = 0;
+            info->fallback = 0;
+            info->reserved = 0;
+            info->est_rel_err = 0.0;
+        }
+    }
+    if (c >= k || r >= n) return;
+    Zc[r + (int64_t)c * lda] = cmk(Z[r + (int64_t)(start + c) * n], 0.0);
+    if (r == 0) {
+        const double l = lam[start + c];
+        lamsel[c] = all_columns ? fmax(l, 0.0) : l;
+    }
+}
+
+// W2 = T_b * sum_z partial_z  for columns c < k (8 columns per workgroup).
+__global__ void __launch_bounds__(256) bt_tw_kernel(const double2 *__restrict__ wpart, int nz, int64_t zstride,
+                                                    const double2 *__restrict__ Tb, int kb, const int *ksel,
+                                                    double2 *W2) {
+    __shared__ double2 Ts[NB][NB + 1];
+    __shared__ double2 W1[NB][9];
+    const int t = threadIdx.x, i = t & 31, cl = t >> 5;
+    const int c = blockIdx.x * 8 + cl;
+    const int k = ksel[0];
+    for (int idx = t; idx < NB * NB; idx += 256) Ts[idx % NB][idx / NB] = Tb[idx];
+    double2 acc = cmk(0.0, 0.0);
+    if (c < k && i < kb)
+        for (int z = 0; z < nz; ++z) acc = cadd(acc, wpart[z * zstride + i + (int64_t)c * NB]);
+    W1[i][cl] = acc;
+    __syncthreads();
+    if (c >= k) return;
+    double2 out = cmk(0.0, 0.0);
+    if (i < kb)
+        for (int l = i; l < kb; ++l) out = cfma(Ts[i][l], W1[l][cl], out);
+    W2[i + (int64_t)c * NB] = out;
+}
+
+__global__ void __launch_bounds__(256) save_kernel(const double *__restrict__ lam, const double2 *__restrict__ Zc,
+                                                   int64_t lda, int n, double *saved) {
+    const int c = blockIdx.y;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    if (c == 0) saved[r] = lam[r];
+    double2 *V = reinterpret_cast<double2 *>(saved + n);
+    V[r + (int64_t)c * n] = Zc[r + (int64_t)c * lda];
+}
+
+// Full Hermitian matrix from an svec (for the derivative's cotangent).
+__global__ void __launch_bounds__(256) unpack_full_kernel(const double *__restrict__ x, double2 *G, int64_t ld,
+                                                          int n) {
+    const int j = blockIdx.y;
+    const int i = j + blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double rs2 = 0.70710678118654752440;
+    if (i == j) {
+        G[i + (int64_t)j * ld] = cmk(x[svec_col_start(n, j)], 0.0);
+    } else {
+        const int64_t o = svec_off(n, i, j);
+        const double2 v = cmk(x[o] * rs2, x[o + 1] * rs2);
+        G[i + (int64_t)j * ld] = v;
+        G[j + (int64_t)i * ld] = cconj(v);
+    }
+}
+
+// saved record -> eigenvalues and V (ld n) views are used directly; this
+// copies V into the workspace layout when the caller passed `saved`.
+__global__ void __launch_bounds__(256) load_saved_kernel(const double *__restrict__ saved, int n, double *lam,
+                                                         double2 *Zc, int64_t lda) {
+    const int c = blockIdx.y;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    if (c == 0) lam[r] = saved[r];
+    const double2 *V = reinterpret_cast<const double2 *>(saved + n);
+    Zc[r + (int64_t)c * lda] = V[r + (int64_t)c * n];
+}
+
+}  // namespace
+
+size_t large_layout(int n, int flags, void *base, LargeWs *w) {
+    size_t off = 0;
+    char *b = static_cast<char *>(base);
+    auto take = [&](size_t bytes) -> void * {
+        void *p = b ? b + off : nullptr;
+        off += aup(bytes);
+        return p;
+    };
+    LargeWs L{};
+    L.n = n;
+    L.lda = (n + 63) / 64 * 64;
+    L.mb = (n + LG_TILE - 1) / LG_TILE;
+    L.npanel = (n - 1 + NB - 1) / NB;
+    const bool full = (flags & 1) != 0;
+    L.kmax = full ? n : n / 2 + 1;
+    L.nchunk = (n + KCHUNK - 1) / KCHUNK;
+    const size_t cdsz = sizeof(double2), dsz = sizeof(double);
+    L.M = (double2 *)take(cdsz * L.lda * n);
+    L.W = (double2 *)take(cdsz * L.lda * NB);
+    L.vbuf = (double2 *)take(cdsz * L.lda);
+    L.tau = (double2 *)take(cdsz * n);
+    L.d = (double *)take(dsz * n);
+    L.e = (double *)take(dsz * n);
+    L.P = (double2 *)take(cdsz * (size_t)L.mb * L.mb * LG_TILE);
+    L.tdot = (double *)take(dsz * (size_t)L.mb * (L.mb + 1) / 2);
+    L.pq = (double2 *)take(cdsz * (size_t)L.mb * 2 * NB);
+    L.T = (double2 *)take(cdsz * (size_t)L.npanel * NB * NB);
+    L.Q0 = (double *)take(dsz * (size_t)n * n);
+    L.Q1 = (double *)take(dsz * (size_t)n * n);
+    L.D0 = (double *)take(dsz * n);
+    L.D1 = (double *)take(dsz * n);
+    L.U = (double *)take(dsz * (size_t)n * n);
+    L.dcd = (double *)take(dsz * (size_t)16 * n);
+    L.dci = (int *)take(sizeof(int) * (size_t)8 * n);
+    L.dcs = (int *)take(sizeof(int) * (size_t)4 * n);
+    L.gdesc = (GemmDesc *)take(sizeof(GemmDesc) * (size_t)(n + 2));
+    L.Zc = (double2 *)take(cdsz * L.lda * L.kmax);
+    L.lamsel = (double *)take(dsz * L.kmax);
+    L.wpart = (double *)take(cdsz * (size_t)L.nchunk * NB * L.kmax);
+    L.W2 = (double2 *)take(cdsz * (size_t)NB * L.kmax);
+    L.ksel = (int *)take(sizeof(int) * 4);
+    L.sgn = (double *)take(dsz);
+    L.B1 = full ? (double2 *)take(cdsz * (size_t)n * n) : nullptr;
+    L.lam = L.D0;
+    L.Zfinal = L.Q0;
+    if (w) *w = L;
+    return off;
+}
+
+hipError_t large_init(const LargeWs &w, hipStream_t st) {
+    hipLaunchKernelGGL(init_status_kernel, dim3(1), dim3(64), 0, st, w.ksel);
+    return hipGetLastError();
+}
+
+hipError_t large_select(const LargeWs &w, psd_dev_info *info, hipStream_t st, bool all_columns) {
+    const int kcols = all_columns ? w.n : w.n / 2 + 1;
+    dim3 grid((w.n + 255) / 256, std::min(kcols, w.kmax));
+    hipLaunchKernelGGL(select_kernel, grid, dim3(256), 0, st, w.lam, w.Zfinal, w.n, all_columns ? 1 : 0, w.Zc,
+                       w.lda, w.lamsel, w.ksel, w.sgn, info);
+    return hipGetLastError();
+}
+
+hipError_t large_backtransform(const LargeWs &w, int ncols_max, hipStream_t st) {
+    const int n = w.n;
+    const int64_t zstride = (int64_t)NB * w.kmax;
+    for (int b = w.npanel - 1; b >= 0; --b) {
+        const int p0 = b * NB;
+        const int kb = std::min(NB, n - 1 - p0);
+        const int mr = n - 1 - p0;
+        const double2 *Vb = w.M + (p0 + 1) + (int64_t)p0 * w.lda;
+        // partials of V_b^H Z over row chunks
+        GemmDesc g{};
+        g.M = kb; g.N = ncols_max; g.K = mr;
+        g.A = GemmOperand{Vb, Vb, w.lda, w.lda, mr, OP_C, nullptr};
+        g.B = GemmOperand{w.Zc + (p0 + 1), w.Zc + (p0 + 1), w.lda, w.lda, mr, OP_N, nullptr};
+        g.C = w.wpart; g.ldc = NB; g.alpha = 1.0; g.beta = 0.0;
+        g.dN = w.ksel;
+        g.kchunk = KCHUNK; g.c_zstride = zstride;
+        hipError_t e = gemm_launch(g, true, EPI_STORE, st);
+        if (e != hipSuccess) return e;
+        const int nz = gemm_kslices(g);
+        hipLaunchKernelGGL(bt_tw_kernel, dim3((ncols_max + 7) / 8), dim3(256), 0, st,
+                           reinterpret_cast<const double2 *>(w.wpart), nz, zstride, w.T + (int64_t)b * NB * NB, kb,
+                           w.ksel, w.W2);
+        // Z[p0+1:, :] -= V_b W2
+        GemmDesc u{};
+        u.M = mr; u.N = ncols_max; u.K = kb;
+        u.A = GemmOperand{Vb, Vb, w.lda, w.lda, kb, OP_N, nullptr};
+        u.B = GemmOperand{w.W2, w.W2, NB, NB, kb, OP_N, nullptr};
+        u.C = w.Zc + (p0 + 1); u.ldc = w.lda; u.alpha = -1.0; u.beta = 1.0;
+        u.dN = w.ksel;
+        e = gemm_launch(u, true, EPI_STORE, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+hipError_t large_reconstruct(const LargeWs &w, const double *x, double *y, int kmax, hipStream_t st) {
+    GemmDesc g{};
+    g.M = g.N = w.n;
+    g.K = kmax;
+    g.lower_only = 1;
+    g.A = GemmOperand{w.Zc, w.Zc, w.lda, w.lda, kmax, OP_N, w.lamsel};
+    g.B = GemmOperand{w.Zc, w.Zc, w.lda, w.lda, kmax, OP_C, nullptr};
+    g.y = y; g.xbase = x; g.svec_n = w.n; g.sign = 1.0;
+    g.dsign = w.sgn;
+    g.dK = w.ksel;
+    return gemm_launch(g, true, EPI_SVEC, st);
+}
+
+hipError_t large_save(const LargeWs &w, double *saved, hipStream_t st) {
+    dim3 grid((w.n + 255) / 256, w.n);
+    hipLaunchKernelGGL(save_kernel, grid, dim3(256), 0, st, w.lam, w.Zc, w.lda, w.n, saved);
+    return hipGetLastError();
+}
+
+// gx = svec(V (Gamma o (V^H G V)) V^H), V = Zc (n x n, ld lda), lambda = w.lam.
+hipError_t large_vjp_from_v(const LargeWs &w, const double *gy, double *gx, hipStream_t st) {
+    const int n = w.n;
+    double2 *G = w.M;   // cotangent (full Hermitian), later Gamma o (V^H G V)
+    double2 *B1 = w.B1;
+    dim3 grid((n + 255) / 256, n);
+    hipLaunchKernelGGL(unpack_full_kernel, grid, dim3(256), 0, st, gy, G, w.lda, n);
+    // B1 = G V   (ld n)
+    GemmDesc a{};
+    a.M = a.N = a.K = n;
+    a.A = GemmOperand{G, G, w.lda, w.lda, n, OP_N, nullptr};
+    a.B = GemmOperand{w.Zc, w.Zc, w.lda, w.lda, n, OP_N, nullptr};
+    a.C = B1; a.ldc = n; a.alpha = 1.0; a.beta = 0.0;
+    hipError_t e = gemm_launch(a, true, EPI_STORE, st);
+    if (e != hipSuccess) return e;
+    // G = Gamma o (V^H B1)   (reuse G's storage, ld lda)
+    GemmDesc b{};
+    b.M = b.N = b.K = n;
+    b.A = GemmOperand{w.Zc, w.Zc, w.lda, w.lda, n, OP_C, nullptr};
+    b.B = GemmOperand{B1, B1, n, n, n, OP_N, nullptr};
+    b.C = G; b.ldc = w.lda; b.alpha = 1.0; b.beta = 0.0;
+    b.lam = w.lam;
+    e = gemm_launch(b, true, EPI_GAMMA, st);
+    if (e != hipSuccess) return e;
+    // B1 = G V^H
+    GemmDesc c{};
+    c.M = c.N = c.K = n;
+    c.A = GemmOperand{G, G, w.lda, w.lda, n, OP_N, nullptr};
+    c.B = GemmOperand{w.Zc, w.Zc, w.lda, w.lda, n, OP_C, nullptr};
+    c.C = B1; c.ldc = n; c.alpha = 1.0; c.beta = 0.0;
+    e = gemm_launch(c, true, EPI_STORE, st);
+    if (e != hipSuccess) return e;
+    // gx = svec(V B1), lower tiles
+    GemmDesc d{};
+    d.M = d.N = d.K = n;
+    d.lower_only = 1;
+    d.A = GemmOperand{w.Zc, w.Zc, w.lda, w.lda, n, OP_N, nullptr};
+    d.B = GemmOperand{B1, B1, n, n, n, OP_N, nullptr};
+    d.y = gx; d.xbase = nullptr; d.svec_n = n; d.sign = 1.0;
+    return gemm_launch(d, true, EPI_SVEC, st);
+}
+
+hipError_t large_load_saved(const LargeWs &w, const double *saved, hipStream_t st) {
+    dim3 grid((w.n + 255) / 256, w.n);
+    hipLaunchKernelGGL(load_saved_kernel, grid, dim3(256), 0, st, saved, w.n, w.D0, w.Zc, w.lda);
+    return hipGetLastError();
+}
+
+}  // namespace psd

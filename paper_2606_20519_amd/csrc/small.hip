@@ -15,6 +15,7 @@
 //      negative eigenvalues), written straight back as svec.
 #include "common.h"
 #include "kernels.h"
+#include "ql.h"
 
 namespace psd {
 
@@ -39,74 +40,10 @@ struct SmallLds {
     int nrot, done, status, ksel, sgn;
 };
 
-// Implicit-shift QL on (d, e) of order n, eigenvectors accumulated into
-// Z (column-major, ld SB_LD, initialised to I by the caller).  Rotations of
-// one sweep are generated by thread 0 and then applied to the rows of Z by
-// all threads.  The sweep is the classical one of Bowdler, Martin, Reinsch
-// and Wilkinson (tql2): Wilkinson-type shift from the leading 2x2, chase from
-// the bottom of the unreduced block up to its top.
 __device__ void small_ql(SmallLds &S, int n) {
-    const int t = threadIdx.x;
-    const double eps = 2.220446049250313e-16;
-    int l = 0, iter = 0;  // meaningful in thread 0 only
-    if (t == 0) { S.e[n - 1] = 0.0; S.done = 0; }
+    int st = ql_implicit(S.d, S.e, S.Z, SB_LD, n, S.rc, S.rs, S.perm, &S.nrot, &S.done);
+    if (threadIdx.x == 0 && st != ST_OK && S.status == ST_OK) S.status = st;
     __syncthreads();
-    while (true) {
-        if (t == 0) {
-            int nrot = 0;
-            while (l < n) {
-                int m = l;
-                for (; m < n - 1; ++m) {
-                    double dd = fabs(S.d[m]) + fabs(S.d[m + 1]);
-                    if (fabs(S.e[m]) <= eps * dd) break;
-                }
-                if (m == l) { ++l; iter = 0; continue; }
-                if (++iter > 60) {
-                    if (S.status == ST_OK) S.status = ST_ENOCONV;
-                    l = n;
-                    break;
-                }
-                double g = (S.d[l + 1] - S.d[l]) / (2.0 * S.e[l]);
-                double r = hypot(g, 1.0);
-                g = S.d[m] - S.d[l] + S.e[l] / (g + copysign(r, g));
-                double s = 1.0, c = 1.0, p = 0.0;
-                int i = m - 1;
-                bool early = false;
-                for (; i >= l; --i) {
-                    double f = s * S.e[i], b = c * S.e[i];
-                    r = hypot(f, g);
-                    S.e[i + 1] = r;
-                    if (r == 0.0) { S.d[i + 1] -= p; S.e[m] = 0.0; early = true; break; }
-                    s = f / r; c = g / r;
-                    g = S.d[i + 1] - p;
-                    r = (S.d[i] - g) * s + 2.0 * c * b;
-                    p = s * r;
-                    S.d[i + 1] = g + p;
-                    g = c * r - b;
-                    S.rc[nrot] = c; S.rs[nrot] = s; S.perm[nrot] = i;
-                    ++nrot;
-                }
-                if (!(early && i >= l)) { S.d[l] -= p; S.e[l] = g; S.e[m] = 0.0; }
-                break;  // one sweep produced: let everybody apply it
-            }
-            S.nrot = nrot;
-            S.done = (l >= n);
-        }
-        __syncthreads();
-        const int nrot = S.nrot;
-        if (t < n) {
-            for (int k = 0; k < nrot; ++k) {
-                const int i = S.perm[k];
-                const double c = S.rc[k], s = S.rs[k];
-                double zi = S.Z[t + i * SB_LD], zi1 = S.Z[t + (i + 1) * SB_LD];
-                S.Z[t + (i + 1) * SB_LD] = s * zi + c * zi1;
-                S.Z[t + i * SB_LD] = c * zi - s * zi1;
-            }
-        }
-        const int done = S.done;
-        __syncthreads();
-        if (done) break;
-    }
 }
 
 // Householder reduction of the Hermitian matrix in S.A (order n) to real
