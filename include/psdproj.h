@@ -116,6 +116,23 @@ psd_status psd_project_vjp(int32_t n, const double *x, const double *saved,
                            const double *gy, double *gx, psd_mode mode, void *ws,
                            size_t ws_bytes, void *stream);
 
+/* Instrumentation (off by default).  Between psd_timing_start and
+ * psd_timing_stop every launch of one kernel family made by this library is
+ * bracketed by a pair of HIP events recorded on the launch stream (at most
+ * max_launches pairs; later launches are not timed).  psd_timing_stop
+ * synchronises those events and returns the summed device time in ms, the
+ * number of launches timed and their algorithmic work: bytes of the matrix
+ * read for PSD_KF_HEMV (the lower triangle of the trailing matrix, 16 bytes
+ * per complex entry), real flops for PSD_KF_GEMM (8 per complex
+ * multiply-add).  Not thread-safe; meant for benchmarks and tests.  The
+ * events are created by psd_timing_start and destroyed by psd_timing_stop. */
+typedef enum {
+    PSD_KF_HEMV = 1,   /* per-column Hermitian matrix-vector tiles of the tridiagonalisation */
+    PSD_KF_GEMM = 2    /* FP64 MFMA GEMMs */
+} psd_kernel_family;
+psd_status psd_timing_start(int32_t family, int32_t max_launches);
+psd_status psd_timing_stop(double *ms, int32_t *launches, double *work);
+
 /* Static description of a status code. */
 const char *psd_status_string(psd_status status);
 

@@ -19,7 +19,8 @@ PSD_FLAG_SAVE = 1
 
 # Every symbol include/psdproj.h declares.
 EXPORTS = ("psd_workspace_size", "psd_saved_size", "psd_project", "psd_project_batched",
-           "psd_project_vjp", "psd_status_string", "psd_version")
+           "psd_project_vjp", "psd_timing_start", "psd_timing_stop", "psd_status_string", "psd_version")
+KF_HEMV, KF_GEMM = 1, 2
 
 
 class PsdError(RuntimeError):
@@ -60,6 +61,10 @@ def lib():
     L.psd_status_string.argtypes = [i32]
     L.psd_status_string.restype = ctypes.c_char_p
     L.psd_version.restype = ctypes.c_char_p
+    L.psd_timing_start.argtypes = [i32, i32]
+    L.psd_timing_start.restype = i32
+    L.psd_timing_stop.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
+    L.psd_timing_stop.restype = i32
     _lib = L
     return L
 
@@ -90,3 +95,14 @@ def workspace_size(sizes, mode: int, flags: int = 0) -> int:
 
 def saved_size(n: int) -> int:
     return int(lib().psd_saved_size(n))
+
+
+def timing_start(family: int, max_launches: int):
+    check(lib().psd_timing_start(family, max_launches), "psd_timing_start")
+
+
+def timing_stop():
+    """-> (total ms, launches timed, algorithmic work)"""
+    ms, n, wk = ctypes.c_double(0), ctypes.c_int32(0), ctypes.c_double(0)
+    check(lib().psd_timing_stop(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(wk)), "psd_timing_stop")
+    return ms.value, n.value, wk.value

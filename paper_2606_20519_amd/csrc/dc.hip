@@ -31,13 +31,14 @@ namespace {
 
 constexpr double EPS = 2.220446049250313e-16;
 constexpr int LEAF_MAX = 64;
+constexpr int PREP_LDS_MAX = 6144;  // 20 bytes per element in LDS
 
 __host__ __device__ inline int leaf_bound(int i, int n, int nl) { return (int)(((int64_t)i * n) / nl); }
 
 // Vectors of the merge workspace (offsets in units of n; a merge [a,b) uses
 // indices a..b-1 of each).
-enum { DZ = 0, DDM, DDD, DDH, DZH, DTAU, DLAM, DZHAT, DRC, DRS, DRHO, DCOUNT };
-enum { IPERM = 0, IKEEP, IDEFL, IRP, IRN, IORG, ICOL, ICOUNT };
+enum { DZ = 0, DDM, DDD, DDH, DZH, DTAU, DLAM, DZHAT, DRC, DRS, DRHO, DNRM, DCOUNT };
+enum { IPERM = 0, IKEEP, IDEFL, IRP, IRN, IORG, ICOL, IROWK, ICOUNT };
 enum { SK = 0, SND, SNR, SCOUNT };
 
 __global__ void __launch_bounds__(256) dc_leaf_kernel(const double *__restrict__ d, const double *__restrict__ e,
@@ -88,8 +89,8 @@ __device__ inline MergeGeo merge_geo(int level, int q, int n, int nl) {
 __global__ void __launch_bounds__(256) dc_prep_kernel(int level, int n, int nl, const double *__restrict__ e,
                                                       const double *__restrict__ Dcur, const double *Qcur,
                                                       double *Qnext, int64_t ldq, double *U, double *dv,
-                                                      int *iv, int *sv, GemmDesc *gd) {
-    __shared__ double red[8];
+                                                      int *iv, int *sv, GemmDesc *gd, int use_lds) {
+    __shared__ int red_k, red_nd, red_nr;
     const int q = blockIdx.x, t = threadIdx.x;
     const MergeGeo g = merge_geo(level, q, n, nl);
     const int a = g.a, n1 = g.m - g.a, n2 = g.b - g.m, nm = g.b - g.a;
@@ -102,6 +103,7 @@ __global__ void __launch_bounds__(256) dc_prep_kernel(int level, int n, int nl, 
     double *rcs = dv + (int64_t)DRC * n + a, *rsn = dv + (int64_t)DRS * n + a;
     int *perm = iv + (int64_t)IPERM * n + a, *keep = iv + (int64_t)IKEEP * n + a;
     int *defl = iv + (int64_t)IDEFL * n + a, *rp = iv + (int64_t)IRP * n + a, *rn = iv + (int64_t)IRN * n + a;
+    int *rowk = iv + (int64_t)IROWK * n + a;
     double zmax = 0.0, dmax = 0.0;
     for (int i = t; i < nm; i += blockDim.x) {
         const double zi = (i < n1) ? Qcur[(g.m - 1) + (int64_t)(a + i) * ldq] * rs2
@@ -126,31 +128,39 @@ __global__ void __launch_bounds__(256) dc_prep_kernel(int level, int n, int nl, 
         zmax = fmax(fmax(mx[0][0], mx[0][1]), fmax(mx[0][2], mx[0][3]));
         dmax = fmax(fmax(mx[1][0], mx[1][1]), fmax(mx[1][2], mx[1][3]));
     }
-    (void)red;
+    // The sequential merge/deflation scan runs on LDS copies when they fit.
+    extern __shared__ __align__(16) unsigned char prep_lds[];
+    const bool in_lds = use_lds != 0;  // the launch sized the LDS for the largest merge
+    double *zl = in_lds ? reinterpret_cast<double *>(prep_lds) : z;
+    double *dl = in_lds ? zl + nm : dd;
+    int *pl = in_lds ? reinterpret_cast<int *>(dl + nm) : perm;
+    if (in_lds) {
+        for (int i = t; i < nm; i += blockDim.x) { zl[i] = z[i]; dl[i] = dd[i]; }
+    }
     __syncthreads();
     if (t == 0) {
         // merge the two ascending halves into one ascending order
         int i1 = 0, i2 = n1, o = 0;
-        while (i1 < n1 && i2 < nm) perm[o++] = (Dm[i2] < Dm[i1]) ? i2++ : i1++;
-        while (i1 < n1) perm[o++] = i1++;
-        while (i2 < nm) perm[o++] = i2++;
+        while (i1 < n1 && i2 < nm) pl[o++] = (dl[i2] < dl[i1]) ? i2++ : i1++;
+        while (i1 < n1) pl[o++] = i1++;
+        while (i2 < nm) pl[o++] = i2++;
         // deflation
         const double tol = 8.0 * EPS * fmax(dmax, rho * zmax);
         int k = 0, nd = 0, nr = 0, prev = -1;
         for (int idx = 0; idx < nm; ++idx) {
-            const int p = perm[idx];
-            if (rho * fabs(z[p]) <= tol) { defl[nd++] = p; continue; }
+            const int p = pl[idx];
+            if (rho * fabs(zl[p]) <= tol) { defl[nd++] = p; continue; }
             if (prev >= 0) {
-                const double tz = hypot(z[prev], z[p]);
-                const double c = z[p] / tz, s = -z[prev] / tz;
-                const double tt = dd[p] - dd[prev];
+                const double tz = hypot(zl[prev], zl[p]);
+                const double c = zl[p] / tz, s = -zl[prev] / tz;
+                const double tt = dl[p] - dl[prev];
                 if (fabs(tt * c * s) <= tol) {
-                    z[p] = tz;
-                    z[prev] = 0.0;
-                    const double dp = dd[prev] * c * c + dd[p] * s * s;
-                    const double dn = dd[prev] * s * s + dd[p] * c * c;
-                    dd[prev] = dp;
-                    dd[p] = dn;
+                    zl[p] = tz;
+                    zl[prev] = 0.0;
+                    const double dp = dl[prev] * c * c + dl[p] * s * s;
+                    const double dn = dl[prev] * s * s + dl[p] * c * c;
+                    dl[prev] = dp;
+                    dl[p] = dn;
                     rp[nr] = prev; rn[nr] = p; rcs[nr] = c; rsn[nr] = s; ++nr;
                     defl[nd++] = prev;
                     --k;
@@ -159,7 +169,24 @@ __global__ void __launch_bounds__(256) dc_prep_kernel(int level, int n, int nl, 
             keep[k++] = p;
             prev = p;
         }
-        for (int i = 0; i < k; ++i) { dh[i] = dd[keep[i]]; zh[i] = z[keep[i]]; }
+        red_k = k;
+        red_nd = nd;
+        red_nr = nr;
+    }
+    __syncthreads();
+    const int k = red_k;
+    // kept values / weights and the row -> kept-index map
+    for (int i = t; i < nm; i += blockDim.x) rowk[i] = -1;
+    __syncthreads();
+    for (int i = t; i < k; i += blockDim.x) {
+        const int p = keep[i];
+        dh[i] = dl[p];
+        zh[i] = zl[p];
+        rowk[p] = i;
+    }
+    for (int i = t; i < nm; i += blockDim.x) dd[i] = dl[i];
+    if (t == 0) {
+        const int nd = red_nd, nr = red_nr;
         sv[q * SCOUNT + SK] = k;
         sv[q * SCOUNT + SND] = nd;
         sv[q * SCOUNT + SNR] = nr;
@@ -179,28 +206,33 @@ __global__ void __launch_bounds__(256) dc_prep_kernel(int level, int n, int nl, 
     }
 }
 
-// Root j of 1 + rho sum_i zh_i^2 / (dh_i - lambda) = 0 (dh ascending, gaps > 0).
-// Returns the origin pole o and tau with lambda = dh[o] + tau.
-__device__ void secular_root(const double *dh, const double *zh, int k, double rho, int j, int *o_out,
-                             double *tau_out) {
+// Root j of 1 + rho sum_i zh_i^2 / (dh_i - lambda) = 0 (dh ascending, gaps
+// > 0), solved by one wave: the lanes split every sum over i and the wave-wide
+// butterfly sums give all lanes the same totals, so all lanes take the same
+// steps.  Returns the origin pole o and tau with lambda = dh[o] + tau.
+__device__ void secular_root_wave(const double *dh, const double *zh, int k, double rho, int j, int *o_out,
+                                  double *tau_out) {
+    const int lane = threadIdx.x & 63;
     int o;
     double lo, hi;
     if (j < k - 1) {
         const double gap = dh[j + 1] - dh[j];
-        double f = 1.0;
-        for (int i = 0; i < k; ++i) f += rho * zh[i] * zh[i] / ((dh[i] - dh[j]) - 0.5 * gap);
+        double f = 0.0;
+        for (int i = lane; i < k; i += 64) f += rho * zh[i] * zh[i] / ((dh[i] - dh[j]) - 0.5 * gap);
+        f = 1.0 + warp_sum(f);
         if (f > 0.0) { o = j; lo = 0.0; hi = 0.5 * gap; }
         else { o = j + 1; lo = -0.5 * gap; hi = 0.0; }
     } else {
         double zz = 0.0;
-        for (int i = 0; i < k; ++i) zz += zh[i] * zh[i];
+        for (int i = lane; i < k; i += 64) zz += zh[i] * zh[i];
+        zz = warp_sum(zz);
         o = j; lo = 0.0; hi = rho * zz;
     }
     const double dO = dh[o];
     double tau = 0.5 * (lo + hi);
     for (int it = 0; it < 100; ++it) {
         double psi = 0.0, phi = 0.0, dpsi = 0.0, dphi = 0.0, sabs = 0.0;
-        for (int i = 0; i < k; ++i) {
+        for (int i = lane; i < k; i += 64) {
             const double diff = (dh[i] - dO) - tau;
             const double w = rho * zh[i] * zh[i];
             const double term = w / diff;
@@ -208,6 +240,8 @@ __device__ void secular_root(const double *dh, const double *zh, int k, double r
             if (i <= j) { psi += term; dpsi += term / diff; }
             else { phi += term; dphi += term / diff; }
         }
+        psi = warp_sum(psi); phi = warp_sum(phi);
+        dpsi = warp_sum(dpsi); dphi = warp_sum(dphi); sabs = warp_sum(sabs);
         const double f = 1.0 + psi + phi;
         if (f < 0.0) lo = tau; else hi = tau;
         if (f == 0.0 || fabs(f) <= 8.0 * EPS * (1.0 + sabs)) break;
@@ -243,22 +277,31 @@ __device__ void secular_root(const double *dh, const double *zh, int k, double r
     *tau_out = tau;
 }
 
+// One wave per root: 4 roots per 256-thread workgroup.
 __global__ void __launch_bounds__(256) dc_secular_kernel(int level, int n, int nl, double *dv, int *iv,
                                                          const int *sv) {
     const int q = blockIdx.y;
     const MergeGeo g = merge_geo(level, q, n, nl);
     const int a = g.a;
     const int k = sv[q * SCOUNT + SK];
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (j >= k) return;
     const double rho = dv[(int64_t)DRHO * n + q];
     const double *dh = dv + (int64_t)DDH * n + a, *zh = dv + (int64_t)DZH * n + a;
     int o;
     double tau;
-    secular_root(dh, zh, k, rho, j, &o, &tau);
-    iv[(int64_t)IORG * n + a + j] = o;
-    dv[(int64_t)DTAU * n + a + j] = tau;
-    dv[(int64_t)DLAM * n + a + j] = dh[o] + tau;
+    secular_root_wave(dh, zh, k, rho, j, &o, &tau);
+    if ((threadIdx.x & 63) == 0) {
+        iv[(int64_t)IORG * n + a + j] = o;
+        dv[(int64_t)DTAU * n + a + j] = tau;
+        dv[(int64_t)DLAM * n + a + j] = dh[o] + tau;
+    }
+}
+
+__device__ __forceinline__ double warp_prod(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v *= __shfl_xor(v, o, 64);
+    return v;
 }
 
 // zhat_i^2 = prod_j (lambda_j - d_i) / (rho prod_{l != i} (d_l - d_i)), paired
@@ -269,20 +312,45 @@ __global__ void __launch_bounds__(256) dc_lowner_kernel(int level, int n, int nl
     const MergeGeo g = merge_geo(level, q, n, nl);
     const int a = g.a;
     const int k = sv[q * SCOUNT + SK];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (i >= k) return;
     const double rho = dv[(int64_t)DRHO * n + q];
     const double *dh = dv + (int64_t)DDH * n + a, *zh = dv + (int64_t)DZH * n + a;
     const double *tau = dv + (int64_t)DTAU * n + a;
     const int *org = iv + (int64_t)IORG * n + a;
     const double di = dh[i];
-    double prod = ((dh[org[k - 1]] - di) + tau[k - 1]) / rho;
-    for (int jj = 0; jj < k - 1; ++jj) {
+    // each factor is a ratio in (0, 1]; lanes multiply disjoint subsets
+    double prod = 1.0;
+    for (int jj = lane; jj < k - 1; jj += 64) {
         const double num = (dh[org[jj]] - di) + tau[jj];
         const double den = (jj < i) ? (dh[jj] - di) : (dh[jj + 1] - di);
         prod *= num / den;
     }
-    dv[(int64_t)DZHAT * n + a + i] = copysign(sqrt(fmax(prod, 0.0)), zh[i]);
+    prod = warp_prod(prod) * (((dh[org[k - 1]] - di) + tau[k - 1]) / rho);
+    if (lane == 0) dv[(int64_t)DZHAT * n + a + i] = copysign(sqrt(fmax(prod, 0.0)), zh[i]);
+}
+
+// Norm of the secular eigenvector of root j: one wave per root.
+__global__ void __launch_bounds__(256) dc_norm_kernel(int level, int n, int nl, double *dv, const int *iv,
+                                                      const int *sv) {
+    const int q = blockIdx.y;
+    const MergeGeo g = merge_geo(level, q, n, nl);
+    const int a = g.a;
+    const int k = sv[q * SCOUNT + SK];
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (j >= k) return;
+    const double *dh = dv + (int64_t)DDH * n + a, *zhat = dv + (int64_t)DZHAT * n + a;
+    const int o = iv[(int64_t)IORG * n + a + j];
+    const double tj = dv[(int64_t)DTAU * n + a + j], dO = dh[o];
+    double s2 = 0.0;
+    for (int i = lane; i < k; i += 64) {
+        const double u = zhat[i] / ((dh[i] - dO) - tj);
+        s2 += u * u;
+    }
+    s2 = warp_sum(s2);
+    if (lane == 0) dv[(int64_t)DNRM * n + a + j] = 1.0 / sqrt(s2);
 }
 
 // Final ascending order of the merged eigenvalues (secular roots + deflated
@@ -315,38 +383,48 @@ __global__ void __launch_bounds__(256) dc_order_kernel(int level, int n, int nl,
     Dnext[a + rank] = v;
 }
 
-// Column `col` of the merge matrix U (row-major, ld n, block at (a, a)).
+// U[r][col] of the merge matrix (row-major, ld n, block at (a, a)), one
+// element per thread: column col holds the normalised secular vector of a
+// root (rows of the kept poles) or the unit vector of a deflated pole.
 __global__ void __launch_bounds__(256) dc_vectors_kernel(int level, int n, int nl, const double *dv,
                                                          const int *iv, const int *sv, double *U) {
+    const int q = blockIdx.z;
+    const MergeGeo g = merge_geo(level, q, n, nl);
+    const int a = g.a, nm = g.b - g.a;
+    const int k = sv[q * SCOUNT + SK];
+    const int col = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int r = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (col >= nm || r >= nm) return;
+    const double *dh = dv + (int64_t)DDH * n + a, *zhat = dv + (int64_t)DZHAT * n + a;
+    const double *tau = dv + (int64_t)DTAU * n + a, *nrm = dv + (int64_t)DNRM * n + a;
+    const int *org = iv + (int64_t)IORG * n + a, *rowk = iv + (int64_t)IROWK * n + a;
+    const int src = iv[(int64_t)ICOL * n + a + col];
+    double u = 0.0;
+    if (src >= 0 && src < k) {
+        const int i = rowk[r];
+        if (i >= 0 && i < k) {
+            const int o = org[src];
+            u = zhat[i] / ((dh[i] - dh[o]) - tau[src]) * nrm[src];
+        }
+    } else if (src < 0 && -1 - src == r) {
+        u = 1.0;
+    }
+    U[(int64_t)(a + r) * n + a + col] = u;
+}
+
+// Undo the deflating rotations (last first) on the rows of U, one column per
+// thread.
+__global__ void __launch_bounds__(256) dc_rotate_kernel(int level, int n, int nl, const double *dv, const int *iv,
+                                                        const int *sv, double *U) {
     const int q = blockIdx.y;
     const MergeGeo g = merge_geo(level, q, n, nl);
     const int a = g.a, nm = g.b - g.a;
-    const int k = sv[q * SCOUNT + SK], nr = sv[q * SCOUNT + SNR];
+    const int nr = sv[q * SCOUNT + SNR];
     const int col = blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= nm) return;
-    const double *dh = dv + (int64_t)DDH * n + a, *zhat = dv + (int64_t)DZHAT * n + a;
-    const double *tau = dv + (int64_t)DTAU * n + a;
+    if (col >= nm || nr == 0) return;
     const double *rcs = dv + (int64_t)DRC * n + a, *rsn = dv + (int64_t)DRS * n + a;
-    const int *keep = iv + (int64_t)IKEEP * n + a, *org = iv + (int64_t)IORG * n + a;
     const int *rp = iv + (int64_t)IRP * n + a, *rn = iv + (int64_t)IRN * n + a;
-    int src = iv[(int64_t)ICOL * n + a + col];
-    if (src >= k || src < -nm) src = -nm - 1;  // only reachable with non-finite input
     double *Uc = U + (int64_t)a * n + a + col;  // U[r][col] = Uc[r * n]
-    for (int r = 0; r < nm; ++r) Uc[(int64_t)r * n] = 0.0;
-    if (src >= 0) {
-        const int j = src, o = org[j];
-        const double tj = tau[j], dO = dh[o];
-        double nrm = 0.0;
-        for (int i = 0; i < k; ++i) {
-            const double u = zhat[i] / ((dh[i] - dO) - tj);
-            nrm += u * u;
-        }
-        const double inv = 1.0 / sqrt(nrm);
-        for (int i = 0; i < k; ++i) Uc[(int64_t)keep[i] * n] = zhat[i] / ((dh[i] - dO) - tj) * inv;
-    } else if (src >= -nm) {
-        Uc[(int64_t)(-1 - src) * n] = 1.0;
-    }
-    // undo the deflating rotations, last first
     for (int r = nr - 1; r >= 0; --r) {
         const int pp = rp[r], pn = rn[r];
         const double c = rcs[r], s = rsn[r];
@@ -365,11 +443,18 @@ int dc_num_leaves(int n) {
 }  // namespace
 
 hipError_t large_dc(LargeWs &w, hipStream_t st) {
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute((const void *)dc_prep_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           PREP_LDS_MAX * 20);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
     const int n = w.n;
     const int nl = dc_num_leaves(n);
     int64_t ldq = n;
     double *Qc = w.Q0, *Qn = w.Q1, *Dc = w.D0, *Dn = w.D1;
-    hipLaunchKernelGGL(dc_leaf_kernel, dim3(nl), dim3(256), 0, st, w.d, w.e, n, nl, Dc, Qc, ldq, w.ksel);
+    hipLaunchKernelGGL(dc_leaf_kernel, dim3(nl), dim3(64), 0, st, w.d, w.e, n, nl, Dc, Qc, ldq, w.ksel);
     for (int level = 1; (1 << level) <= nl; ++level) {
         const int nmerge = nl >> level;
         int maxnm = 0, maxhalf = 0;
@@ -379,13 +464,19 @@ hipError_t large_dc(LargeWs &w, hipStream_t st) {
             maxnm = std::max(maxnm, b - a);
             maxhalf = std::max(maxhalf, std::max(m - a, b - m));
         }
-        hipLaunchKernelGGL(dc_prep_kernel, dim3(nmerge), dim3(256), 0, st, level, n, nl, w.e, Dc, Qc, Qn, ldq, w.U,
-                           w.dcd, w.dci, w.dcs, w.gdesc);
-        dim3 grid((maxnm + 255) / 256, nmerge);
-        hipLaunchKernelGGL(dc_secular_kernel, grid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs);
-        hipLaunchKernelGGL(dc_lowner_kernel, grid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs);
-        hipLaunchKernelGGL(dc_order_kernel, grid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs, Dn);
-        hipLaunchKernelGGL(dc_vectors_kernel, grid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs, w.U);
+        const int use_lds = maxnm <= PREP_LDS_MAX ? 1 : 0;
+        const size_t prep_lds = use_lds ? (size_t)maxnm * 20 : 0;
+        hipLaunchKernelGGL(dc_prep_kernel, dim3(nmerge), dim3(256), prep_lds, st, level, n, nl, w.e, Dc, Qc, Qn,
+                           ldq, w.U, w.dcd, w.dci, w.dcs, w.gdesc, use_lds);
+        dim3 wgrid((maxnm + 3) / 4, nmerge);
+        dim3 tgrid((maxnm + 255) / 256, nmerge);
+        hipLaunchKernelGGL(dc_secular_kernel, wgrid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs);
+        hipLaunchKernelGGL(dc_lowner_kernel, wgrid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs);
+        hipLaunchKernelGGL(dc_norm_kernel, wgrid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs);
+        hipLaunchKernelGGL(dc_order_kernel, tgrid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs, Dn);
+        dim3 vgrid((maxnm + 63) / 64, (maxnm + 3) / 4, nmerge);
+        hipLaunchKernelGGL(dc_vectors_kernel, vgrid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs, w.U);
+        hipLaunchKernelGGL(dc_rotate_kernel, tgrid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs, w.U);
         hipError_t e = gemm_launch_batched(w.gdesc, 2 * nmerge, maxhalf, maxnm, false, st);
         if (e != hipSuccess) return e;
         std::swap(Qc, Qn);

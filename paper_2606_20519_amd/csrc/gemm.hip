@@ -9,6 +9,7 @@
 // (checked on gfx950 with one-hot inputs; the f32/bf16 forms differ).
 #include "common.h"
 #include "gemm.h"
+#include "timing.h"
 
 namespace psd {
 
@@ -230,14 +231,22 @@ hipError_t launch_ops(const GemmDesc &d, hipStream_t st) {
 
 hipError_t gemm_launch(const GemmDesc &d, bool complex_data, int epilogue, hipStream_t st) {
     if (d.M <= 0 || d.N <= 0) return hipSuccess;
+    const int slot = timing_begin(KF_GEMM, st);
+    hipError_t e;
     if (complex_data) {
         switch (epilogue) {
-            case EPI_SVEC: return launch_ops<cd, EPI_SVEC>(d, st);
-            case EPI_GAMMA: return launch_ops<cd, EPI_GAMMA>(d, st);
-            default: return launch_ops<cd, EPI_STORE>(d, st);
+            case EPI_SVEC: e = launch_ops<cd, EPI_SVEC>(d, st); break;
+            case EPI_GAMMA: e = launch_ops<cd, EPI_GAMMA>(d, st); break;
+            default: e = launch_ops<cd, EPI_STORE>(d, st); break;
         }
+    } else {
+        e = launch_ops<double, EPI_STORE>(d, st);
     }
-    return launch_ops<double, EPI_STORE>(d, st);
+    // algorithmic flops (upper bound when N or K is only known on the device)
+    double f = (complex_data ? 8.0 : 2.0) * (double)d.M * (double)d.N * (double)d.K;
+    if (d.lower_only) f *= 0.5;
+    timing_end(slot, st, f);
+    return e;
 }
 
 hipError_t gemm_launch_batched(const GemmDesc *ddesc, int count, int maxM, int maxN, bool complex_data,

@@ -14,7 +14,7 @@ namespace psd {
 
 constexpr int LG_NB = 32;      // panel width of the tridiagonalisation
 constexpr int LG_TILE = 64;    // HEMV tile
-constexpr int DC_LEAF = 48;    // largest leaf of the divide and conquer
+constexpr int DC_LEAF = 4;     // largest leaf of the divide and conquer
 
 struct LargeWs {
     int n;
@@ -31,6 +31,7 @@ struct LargeWs {
     double2 *P;         // mb*mb*64 HEMV partials
     double *tdot;       // mb*(mb+1)/2 partial v^H A v
     double2 *pq;        // mb * 2 * NB
+    double *npart;      // mb sigma partials of the next column
     double2 *T;         // npanel * NB * NB block-reflector factors
     // divide and conquer
     double *Q0, *Q1;    // n x n (ld n) eigenvector ping-pong

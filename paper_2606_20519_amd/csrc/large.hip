@@ -159,6 +159,7 @@ size_t large_layout(int n, int flags, void *base, LargeWs *w) {
     L.P = (double2 *)take(cdsz * (size_t)L.mb * L.mb * LG_TILE);
     L.tdot = (double *)take(dsz * (size_t)L.mb * (L.mb + 1) / 2);
     L.pq = (double2 *)take(cdsz * (size_t)L.mb * 2 * NB);
+    L.npart = (double *)take(dsz * (size_t)L.mb);
     L.T = (double2 *)take(cdsz * (size_t)L.npanel * NB * NB);
     L.Q0 = (double *)take(dsz * (size_t)n * n);
     L.Q1 = (double *)take(dsz * (size_t)n * n);
