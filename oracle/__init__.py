@@ -190,3 +190,57 @@ def constructed_projection(u, lam): return default().constructed_projection(u, l
 
 def num_threads() -> int:
     return default().num_threads()
+
+
+# ---------------------------------------------------------------------------
+# Newton-Schulz reference for the mixed-precision form (attribution of error)
+# ---------------------------------------------------------------------------
+#
+# The paper's outlook (Sec. V, "Approximate semidefinite-cone projections")
+# proposes replacing the eigendecomposition by a matrix polynomial that
+# approximates the eigenvalue threshold with matrix-matrix products only.
+# The simplest such polynomial is the Newton-Schulz iteration for the matrix
+# sign function, X_{k+1} = 1/2 X_k (3I - X_k^2), started from X_0 = X/alpha
+# with alpha >= ||X||_2 (it converges to sign(X) for spectra inside
+# (-sqrt3, sqrt3)); the projection then follows from Pi(X) = (X + X sign X)/2
+# since max(t, 0) = (t + t sgn t)/2.  These functions are the plain FP64
+# version of that recurrence (NumPy matmul as the only library step), used to
+# attribute the GPU mixed form's error to truncation versus rounding.
+
+def ns_scalar_map(t, iters: int):
+    """The scalar recurrence t <- 1.5 t - 0.5 t^3 applied `iters` times
+    (elementwise, float64)."""
+    t = np.asarray(t, dtype=np.float64).copy()
+    for _ in range(iters):
+        t = 1.5 * t - 0.5 * t ** 3
+    return t
+
+
+def ns_constructed_projection(u, lam, alpha: float, iters: int) -> np.ndarray:
+    """Exact-arithmetic Newton-Schulz projection of X = U diag(lam) U^H after
+    `iters` steps: U diag((lam + lam p(lam/alpha))/2) U^H as svec, where p is
+    the iterated scalar map.  Only per-eigenvalue arithmetic."""
+    lam = np.asarray(lam, dtype=np.float64)
+    s = ns_scalar_map(lam / alpha, iters)
+    f = 0.5 * (lam + lam * s)
+    u = np.asarray(u, dtype=np.complex128)
+    return default().pack((u * f[None, :]) @ u.conj().T)
+
+
+def ns_matrix_projection(x_svec, n: int, alpha: float, iters: int) -> np.ndarray:
+    """FP64 Newton-Schulz projection by matrix products: X_0 = X/alpha,
+    X_{k+1} = X_k (3I - X_k^2)/2 for `iters` steps, then (X + X X_K)/2, whose
+    Hermitian part is returned as svec."""
+    x = default().unpack(x_svec, n)
+    xk = x / alpha
+    eye = np.eye(n)
+    for _ in range(iters):
+        xk = 0.5 * xk @ (3.0 * eye - xk @ xk)
+    p = 0.5 * (x + x @ xk)
+    return default().pack(0.5 * (p + p.conj().T))
+
+
+def spectral_norm(x_svec, n: int) -> float:
+    """||mat(x)||_2 from LAPACK eigenvalues (library routine)."""
+    w = np.linalg.eigvalsh(default().unpack(x_svec, n))
+    return float(np.abs(w).max()) if n else 0.0

@@ -330,3 +330,53 @@ def test_vjp_constructed_spectrum(orc):
                 gam[i, j] = max(a, b) / (max(a, b) - min(a, b))
     ref = u @ (gam * (u.conj().T @ e @ u)) @ u.conj().T
     assert rel(orc.vjp(sx, orc.pack(e), n), orc.pack(ref)) <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# Newton-Schulz reference (mixed form attribution)
+# --------------------------------------------------------------------------
+
+def test_ns_scalar_map_fixed_points_and_sign():
+    import oracle
+    t = np.array([-1.0, 1.0, 0.0])
+    assert np.array_equal(oracle.ns_scalar_map(t, 10), t)
+    x = np.array([-1.5, -0.3, -1e-3, 1e-3, 0.2, 1.7])
+    s = oracle.ns_scalar_map(x, 40)
+    np.testing.assert_allclose(s, np.sign(x), rtol=0, atol=1e-12)
+    # one step is the cubic 1.5 t - 0.5 t^3 (hand value at t = 0.5: 0.6875)
+    assert oracle.ns_scalar_map(np.array([0.5]), 1)[0] == 0.6875
+
+
+@pytest.mark.parametrize("n", [12, 40])
+def test_ns_matrix_matches_scalar_on_constructed_spectra(orc, n):
+    import oracle
+    sx, u, lam = W.constructed(n, 77 + n, gap=1e-3)
+    alpha = 1.05
+    for iters in (3, 12, 30):
+        a = oracle.ns_matrix_projection(sx, n, alpha, iters)
+        b = oracle.ns_constructed_projection(u, lam, alpha, iters)
+        assert rel(a, b) <= 1e-12
+    # converged iterations reproduce the exact projection
+    exact = orc.constructed_projection(u, lam)
+    assert rel(oracle.ns_constructed_projection(u, lam, alpha, 40), exact) <= 1e-13
+    assert rel(oracle.ns_matrix_projection(sx, n, alpha, 40), orc.project(sx, n)) <= 1e-12
+
+
+def test_ns_truncation_bounded_by_small_eigenvalues(orc):
+    # Components with |lambda| below the resolved band contribute at most
+    # |lambda| each to the truncated projection's error.
+    import oracle
+    n = 30
+    sx, u, lam = W.constructed(n, 5, gap=1e-6)
+    for iters in (5, 15, 25):
+        s = oracle.ns_scalar_map(lam / 1.0, iters)
+        err = np.linalg.norm(oracle.ns_constructed_projection(u, lam, 1.0, iters) - orc.constructed_projection(u, lam))
+        bound = np.sqrt(np.sum((0.5 * lam * (s - np.sign(lam))) ** 2))
+        assert abs(err - bound) <= 1e-12 * max(1.0, bound)
+        assert bound <= np.sqrt(np.sum(lam[np.abs(s) < 1 - 1e-12] ** 2)) + 1e-15
+
+
+def test_spectral_norm_pin(orc):
+    import oracle
+    sx, u, lam = W.constructed(20, 3)
+    assert abs(oracle.spectral_norm(sx, 20) - np.abs(lam).max()) <= 1e-13
