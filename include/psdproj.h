@@ -59,7 +59,8 @@ typedef enum {
 typedef enum {
     PSD_FP64_EIG = 0,     /* FP64 eigendecomposition path (exact up to rounding) */
     PSD_MIXED_BF16 = 1,   /* Newton-Schulz sign iteration, BF16 MFMA + FP64 correction */
-    PSD_MIXED_FP32 = 2    /* Newton-Schulz sign iteration, FP32 MFMA + FP64 correction */
+    PSD_MIXED_FP32 = 2    /* Newton-Schulz sign iteration, FP32 MFMA + FP64 correction;
+                             blocks of order <= 64 always take the exact LDS kernel */
 } psd_mode;
 
 /* Per-block result record, written by the device (device or pinned host
@@ -71,7 +72,8 @@ typedef struct {
     int32_t iters;        /* NS iterations (mixed) or 0 */
     int32_t fallback;     /* 1 if a mixed request fell back to the FP64 path */
     int32_t reserved;
-    double est_rel_err;   /* mixed: estimated relative error; FP64: 0 */
+    double est_rel_err;   /* mixed: ||I - S^2||_F / sqrt(n) of the sign estimate S; FP64: 0 */
+    double scale;         /* mixed: spectral scale alpha (~1.1 ||X||_2); FP64: 0 */
 } psd_info;
 
 /* Workspace bytes needed to serve `nblocks` blocks of orders n[0..nblocks)
@@ -132,6 +134,12 @@ typedef enum {
 } psd_kernel_family;
 psd_status psd_timing_start(int32_t family, int32_t max_launches);
 psd_status psd_timing_stop(double *ms, int32_t *launches, double *work);
+
+/* Newton-Schulz settings of the mixed modes (process-wide; not
+ * thread-safe): `iters` low-precision iterations (>= 1, default 40, enough for
+ * eigenvalues down to about 1e-6 ||X||_2) and `corrections` FP64 correction
+ * steps (>= 0, default 2).  Returns PSD_EINVAL outside 1..200 / 0..8. */
+psd_status psd_set_ns_iterations(int32_t iters, int32_t corrections);
 
 /* Static description of a status code. */
 const char *psd_status_string(psd_status status);

@@ -20,9 +20,16 @@ import torch
 from . import _lib
 from ._lib import MODES, PSD_FLAG_SAVE, PsdError, PsdInfo, check  # noqa: F401
 
-__all__ = ["project", "project_batched", "vjp", "PSDProject", "workspace", "PsdError", "MODES"]
+__all__ = ["project", "project_batched", "vjp", "PSDProject", "workspace", "set_ns_iterations", "PsdError",
+           "MODES"]
 
 _ws_cache: dict = {}
+INFO_WORDS = ctypes.sizeof(PsdInfo) // 4
+
+
+def set_ns_iterations(iters: int = 40, corrections: int = 2):
+    """Newton-Schulz iterations and FP64 correction steps of the mixed modes."""
+    _lib.set_ns_iterations(iters, corrections)
 
 
 def _mode(mode) -> int:
@@ -68,7 +75,7 @@ def project(x: torch.Tensor, n: int, mode="fp64", out: torch.Tensor = None, info
     _check_vec(y, n * n, "out")
     m = _mode(mode)
     ws = workspace([n], m, x.device, PSD_FLAG_SAVE if saved is not None else 0)
-    inf_t = torch.zeros(8, dtype=torch.int32, device=x.device) if info else None
+    inf_t = torch.zeros(INFO_WORDS, dtype=torch.int32, device=x.device) if info else None
     st = _lib.lib().psd_project(n, _ptr(x), _ptr(y), m, _ptr(ws), ws.numel(), ctypes.c_void_p(_stream_ptr(x.device)),
                                 _ptr(inf_t), _ptr(saved))
     check(st, "psd_project")
@@ -92,7 +99,7 @@ def project_batched(x: torch.Tensor, sizes, mode="fp64", out: torch.Tensor = Non
     _check_vec(y, total, "out")
     m = _mode(mode)
     ws = workspace(sizes, m, x.device)
-    inf_t = torch.zeros(8 * len(sizes), dtype=torch.int32, device=x.device) if info else None
+    inf_t = torch.zeros(INFO_WORDS * len(sizes), dtype=torch.int32, device=x.device) if info else None
     st = _lib.lib().psd_project_batched(len(sizes), _lib.int_array(sizes), _ptr(x), _ptr(y), m, _ptr(ws),
                                         ws.numel(), ctypes.c_void_p(_stream_ptr(x.device)), _ptr(inf_t))
     check(st, "psd_project_batched")
@@ -125,19 +132,33 @@ def vjp(gy: torch.Tensor, n: int, x: torch.Tensor = None, saved: torch.Tensor = 
 
 
 class PSDProject(torch.autograd.Function):
-    """y = svec(Pi(mat(x))) with backward gx = svec(DPi(X)[mat(gy)])."""
+    """y = svec(Pi(mat(x))) with backward gx = svec(DPi(X)[mat(gy)]).
+
+    fp64: the forward saves the eigen-pair and the backward reuses it.
+    Mixed modes: the forward is the Newton-Schulz form (no eigenvectors), so
+    it saves x and the backward recomputes the FP64 eigen-pair."""
 
     @staticmethod
     def forward(ctx, x, n, mode="fp64"):
-        saved = torch.empty(saved_numel(n), dtype=torch.float64, device=x.device)
-        y = project(x.detach().contiguous(), n, mode, saved=saved)
-        ctx.save_for_backward(saved)
+        xd = x.detach().contiguous()
         ctx.n = n
         ctx.mode = mode
+        if _mode(mode) == MODES["fp64"]:
+            saved = torch.empty(saved_numel(n), dtype=torch.float64, device=x.device)
+            y = project(xd, n, mode, saved=saved)
+            ctx.save_for_backward(saved)
+            ctx.from_x = False
+        else:
+            y = project(xd, n, mode)
+            ctx.save_for_backward(xd)
+            ctx.from_x = True
         return y
 
     @staticmethod
     def backward(ctx, gy):
-        (saved,) = ctx.saved_tensors
-        gx = vjp(gy.contiguous(), ctx.n, saved=saved, mode=ctx.mode)
+        (t,) = ctx.saved_tensors
+        if ctx.from_x:
+            gx = vjp(gy.contiguous(), ctx.n, x=t, mode=ctx.mode)
+        else:
+            gx = vjp(gy.contiguous(), ctx.n, saved=t, mode=ctx.mode)
         return gx, None, None

@@ -19,7 +19,8 @@ PSD_FLAG_SAVE = 1
 
 # Every symbol include/psdproj.h declares.
 EXPORTS = ("psd_workspace_size", "psd_saved_size", "psd_project", "psd_project_batched",
-           "psd_project_vjp", "psd_timing_start", "psd_timing_stop", "psd_status_string", "psd_version")
+           "psd_project_vjp", "psd_timing_start", "psd_timing_stop", "psd_set_ns_iterations",
+           "psd_status_string", "psd_version")
 KF_HEMV, KF_GEMM = 1, 2
 
 
@@ -32,7 +33,7 @@ class PsdError(RuntimeError):
 class PsdInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("n_pos", ctypes.c_int32), ("n_neg", ctypes.c_int32),
                 ("iters", ctypes.c_int32), ("fallback", ctypes.c_int32), ("reserved", ctypes.c_int32),
-                ("est_rel_err", ctypes.c_double)]
+                ("est_rel_err", ctypes.c_double), ("scale", ctypes.c_double)]
 
 
 _lib = None
@@ -61,6 +62,8 @@ def lib():
     L.psd_status_string.argtypes = [i32]
     L.psd_status_string.restype = ctypes.c_char_p
     L.psd_version.restype = ctypes.c_char_p
+    L.psd_set_ns_iterations.argtypes = [i32, i32]
+    L.psd_set_ns_iterations.restype = i32
     L.psd_timing_start.argtypes = [i32, i32]
     L.psd_timing_start.restype = i32
     L.psd_timing_stop.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
@@ -106,3 +109,7 @@ def timing_stop():
     ms, n, wk = ctypes.c_double(0), ctypes.c_int32(0), ctypes.c_double(0)
     check(lib().psd_timing_stop(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(wk)), "psd_timing_stop")
     return ms.value, n.value, wk.value
+
+
+def set_ns_iterations(iters: int, corrections: int):
+    check(lib().psd_set_ns_iterations(iters, corrections), "psd_set_ns_iterations")

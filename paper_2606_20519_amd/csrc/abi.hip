@@ -11,6 +11,7 @@
 #include "../../include/psdproj.h"
 #include "kernels.h"
 #include "large.h"
+#include "mixed.h"
 
 using namespace psd;
 
@@ -47,8 +48,10 @@ struct Carve {
 
 // Workspace of one FP64 large-block computation of order n.
 size_t large_ws_bytes(int n, int mode, int flags) {
-    (void)mode;
-    return large_layout(n, flags, nullptr, nullptr);
+    size_t b = large_layout(n, flags, nullptr, nullptr);
+    if ((mode == PSD_MIXED_BF16 || mode == PSD_MIXED_FP32) && !(flags & PSD_FLAG_SAVE))
+        b = std::max(b, mixed_layout(n, mode, nullptr, nullptr));
+    return b;
 }
 
 // Full FP64 eigen pipeline on one block: unpack, tridiagonalise, block
@@ -82,11 +85,34 @@ hipError_t large_project(int n, const double *x, double *y, void *ws, hipStream_
 
 psd_status status_of(hipError_t e) { return e == hipSuccess ? PSD_OK : PSD_EDEVICE; }
 
+int g_ns_iters = 40;
+int g_ns_corr = 2;
+
+bool is_mixed(int mode) { return mode == PSD_MIXED_BF16 || mode == PSD_MIXED_FP32; }
+
+// One block of order n > 64: the mixed path for mixed modes, else FP64.
+hipError_t project_block(int n, const double *x, double *y, psd_mode mode, void *ws, hipStream_t s,
+                         psd_dev_info *info, double *saved) {
+    if (is_mixed(mode) && !saved) {
+        MixedWs w;
+        mixed_layout(n, mode, ws, &w);
+        return mixed_project(w, mode, x, y, info, g_ns_iters, g_ns_corr, s);
+    }
+    return large_project(n, x, y, ws, s, info, saved);
+}
+
 }  // namespace
 
 extern "C" {
 
 const char *psd_version(void) { return "psdproj 0.1 (gfx950)"; }
+
+psd_status psd_set_ns_iterations(int32_t iters, int32_t corrections) {
+    if (iters < 1 || iters > 200 || corrections < 0 || corrections > 8) return PSD_EINVAL;
+    g_ns_iters = iters;
+    g_ns_corr = corrections;
+    return PSD_OK;
+}
 
 const char *psd_status_string(psd_status s) {
     switch (s) {
@@ -131,14 +157,13 @@ psd_status psd_project(int32_t n, const double *x, double *y, psd_mode mode, voi
     if (st != PSD_OK) return st;
     if (ws_bytes < need || (need && !ws)) return PSD_EWORKSPACE;
     if (ws && (reinterpret_cast<uintptr_t>(ws) % kAlign)) return PSD_EINVAL;
-    if (mode != PSD_FP64_EIG) return PSD_EUNSUPPORTED;
     hipStream_t s = static_cast<hipStream_t>(stream);
     psd_dev_info *dinfo = reinterpret_cast<psd_dev_info *>(info);
     if (n <= 64) {
         SmallJob job{0, 0, n, 0};
         return status_of(launch_small_one(job, x, y, dinfo, saved, s));
     }
-    return status_of(large_project(n, x, y, ws, s, dinfo, saved));
+    return status_of(project_block(n, x, y, mode, ws, s, dinfo, saved));
 }
 
 psd_status psd_project_batched(int32_t nblocks, const int32_t *n, const double *x, double *y,
@@ -167,7 +192,6 @@ psd_status psd_project_batched(int32_t nblocks, const int32_t *n, const double *
         else large.push_back(b);
         off += (int64_t)n[b] * n[b];
     }
-    if (mode != PSD_FP64_EIG) return PSD_EUNSUPPORTED;
     Carve cv(ws);
     SmallJob *djobs = cv.take<SmallJob>(small.size());
     void *lws = cv.base + cv.used;
@@ -178,7 +202,7 @@ psd_status psd_project_batched(int32_t nblocks, const int32_t *n, const double *
         for (int b = 0; b < nblocks; ++b) {
             if (li < (int)large.size() && large[li] == b) {
                 psd_dev_info *inf = infos ? reinterpret_cast<psd_dev_info *>(infos) + b : nullptr;
-                hipError_t e = large_project(n[b], x + o, y + o, lws, s, inf, nullptr);
+                hipError_t e = project_block(n[b], x + o, y + o, mode, lws, s, inf, nullptr);
                 if (e != hipSuccess) return PSD_EDEVICE;
                 ++li;
             }
@@ -207,7 +231,8 @@ psd_status psd_project_vjp(int32_t n, const double *x, const double *saved, cons
     if (st != PSD_OK) return st;
     if (ws_bytes < need || !ws) return PSD_EWORKSPACE;
     if (reinterpret_cast<uintptr_t>(ws) % kAlign) return PSD_EINVAL;
-    if (mode != PSD_FP64_EIG) return PSD_EUNSUPPORTED;
+    // The derivative is the Daleckii-Krein formula on the FP64 eigen-pair in
+    // every mode (the Newton-Schulz form yields no eigenvectors).
     hipStream_t s = static_cast<hipStream_t>(stream);
     LargeWs w;
     large_layout(n, PSD_FLAG_SAVE, ws, &w);

@@ -52,6 +52,10 @@ struct GemmDesc {
     // writes its partial product to C + z*c_zstride (beta must be 0).
     int kchunk;
     int64_t c_zstride;
+    // EPI_STORE: out = alpha*acc + beta*C + diag_add*delta_ij
+    double diag_add;
+    // EPI_SVEC: y = xscale*x + sign*acc (0 means 1, the default)
+    double xscale;
 };
 
 // Launch one GEMM described by `d` (grid sized from d) on stream st.

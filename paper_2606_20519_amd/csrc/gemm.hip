@@ -170,13 +170,14 @@ __device__ void gemm_tile(const GemmDesc &dd, int ti, int tj, int tz) {
                     const int64_t n = d.svec_n;
                     const double sgn = d.dsign ? *d.dsign : d.sign;
                     const double *xb = (d.dsign && sgn > 0.0) ? nullptr : d.xbase;
+                    const double xs = d.xscale != 0.0 ? d.xscale : 1.0;
                     if (i == j) {
                         const int64_t o = svec_col_start((int)n, j);
-                        const double base = xb ? xb[o] : 0.0;
+                        const double base = xb ? xs * xb[o] : 0.0;
                         d.y[o] = base + sgn * re;
                     } else {
                         const int64_t o = svec_off((int)n, i, j);
-                        const double b0 = xb ? xb[o] : 0.0, b1 = xb ? xb[o + 1] : 0.0;
+                        const double b0 = xb ? xs * xb[o] : 0.0, b1 = xb ? xs * xb[o + 1] : 0.0;
                         d.y[o] = b0 + sgn * rt2 * re;
                         d.y[o + 1] = b1 + sgn * rt2 * im;
                     }
@@ -189,14 +190,14 @@ __device__ void gemm_tile(const GemmDesc &dd, int ti, int tj, int tz) {
                 T *C = static_cast<T *>(d.C);
                 const int64_t idx = i + (int64_t)j * d.ldc;
                 if constexpr (CPLX) {
-                    cd out = cmk(d.alpha * re, d.alpha * im);
+                    cd out = cmk(d.alpha * re + (i == j ? d.diag_add : 0.0), d.alpha * im);
                     if (d.beta != 0.0) {
                         const cd c0 = *reinterpret_cast<const cd *>(&C[idx]);
                         out = cmk(out.x + d.beta * c0.x, out.y + d.beta * c0.y);
                     }
                     *reinterpret_cast<cd *>(&C[idx]) = out;
                 } else {
-                    double out = d.alpha * re;
+                    double out = d.alpha * re + (i == j ? d.diag_add : 0.0);
                     if (d.beta != 0.0) out += d.beta * *reinterpret_cast<const double *>(&C[idx]);
                     *reinterpret_cast<double *>(&C[idx]) = out;
                 }

@@ -11,6 +11,7 @@ namespace psd {
 struct psd_dev_info {
     int32_t status, n_pos, n_neg, iters, fallback, reserved;
     double est_rel_err;
+    double scale;
 };
 
 // One small block (order <= 64) for the whole-block LDS kernel.

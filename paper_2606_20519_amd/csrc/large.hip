@@ -60,6 +60,7 @@ __global__ void __launch_bounds__(256) select_kernel(const double *__restrict__ 
             info->fallback = 0;
             info->reserved = 0;
             info->est_rel_err = 0.0;
+            info->scale = 0.0;
         }
     }
     if (c >= k || r >= n) return;

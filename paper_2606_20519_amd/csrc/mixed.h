@@ -1,0 +1,26 @@
+// Workspace and launcher of the mixed-precision Newton-Schulz projection.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+#include "kernels.h"
+
+namespace psd {
+
+struct MixedWs {
+    int n;
+    int64_t lda;        // FP64 matrices (complex, column-major)
+    int npad;           // low-precision planes: npad x npad, npad % 64 == 0
+    double2 *M, *S, *S2, *T64;
+    void *lo0, *lo1, *lo2;   // two planes (re, im) each
+    double2 *q, *qprev, *wv, *P;
+    double *ab, *alpha, *red;
+    int *status;
+};
+
+// mode: 1 = BF16, 2 = FP32 low-precision iterations.
+size_t mixed_layout(int n, int mode, void *base, MixedWs *w);
+hipError_t mixed_project(const MixedWs &w, int mode, const double *x, double *y, psd_dev_info *info, int iters,
+                         int corr, hipStream_t st);
+
+}  // namespace psd

@@ -1,0 +1,480 @@
+// Mixed-precision projection by the Newton-Schulz sign iteration.
+//
+// Pi(X) = (X + X sign(X)) / 2, because max(t, 0) = (t + t sgn t)/2 on each
+// eigenvalue.  sign(X) is the limit of X_{k+1} = X_k (3I - X_k^2)/2 from
+// X_0 = X/alpha with alpha >= ||X||_2 (the cubic converges to sgn t for
+// |t| < sqrt3): a composite matrix polynomial built from matrix products only,
+// the kind of factorisation-free projection the paper's outlook proposes
+// (Sec. V, "Approximate semidefinite-cone projections").
+//
+// Stages (FP64 only where it buys accuracy):
+//  * scale: alpha from a short FP64 Lanczos run (24 Hermitian mat-vecs, then
+//    the eigenvalues of the small tridiagonal by QL), alpha = 1.1 max|theta|;
+//  * X_0 = X/alpha rounded (RNE) to BF16 or FP32 planar complex;
+//  * K iterations, each two complex GEMMs on the MFMA cores with FP32
+//    accumulation: T = 3I - X_k^2, then X_{k+1} = X_k T / 2 (epilogues fused);
+//    the last product is kept in FP64;
+//  * c FP64 correction steps S <- S (3I - S^2)/2 (FP64 MFMA GEMMs), which
+//    square the error of every eigencomponent whose sign the low-precision
+//    iterations already resolved;
+//  * Pi = X/2 + X S/2 by one FP64 GEMM over the lower tiles writing the svec;
+//    est_rel_err = ||I - S^2||_F / sqrt(n) of the S entering the last
+//    correction, n_pos from tr S.
+// Components with |lambda| below the low precision's resolution (about
+// u ||X||: u = 2^-8 for BF16, 2^-24 for FP32) cannot be classified; their
+// contribution to the error is at most |lambda| each.
+#include <algorithm>
+
+#include "common.h"
+#include "large.h"
+#include "mixed.h"
+#include "ql.h"
+
+namespace psd {
+
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+
+constexpr int LZ_STEPS = 24;
+constexpr int LZ_SPLIT = 16;  // column splits of the Lanczos mat-vec
+
+// Counter-based pseudo-random value in [-0.5, 0.5) (splitmix64).
+__device__ inline double hash_unit(uint64_t x) {
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    x ^= x >> 31;
+    return (double)(x >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+}
+
+__global__ void __launch_bounds__(1024) lz_init_kernel(int n, double2 *q, double2 *qprev, double *ab) {
+    __shared__ double red[32];
+    double part = 0.0;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+        const double2 v = cmk(hash_unit(2 * (uint64_t)r), hash_unit(2 * (uint64_t)r + 1));
+        q[r] = v;
+        qprev[r] = cmk(0.0, 0.0);
+        part += cabs2(v);
+    }
+    const double inv = 1.0 / sqrt(block_sum(part, red));
+    for (int r = threadIdx.x; r < n; r += blockDim.x) q[r] = cscale(q[r], inv);
+    if (threadIdx.x < 2 * LZ_STEPS + 4) ab[threadIdx.x] = 0.0;
+}
+
+// P[cs][row] = sum over the column chunk cs of M(row, col) q(col).
+__global__ void __launch_bounds__(256) lz_gemv_kernel(const double2 *__restrict__ M, int64_t lda, int n,
+                                                      const double2 *__restrict__ q, double2 *P) {
+    __shared__ double2 part[4][64];
+    const int rb = blockIdx.x, cs = blockIdx.y, t = threadIdx.x, r = t & 63, g = t >> 6;
+    const int row = rb * 64 + r;
+    const int chunk = (n + LZ_SPLIT - 1) / LZ_SPLIT;
+    const int c0 = cs * chunk, c1 = min(n, c0 + chunk);
+    double2 acc = cmk(0.0, 0.0);
+    if (row < n) {
+#pragma unroll 4
+        for (int c = c0 + g; c < c1; c += 4) acc = cfma(M[row + (int64_t)c * lda], q[c], acc);
+    }
+    part[g][r] = acc;
+    __syncthreads();
+    if (t < 64 && row < n)
+        P[(int64_t)cs * n + row] = cadd(cadd(part[0][t], part[1][t]), cadd(part[2][t], part[3][t]));
+}
+
+// One Lanczos step on a single workgroup: y = sum P, a = Re q^H y,
+// w = y - a q - b_prev q_prev, b = ||w||, (q_prev, q) <- (q, w / b).
+__global__ void __launch_bounds__(1024) lz_step_kernel(int n, int step, const double2 *__restrict__ P, double2 *q,
+                                                       double2 *qprev, double2 *wv, double *ab) {
+    __shared__ double red[32];
+    if (ab[2 * LZ_STEPS + 2] != 0.0) return;  // broke down earlier
+    double part = 0.0;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+        double2 y = cmk(0.0, 0.0);
+        for (int cs = 0; cs < LZ_SPLIT; ++cs) y = cadd(y, P[(int64_t)cs * n + r]);
+        wv[r] = y;
+        part += cmulc(q[r], y).x;
+    }
+    const double a = block_sum(part, red);
+    const double bprev = step > 0 ? ab[LZ_STEPS + step - 1] : 0.0;
+    part = 0.0;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+        const double2 w = csub(csub(wv[r], cscale(q[r], a)), cscale(qprev[r], bprev));
+        wv[r] = w;
+        part += cabs2(w);
+    }
+    const double b = sqrt(block_sum(part, red));
+    if (threadIdx.x == 0) {
+        ab[step] = a;
+        ab[LZ_STEPS + step] = b;
+        ab[2 * LZ_STEPS] = step + 1;  // steps done
+    }
+    const double nrmx = fabs(a) + bprev;
+    if (!(b > 1e-14 * nrmx)) {
+        if (threadIdx.x == 0) ab[2 * LZ_STEPS + 2] = 1.0;  // invariant subspace: Ritz values exact
+        return;
+    }
+    const double inv = 1.0 / b;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+        qprev[r] = q[r];
+        q[r] = cscale(wv[r], inv);
+    }
+}
+
+// alpha = 1.1 max |theta| over the Ritz values of the Lanczos tridiagonal.
+__global__ void __launch_bounds__(64) lz_final_kernel(const double *ab, double *alpha_out) {
+    __shared__ double d[64], e[64], Z[LZ_STEPS * LZ_STEPS], rc[64], rs[64];
+    __shared__ int ri[64], nrot_s, done_s;
+    const int k = (int)ab[2 * LZ_STEPS];
+    const int t = threadIdx.x;
+    if (t < k) { d[t] = ab[t]; e[t] = t < k - 1 ? ab[LZ_STEPS + t] : 0.0; }
+    for (int idx = t; idx < k * k; idx += blockDim.x) Z[idx] = (idx % k == idx / k) ? 1.0 : 0.0;
+    __syncthreads();
+    if (k > 0) ql_implicit(d, e, Z, k, k, rc, rs, ri, &nrot_s, &done_s);
+    if (t == 0) {
+        double m = 0.0;
+        for (int i = 0; i < k; ++i) m = fmax(m, fabs(d[i]));
+        *alpha_out = m > 0.0 ? 1.1 * m : 1.0;
+    }
+}
+
+// Full Hermitian matrix from the svec (M = conj X, see common.h); flags
+// non-finite entries.
+__global__ void __launch_bounds__(256) mx_unpack_kernel(const double *__restrict__ x, double2 *M, int64_t lda, int n,
+                                                        int *status) {
+    const int j = blockIdx.y;
+    const int i = j + blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double rs2 = 0.70710678118654752440;
+    double2 v;
+    if (i == j) {
+        v = cmk(x[svec_col_start(n, j)], 0.0);
+    } else {
+        const int64_t o = svec_off(n, i, j);
+        v = cmk(x[o] * rs2, x[o + 1] * rs2);
+        M[j + (int64_t)i * lda] = cconj(v);
+    }
+    if (!(isfinite(v.x) && isfinite(v.y))) status[2] = ST_ENONFINITE;
+    M[i + (int64_t)j * lda] = v;
+}
+
+__global__ void mx_init_kernel(int *status) {
+    if (threadIdx.x < 4) status[threadIdx.x] = 0;
+}
+
+template <typename L>
+__device__ __forceinline__ L to_low(float v);
+template <>
+__device__ __forceinline__ __bf16 to_low<__bf16>(float v) { return (__bf16)v; }
+template <>
+__device__ __forceinline__ float to_low<float>(float v) { return v; }
+
+// X0 = M / alpha in low precision, planar, ld = npad; zero padding.
+template <typename L>
+__global__ void __launch_bounds__(256) ns_scale_kernel(const double2 *__restrict__ M, int64_t lda, int n, int npad,
+                                                       const double *alpha, L *Xre, L *Xim) {
+    const int j = blockIdx.y;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= npad) return;
+    const double inv = 1.0 / *alpha;
+    double2 v = cmk(0.0, 0.0);
+    if (i < n && j < n) v = M[i + (int64_t)j * lda];
+    Xre[i + (int64_t)j * npad] = to_low<L>((float)(v.x * inv));
+    Xim[i + (int64_t)j * npad] = to_low<L>((float)(v.y * inv));
+}
+
+enum { NS_EPI_T = 0, NS_EPI_HALF = 1, NS_EPI_F64 = 2 };
+
+// C = A B for Hermitian A, B that commute (polynomials in the same X), so C
+// is Hermitian: only the lower tiles (ti >= tj) are computed, and each is
+// written together with its conjugate mirror, which keeps every iterate
+// exactly Hermitian in storage (diagonal imaginary parts set to zero).  That
+// exactness matters: A(i,k) is read as conj(A(k,i)) so that both operands
+// stream along k within a column, and for a non-Hermitian iterate this
+// would multiply by A^H -- a substitution under which rounding errors that
+// anticommute with sign(X) double at every step.
+// Planar low precision, column-major, ld npad (npad % 64 == 0), FP32
+// accumulation on the MFMA cores.  Tile 64x64x32, 4 waves in 2x2, each
+// 32x32 = 2x2 MFMA blocks of 16x16.
+template <typename L>
+__global__ void __launch_bounds__(256) ns_gemm_kernel(const L *__restrict__ Are, const L *__restrict__ Aim,
+                                                      const L *__restrict__ Bre, const L *__restrict__ Bim, int npad,
+                                                      int epi, L *Cre, L *Cim, double2 *C64, int64_t ld64, int n) {
+    constexpr bool BF = sizeof(L) == 2;
+    constexpr int KP = 32 + (BF ? 8 : 4);  // padded k extent in LDS
+    __shared__ __align__(16) L sAr[64][KP], sAi[64][KP], sBr[64][KP], sBi[64][KP];
+    const int tb = blockIdx.x;
+    int ti = (int)((sqrt(8.0 * tb + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= tb) ++ti;
+    while (ti * (ti + 1) / 2 > tb) --ti;
+    const int tj = tb - ti * (ti + 1) / 2;
+    const int i0 = ti * 64, j0 = tj * 64;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w & 1, wn = w >> 1;
+    v4f accr[2][2], acci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) { accr[a][b] = v4f{0, 0, 0, 0}; acci[a][b] = v4f{0, 0, 0, 0}; }
+    // loader: thread t covers row (t/4) of the tile, k = 8*(t%4) .. +7
+    const int lr = t >> 2, lk = (t & 3) * 8;
+    for (int k0 = 0; k0 < npad; k0 += 32) {
+        {
+            const int64_t ao = (int64_t)(k0 + lk) + (int64_t)(i0 + lr) * npad;
+            const int64_t bo = (int64_t)(k0 + lk) + (int64_t)(j0 + lr) * npad;
+            if constexpr (BF) {
+                const uint4 ar = *reinterpret_cast<const uint4 *>(Are + ao);
+                uint4 ai = *reinterpret_cast<const uint4 *>(Aim + ao);
+                ai.x ^= 0x80008000u; ai.y ^= 0x80008000u; ai.z ^= 0x80008000u; ai.w ^= 0x80008000u;  // conj
+                *reinterpret_cast<uint4 *>(&sAr[lr][lk]) = ar;
+                *reinterpret_cast<uint4 *>(&sAi[lr][lk]) = ai;
+                *reinterpret_cast<uint4 *>(&sBr[lr][lk]) = *reinterpret_cast<const uint4 *>(Bre + bo);
+                *reinterpret_cast<uint4 *>(&sBi[lr][lk]) = *reinterpret_cast<const uint4 *>(Bim + bo);
+            } else {
+#pragma unroll
+                for (int h = 0; h < 8; h += 4) {
+                    const float4 ar = *reinterpret_cast<const float4 *>(Are + ao + h);
+                    const float4 ai = *reinterpret_cast<const float4 *>(Aim + ao + h);
+                    *reinterpret_cast<float4 *>(&sAr[lr][lk + h]) = ar;
+                    *reinterpret_cast<float4 *>(&sAi[lr][lk + h]) = make_float4(-ai.x, -ai.y, -ai.z, -ai.w);
+                    *reinterpret_cast<float4 *>(&sBr[lr][lk + h]) = *reinterpret_cast<const float4 *>(Bre + bo + h);
+                    *reinterpret_cast<float4 *>(&sBi[lr][lk + h]) = *reinterpret_cast<const float4 *>(Bim + bo + h);
+                }
+            }
+        }
+        __syncthreads();
+        const int ii = lane & 15, kg = lane >> 4;
+        if constexpr (BF) {
+            v8bf ar[2], ai[2], ain[2], br[2], bi[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                ar[a] = *reinterpret_cast<const v8bf *>(&sAr[wm * 32 + a * 16 + ii][kg * 8]);
+                ai[a] = *reinterpret_cast<const v8bf *>(&sAi[wm * 32 + a * 16 + ii][kg * 8]);
+                v8s neg = *reinterpret_cast<const v8s *>(&ai[a]) ^ (short)0x8000;
+                ain[a] = *reinterpret_cast<const v8bf *>(&neg);
+            }
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                br[b] = *reinterpret_cast<const v8bf *>(&sBr[wn * 32 + b * 16 + ii][kg * 8]);
+                bi[b] = *reinterpret_cast<const v8bf *>(&sBi[wn * 32 + b * 16 + ii][kg * 8]);
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    accr[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar[a], br[b], accr[a][b], 0, 0, 0);
+                    accr[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ain[a], bi[b], accr[a][b], 0, 0, 0);
+                    acci[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar[a], bi[b], acci[a][b], 0, 0, 0);
+                    acci[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a], br[b], acci[a][b], 0, 0, 0);
+                }
+        } else {
+#pragma unroll
+            for (int ks = 0; ks < 32; ks += 4) {
+                float ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    ar[a] = sAr[wm * 32 + a * 16 + ii][ks + kg];
+                    ai[a] = sAi[wm * 32 + a * 16 + ii][ks + kg];
+                }
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    br[b] = sBr[wn * 32 + b * 16 + ii][ks + kg];
+                    bi[b] = sBi[wn * 32 + b * 16 + ii][ks + kg];
+                }
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        accr[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[a], br[b], accr[a][b], 0, 0, 0);
+                        accr[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai[a], bi[b], accr[a][b], 0, 0, 0);
+                        acci[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[a], bi[b], acci[a][b], 0, 0, 0);
+                        acci[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[a], br[b], acci[a][b], 0, 0, 0);
+                    }
+            }
+        }
+        __syncthreads();
+    }
+    // epilogue; f32-accumulating 16x16 MFMA layout: D[i][j] in lane
+    // j + 16*(i/4), element i % 4
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = i0 + wm * 32 + a * 16 + 4 * (lane >> 4) + v;
+                const int j = j0 + wn * 32 + b * 16 + (lane & 15);
+                if (i < j) continue;  // the mirror of (j, i) covers it
+                float re = accr[a][b][v], im = acci[a][b][v];
+                if (epi == NS_EPI_T) { re = (i == j ? 3.0f : 0.0f) - re; im = -im; }
+                else { re *= 0.5f; im *= 0.5f; }
+                if (i == j) im = 0.0f;
+                if (epi != NS_EPI_F64) {
+                    const L lr = to_low<L>(re), li = to_low<L>(im), lni = to_low<L>(-im);
+                    const int64_t o = (int64_t)i + (int64_t)j * npad, om = (int64_t)j + (int64_t)i * npad;
+                    Cre[o] = lr; Cim[o] = li;
+                    Cre[om] = lr; Cim[om] = lni;
+                } else if (i < n && j < n) {
+                    C64[i + (int64_t)j * ld64] = cmk((double)re, (double)im);
+                    C64[j + (int64_t)i * ld64] = cmk((double)re, -(double)im);
+                }
+            }
+}
+
+// ||T - 2I||_F^2 (T = 3I - S^2, so T - 2I = I - S^2) and tr S: partials per
+// column block (one workgroup per 16 columns), then one workgroup writes the
+// info record.
+constexpr int RES_COLS = 16;
+__global__ void __launch_bounds__(256) ns_residual_part_kernel(const double2 *__restrict__ T,
+                                                               const double2 *__restrict__ S, int64_t lda, int n,
+                                                               double *red_out) {
+    __shared__ double red[8];
+    const int j0 = blockIdx.x * RES_COLS;
+    double r2 = 0.0, tr = 0.0;
+    for (int j = j0; j < min(n, j0 + RES_COLS); ++j)
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            double2 v = T[i + (int64_t)j * lda];
+            if (i == j) { v.x -= 2.0; tr += S[i + (int64_t)i * lda].x; }
+            r2 += cabs2(v);
+        }
+    r2 = block_sum(r2, red);
+    tr = block_sum(tr, red + 4);
+    if (threadIdx.x == 0) { red_out[2 * blockIdx.x] = r2; red_out[2 * blockIdx.x + 1] = tr; }
+}
+
+__global__ void __launch_bounds__(256) ns_residual_final_kernel(const double *__restrict__ red_in, int nb, int n,
+                                                                int iters, const double *alpha, const int *status,
+                                                                psd_dev_info *info) {
+    __shared__ double red[8];
+    double r2 = 0.0, tr = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) { r2 += red_in[2 * b]; tr += red_in[2 * b + 1]; }
+    r2 = block_sum(r2, red);
+    tr = block_sum(tr, red + 4);
+    if (threadIdx.x == 0 && info) {
+        const int npos = (int)llround(0.5 * (n + tr));
+        info->status = status[2];
+        info->n_pos = min(max(npos, 0), n);
+        info->n_neg = n - info->n_pos;
+        info->iters = iters;
+        info->fallback = 0;
+        info->reserved = 0;
+        info->est_rel_err = sqrt(r2 / n);
+        info->scale = *alpha;
+    }
+}
+
+template <typename L>
+hipError_t ns_run(const MixedWs &w, const double *x, double *y, psd_dev_info *info, int iters, int corr,
+                  hipStream_t st) {
+    const int n = w.n, npad = w.npad;
+    const int64_t plane = (int64_t)npad * npad;
+    L *X = reinterpret_cast<L *>(w.lo0), *T = reinterpret_cast<L *>(w.lo1), *X2 = reinterpret_cast<L *>(w.lo2);
+    dim3 sg((npad + 255) / 256, npad);
+    hipLaunchKernelGGL((ns_scale_kernel<L>), sg, dim3(256), 0, st, w.M, w.lda, n, npad, w.alpha, X, X + plane);
+    const int mt = npad / 64;
+    dim3 gg(mt * (mt + 1) / 2);
+    for (int k = 0; k < iters; ++k) {
+        hipLaunchKernelGGL((ns_gemm_kernel<L>), gg, dim3(256), 0, st, X, X + plane, X, X + plane, npad, (int)NS_EPI_T,
+                           T, T + plane, (double2 *)nullptr, (int64_t)0, n);
+        const bool last = k == iters - 1;
+        hipLaunchKernelGGL((ns_gemm_kernel<L>), gg, dim3(256), 0, st, X, X + plane, T, T + plane, npad,
+                           last ? (int)NS_EPI_F64 : (int)NS_EPI_HALF, X2, X2 + plane, w.S, w.lda, n);
+        std::swap(X, X2);
+    }
+    // FP64 corrections S <- S (3I - S^2) / 2
+    double2 *S = w.S, *S2 = w.S2;
+    for (int c = 0; c < corr; ++c) {
+        GemmDesc a{};
+        a.M = a.N = a.K = n;
+        a.A = GemmOperand{S, S, w.lda, w.lda, n, OP_N, nullptr};
+        a.B = GemmOperand{S, S, w.lda, w.lda, n, OP_N, nullptr};
+        a.C = w.T64; a.ldc = w.lda; a.alpha = -1.0; a.beta = 0.0; a.diag_add = 3.0;
+        hipError_t e = gemm_launch(a, true, EPI_STORE, st);
+        if (e != hipSuccess) return e;
+        GemmDesc b{};
+        b.M = b.N = b.K = n;
+        b.A = GemmOperand{S, S, w.lda, w.lda, n, OP_N, nullptr};
+        b.B = GemmOperand{w.T64, w.T64, w.lda, w.lda, n, OP_N, nullptr};
+        b.C = S2; b.ldc = w.lda; b.alpha = 0.5; b.beta = 0.0;
+        e = gemm_launch(b, true, EPI_STORE, st);
+        if (e != hipSuccess) return e;
+        std::swap(S, S2);
+    }
+    if (corr == 0) {
+        GemmDesc a{};
+        a.M = a.N = a.K = n;
+        a.A = GemmOperand{S, S, w.lda, w.lda, n, OP_N, nullptr};
+        a.B = GemmOperand{S, S, w.lda, w.lda, n, OP_N, nullptr};
+        a.C = w.T64; a.ldc = w.lda; a.alpha = -1.0; a.beta = 0.0; a.diag_add = 3.0;
+        hipError_t e = gemm_launch(a, true, EPI_STORE, st);
+        if (e != hipSuccess) return e;
+    }
+    const int nrb = (n + RES_COLS - 1) / RES_COLS;
+    hipLaunchKernelGGL(ns_residual_part_kernel, dim3(nrb), dim3(256), 0, st, w.T64, S, w.lda, n, w.red);
+    hipLaunchKernelGGL(ns_residual_final_kernel, dim3(1), dim3(256), 0, st, w.red, nrb, n, iters, w.alpha, w.status,
+                       info);
+    // Pi = X/2 + X S / 2, lower tiles, straight into the svec
+    GemmDesc f{};
+    f.M = f.N = f.K = n;
+    f.lower_only = 1;
+    f.A = GemmOperand{w.M, w.M, w.lda, w.lda, n, OP_N, nullptr};
+    f.B = GemmOperand{S, S, w.lda, w.lda, n, OP_N, nullptr};
+    f.y = y; f.xbase = x; f.svec_n = n; f.sign = 0.5; f.xscale = 0.5;
+    return gemm_launch(f, true, EPI_SVEC, st);
+}
+
+}  // namespace
+
+size_t mixed_layout(int n, int mode, void *base, MixedWs *w) {
+    size_t off = 0;
+    char *b = static_cast<char *>(base);
+    auto take = [&](size_t bytes) -> void * {
+        void *p = b ? b + off : nullptr;
+        off += (bytes + 255) / 256 * 256;
+        return p;
+    };
+    MixedWs W{};
+    W.n = n;
+    W.lda = (n + 63) / 64 * 64;
+    W.npad = W.lda;
+    const size_t lowsz = mode == 1 ? 2 : 4;
+    const size_t plane2 = 2 * (size_t)W.npad * W.npad * lowsz;
+    const size_t cmat = sizeof(double2) * (size_t)W.lda * n;
+    W.M = (double2 *)take(cmat);
+    W.S = (double2 *)take(cmat);
+    W.S2 = (double2 *)take(cmat);
+    W.T64 = (double2 *)take(cmat);
+    W.lo0 = take(plane2);
+    W.lo1 = take(plane2);
+    W.lo2 = take(plane2);
+    W.q = (double2 *)take(sizeof(double2) * (size_t)W.lda);
+    W.qprev = (double2 *)take(sizeof(double2) * (size_t)W.lda);
+    W.wv = (double2 *)take(sizeof(double2) * (size_t)W.lda);
+    W.P = (double2 *)take(sizeof(double2) * (size_t)LZ_SPLIT * n);
+    W.ab = (double *)take(sizeof(double) * (2 * LZ_STEPS + 8));
+    W.alpha = (double *)take(sizeof(double));
+    W.status = (int *)take(sizeof(int) * 4);
+    W.red = (double *)take(sizeof(double) * 2 * ((size_t)(n + 15) / 16 + 1));
+    if (w) *w = W;
+    return off;
+}
+
+hipError_t mixed_project(const MixedWs &w, int mode, const double *x, double *y, psd_dev_info *info, int iters,
+                         int corr, hipStream_t st) {
+    const int n = w.n;
+    if (iters < 1) iters = 1;
+    hipLaunchKernelGGL(mx_init_kernel, dim3(1), dim3(64), 0, st, w.status);
+    hipLaunchKernelGGL(mx_unpack_kernel, dim3((n + 255) / 256, n), dim3(256), 0, st, x, w.M, w.lda, n, w.status);
+    // spectral scale
+    hipLaunchKernelGGL(lz_init_kernel, dim3(1), dim3(1024), 0, st, n, w.q, w.qprev, w.ab);
+    const int steps = std::min(LZ_STEPS, n);
+    for (int s = 0; s < steps; ++s) {
+        hipLaunchKernelGGL(lz_gemv_kernel, dim3((n + 63) / 64, LZ_SPLIT), dim3(256), 0, st, w.M, w.lda, n, w.q, w.P);
+        hipLaunchKernelGGL(lz_step_kernel, dim3(1), dim3(1024), 0, st, n, s, w.P, w.q, w.qprev, w.wv, w.ab);
+    }
+    hipLaunchKernelGGL(lz_final_kernel, dim3(1), dim3(64), 0, st, w.ab, w.alpha);
+    if (mode == 1) return ns_run<__bf16>(w, x, y, info, iters, corr, st);
+    return ns_run<float>(w, x, y, info, iters, corr, st);
+}
+
+}  // namespace psd

@@ -194,7 +194,7 @@ small_project_kernel(const SmallJob *jobs, SmallJob single, const double *__rest
         }
         if (t == 0 && infos) {
             psd_dev_info &I = infos[job.info_index];
-            I.status = ST_ENONFINITE; I.n_pos = 0; I.n_neg = 0; I.iters = 0; I.fallback = 0; I.est_rel_err = 0.0;
+            I.status = ST_ENONFINITE; I.n_pos = 0; I.n_neg = 0; I.iters = 0; I.fallback = 0; I.est_rel_err = 0.0; I.scale = 0.0; I.scale = 0.0;
         }
         return;
     }
@@ -229,7 +229,7 @@ small_project_kernel(const SmallJob *jobs, SmallJob single, const double *__rest
         if (infos) {
             psd_dev_info &I = infos[job.info_index];
             I.status = S.status; I.n_pos = npos; I.n_neg = nneg;
-            I.iters = 0; I.fallback = 0; I.est_rel_err = 0.0;
+            I.iters = 0; I.fallback = 0; I.est_rel_err = 0.0; I.scale = 0.0;
         }
     }
     __syncthreads();
