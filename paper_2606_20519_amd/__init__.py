@@ -20,8 +20,8 @@ import torch
 from . import _lib
 from ._lib import MODES, PSD_FLAG_SAVE, PsdError, PsdInfo, check  # noqa: F401
 
-__all__ = ["project", "project_batched", "vjp", "PSDProject", "workspace", "set_ns_iterations", "PsdError",
-           "MODES"]
+__all__ = ["project", "project_batched", "vjp", "PSDProject", "Plan", "workspace", "set_ns_iterations",
+           "PsdError", "MODES"]
 
 _ws_cache: dict = {}
 INFO_WORDS = ctypes.sizeof(PsdInfo) // 4
@@ -162,3 +162,60 @@ class PSDProject(torch.autograd.Function):
         else:
             gx = vjp(gy.contiguous(), ctx.n, saved=t, mode=ctx.mode)
         return gx, None, None
+
+
+class Plan:
+    """All blocks of one cone projected by a single graph launch
+    (psd_plan_* in the C ABI).  Typical use: create once per cone layout,
+    then `execute(x, out=y)` every SCS iteration with the same buffers."""
+
+    def __init__(self, sizes, mode="fp64", concurrency: int = 0, device="cuda:0"):
+        self.sizes = [int(s) for s in sizes]
+        self.mode = _mode(mode)
+        self.device = torch.device(device)
+        h = ctypes.c_void_p(0)
+        check(_lib.lib().psd_plan_create(len(self.sizes), _lib.int_array(self.sizes), self.mode, concurrency,
+                                          ctypes.byref(h)), "psd_plan_create")
+        self._h = h
+        self.total = sum(s * s for s in self.sizes)
+        self._ws = None
+
+    @property
+    def concurrency(self) -> int:
+        return int(_lib.lib().psd_plan_concurrency(self._h))
+
+    def workspace(self, concurrency: int = 0) -> torch.Tensor:
+        nb = ctypes.c_size_t(0)
+        check(_lib.lib().psd_plan_workspace_size(self._h, concurrency, ctypes.byref(nb)), "psd_plan_workspace_size")
+        if self._ws is None or self._ws.numel() < nb.value:
+            self._ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def execute(self, x: torch.Tensor, out: torch.Tensor = None, infos: torch.Tensor = None) -> torch.Tensor:
+        _check_vec(x, self.total, "x")
+        y = torch.empty_like(x) if out is None else out
+        _check_vec(y, self.total, "out")
+        ws = self.workspace()
+        st = _lib.lib().psd_plan_execute(self._h, _ptr(x), _ptr(y), _ptr(ws), ws.numel(),
+                                         ctypes.c_void_p(_stream_ptr(x.device)), _ptr(infos))
+        check(st, "psd_plan_execute")
+        return y
+
+    def tune(self, x: torch.Tensor, out: torch.Tensor, reps: int = 3, max_concurrency: int = 32) -> int:
+        ws = self.workspace(max_concurrency)
+        best = ctypes.c_int32(0)
+        st = _lib.lib().psd_plan_tune(self._h, _ptr(x), _ptr(out), _ptr(ws), ws.numel(),
+                                      ctypes.c_void_p(_stream_ptr(x.device)), reps, ctypes.byref(best))
+        check(st, "psd_plan_tune")
+        return int(best.value)
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _lib.lib().psd_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -19,8 +19,9 @@ PSD_FLAG_SAVE = 1
 
 # Every symbol include/psdproj.h declares.
 EXPORTS = ("psd_workspace_size", "psd_saved_size", "psd_project", "psd_project_batched",
-           "psd_project_vjp", "psd_timing_start", "psd_timing_stop", "psd_set_ns_iterations",
-           "psd_status_string", "psd_version")
+           "psd_project_vjp", "psd_plan_create", "psd_plan_workspace_size", "psd_plan_concurrency",
+           "psd_plan_execute", "psd_plan_tune", "psd_plan_destroy", "psd_timing_start", "psd_timing_stop",
+           "psd_set_ns_iterations", "psd_status_string", "psd_version")
 KF_HEMV, KF_GEMM = 1, 2
 
 
@@ -62,6 +63,18 @@ def lib():
     L.psd_status_string.argtypes = [i32]
     L.psd_status_string.restype = ctypes.c_char_p
     L.psd_version.restype = ctypes.c_char_p
+    L.psd_plan_create.argtypes = [i32, ctypes.POINTER(i32), i32, i32, ctypes.POINTER(vp)]
+    L.psd_plan_create.restype = i32
+    L.psd_plan_workspace_size.argtypes = [vp, i32, ctypes.POINTER(sz)]
+    L.psd_plan_workspace_size.restype = i32
+    L.psd_plan_concurrency.argtypes = [vp]
+    L.psd_plan_concurrency.restype = i32
+    L.psd_plan_execute.argtypes = [vp, vp, vp, vp, sz, vp, vp]
+    L.psd_plan_execute.restype = i32
+    L.psd_plan_tune.argtypes = [vp, vp, vp, vp, sz, vp, i32, ctypes.POINTER(i32)]
+    L.psd_plan_tune.restype = i32
+    L.psd_plan_destroy.argtypes = [vp]
+    L.psd_plan_destroy.restype = i32
     L.psd_set_ns_iterations.argtypes = [i32, i32]
     L.psd_set_ns_iterations.restype = i32
     L.psd_timing_start.argtypes = [i32, i32]

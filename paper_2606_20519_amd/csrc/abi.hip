@@ -103,6 +103,23 @@ hipError_t project_block(int n, const double *x, double *y, psd_mode mode, void 
 
 }  // namespace
 
+namespace psd {
+
+hipError_t project_block_ext(int n, const double *x, double *y, psd_mode mode, void *ws, hipStream_t s,
+                             psd_dev_info *info) {
+    return project_block(n, x, y, mode, ws, s, info, nullptr);
+}
+
+size_t block_ws_bytes(int n, psd_mode mode) { return large_ws_bytes(n, mode, 0); }
+
+hipError_t prepare_kernel_attributes() {
+    hipError_t e = small_prepare();
+    if (e != hipSuccess) return e;
+    return dc_prepare();
+}
+
+}  // namespace psd
+
 extern "C" {
 
 const char *psd_version(void) { return "psdproj 0.1 (gfx950)"; }

@@ -442,13 +442,21 @@ int dc_num_leaves(int n) {
 
 }  // namespace
 
-hipError_t large_dc(LargeWs &w, hipStream_t st) {
+hipError_t dc_prepare() {
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute((const void *)dc_prep_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            PREP_LDS_MAX * 20);
         if (e != hipSuccess) return e;
         attr = true;
+    }
+    return hipSuccess;
+}
+
+hipError_t large_dc(LargeWs &w, hipStream_t st) {
+    {
+        hipError_t e = dc_prepare();
+        if (e != hipSuccess) return e;
     }
     const int n = w.n;
     const int nl = dc_num_leaves(n);

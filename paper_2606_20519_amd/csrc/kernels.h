@@ -23,6 +23,9 @@ struct SmallJob {
 };
 
 size_t small_lds_bytes();
+// One-time kernel attribute setup (dynamic LDS limits); call outside graph capture.
+hipError_t small_prepare();
+hipError_t dc_prepare();
 hipError_t launch_small(const SmallJob *jobs, int njobs, const double *x, double *y,
                         psd_dev_info *infos, double *saved, hipStream_t st);
 hipError_t launch_small_one(const SmallJob &job, const double *x, double *y, psd_dev_info *info,

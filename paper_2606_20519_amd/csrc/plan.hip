@@ -1,0 +1,263 @@
+// Plans: the blocks of one SCS cone (App. D.1: the cone is a product of PSD
+// blocks; for the see-saw's process step, the d^4 x d^4 W blocks, and for the
+// batched workload also the d^2 x d^2 instrument Choi blocks) projected by a
+// single hipGraph launch.
+//
+// The graph is captured on a stream the plan owns: a fork event, the
+// whole-block LDS kernel for every block of order <= 64 (one workgroup per
+// block), the large blocks spread round-robin over K side streams (each with
+// its own workspace slot, so K large blocks are in flight at once), and a
+// join.  Executing a plan whose buffers were already captured is one
+// hipGraphLaunch on the caller's stream.  K is chosen by psd_plan_tune: it
+// replays the graph for each candidate, keeps the fastest and records it in a
+// small JSON-lines cache (PSD_TUNE_CACHE, default ./psdproj_tune.jsonl) keyed
+// by the device architecture, the mode and the block sizes; psd_plan_create
+// reads that cache.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/psdproj.h"
+#include "kernels.h"
+#include "large.h"
+#include "mixed.h"
+
+namespace psd {
+// defined in abi.hip
+hipError_t project_block_ext(int n, const double *x, double *y, psd_mode mode, void *ws, hipStream_t s,
+                             psd_dev_info *info);
+size_t block_ws_bytes(int n, psd_mode mode);
+hipError_t prepare_kernel_attributes();
+}  // namespace psd
+
+using namespace psd;
+
+namespace {
+
+constexpr int kMaxConcurrency = 32;
+
+struct GraphEntry {
+    const double *x;
+    double *y;
+    void *ws;
+    psd_info *infos;
+    int K;
+    hipGraphExec_t exec;
+};
+
+std::string tune_key(const std::vector<int> &n, int mode) {
+    std::string k = "gfx950:mode" + std::to_string(mode) + ":";
+    for (size_t i = 0; i < n.size(); ++i) k += (i ? "," : "") + std::to_string(n[i]);
+    return k;
+}
+
+const char *tune_path() {
+    const char *p = std::getenv("PSD_TUNE_CACHE");
+    return (p && *p) ? p : "psdproj_tune.jsonl";
+}
+
+// Last recorded concurrency for `key`, or 0.
+int tune_lookup(const std::string &key) {
+    FILE *f = std::fopen(tune_path(), "r");
+    if (!f) return 0;
+    char line[1 << 14];
+    int best = 0;
+    const std::string pat = "\"key\": \"" + key + "\"";
+    while (std::fgets(line, sizeof line, f)) {
+        if (!std::strstr(line, pat.c_str())) continue;
+        const char *c = std::strstr(line, "\"concurrency\": ");
+        if (c) best = std::atoi(c + 15);
+    }
+    std::fclose(f);
+    return best;
+}
+
+void tune_record(const std::string &key, int K, double ms) {
+    FILE *f = std::fopen(tune_path(), "a");
+    if (!f) return;
+    std::fprintf(f, "{\"key\": \"%s\", \"concurrency\": %d, \"ms\": %.6f}\n", key.c_str(), K, ms);
+    std::fclose(f);
+}
+
+}  // namespace
+
+struct psd_plan_s {
+    std::vector<int> n;
+    std::vector<int64_t> off;
+    psd_mode mode;
+    int K = 1;
+    int nlarge = 0;
+    size_t slot_bytes = 0;
+    std::vector<SmallJob> small;
+    SmallJob *dsmall = nullptr;
+    hipStream_t cap = nullptr;
+    hipStream_t side[kMaxConcurrency] = {};
+    hipEvent_t fork = nullptr, join[kMaxConcurrency] = {};
+    std::vector<GraphEntry> graphs;
+};
+
+namespace {
+
+hipError_t capture(psd_plan_s *p, const double *x, double *y, void *ws, psd_info *infos, int K,
+                   hipGraphExec_t *out) {
+    hipError_t e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t err = hipSuccess;
+    auto chk = [&](hipError_t r) { if (err == hipSuccess && r != hipSuccess) err = r; };
+    chk(hipEventRecord(p->fork, p->cap));
+    for (int i = 0; i < K; ++i) chk(hipStreamWaitEvent(p->side[i], p->fork, 0));
+    psd_dev_info *di = reinterpret_cast<psd_dev_info *>(infos);
+    if (!p->small.empty()) chk(launch_small(p->dsmall, (int)p->small.size(), x, y, di, nullptr, p->cap));
+    int li = 0;
+    for (size_t b = 0; b < p->n.size(); ++b) {
+        if (p->n[b] <= 64) continue;
+        const int slot = li % K;
+        char *wsl = static_cast<char *>(ws) + (size_t)slot * p->slot_bytes;
+        chk(project_block_ext(p->n[b], x + p->off[b], y + p->off[b], p->mode, wsl, p->side[slot],
+                              di ? di + b : nullptr));
+        ++li;
+    }
+    for (int i = 0; i < K; ++i) {
+        chk(hipEventRecord(p->join[i], p->side[i]));
+        chk(hipStreamWaitEvent(p->cap, p->join[i], 0));
+    }
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(p->cap, &g);
+    if (err == hipSuccess) err = e;
+    if (err == hipSuccess) err = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    return err;
+}
+
+hipGraphExec_t find_graph(psd_plan_s *p, const double *x, double *y, void *ws, psd_info *infos, int K) {
+    for (auto &g : p->graphs)
+        if (g.x == x && g.y == y && g.ws == ws && g.infos == infos && g.K == K) return g.exec;
+    return nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+psd_status psd_plan_create(int32_t nblocks, const int32_t *n, psd_mode mode, int32_t concurrency,
+                           psd_plan *plan) {
+    if (nblocks < 1 || !n || !plan || concurrency < 0 || concurrency > kMaxConcurrency) return PSD_EINVAL;
+    if (mode != PSD_FP64_EIG && mode != PSD_MIXED_BF16 && mode != PSD_MIXED_FP32) return PSD_EINVAL;
+    psd_plan_s *p = new (std::nothrow) psd_plan_s();
+    if (!p) return PSD_ENOMEM;
+    p->mode = mode;
+    int64_t off = 0;
+    for (int b = 0; b < nblocks; ++b) {
+        if (n[b] < 1) { delete p; return PSD_EINVAL; }
+        p->n.push_back(n[b]);
+        p->off.push_back(off);
+        if (n[b] <= 64) p->small.push_back(SmallJob{off, 0, n[b], b});
+        else {
+            ++p->nlarge;
+            p->slot_bytes = std::max(p->slot_bytes, block_ws_bytes(n[b], mode));
+        }
+        off += (int64_t)n[b] * n[b];
+    }
+    p->slot_bytes = (p->slot_bytes + 255) / 256 * 256;
+    int K = concurrency;
+    if (K == 0) K = tune_lookup(tune_key(p->n, mode));
+    if (K == 0) K = 4;
+    p->K = std::max(1, std::min(K, std::max(1, p->nlarge)));
+    bool ok = prepare_kernel_attributes() == hipSuccess &&
+              hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; ok && i < kMaxConcurrency; ++i)
+        ok = hipStreamCreateWithFlags(&p->side[i], hipStreamNonBlocking) == hipSuccess &&
+             hipEventCreateWithFlags(&p->join[i], hipEventDisableTiming) == hipSuccess;
+    if (ok && !p->small.empty()) {
+        ok = hipMalloc(&p->dsmall, p->small.size() * sizeof(SmallJob)) == hipSuccess &&
+             hipMemcpy(p->dsmall, p->small.data(), p->small.size() * sizeof(SmallJob), hipMemcpyHostToDevice) ==
+                 hipSuccess;
+    }
+    if (!ok) {
+        psd_plan_destroy(p);
+        return PSD_EDEVICE;
+    }
+    *plan = p;
+    return PSD_OK;
+}
+
+psd_status psd_plan_workspace_size(psd_plan p, int32_t concurrency, size_t *bytes) {
+    if (!p || !bytes || concurrency < 0 || concurrency > kMaxConcurrency) return PSD_EINVAL;
+    const int K = concurrency ? concurrency : p->K;
+    *bytes = (size_t)K * p->slot_bytes + 256;
+    return PSD_OK;
+}
+
+int32_t psd_plan_concurrency(psd_plan p) { return p ? p->K : 0; }
+
+psd_status psd_plan_execute(psd_plan p, const double *x, double *y, void *ws, size_t ws_bytes, void *stream,
+                            psd_info *infos) {
+    if (!p || !x || !y) return PSD_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) & 7u) return PSD_EINVAL;
+    const size_t need = (size_t)p->K * p->slot_bytes;
+    if (p->nlarge && (!ws || ws_bytes < need)) return PSD_EWORKSPACE;
+    if (ws && (reinterpret_cast<uintptr_t>(ws) % 256)) return PSD_EINVAL;
+    hipGraphExec_t ex = find_graph(p, x, y, ws, infos, p->K);
+    if (!ex) {
+        if (capture(p, x, y, ws, infos, p->K, &ex) != hipSuccess) return PSD_EDEVICE;
+        p->graphs.push_back(GraphEntry{x, y, ws, infos, p->K, ex});
+    }
+    return hipGraphLaunch(ex, static_cast<hipStream_t>(stream)) == hipSuccess ? PSD_OK : PSD_EDEVICE;
+}
+
+psd_status psd_plan_tune(psd_plan p, const double *x, double *y, void *ws, size_t ws_bytes, void *stream,
+                         int32_t reps, int32_t *best_out) {
+    if (!p || !x || !y || reps < 1) return PSD_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t t0, t1;
+    if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) return PSD_EDEVICE;
+    int best = p->K;
+    double best_ms = 1e300;
+    const int maxK = std::max(1, std::min(p->nlarge, kMaxConcurrency));
+    std::vector<int> cand;
+    for (int K = 1; K < maxK; K *= 2) cand.push_back(K);
+    cand.push_back(maxK);
+    for (int K : cand) {
+        if ((size_t)K * p->slot_bytes > ws_bytes) break;
+        const int saved = p->K;
+        p->K = K;
+        psd_status st = psd_plan_execute(p, x, y, ws, ws_bytes, stream, nullptr);  // capture + warm up
+        if (st != PSD_OK) { p->K = saved; continue; }
+        (void)hipEventRecord(t0, s);
+        for (int r = 0; r < reps && st == PSD_OK; ++r) st = psd_plan_execute(p, x, y, ws, ws_bytes, stream, nullptr);
+        (void)hipEventRecord(t1, s);
+        (void)hipEventSynchronize(t1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, t0, t1);
+        p->K = saved;
+        if (st == PSD_OK && ms / reps < best_ms) { best_ms = ms / reps; best = K; }
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    p->K = best;
+    tune_record(tune_key(p->n, p->mode), best, best_ms);
+    if (best_out) *best_out = best;
+    return PSD_OK;
+}
+
+psd_status psd_plan_destroy(psd_plan p) {
+    if (!p) return PSD_EINVAL;
+    for (auto &g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+    if (p->dsmall) (void)hipFree(p->dsmall);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    if (p->fork) (void)hipEventDestroy(p->fork);
+    for (int i = 0; i < kMaxConcurrency; ++i) {
+        if (p->side[i]) (void)hipStreamDestroy(p->side[i]);
+        if (p->join[i]) (void)hipEventDestroy(p->join[i]);
+    }
+    delete p;
+    return PSD_OK;
+}
+
+}  // extern "C"

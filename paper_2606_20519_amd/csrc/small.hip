@@ -291,6 +291,8 @@ static hipError_t small_attr() {
     return e;
 }
 
+hipError_t small_prepare() { return small_attr(); }
+
 hipError_t launch_small(const SmallJob *jobs, int njobs, const double *x, double *y,
                         psd_dev_info *infos, double *saved, hipStream_t st) {
     hipError_t e = small_attr();

@@ -22,6 +22,8 @@ TimingState g_timing;
 int timing_begin(int family, hipStream_t st) {
     TimingState &T = g_timing;
     if (T.family != family || T.used >= T.max) return -1;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return -1;
     const int slot = T.used++;
     if (hipEventRecord(T.ev[2 * slot], st) != hipSuccess) return -1;
     return slot;

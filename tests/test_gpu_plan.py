@@ -1,0 +1,124 @@
+"""GPU checks of plans: the blocks of a cone (per instance one W block of
+order d^4 and eight Choi blocks of order d^2) projected by one graph launch.
+
+Every replay is compared with the eager result (bitwise: same kernels, same
+order per block) and with the oracle; eager work and synchronisations run
+between replays."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_20519_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2606_20519_amd as P
+    P.set_ns_iterations(40, 2)
+    return P
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def blocks(x, sizes):
+    off = 0
+    for m in sizes:
+        yield off, m, x[off:off + m * m]
+        off += m * m
+
+
+@pytest.mark.parametrize("concurrency", [1, 2, 3])
+def test_plan_replays_match_eager_and_oracle(P, concurrency):
+    import torch
+    d, inst = 3, 3
+    x_np, sizes = W.cone(d, inst)
+    x = dev(x_np)
+    eager = P.project_batched(x, sizes).cpu().numpy()
+    plan = P.Plan(sizes, "fp64", concurrency=concurrency)
+    assert plan.concurrency == min(concurrency, inst)
+    y = torch.empty_like(x)
+    for rep in range(3):
+        y.fill_(float("nan"))
+        plan.execute(x, out=y)
+        torch.cuda.synchronize()
+        got = y.cpu().numpy()
+        assert np.array_equal(got, eager), f"replay {rep}"
+        # eager work between replays
+        z = P.project(dev(W.gue(20, rep)), 20)
+        torch.cuda.synchronize()
+        del z
+    for off, m, s in blocks(x_np, sizes):
+        assert rel(eager[off:off + m * m], oracle.project(s, m)) <= 1e-10
+    plan.close()
+
+
+def test_plan_d5_cone_oracle_sample(P):
+    import torch
+    d, inst = 5, 4
+    x_np, sizes = W.cone(d, inst)
+    x = dev(x_np)
+    plan = P.Plan(sizes, "fp64", concurrency=4)
+    infos = torch.zeros(len(sizes) * P.INFO_WORDS, dtype=torch.int32, device="cuda:0")
+    y = plan.execute(x, infos=infos)
+    torch.cuda.synchronize()
+    y = y.cpu().numpy()
+    # oracle on instance 0 (W and its 8 Choi blocks) and the Choi blocks of all instances
+    for b, (off, m, s) in enumerate(blocks(x_np, sizes)):
+        if b < 9 or m <= 64:
+            assert rel(y[off:off + m * m], oracle.project(s, m)) <= 1e-10, (b, m)
+    st = infos.cpu().numpy().view(np.int32).reshape(len(sizes), -1)[:, 0]
+    assert (st == 0).all()
+    plan.close()
+
+
+def test_plan_tune_and_cache(P, tmp_path):
+    import torch
+    os.environ["PSD_TUNE_CACHE"] = str(tmp_path / "tune.jsonl")
+    try:
+        x_np, sizes = W.cone(4, 4)
+        x = dev(x_np)
+        y = torch.empty_like(x)
+        plan = P.Plan(sizes, "fp64")
+        best = plan.tune(x, y, reps=2, max_concurrency=4)
+        assert 1 <= best <= 4 and plan.concurrency == best
+        text = open(tmp_path / "tune.jsonl").read()
+        assert '"concurrency": %d' % best in text
+        plan.close()
+        # a new plan for the same layout picks the recorded value
+        plan2 = P.Plan(sizes, "fp64")
+        assert plan2.concurrency == best
+        ref = P.project_batched(x, sizes).cpu().numpy()
+        assert np.array_equal(plan2.execute(x).cpu().numpy(), ref)
+        plan2.close()
+    finally:
+        del os.environ["PSD_TUNE_CACHE"]
+
+
+def test_plan_mixed_matches_eager(P):
+    import torch
+    x_np, sizes = W.cone(3, 2)
+    x = dev(x_np)
+    eager = P.project_batched(x, sizes, mode="mixed_fp32").cpu().numpy()
+    plan = P.Plan(sizes, "mixed_fp32", concurrency=2)
+    for _ in range(2):
+        y = plan.execute(x)
+        torch.cuda.synchronize()
+        assert np.array_equal(y.cpu().numpy(), eager)
+    for off, m, s in blocks(x_np, sizes):
+        tol = 1e-10 if m <= 64 else 3e-6
+        assert rel(eager[off:off + m * m], oracle.project(s, m)) <= tol
+    plan.close()
