@@ -1,19 +1,27 @@
 #!/usr/bin/env python3
 """Throughput of the PSD-cone projection on one MI355X.
 
-Default workload: the n = 625 (d = 5) warm-start sequence -- 50 SCS-like
+Default workload (c2): the n = 625 (d = 5) warm-start sequence -- 50 SCS-like
 iterates X_{k+1} = X_k + 1e-3 (H_k + H_k^H)/2 of a Hermitian (G + G^H)/2 --
 each projected by the FP64 eigen path (unpack, blocked Householder
 tridiagonalisation, divide and conquer, back-transform, fused clamp +
 reconstruction + svec pack).  One step = the 50 projections.  Inputs are
 resident in HBM before the timed region.
 
-Prints one JSON line: projections/s, algorithmic TFLOP/s, the roofline of the
-dominant kernel (per-column HEMV of the tridiagonalisation, timed live with
-HIP events on its launch stream) and the CPU oracle timed on a bounded
-sample of the same workload.
+Other workloads (one JSON line each, selected with --workload):
+  c1  50 blocks of order 16 (d = 2), one batched launch per step
+  c3  orders 1296 and 2401 (d = 6, 7), spectra in [-1,-1e-6] u [1e-6,1],
+      --mode mixed_bf16 | mixed_fp32 | fp64 (--n picks the order)
+  c4  one cone of 32 instances x [W (d^4) + 8 Choi (d^2)] by one graph
+      launch per step (--d picks d, --mode the precision)
+  c5  order 4096 (d = 8): forward projection, and the derivative (VJP) timed
+      after it (--mode fp64 | mixed_*)
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c2|c1|c5]
+The JSON line carries the roofline of the dominant kernel, timed live with
+HIP events recorded by the library on the kernel's own launch stream, and the
+CPU oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c2]
 """
 import argparse
 import json
@@ -24,15 +32,10 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
-PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (vector = MFMA)
-
-WORKLOADS = {
-    # name: (n, iterates, seed, description)
-    "c2": (625, 50, 1002, "d=5 warm-start sequence: 50 iterates of a 625x625 Hermitian block, FP64 eig path"),
-    "c1": (16, 50, 1001, "d=2 process matrix 16x16, 50 seeded blocks, FP64 eig path"),
-    "c5": (4096, 2, 1005, "d=8 process matrix 4096x4096, FP64 eig path"),
-}
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
+PEAK_FP64_TFLOPS = 78.6        # MI355X dense FP64 (vector = MFMA)
+PEAK_FP32_TFLOPS = 157.3       # MI355X dense FP32 MFMA
+PEAK_BF16_TFLOPS = 2500.0      # MI355X dense BF16 MFMA
 
 
 def flops_eig(n: int, k: int) -> float:
@@ -42,19 +45,29 @@ def flops_eig(n: int, k: int) -> float:
     return 16.0 / 3.0 * n ** 3 + 8.0 * n * n * k + 4.0 * n * n * k
 
 
+def flops_ns(n: int, iters: int, corr: int) -> float:
+    """Algorithmic real flops of one mixed projection: per iteration two
+    Hermitian products (lower half: 4 n^3 each), per FP64 correction two full
+    complex products (8 n^3 each), and the final product (lower half)."""
+    return iters * 2 * 4.0 * n ** 3 + corr * 2 * 8.0 * n ** 3 + 4.0 * n ** 3
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--mode", default=None, help="fp64 | mixed_bf16 | mixed_fp32")
+    ap.add_argument("--n", type=int, default=1296, help="order for c3")
+    ap.add_argument("--d", type=int, default=5, help="local dimension for c4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=2, help="iterates projected by the CPU oracle")
+    ap.add_argument("--cpu-sample", type=int, default=2, help="blocks projected by the CPU oracle")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1 "
-                                   "(the projection of one block does not shard across GPUs here)"}))
+                                   "(each cone block is projected on one GPU here)"}))
         sys.exit(2)
 
     import numpy as np
@@ -64,37 +77,96 @@ def main():
     from paper_2606_20519_amd import _lib
     from paper_2606_20519_amd import workloads as W
 
-    n, count, seed, desc = WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
-    if args.workload == "c2":
-        xs_np = W.warm_sequence(n, seed, count)
-    else:
-        xs_np = [W.gue(n, seed + i) for i in range(count)]
-    X = torch.from_numpy(np.stack(xs_np)).to(dev)          # resident in HBM
-    Y = torch.empty_like(X)
     stream = torch.cuda.current_stream(dev)
+    wl = args.workload
+    mode = args.mode or ("mixed_bf16" if wl == "c3" else "fp64")
+    iters, corr = 40, 2
+    P.set_ns_iterations(iters, corr)
 
-    def step():
-        for i in range(count):
-            P.project(X[i], n, out=Y[i])
+    # ---- inputs (host, seeded) -> HBM
+    plan = None
+    extra = {}
+    if wl == "c2":
+        n, count = 625, 50
+        xs_np = W.warm_sequence(n, 1002, count)
+        desc = "d=5 warm-start sequence: 50 iterates of a 625x625 Hermitian block"
+        sizes = [n] * count
+    elif wl == "c1":
+        n, count = 16, 50
+        xs_np = [W.gue(n, 1001 + i) for i in range(count)]
+        desc = "d=2 process matrices: 50 blocks of order 16, one batched launch"
+        sizes = [n] * count
+    elif wl == "c3":
+        n, count = args.n, 2
+        cons = [W.constructed(n, 1003 + i, gap=1e-6) for i in range(count)]
+        xs_np = [c[0] for c in cons]
+        desc = f"order {n}, spectra in [-1,-1e-6] u [1e-6,1] (constructed, Haar U)"
+        sizes = [n] * count
+    elif wl == "c4":
+        d = args.d
+        x_cone, sizes = W.cone(d, 32)
+        n, count = d ** 4, 1
+        xs_np = [x_cone]
+        desc = f"one cone, d={d}: 32 instances x [W {d**4}x{d**4} + 8 Choi {d*d}x{d*d}], one graph launch"
+    else:  # c5
+        n, count = 4096, 1
+        xs_np = [W.gue(n, 1005)]
+        g_np = W.gue(n, 1006)
+        desc = "d=8 process matrix 4096x4096: forward projection and DK derivative"
+        sizes = [n]
+    if wl in ("c2", "c3", "c5"):
+        X = torch.from_numpy(np.stack(xs_np)).to(dev)
+        Y = torch.empty_like(X)
+    else:
+        X = torch.from_numpy(np.concatenate(xs_np)).to(dev)
+        Y = torch.empty_like(X)
 
-    # side counts (k = min(k+, k-)) for the algorithmic flops, outside timing
+    if wl == "c4":
+        plan = P.Plan(sizes, mode)
+
+        def step():
+            plan.execute(X, out=Y)
+    elif wl == "c1":
+        def step():
+            P.project_batched(X, sizes, mode, out=Y)
+    else:
+        def step():
+            for i in range(count):
+                P.project(X[i], n, mode, out=Y[i])
+
+    # side counts for the algorithmic flops (outside timing)
     ks = []
-    for i in range(count):
-        _, inf = P.project(X[i], n, out=Y[i], info=True)
-        ks.append(min(inf["n_pos"], inf["n_neg"]))
-    flops_step = sum(flops_eig(n, k) for k in ks)
+    if wl in ("c2", "c5") or (wl == "c3" and mode == "fp64"):
+        for i in range(count):
+            _, inf = P.project(X[i], n, "fp64", out=Y[i], info=True)
+            ks.append(min(inf["n_pos"], inf["n_neg"]))
+    if mode == "fp64":
+        if wl == "c4":
+            flops_step = sum(flops_eig(m, m // 2) for m in sizes if m > 64)
+        elif wl == "c1":
+            flops_step = 0.0
+        else:
+            flops_step = sum(flops_eig(n, k) for k in ks)
+    else:
+        flops_step = sum(flops_ns(m, iters, corr) for m in sizes if m > 64)
 
+    if wl == "c4":
+        plan.execute(X, out=Y)   # capture outside timing
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
 
-    # timed region; the dominant kernel is timed with HIP events on its own
-    # launch stream: the library brackets the HEMV launches of the first
-    # projection of the timed region (n-1 launches, one per column)
-    hemv_sample = max(1, n - 1) if n > 64 else 0
-    if hemv_sample:
-        _lib.timing_start(_lib.KF_HEMV, hemv_sample)
+    # dominant kernel: HEMV of the tridiagonalisation (FP64) or the
+    # Newton-Schulz GEMMs (mixed); the library brackets its launches with HIP
+    # events on their launch stream -- the first projection's launches
+    fam = None
+    if mode == "fp64" and n > 64 and wl != "c4":
+        fam, sample = _lib.KF_HEMV, n - 1
+    elif mode != "fp64" and wl != "c4":
+        fam, sample = _lib.KF_NS, 2 * iters
+    if fam:
+        _lib.timing_start(fam, sample)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -104,48 +176,95 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    hemv = _lib.timing_stop() if hemv_sample else (0.0, 0, 0.0)
+    timed = _lib.timing_stop() if fam else (0.0, 0, 0.0)
 
     wall = t1 - t0
     ms_per_step = 1e3 * wall / args.steps
-    proj_s = count * args.steps / wall
+    blocks_per_step = len(sizes) if wl in ("c1", "c4") else count
+    value = (1 if wl == "c4" else blocks_per_step) * args.steps / wall
     tflops = flops_step * args.steps / wall / 1e12
 
     roofline = None
-    if hemv[1] > 0:
-        avg_ms = hemv[0] / hemv[1]
-        bytes_per_launch = hemv[2] / hemv[1]
-        achieved = hemv[2] / (hemv[0] * 1e-3) / 1e9
-        roofline = {
-            "kernel": "hemv_kernel (per-column Hermitian matrix-vector tiles, tridiagonalisation)",
-            "bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
-            "launches_timed": hemv[1], "avg_launch_us": round(1e3 * avg_ms, 3),
-            "algorithmic_bytes_per_launch": round(bytes_per_launch, 1),
-            "sample": "all HEMV launches of the first projection in the timed region",
-            "share_of_projection": round(hemv[0] / (ms_per_step / count), 4),
-        }
+    if timed[1] > 0:
+        avg_ms = timed[0] / timed[1]
+        if fam == _lib.KF_HEMV:
+            achieved = timed[2] / (timed[0] * 1e-3) / 1e9
+            roofline = {"kernel": "hemv_kernel (per-column Hermitian matrix-vector tiles, tridiagonalisation)",
+                        "bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                        "algorithmic_bytes_per_launch": round(timed[2] / timed[1], 1)}
+        else:
+            peak = PEAK_BF16_TFLOPS if mode == "mixed_bf16" else PEAK_FP32_TFLOPS
+            achieved = timed[2] / (timed[0] * 1e-3) / 1e12
+            roofline = {"kernel": f"ns_gemm_kernel<{'bf16' if mode == 'mixed_bf16' else 'f32'}> "
+                                  "(Hermitian-half complex GEMM, Newton-Schulz)",
+                        "bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                        "frac": round(achieved / peak, 4), "traffic": None,
+                        "algorithmic_flops_per_launch": round(timed[2] / timed[1], 1)}
+        roofline.update({"launches_timed": timed[1], "avg_launch_us": round(1e3 * avg_ms, 3),
+                         "sample": "launches of the first projection in the timed region",
+                         "share_of_step": round(timed[0] / ms_per_step, 4)})
 
-    # parity of the timed output on a sample, and the CPU oracle baseline
-    cpu = None
-    err = None
+    if wl == "c5":
+        # derivative after the forward (eigen-pair saved by the forward)
+        sv = torch.empty(P.saved_numel(n), dtype=torch.float64, device=dev)
+        G = torch.from_numpy(g_np).to(dev)
+        P.project(X[0], n, "fp64", out=Y[0], saved=sv)
+        gx = P.vjp(G, n, saved=sv)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            P.vjp(G, n, saved=sv, out=gx)
+        torch.cuda.synchronize()
+        extra["vjp_per_s"] = round(args.steps / (time.perf_counter() - t), 4)
+        extra["vjp_algorithmic_tflops"] = round(32.0 * n ** 3 * extra["vjp_per_s"] / 1e12, 3)
+
+    # parity on a sample of the timed outputs; CPU oracle baseline
+    cpu, err = None, None
     if not args.no_cpu_baseline:
         import oracle
-        m = max(1, min(args.cpu_sample, count))
-        t = time.perf_counter()
-        refs = [oracle.project(xs_np[i], n) for i in range(m)]
-        dt = time.perf_counter() - t
-        ycpu = Y[:m].cpu().numpy()
-        err = max(float(np.linalg.norm(ycpu[i] - refs[i]) / np.linalg.norm(refs[i])) for i in range(m))
-        cpu = {"value": round(m / dt, 5), "unit": "projections/s", "cores": oracle.num_threads(),
-               "kind": "oracle",
-               "sample": f"first {m} of the {count} iterates (n={n}), cyclic Jacobi round-robin FP64, "
-                         f"{dt:.1f} s"}
+        y_np = Y.cpu().numpy()
+        if wl in ("c1", "c4"):
+            flat_x, flat_y = xs_np[0] if wl == "c4" else np.concatenate(xs_np), y_np.reshape(-1)
+            offs, o = [], 0
+            for m in sizes:
+                offs.append(o)
+                o += m * m
+            pick = [0] + [i for i, m in enumerate(sizes) if m <= 64][:max(0, args.cpu_sample - 1)]
+            pick = pick[:max(1, args.cpu_sample)]
+            t = time.perf_counter()
+            refs = [oracle.project(flat_x[offs[i]:offs[i] + sizes[i] ** 2], sizes[i]) for i in pick]
+            dt = time.perf_counter() - t
+            err = max(float(np.linalg.norm(flat_y[offs[i]:offs[i] + sizes[i] ** 2] - r) / np.linalg.norm(r))
+                      for i, r in zip(pick, refs))
+            sample = f"blocks {pick} of the cone (orders {[sizes[i] for i in pick]})"
+            value_cpu = len(pick) / dt
+            unit = "block projections/s"
+        else:
+            m = max(1, min(args.cpu_sample, count))
+            if n > 1300:
+                # bounded sample: the oracle's Jacobi at this order takes minutes
+                sample = f"skipped at n={n} (oracle Jacobi at this order exceeds the time bound)"
+                value_cpu, dt, unit = None, 0.0, "projections/s"
+                if wl == "c3":
+                    exact = oracle.constructed_projection(cons[0][1], cons[0][2])
+                    err = float(np.linalg.norm(y_np[0] - exact) / np.linalg.norm(exact))
+            else:
+                t = time.perf_counter()
+                refs = [oracle.project(xs_np[i], n) for i in range(m)]
+                dt = time.perf_counter() - t
+                err = max(float(np.linalg.norm(y_np[i] - refs[i]) / np.linalg.norm(refs[i])) for i in range(m))
+                sample = f"first {m} of the {count} blocks (n={n}), cyclic Jacobi round-robin FP64, {dt:.1f} s"
+                value_cpu = m / dt
+                unit = "projections/s"
+        cpu = {"value": round(value_cpu, 5) if value_cpu else None, "unit": unit, "cores": oracle.num_threads(),
+               "kind": "oracle", "sample": sample}
 
+    metric = {"c4": "PSD cone projections/sec (one graph launch per cone)"}.get(wl, "PSD projections/sec")
     out = {
-        "metric": "PSD projections/sec (FP64 eig path)",
-        "value": round(proj_s, 3),
-        "unit": "projections/s",
+        "metric": metric + f" ({mode})",
+        "value": round(value, 4),
+        "unit": "cones/s" if wl == "c4" else "projections/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
@@ -153,16 +272,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {"fp64": "f64", "mixed_bf16": "bf16+f64", "mixed_fp32": "f32+f64"}[mode],
         "data": "synthetic",
-        "config": {"workload": desc, "n": n, "blocks_per_step": count, "mode": "fp64",
+        "config": {"workload": desc, "n": n, "blocks_per_step": blocks_per_step, "mode": mode,
                    "algorithmic_tflops": round(tflops, 3),
-                   "fp64_peak_frac": round(tflops / PEAK_FP64_TFLOPS, 4),
+                   "peak_frac": round(tflops / (PEAK_FP64_TFLOPS if mode == "fp64" else
+                                                (PEAK_BF16_TFLOPS if mode == "mixed_bf16" else PEAK_FP32_TFLOPS)), 5),
                    "gpu_ms_per_step": round(ev0.elapsed_time(ev1) / args.steps, 3),
-                   "rel_err_vs_oracle": err},
+                   "rel_err_vs_oracle": err, **extra},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if plan is not None:
+        out["config"]["concurrency"] = plan.concurrency
+        plan.close()
     print(json.dumps(out), flush=True)
 
 
