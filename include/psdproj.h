@@ -163,7 +163,8 @@ psd_status psd_plan_destroy(psd_plan plan);
  * events are created by psd_timing_start and destroyed by psd_timing_stop. */
 typedef enum {
     PSD_KF_HEMV = 1,   /* per-column Hermitian matrix-vector tiles of the tridiagonalisation */
-    PSD_KF_GEMM = 2    /* FP64 MFMA GEMMs */
+    PSD_KF_GEMM = 2,   /* FP64 MFMA GEMMs */
+    PSD_KF_NS = 3      /* low-precision Newton-Schulz GEMMs (flops of the lower tiles computed) */
 } psd_kernel_family;
 psd_status psd_timing_start(int32_t family, int32_t max_launches);
 psd_status psd_timing_stop(double *ms, int32_t *launches, double *work);

@@ -22,7 +22,7 @@ EXPORTS = ("psd_workspace_size", "psd_saved_size", "psd_project", "psd_project_b
            "psd_project_vjp", "psd_plan_create", "psd_plan_workspace_size", "psd_plan_concurrency",
            "psd_plan_execute", "psd_plan_tune", "psd_plan_destroy", "psd_timing_start", "psd_timing_stop",
            "psd_set_ns_iterations", "psd_status_string", "psd_version")
-KF_HEMV, KF_GEMM = 1, 2
+KF_HEMV, KF_GEMM, KF_NS = 1, 2, 3
 
 
 class PsdError(RuntimeError):

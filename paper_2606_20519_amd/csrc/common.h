@@ -57,6 +57,34 @@ __device__ __forceinline__ double warp_sum(double v) {
     return v;
 }
 
+// Sums K doubles (K a power of two, 2 <= K <= 32) over the 64 lanes of a
+// wave.  Each exchange stage sends half of the live values to the partner
+// lane and keeps the other half, so the K sums cost K - 1 + log2(64 / K)
+// shuffles instead of K * 6.  Lane l returns the total of value l / (64 / K).
+template <int CNT, int O, int K>
+__device__ __forceinline__ void wave_split_stage(double (&v)[K], int lane) {
+    if constexpr (CNT > 1) {
+        const bool up = (lane & O) != 0;
+#pragma unroll
+        for (int i = 0; i < CNT / 2; ++i) {
+            const double send = up ? v[i] : v[i + CNT / 2];
+            const double keep = up ? v[i + CNT / 2] : v[i];
+            v[i] = keep + __shfl_xor(send, O, 64);
+        }
+        wave_split_stage<CNT / 2, O / 2, K>(v, lane);
+    }
+}
+
+template <int K>
+__device__ __forceinline__ double wave_sum_split(double (&v)[K]) {
+    static_assert(K >= 2 && K <= 32 && (K & (K - 1)) == 0, "K");
+    wave_split_stage<K, 32, K>(v, threadIdx.x & 63);
+    double r = v[0];
+#pragma unroll
+    for (int o = 32 / K; o > 0; o >>= 1) r += __shfl_xor(r, o, 64);
+    return r;
+}
+
 // Block-wide sum of one double; `red` is LDS scratch of >= blockDim/64 doubles.
 // All threads receive the total.  Contains two barriers.
 __device__ inline double block_sum(double v, double *red) {

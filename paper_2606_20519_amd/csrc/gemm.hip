@@ -9,210 +9,26 @@
 // (checked on gfx950 with one-hot inputs; the f32/bf16 forms differ).
 #include "common.h"
 #include "gemm.h"
+#include "gemm_tile.h"
 #include "timing.h"
 
 namespace psd {
 
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16, PAD = 4, NT = 256;
-
-typedef double v4d __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ double zero_of(double) { return 0.0; }
-__device__ __forceinline__ cd zero_of(cd) { return cmk(0.0, 0.0); }
-__device__ __forceinline__ double conj_of(double v) { return v; }
-__device__ __forceinline__ cd conj_of(cd v) { return cconj(v); }
-__device__ __forceinline__ double scale_of(double v, double s) { return v * s; }
-__device__ __forceinline__ cd scale_of(cd v, double s) { return cscale(v, s); }
-
-// op(X)[r][c] where for A (r, c) = (i, k) and for B (r, c) = (k, j).
-// `kdim` tells which of r/c is the K index (0: r, 1: c).
-template <typename T, int OP, int KDIM>
-__device__ __forceinline__ T op_elem(const GemmOperand &o, int r, int c) {
-    const int k = KDIM == 0 ? r : c;
-    const bool second = k >= o.ksplit;
-    const T *p = static_cast<const T *>(second ? o.p1 : o.p0);
-    const int64_t ld = second ? o.ld1 : o.ld0;
-    const int kk = second ? k - o.ksplit : k;
-    const int rr = KDIM == 0 ? kk : r, cc = KDIM == 0 ? c : kk;
-    T v = (OP == OP_N) ? p[rr + (int64_t)cc * ld] : conj_of(p[cc + (int64_t)rr * ld]);
-    return v;
-}
-
-__device__ __forceinline__ double gamma_dk(double a, double b) {
-    const bool pa = a > 0.0, pb = b > 0.0;
-    if (pa && pb) return 1.0;
-    if (!pa && !pb) return 0.0;
-    return pa ? a / (a - b) : b / (b - a);
-}
-
-template <typename T, int OPA, int OPB, int EPI>
-__device__ void gemm_tile(const GemmDesc &dd, int ti, int tj, int tz) {
-    __shared__ T As[BK][BM + PAD];
-    __shared__ T Bs[BK][BN + PAD];
-    GemmDesc d = dd;
-    if (d.dN) d.N = min(d.N, *d.dN);
-    if (d.dK) d.K = min(d.K, *d.dK);
-    const int i0 = ti * BM, j0 = tj * BN;
-    if (i0 >= d.M || j0 >= d.N) return;
-    if (d.lower_only && i0 + BM - 1 < j0) return;
-    int kbeg = 0;
-    if (d.kchunk > 0) {
-        kbeg = tz * d.kchunk;
-        d.K = min(d.K, kbeg + d.kchunk);
-        d.C = static_cast<void *>(static_cast<char *>(d.C) + (int64_t)tz * d.c_zstride * sizeof(T));
-    }
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int wm = w & 1, wn = w >> 1;
-    constexpr bool CPLX = sizeof(T) == 16;
-
-    v4d acc_r[2][2], acc_i[2][2];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            acc_r[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
-            acc_i[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
-        }
-
-    for (int k0 = kbeg; k0 < d.K; k0 += BK) {
-        // ---- A tile: op(A)[i0 + i][k0 + k]
-        if (OPA == OP_N) {
-            const int i = t & 63;
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int k = (t >> 6) + 4 * s;
-                T v = zero_of(T());
-                if (i0 + i < d.M && k0 + k < d.K) {
-                    v = op_elem<T, OP_N, 1>(d.A, i0 + i, k0 + k);
-                    if (d.A.kscale) v = scale_of(v, d.A.kscale[k0 + k]);
-                }
-                As[k][i] = v;
-            }
-        } else {
-            const int k = t & 15;
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int i = (t >> 4) + 16 * s;
-                T v = zero_of(T());
-                if (i0 + i < d.M && k0 + k < d.K) {
-                    v = op_elem<T, OP_C, 1>(d.A, i0 + i, k0 + k);
-                    if (d.A.kscale) v = scale_of(v, d.A.kscale[k0 + k]);
-                }
-                As[k][i] = v;
-            }
-        }
-        // ---- B tile: op(B)[k0 + k][j0 + j]
-        if (OPB == OP_N) {
-            const int k = t & 15;
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int j = (t >> 4) + 16 * s;
-                T v = zero_of(T());
-                if (j0 + j < d.N && k0 + k < d.K) v = op_elem<T, OP_N, 0>(d.B, k0 + k, j0 + j);
-                Bs[k][j] = v;
-            }
-        } else {
-            const int j = t & 63;
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int k = (t >> 6) + 4 * s;
-                T v = zero_of(T());
-                if (j0 + j < d.N && k0 + k < d.K) v = op_elem<T, OP_C, 0>(d.B, k0 + k, j0 + j);
-                Bs[k][j] = v;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int ks = 0; ks < BK; ks += 4) {
-            const int kr = ks + (lane >> 4), ii = lane & 15;
-            T af[2], bf[2];
-#pragma unroll
-            for (int a = 0; a < 2; ++a) af[a] = As[kr][wm * 32 + a * 16 + ii];
-#pragma unroll
-            for (int b = 0; b < 2; ++b) bf[b] = Bs[kr][wn * 32 + b * 16 + ii];
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    if constexpr (CPLX) {
-                        const cd x = *reinterpret_cast<const cd *>(&af[a]);
-                        const cd y = *reinterpret_cast<const cd *>(&bf[b]);
-                        acc_r[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, y.x, acc_r[a][b], 0, 0, 0);
-                        acc_r[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(-x.y, y.y, acc_r[a][b], 0, 0, 0);
-                        acc_i[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, y.y, acc_i[a][b], 0, 0, 0);
-                        acc_i[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.y, y.x, acc_i[a][b], 0, 0, 0);
-                    } else {
-                        const double x = *reinterpret_cast<const double *>(&af[a]);
-                        const double y = *reinterpret_cast<const double *>(&bf[b]);
-                        acc_r[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc_r[a][b], 0, 0, 0);
-                    }
-                }
-        }
-        __syncthreads();
-    }
-
-    // ---- epilogue
-    const double rt2 = 1.41421356237309504880;
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int i = i0 + wm * 32 + a * 16 + (lane >> 4) + 4 * v;
-                const int j = j0 + wn * 32 + b * 16 + (lane & 15);
-                if (i >= d.M || j >= d.N) continue;
-                double re = acc_r[a][b][v], im = CPLX ? acc_i[a][b][v] : 0.0;
-                if (EPI == EPI_SVEC) {
-                    if (i < j) continue;
-                    const int64_t n = d.svec_n;
-                    const double sgn = d.dsign ? *d.dsign : d.sign;
-                    const double *xb = (d.dsign && sgn > 0.0) ? nullptr : d.xbase;
-                    const double xs = d.xscale != 0.0 ? d.xscale : 1.0;
-                    if (i == j) {
-                        const int64_t o = svec_col_start((int)n, j);
-                        const double base = xb ? xs * xb[o] : 0.0;
-                        d.y[o] = base + sgn * re;
-                    } else {
-                        const int64_t o = svec_off((int)n, i, j);
-                        const double b0 = xb ? xs * xb[o] : 0.0, b1 = xb ? xs * xb[o + 1] : 0.0;
-                        d.y[o] = b0 + sgn * rt2 * re;
-                        d.y[o + 1] = b1 + sgn * rt2 * im;
-                    }
-                    continue;
-                }
-                if (EPI == EPI_GAMMA) {
-                    const double g = gamma_dk(d.lam[i], d.lam[j]);
-                    re *= g; im *= g;
-                }
-                T *C = static_cast<T *>(d.C);
-                const int64_t idx = i + (int64_t)j * d.ldc;
-                if constexpr (CPLX) {
-                    cd out = cmk(d.alpha * re + (i == j ? d.diag_add : 0.0), d.alpha * im);
-                    if (d.beta != 0.0) {
-                        const cd c0 = *reinterpret_cast<const cd *>(&C[idx]);
-                        out = cmk(out.x + d.beta * c0.x, out.y + d.beta * c0.y);
-                    }
-                    *reinterpret_cast<cd *>(&C[idx]) = out;
-                } else {
-                    double out = d.alpha * re + (i == j ? d.diag_add : 0.0);
-                    if (d.beta != 0.0) out += d.beta * *reinterpret_cast<const double *>(&C[idx]);
-                    *reinterpret_cast<double *>(&C[idx]) = out;
-                }
-            }
-}
+using namespace gemmdev;
 
 template <typename T, int OPA, int OPB, int EPI>
 __global__ void __launch_bounds__(NT) gemm_kernel(GemmDesc d) {
-    gemm_tile<T, OPA, OPB, EPI>(d, blockIdx.x, blockIdx.y, blockIdx.z);
+    __shared__ GemmLds<T> L;
+    gemm_tile<T, OPA, OPB, EPI>(d, blockIdx.x, blockIdx.y, blockIdx.z, L);
 }
 
 template <typename T, int OPA, int OPB>
 __global__ void __launch_bounds__(NT) gemm_kernel_batched(const GemmDesc *ds) {
+    __shared__ GemmLds<T> L;
     const GemmDesc d = ds[blockIdx.z];
-    gemm_tile<T, OPA, OPB, EPI_STORE>(d, blockIdx.x, blockIdx.y, 0);
+    gemm_tile<T, OPA, OPB, EPI_STORE>(d, blockIdx.x, blockIdx.y, 0, L);
 }
 
 template <typename T, int EPI>

@@ -29,6 +29,7 @@
 #include "large.h"
 #include "mixed.h"
 #include "ql.h"
+#include "timing.h"
 
 namespace psd {
 
@@ -373,12 +374,18 @@ hipError_t ns_run(const MixedWs &w, const double *x, double *y, psd_dev_info *in
     hipLaunchKernelGGL((ns_scale_kernel<L>), sg, dim3(256), 0, st, w.M, w.lda, n, npad, w.alpha, X, X + plane);
     const int mt = npad / 64;
     dim3 gg(mt * (mt + 1) / 2);
+    // complex multiply-adds of the lower tiles actually computed, 8 flops each
+    const double ns_flops = 8.0 * 64.0 * 64.0 * (double)npad * (double)(mt * (mt + 1) / 2);
     for (int k = 0; k < iters; ++k) {
+        int slot = timing_begin(KF_NS, st);
         hipLaunchKernelGGL((ns_gemm_kernel<L>), gg, dim3(256), 0, st, X, X + plane, X, X + plane, npad, (int)NS_EPI_T,
                            T, T + plane, (double2 *)nullptr, (int64_t)0, n);
+        timing_end(slot, st, ns_flops);
         const bool last = k == iters - 1;
+        slot = timing_begin(KF_NS, st);
         hipLaunchKernelGGL((ns_gemm_kernel<L>), gg, dim3(256), 0, st, X, X + plane, T, T + plane, npad,
                            last ? (int)NS_EPI_F64 : (int)NS_EPI_HALF, X2, X2 + plane, w.S, w.lda, n);
+        timing_end(slot, st, ns_flops);
         std::swap(X, X2);
     }
     // FP64 corrections S <- S (3I - S^2) / 2

@@ -20,6 +20,8 @@
 // the next column's sigma partials.  Partial sums go to fixed slots, no
 // atomics: the result is deterministic.  Only the lower triangle (row >=
 // column) of M is ever read.
+#include <algorithm>
+
 #include "common.h"
 #include "large.h"
 #include "timing.h"
@@ -30,6 +32,9 @@ namespace {
 
 constexpr int TT = LG_TILE;
 constexpr int NB = LG_NB;
+// per-wave register staging below: 2c < 4 * (NB / 2) panel columns, c*c <= NB*NB
+// T-factor entries over 256 threads, TT / 4 tile columns per wave
+static_assert(TT == 64 && NB % 8 == 0 && (NB * NB) % 256 == 0, "staging layout");
 
 // svec -> lower triangle of M (M = conj X, see common.h); flags non-finite.
 __global__ void __launch_bounds__(256) unpack_kernel(const double *__restrict__ x, double2 *M, int64_t lda, int n,
@@ -69,14 +74,18 @@ __device__ __forceinline__ Refl make_refl(double2 alpha, double sigma) {
 }
 
 // sigma partial of column j (first column of a panel): rows > j+1.
-__global__ void __launch_bounds__(512) norm_kernel(const double2 *__restrict__ M, int64_t lda, int n, int j,
-                                                   double *npart) {
+__device__ void norm_body(const double2 *__restrict__ M, int64_t lda, int n, int j, double *npart) {
     __shared__ double red[16];
     const double2 *col = M + (int64_t)j * lda;
     double part = 0.0;
     for (int r = j + 2 + threadIdx.x; r < n; r += blockDim.x) part += cabs2(col[r]);
     const double sum = block_sum(part, red);
     if (threadIdx.x == 0) npart[0] = sum;
+}
+
+__global__ void __launch_bounds__(512) norm_kernel(const double2 *__restrict__ M, int64_t lda, int n, int j,
+                                                   double *npart) {
+    norm_body(M, lda, n, j, npart);
 }
 
 // Last diagonal entry of T.
@@ -92,16 +101,22 @@ __global__ void final_kernel(const double2 *__restrict__ M, int64_t lda, int n, 
 //   tdot[tile]  = w * Re(v_I^H A_IJ v_J), w = 1 (diagonal) or 2
 // Diagonal-tile workgroups write v for their rows into vbuf and produce
 // p = V^H v and q = W^H v over their 64 rows for the c panel columns done.
-__global__ void __launch_bounds__(256) hemv_kernel(const double2 *__restrict__ M, int64_t lda, int n, int j,
-                                                   int mt, const double *__restrict__ npart, int nparts,
-                                                   double2 *vbuf, const double2 *__restrict__ W, int p0, int c,
-                                                   double2 *P, double *tdot, double2 *pq, double2 *taus,
-                                                   double *d, double *e) {
-    __shared__ double2 tile[TT * (TT + 1)];
-    __shared__ double2 vI[TT], vJ[TT];
-    __shared__ double2 rowp[4][TT], colp[4][TT];
+struct HemvLds {
+    double2 tile[TT * (TT + 1)];
+    double2 vI[TT], vJ[TT];
+    double2 rowp[4][TT], colp[4][TT];
+};
+
+__device__ void hemv_tile(const double2 *__restrict__ M, int64_t lda, int n, int j, int mt,
+                          const double *__restrict__ npart, int nparts, double2 *vbuf,
+                          const double2 *__restrict__ W, int p0, int c, double2 *P, double *tdot, double2 *pq,
+                          double2 *taus, double *d, double *e, int b, HemvLds &L) {
+    auto &tile = L.tile;
+    auto &vI = L.vI;
+    auto &vJ = L.vJ;
+    auto &rowp = L.rowp;
+    auto &colp = L.colp;
     const int s = j + 1;
-    const int b = blockIdx.x;
     int I = (int)((sqrt(8.0 * b + 1.0) - 1.0) * 0.5);
     while ((I + 1) * (I + 2) / 2 <= b) ++I;
     while (I * (I + 1) / 2 > b) --I;
@@ -109,31 +124,49 @@ __global__ void __launch_bounds__(256) hemv_kernel(const double2 *__restrict__ M
     const int t = threadIdx.x, lane = t & 63, g = t >> 6;
     const int r0 = s + I * TT, c0 = s + J * TT;
     const double2 *colj = M + (int64_t)j * lda;
-    // sigma: every wave reduces the same partials in the same lane order
-    double sp = 0.0;
+    const bool diag = I == J;
+    const bool rowok = r0 + lane < n;
+    // The global loads of the tile are issued in two groups ahead of their
+    // use: two memory round trips per tile instead of a chain of them.
+    double sp = 0.0;  // sigma: every wave reduces the same partials in the same lane order
     for (int k = lane; k < nparts; k += 64) sp += npart[k];
-    const double sigma = warp_sum(sp);
-    const Refl h = make_refl(colj[s], sigma);
-    {
-        const bool rowok = r0 + lane < n;
+    const double2 alpha = colj[s];
+    const double djj = (b == 0 && t == 0) ? colj[j].x : 0.0;
+    double2 tv[TT / 4];  // tile column g + 4k, row lane
 #pragma unroll
-        for (int cc = g; cc < TT; cc += 4) {
-            const int col = c0 + cc;
-            double2 v = cmk(0.0, 0.0);
-            if (rowok && col < n && (I != J || lane >= cc)) v = M[(r0 + lane) + (int64_t)col * lda];
-            tile[cc * (TT + 1) + lane] = v;
-        }
-        if (t < 2 * TT) {
-            const int row = (t < TT ? r0 : c0) + lane;
-            double2 v = cmk(0.0, 0.0);
-            if (row == s) v = cmk(1.0, 0.0);
-            else if (row < n) v = cmul(colj[row], h.scale);
-            if (t < TT) vI[t] = v; else vJ[t - TT] = v;
+    for (int k = 0; k < TT / 4; ++k) {
+        const int cc = g + 4 * k, col = c0 + cc;
+        tv[k] = (rowok && col < n && (!diag || lane >= cc)) ? M[(r0 + lane) + (int64_t)col * lda] : cmk(0.0, 0.0);
+    }
+    const int vrow = (t < TT ? r0 : c0) + lane;  // threads < 2*TT: entries of v_I, v_J
+    const double2 cv = (t < 2 * TT && vrow < n && vrow != s) ? colj[vrow] : cmk(0.0, 0.0);
+    const double sigma = warp_sum(sp);
+    const Refl h = make_refl(alpha, sigma);
+#pragma unroll
+    for (int k = 0; k < TT / 4; ++k) tile[(g + 4 * k) * (TT + 1) + lane] = tv[k];
+    if (t < 2 * TT) {
+        double2 v = cmk(0.0, 0.0);
+        if (vrow == s) v = cmk(1.0, 0.0);
+        else if (vrow < n) v = cmul(cv, h.scale);
+        if (t < TT) vI[t] = v; else vJ[t - TT] = v;
+    }
+    // second group of loads, in flight while the strips are summed (issuing
+    // them with the first group would spill registers)
+    __builtin_amdgcn_sched_barrier(0);
+    // diagonal tiles: rows of the panel's V (q < c) and W (q >= c) columns, q = g + 4k
+    double2 xq[TT / 4];
+#pragma unroll
+    for (int k = 0; k < TT / 4; ++k) {
+        const int q = g + 4 * k;
+        xq[k] = cmk(0.0, 0.0);
+        if (diag && q < 2 * c && rowok) {
+            const double2 *col = (q < c) ? (M + (int64_t)(p0 + q) * lda) : (W + (int64_t)(q - c) * lda);
+            xq[k] = col[r0 + lane];
         }
     }
     __syncthreads();
     if (b == 0 && t == 0) {
-        d[j] = colj[j].x;
+        d[j] = djj;
         e[j] = h.beta;
         taus[j] = h.tau;
     }
@@ -160,19 +193,21 @@ __global__ void __launch_bounds__(256) hemv_kernel(const double2 *__restrict__ M
         colp[g][lane] = cacc;
     }
     // diagonal tiles: p = V^H v, q = W^H v over these rows, 2c columns,
-    // column cc on wave cc % 4 with the 64 rows on the lanes
-    if (I == J && c > 0) {
-        const bool ok = r0 + lane < n;
+    // column q on wave q % 4 with the 64 rows on the lanes
+    if (diag && c > 0) {
         const double2 vl = vI[lane];
-        for (int q = g; q < 2 * c; q += 4) {
-            const bool isv = q < c;
-            const int cc = isv ? q : q - c;
-            const double2 *col = isv ? (M + (int64_t)(p0 + cc) * lda) : (W + (int64_t)cc * lda);
-            const double2 x = ok ? col[r0 + lane] : cmk(0.0, 0.0);
-            const double2 pr = cmulc(x, vl);
-            const double re = warp_sum(pr.x), im = warp_sum(pr.y);
-            if (lane == 0) pq[((int64_t)I * 2 + (isv ? 0 : 1)) * NB + cc] = cmk(re, im);
+        double pv[TT / 2];  // {re, im} of column g + 4k at 2k, 2k + 1
+#pragma unroll
+        for (int k = 0; k < TT / 4; ++k) {
+            const double2 pr = cmulc(xq[k], vl);
+            pv[2 * k] = pr.x;
+            pv[2 * k + 1] = pr.y;
         }
+        const double sum = wave_sum_split(pv);  // lane l: value l / 2
+        const int q = g + 4 * (lane >> 2);
+        if ((lane & 1) == 0 && q < 2 * c)
+            reinterpret_cast<double *>(pq)[2 * (((int64_t)I * 2 + (q < c ? 0 : 1)) * NB + (q < c ? q : q - c)) +
+                                           ((lane >> 1) & 1)] = sum;
     }
     __syncthreads();
     if (t < TT) {
@@ -186,7 +221,25 @@ __global__ void __launch_bounds__(256) hemv_kernel(const double2 *__restrict__ M
         const double2 z = cadd(cadd(colp[0][cc], colp[1][cc]), cadd(colp[2][cc], colp[3][cc]));
         P[((int64_t)J * mt + I) * TT + cc] = z;
     }
+    __syncthreads();  // LDS reuse by a following call in the same workgroup
 }
+
+__global__ void __launch_bounds__(256, 2) hemv_kernel(const double2 *__restrict__ M, int64_t lda, int n, int j,
+                                                   int mt, const double *__restrict__ npart, int nparts,
+                                                   double2 *vbuf, const double2 *__restrict__ W, int p0, int c,
+                                                   double2 *P, double *tdot, double2 *pq, double2 *taus,
+                                                   double *d, double *e) {
+    __shared__ HemvLds L;
+    hemv_tile(M, lda, n, j, mt, npart, nparts, vbuf, W, p0, c, P, tdot, pq, taus, d, e, blockIdx.x, L);
+}
+
+struct WLds {
+    double2 pS[NB], qS[NB], Ws[NB], Vs[NB];
+    double2 Tl[NB][NB + 1];
+    double red[8];
+    double2 ypart[4][TT], upart[4][TT], apart[4][TT];
+    double2 wsh;
+};
 
 // Rows of block I (64 rows from s): stores v into the reflector column j,
 // w = tau u + a2 v into W[:, c] with u = y - V q - W p, and -- when column
@@ -194,69 +247,137 @@ __global__ void __launch_bounds__(256) hemv_kernel(const double2 *__restrict__ M
 // writes its sigma partial (rows > j+2).  Workgroup 0 also appends column c
 // of the block-reflector factor: T(c,c) = tau, T(0:c,c) = -tau T(0:c,0:c) p,
 // since p = V^H v_c = G(0:c, c) for v_c vanishing above row j+1.
-__global__ void __launch_bounds__(256) w_kernel(double2 *M, int64_t lda, int n, int j, int mt, int nt,
-                                                const double2 *__restrict__ vbuf, double2 *W, int p0, int c,
-                                                int next_in_panel, const double2 *__restrict__ P,
-                                                const double *__restrict__ tdot, const double2 *__restrict__ pq,
-                                                const double2 *__restrict__ taus, double2 *Tb, double *npart) {
-    __shared__ double2 pS[NB], qS[NB], Ws[NB], Vs[NB];
-    __shared__ double2 Tl[NB][NB + 1];
-    __shared__ double red[8];
-    __shared__ double2 ypart[4][TT], upart[4][TT], apart[4][TT];
-    __shared__ double2 wsh;
+__device__ void w_rows(double2 *M, int64_t lda, int n, int j, int mt, int nt, const double2 *__restrict__ vbuf,
+                       double2 *W, int p0, int c, int next_in_panel, const double2 *__restrict__ P,
+                       const double *__restrict__ tdot, const double2 *__restrict__ pq,
+                       const double2 *__restrict__ taus, double2 *Tb, double *npart, int I, WLds &L) {
+    auto &pS = L.pS;
+    auto &qS = L.qS;
+    auto &Ws = L.Ws;
+    auto &Vs = L.Vs;
+    auto &Tl = L.Tl;
+    auto &red = L.red;
+    auto &ypart = L.ypart;
+    auto &upart = L.upart;
+    auto &apart = L.apart;
+    auto &wsh = L.wsh;
     const int s = j + 1;
-    const int I = blockIdx.x, t = threadIdx.x;
+    const int t = threadIdx.x;
     const int r = t & 63, g = t >> 6;
     const int row = s + I * TT + r;
+    const bool rowok = row < n;
+    // The global loads are issued in two groups ahead of their use (the
+    // stores below could alias them, so the compiler would not hoist them).
     const double2 tj = taus[j];
-    // p = V^H v, q = W^H v: column q on wave q % 4, row blocks on the lanes
-    for (int q = g; q < 2 * c; q += 4) {
-        const bool isv = q < c;
-        const int cc = isv ? q : q - c;
-        double2 acc = cmk(0.0, 0.0);
-        for (int bb = r; bb < mt; bb += 64) acc = cadd(acc, pq[((int64_t)bb * 2 + (isv ? 0 : 1)) * NB + cc]);
-        const double re = warp_sum(acc.x), im = warp_sum(acc.y);
-        if (r == 0) { if (isv) pS[cc] = cmk(re, im); else qS[cc] = cmk(re, im); }
+    double2 pqv[NB / 2];  // p (q < c) / q (q >= c) partials of column q = g + 4k, row blocks on the lanes
+#pragma unroll
+    for (int k = 0; k < NB / 2; ++k) {
+        const int q = g + 4 * k;
+        pqv[k] = cmk(0.0, 0.0);
+        if (q < 2 * c) {
+            const double2 *src = pq + (q < c ? q : NB + q - c);  // row block bb at src[bb * 2 * NB]
+            if (r < mt) pqv[k] = src[(int64_t)r * 2 * NB];
+            for (int bb = r + 64; bb < mt; bb += 64) pqv[k] = cadd(pqv[k], src[(int64_t)bb * 2 * NB]);  // n > 4097
+        }
+    }
+    double2 wsv = cmk(0.0, 0.0), vsv = cmk(0.0, 0.0);
+    if (next_in_panel && t >= 64 && t < 64 + c) {
+        wsv = W[s + (int64_t)(t - 64) * lda];
+        vsv = M[s + (int64_t)(p0 + t - 64) * lda];
+    }
+    double2 tlv[NB * NB / 256];
+#pragma unroll
+    for (int k = 0; k < NB * NB / 256; ++k) {
+        const int idx = t + 256 * k;
+        tlv[k] = (I == 0 && idx < c * c) ? Tb[(idx % c) + (idx / c) * NB] : cmk(0.0, 0.0);
+    }
+    // p = V^H v, q = W^H v
+    {
+        double pv[NB];  // {re, im} of column g + 4k at 2k, 2k + 1
+#pragma unroll
+        for (int k = 0; k < NB / 2; ++k) {
+            pv[2 * k] = pqv[k].x;
+            pv[2 * k + 1] = pqv[k].y;
+        }
+        const double sum = wave_sum_split(pv);  // lane l: value l / 2
+        const int q = g + 4 * (r >> 2);
+        if ((r & 1) == 0 && q < 2 * c)
+            (q < c ? reinterpret_cast<double *>(pS) + 2 * q : reinterpret_cast<double *>(qS) + 2 * (q - c))[(r >> 1) & 1] =
+                sum;
     }
     if (next_in_panel && t >= 64 && t < 64 + c) {
-        Ws[t - 64] = W[s + (int64_t)(t - 64) * lda];
-        Vs[t - 64] = M[s + (int64_t)(p0 + t - 64) * lda];
+        Ws[t - 64] = wsv;
+        Vs[t - 64] = vsv;
     }
-    if (I == 0)
-        for (int idx = t; idx < c * c; idx += blockDim.x) Tl[idx % c][idx / c] = Tb[(idx % c) + (idx / c) * NB];
-    double part = 0.0;
-    for (int bb = t; bb < nt; bb += blockDim.x) part += tdot[bb];
+#pragma unroll
+    for (int k = 0; k < NB * NB / 256; ++k) {
+        const int idx = t + 256 * k;
+        if (I == 0 && idx < c * c) Tl[idx % c][idx / c] = tlv[k];
+    }
+    __builtin_amdgcn_sched_barrier(0);  // second group of loads (one group would spill)
+    // (fixed-length unrolled chunks: a loop with a data-dependent trip count
+    // would wait for each load before issuing the next)
+    double part = 0.0;  // 256 threads
+    for (int base = t; base < nt; base += 8 * 256) {
+        double tv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) tv[u] = (base + 256 * u < nt) ? tdot[base + 256 * u] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) part += tv[u];
+    }
+    double2 y = cmk(0.0, 0.0);
+    for (int base = g; base < mt; base += 64) {
+        double2 yv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            yv[u] = (base + 4 * u < mt) ? P[((int64_t)I * mt + base + 4 * u) * TT + r] : cmk(0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) y = cadd(y, yv[u]);
+    }
+    double2 vr[NB / 4], wr[NB / 4];  // panel columns g + 4k of V and W at this row
+#pragma unroll
+    for (int k = 0; k < NB / 4; ++k) {
+        const int cc = g + 4 * k;
+        const bool ok = rowok && cc < c;
+        vr[k] = ok ? M[row + (int64_t)(p0 + cc) * lda] : cmk(0.0, 0.0);
+        wr[k] = ok ? W[row + (int64_t)cc * lda] : cmk(0.0, 0.0);
+    }
+    double2 ys = cmk(0.0, 0.0);
+    if (next_in_panel && g == 0) {
+        if (r < mt) ys = P[(int64_t)r * TT];
+        for (int sl = r + 64; sl < mt; sl += 64) ys = cadd(ys, P[(int64_t)sl * TT]);  // n > 4097
+    }
+    double2 vrow = cmk(0.0, 0.0), mnext = cmk(0.0, 0.0);
+    if (t < TT && rowok) {
+        vrow = vbuf[row];
+        if (next_in_panel) mnext = M[row + (int64_t)(j + 1) * lda];
+    }
     const double vAv = block_sum(part, red);  // barriers: pS/qS/Ws/Vs/Tl visible after it
-    double qp = 0.0;
-    for (int cc = 0; cc < c; ++cc) qp += cmulc(qS[cc], pS[cc]).x;
+    // Re q^H p: lanes over the panel columns (every wave, same order)
+    const double qp = warp_sum(r < c ? cmulc(qS[r], pS[r]).x : 0.0);
     const double a2 = -0.5 * cabs2(tj) * (vAv - 2.0 * qp);
-    // block-reflector factor, column c
-    if (I == 0 && t <= c) {
-        double2 out;
-        if (t == c) {
-            out = tj;
-        } else {
-            double2 z = cmk(0.0, 0.0);
-            for (int l = t; l < c; ++l) z = cfma(Tl[t][l], pS[l], z);
-            out = cscale(cmul(tj, z), -1.0);
-        }
-        Tb[t + c * NB] = out;
+    // block-reflector factor, column c: row i on the 8 lanes 8i..8i+7
+    if (I == 0) {
+        const int ti = t >> 3, ch = t & 7;
+        double2 z = cmk(0.0, 0.0);
+        if (ti < c)
+            for (int l = ti + ch; l < c; l += 8) z = cfma(Tl[ti][l], pS[l], z);
+#pragma unroll
+        for (int o = 1; o < 8; o <<= 1) z = cadd(z, cmk(__shfl_xor(z.x, o, 64), __shfl_xor(z.y, o, 64)));
+        if (ch == 0 && ti <= c) Tb[ti + c * NB] = (ti == c) ? tj : cscale(cmul(tj, z), -1.0);
     }
-    // y, V q + W p and (for column j+1) the panel terms, split over 4 groups
+    // V q + W p and (for column j+1) the panel terms, split over 4 groups
     {
-        double2 y = cmk(0.0, 0.0), u = cmk(0.0, 0.0), a = cmk(0.0, 0.0);
-#pragma unroll 4
-        for (int sl = g; sl < mt; sl += 4) y = cadd(y, P[((int64_t)I * mt + sl) * TT + r]);
-        if (row < n) {
-#pragma unroll 4
-            for (int cc = g; cc < c; cc += 4) {
-                const double2 vr = M[row + (int64_t)(p0 + cc) * lda];
-                const double2 wr = W[row + (int64_t)cc * lda];
-                u = cfma(vr, qS[cc], u);
-                u = cfma(wr, pS[cc], u);
+        double2 u = cmk(0.0, 0.0), a = cmk(0.0, 0.0);
+#pragma unroll
+        for (int k = 0; k < NB / 4; ++k) {
+            const int cc = g + 4 * k;
+            if (cc < c) {
+                u = cfma(vr[k], qS[cc], u);
+                u = cfma(wr[k], pS[cc], u);
                 if (next_in_panel) {
-                    a = cfma(vr, cconj(Ws[cc]), a);
-                    a = cfma(wr, cconj(Vs[cc]), a);
+                    a = cfma(vr[k], cconj(Ws[cc]), a);
+                    a = cfma(wr[k], cconj(Vs[cc]), a);
                 }
             }
         }
@@ -266,30 +387,24 @@ __global__ void __launch_bounds__(256) w_kernel(double2 *M, int64_t lda, int n, 
     }
     // w at row s, needed by every block for column j+1 (wave 0)
     if (next_in_panel && g == 0) {
-        double2 ys = cmk(0.0, 0.0);
-        for (int sl = r; sl < mt; sl += 64) ys = cadd(ys, P[(int64_t)sl * TT + 0]);
+        // y(s) - (V q)(s) - (W p)(s), the panel columns on the lanes
+        if (r < c) ys = csub(ys, cadd(cmul(Vs[r], qS[r]), cmul(Ws[r], pS[r])));
         ys = cmk(warp_sum(ys.x), warp_sum(ys.y));
-        if (r == 0) {
-            for (int cc = 0; cc < c; ++cc) {
-                ys = csub(ys, cmul(Vs[cc], qS[cc]));
-                ys = csub(ys, cmul(Ws[cc], pS[cc]));
-            }
-            wsh = cadd(cmul(tj, ys), cmk(a2, 0.0));  // v[s] = 1
-        }
+        if (r == 0) wsh = cadd(cmul(tj, ys), cmk(a2, 0.0));  // v[s] = 1
     }
     __syncthreads();
     double nrm = 0.0;
-    if (t < TT && row < n) {
-        const double2 y = cadd(cadd(ypart[0][r], ypart[1][r]), cadd(ypart[2][r], ypart[3][r]));
+    if (t < TT && rowok) {
+        const double2 yy = cadd(cadd(ypart[0][r], ypart[1][r]), cadd(ypart[2][r], ypart[3][r]));
         const double2 vq = cadd(cadd(upart[0][r], upart[1][r]), cadd(upart[2][r], upart[3][r]));
-        const double2 v = vbuf[row];
+        const double2 v = vrow;
         M[row + (int64_t)j * lda] = v;
-        const double2 w = cfma(cmk(a2, 0.0), v, cmul(tj, csub(y, vq)));
+        const double2 w = cfma(cmk(a2, 0.0), v, cmul(tj, csub(yy, vq)));
         W[row + (int64_t)c * lda] = w;
         if (next_in_panel) {
             // column j+1 of A_cur = A - V W^H - W V^H over panel columns 0..c
             const double2 pa = cadd(cadd(apart[0][r], apart[1][r]), cadd(apart[2][r], apart[3][r]));
-            double2 a = csub(M[row + (int64_t)(j + 1) * lda], pa);
+            double2 a = csub(mnext, pa);
             a = csub(a, cmul(v, cconj(wsh)));
             a = csub(a, w);  // W(row,c) conj(V(s,c)), V(s,c) = 1
             M[row + (int64_t)(j + 1) * lda] = a;
@@ -300,6 +415,16 @@ __global__ void __launch_bounds__(256) w_kernel(double2 *M, int64_t lda, int n, 
         const double sum = block_sum(nrm, red);
         if (t == 0) npart[I] = sum;
     }
+    __syncthreads();  // LDS reuse by a following call in the same workgroup
+}
+
+__global__ void __launch_bounds__(256) w_kernel(double2 *M, int64_t lda, int n, int j, int mt, int nt,
+                                                const double2 *__restrict__ vbuf, double2 *W, int p0, int c,
+                                                int next_in_panel, const double2 *__restrict__ P,
+                                                const double *__restrict__ tdot, const double2 *__restrict__ pq,
+                                                const double2 *__restrict__ taus, double2 *Tb, double *npart) {
+    __shared__ WLds L;
+    w_rows(M, lda, n, j, mt, nt, vbuf, W, p0, c, next_in_panel, P, tdot, pq, taus, Tb, npart, blockIdx.x, L);
 }
 
 // Zero the upper triangle (incl. diagonal) of the reflector columns so that
@@ -310,6 +435,7 @@ __global__ void __launch_bounds__(256) clean_kernel(double2 *M, int64_t lda, int
     if (i > j || j >= n) return;
     M[i + (int64_t)j * lda] = cmk(0.0, 0.0);
 }
+
 
 }  // namespace
 
