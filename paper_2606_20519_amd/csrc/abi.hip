@@ -54,6 +54,44 @@ size_t large_ws_bytes(int n, int mode, int flags) {
     return b;
 }
 
+// Lockstep groups: FP64 blocks of one order n > 64 go through the path
+// together, at most group_cap(n) at a time (32, fewer where 32 workspace
+// slots would pass 4 GiB).
+constexpr int kMaxGroup = 32;
+constexpr size_t kGroupBytes = size_t(4) << 30;
+
+int group_cap(int n) {
+    const size_t slot = large_layout(n, 0, nullptr, nullptr);
+    return (int)std::max<size_t>(1, std::min<size_t>(kMaxGroup, kGroupBytes / slot));
+}
+
+// The large blocks of an FP64 call split into groups (same order, in order
+// of first appearance, each at most group_cap members).
+std::vector<psd::GroupChunk> make_chunks(int nblocks, const int32_t *n) {
+    std::vector<psd::GroupChunk> out;
+    std::vector<int> done(nblocks, 0);
+    for (int b = 0; b < nblocks; ++b) {
+        if (n[b] <= 64 || done[b]) continue;
+        const int cap = group_cap(n[b]);
+        psd::GroupChunk cur{n[b], {}};
+        for (int c = b; c < nblocks; ++c) {
+            if (n[c] != n[b] || done[c]) continue;
+            done[c] = 1;
+            cur.blocks.push_back(c);
+            if ((int)cur.blocks.size() == cap) {
+                out.push_back(cur);
+                cur.blocks.clear();
+            }
+        }
+        if (!cur.blocks.empty()) out.push_back(cur);
+    }
+    return out;
+}
+
+size_t chunk_ws_bytes(const psd::GroupChunk &c) {
+    return c.blocks.size() * large_layout(c.n, 0, nullptr, nullptr);
+}
+
 // Full FP64 eigen pipeline on one block: unpack, tridiagonalise, block
 // reflectors, divide and conquer.  Leaves w.lam / w.Zfinal set.
 hipError_t large_eigen(LargeWs &w, const double *x, hipStream_t s) {
@@ -83,6 +121,25 @@ hipError_t large_project(int n, const double *x, double *y, void *ws, hipStream_
     return large_reconstruct(w, x, y, w.kmax, s);
 }
 
+// Lockstep group: nmem FP64 blocks of order n, member b reading x + ioff[b]
+// and writing y + ioff[b] (device table), info record infos[infoidx[b]],
+// workspace slot b at ws + b * slot bytes.  Every launch of the path covers
+// all members, so one group costs the launches of one block.
+hipError_t large_project_group(int n, int nmem, const double *x, double *y, const int64_t *ioff, const int *infoidx,
+                               psd_dev_info *infos, void *ws, hipStream_t s) {
+    LargeWs w;
+    const size_t slot = large_layout(n, 0, ws, &w);
+    w.nmem = nmem;
+    w.zs = (int64_t)slot;
+    w.ioff = ioff;
+    w.infoidx = infoidx;
+    hipError_t e = large_eigen(w, x, s);
+    if (e != hipSuccess) return e;
+    if ((e = large_select(w, infos, s, false)) != hipSuccess) return e;
+    if ((e = large_backtransform(w, w.kmax, s)) != hipSuccess) return e;
+    return large_reconstruct(w, x, y, w.kmax, s);
+}
+
 psd_status status_of(hipError_t e) { return e == hipSuccess ? PSD_OK : PSD_EDEVICE; }
 
 int g_ns_iters = 40;
@@ -104,6 +161,13 @@ hipError_t project_block(int n, const double *x, double *y, psd_mode mode, void 
 }  // namespace
 
 namespace psd {
+
+std::vector<GroupChunk> group_chunks(int nblocks, const int32_t *n) { return make_chunks(nblocks, n); }
+size_t group_ws_bytes(const GroupChunk &c) { return chunk_ws_bytes(c); }
+hipError_t project_group_ext(int n, int nmem, const double *x, double *y, const int64_t *ioff, const int *infoidx,
+                             psd_dev_info *infos, void *ws, hipStream_t s) {
+    return large_project_group(n, nmem, x, y, ioff, infoidx, infos, ws, s);
+}
 
 hipError_t project_block_ext(int n, const double *x, double *y, psd_mode mode, void *ws, hipStream_t s,
                              psd_dev_info *info) {
@@ -159,7 +223,14 @@ psd_status psd_workspace_size(int32_t nblocks, const int32_t *n, psd_mode mode, 
         if (n[b] <= 64 && !(flags & PSD_FLAG_SAVE)) ++small;
         else large = std::max(large, large_ws_bytes(n[b], mode, flags));
     }
-    *bytes = align_up(small * sizeof(SmallJob)) + large + kAlign;
+    size_t tables = 0;
+    if (nblocks > 1 && mode == PSD_FP64_EIG && !(flags & PSD_FLAG_SAVE)) {
+        // lockstep groups: member slots side by side, plus the offset and
+        // info-index tables
+        for (const auto &c : make_chunks(nblocks, n)) large = std::max(large, chunk_ws_bytes(c));
+        tables = align_up(sizeof(int64_t) * nblocks) + align_up(sizeof(int) * nblocks);
+    }
+    *bytes = align_up(small * sizeof(SmallJob)) + tables + large + kAlign;
     return PSD_OK;
 }
 
@@ -203,35 +274,62 @@ psd_status psd_project_batched(int32_t nblocks, const int32_t *n, const double *
 
     std::vector<SmallJob> small;
     std::vector<int> large;
+    std::vector<int64_t> boff(nblocks);
     int64_t off = 0;
     for (int b = 0; b < nblocks; ++b) {
+        boff[b] = off;
         if (n[b] <= 64) small.push_back(SmallJob{off, 0, n[b], b});
         else large.push_back(b);
         off += (int64_t)n[b] * n[b];
     }
+    psd_dev_info *dinfos = reinterpret_cast<psd_dev_info *>(infos);
+    const bool grouped = mode == PSD_FP64_EIG && nblocks > 1;
     Carve cv(ws);
     SmallJob *djobs = cv.take<SmallJob>(small.size());
+    const size_t ioff_at = cv.used;
+    int64_t *dioff = grouped ? cv.take<int64_t>(nblocks) : nullptr;
+    const size_t idx_at = cv.used;
+    int *didx = grouped ? cv.take<int>(nblocks) : nullptr;
     void *lws = cv.base + cv.used;
-    {
+    std::vector<GroupChunk> chunks;
+    if (grouped) chunks = make_chunks(nblocks, n);
+    // One host-to-device copy of the job and group tables.  Pageable source:
+    // the copy is staged before hipMemcpyAsync returns.
+    if (cv.used > 0 && (!small.empty() || grouped)) {
+        std::vector<char> host(cv.used, 0);
+        if (!small.empty()) std::memcpy(host.data(), small.data(), small.size() * sizeof(SmallJob));
+        if (grouped) {
+            int64_t *hoff = reinterpret_cast<int64_t *>(host.data() + ioff_at);
+            int *hidx = reinterpret_cast<int *>(host.data() + idx_at);
+            int pos = 0;
+            for (const auto &c : chunks)
+                for (int b : c.blocks) {
+                    hoff[pos] = boff[b];
+                    hidx[pos] = b;
+                    ++pos;
+                }
+        }
+        hipError_t e = hipMemcpyAsync(ws, host.data(), cv.used, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return PSD_EDEVICE;
+    }
+    if (grouped) {
+        int pos = 0;
+        for (const auto &c : chunks) {
+            const int cnt = (int)c.blocks.size();
+            hipError_t e = large_project_group(c.n, cnt, x, y, dioff + pos, didx + pos, dinfos, lws, s);
+            if (e != hipSuccess) return PSD_EDEVICE;
+            pos += cnt;
+        }
+    } else {
         // large blocks one after another on the stream, sharing one workspace
-        int64_t o = 0;
-        int li = 0;
-        for (int b = 0; b < nblocks; ++b) {
-            if (li < (int)large.size() && large[li] == b) {
-                psd_dev_info *inf = infos ? reinterpret_cast<psd_dev_info *>(infos) + b : nullptr;
-                hipError_t e = project_block(n[b], x + o, y + o, mode, lws, s, inf, nullptr);
-                if (e != hipSuccess) return PSD_EDEVICE;
-                ++li;
-            }
-            o += (int64_t)n[b] * n[b];
+        for (int b : large) {
+            psd_dev_info *inf = dinfos ? dinfos + b : nullptr;
+            hipError_t e = project_block(n[b], x + boff[b], y + boff[b], mode, lws, s, inf, nullptr);
+            if (e != hipSuccess) return PSD_EDEVICE;
         }
     }
     if (!small.empty()) {
-        // Pageable source: the copy is staged before hipMemcpyAsync returns.
-        hipError_t e = hipMemcpyAsync(djobs, small.data(), small.size() * sizeof(SmallJob),
-                                      hipMemcpyHostToDevice, s);
-        if (e != hipSuccess) return PSD_EDEVICE;
-        e = launch_small(djobs, (int)small.size(), x, y, reinterpret_cast<psd_dev_info *>(infos), nullptr, s);
+        hipError_t e = launch_small(djobs, (int)small.size(), x, y, dinfos, nullptr, s);
         if (e != hipSuccess) return PSD_EDEVICE;
     }
     return PSD_OK;

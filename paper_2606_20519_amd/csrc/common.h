@@ -98,6 +98,15 @@ __device__ inline double block_sum(double v, double *red) {
     return t;
 }
 
+// Lockstep groups of same-order blocks: member b owns the workspace slot
+// b * zs bytes after member 0's, so every workspace pointer of member b is
+// member 0's moved by that much (the member index comes from a grid
+// dimension; a single block is the group of one with zs = 0).
+template <class T>
+__device__ __forceinline__ T *member_ptr(T *p, int64_t zs, int b) {
+    return (p && b) ? (T *)((const char *)p + (int64_t)b * zs) : p;
+}
+
 // Device-side status codes (mirror psd_status).
 enum { ST_OK = 0, ST_ENONFINITE = 4, ST_ENOCONV = 5 };
 

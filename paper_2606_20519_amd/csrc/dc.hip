@@ -43,7 +43,15 @@ enum { SK = 0, SND, SNR, SCOUNT };
 
 __global__ void __launch_bounds__(256) dc_leaf_kernel(const double *__restrict__ d, const double *__restrict__ e,
                                                       int n, int nl, double *D, double *Q, int64_t ldq,
-                                                      int *status) {
+                                                      int *status, int64_t zs) {
+    {
+        const int mb = blockIdx.z;
+        d = member_ptr(d, zs, mb);
+        e = member_ptr(e, zs, mb);
+        D = member_ptr(D, zs, mb);
+        Q = member_ptr(Q, zs, mb);
+        status = member_ptr(status, zs, mb);
+    }
     __shared__ double dl[LEAF_MAX], el[LEAF_MAX], Z[LEAF_MAX * LEAF_MAX];
     __shared__ double rc[LEAF_MAX], rs[LEAF_MAX];
     __shared__ int ri[LEAF_MAX], rankv[LEAF_MAX];
@@ -89,7 +97,19 @@ __device__ inline MergeGeo merge_geo(int level, int q, int n, int nl) {
 __global__ void __launch_bounds__(256) dc_prep_kernel(int level, int n, int nl, const double *__restrict__ e,
                                                       const double *__restrict__ Dcur, const double *Qcur,
                                                       double *Qnext, int64_t ldq, double *U, double *dv,
-                                                      int *iv, int *sv, GemmDesc *gd, int use_lds) {
+                                                      int *iv, int *sv, GemmDesc *gd, int use_lds, int64_t zs) {
+    {
+        const int mb = blockIdx.z;
+        e = member_ptr(e, zs, mb);
+        Dcur = member_ptr(Dcur, zs, mb);
+        Qcur = member_ptr(Qcur, zs, mb);
+        Qnext = member_ptr(Qnext, zs, mb);
+        U = member_ptr(U, zs, mb);
+        dv = member_ptr(dv, zs, mb);
+        iv = member_ptr(iv, zs, mb);
+        sv = member_ptr(sv, zs, mb);
+        gd = member_ptr(gd, zs, mb);
+    }
     __shared__ int red_k, red_nd, red_nr;
     const int q = blockIdx.x, t = threadIdx.x;
     const MergeGeo g = merge_geo(level, q, n, nl);
@@ -279,7 +299,13 @@ __device__ void secular_root_wave(const double *dh, const double *zh, int k, dou
 
 // One wave per root: 4 roots per 256-thread workgroup.
 __global__ void __launch_bounds__(256) dc_secular_kernel(int level, int n, int nl, double *dv, int *iv,
-                                                         const int *sv) {
+                                                         const int *sv, int64_t zs) {
+    {
+        const int mb = blockIdx.z;
+        dv = member_ptr(dv, zs, mb);
+        iv = member_ptr(iv, zs, mb);
+        sv = member_ptr(sv, zs, mb);
+    }
     const int q = blockIdx.y;
     const MergeGeo g = merge_geo(level, q, n, nl);
     const int a = g.a;
@@ -307,7 +333,13 @@ __device__ __forceinline__ double warp_prod(double v) {
 // zhat_i^2 = prod_j (lambda_j - d_i) / (rho prod_{l != i} (d_l - d_i)), paired
 // so that every factor is a ratio in (0, 1] (interlacing).
 __global__ void __launch_bounds__(256) dc_lowner_kernel(int level, int n, int nl, double *dv, const int *iv,
-                                                        const int *sv) {
+                                                        const int *sv, int64_t zs) {
+    {
+        const int mb = blockIdx.z;
+        dv = member_ptr(dv, zs, mb);
+        iv = member_ptr(iv, zs, mb);
+        sv = member_ptr(sv, zs, mb);
+    }
     const int q = blockIdx.y;
     const MergeGeo g = merge_geo(level, q, n, nl);
     const int a = g.a;
@@ -333,7 +365,13 @@ __global__ void __launch_bounds__(256) dc_lowner_kernel(int level, int n, int nl
 
 // Norm of the secular eigenvector of root j: one wave per root.
 __global__ void __launch_bounds__(256) dc_norm_kernel(int level, int n, int nl, double *dv, const int *iv,
-                                                      const int *sv) {
+                                                      const int *sv, int64_t zs) {
+    {
+        const int mb = blockIdx.z;
+        dv = member_ptr(dv, zs, mb);
+        iv = member_ptr(iv, zs, mb);
+        sv = member_ptr(sv, zs, mb);
+    }
     const int q = blockIdx.y;
     const MergeGeo g = merge_geo(level, q, n, nl);
     const int a = g.a;
@@ -357,7 +395,14 @@ __global__ void __launch_bounds__(256) dc_norm_kernel(int level, int n, int nl, 
 // values); ties broken by element id.  Writes the eigenvalues and, per final
 // column, its source (j >= 0: root j; -(1+p): deflated local index p).
 __global__ void __launch_bounds__(256) dc_order_kernel(int level, int n, int nl, const double *dv, int *iv,
-                                                       const int *sv, double *Dnext) {
+                                                       const int *sv, double *Dnext, int64_t zs) {
+    {
+        const int mb = blockIdx.z;
+        dv = member_ptr(dv, zs, mb);
+        iv = member_ptr(iv, zs, mb);
+        sv = member_ptr(sv, zs, mb);
+        Dnext = member_ptr(Dnext, zs, mb);
+    }
     const int q = blockIdx.y;
     const MergeGeo g = merge_geo(level, q, n, nl);
     const int a = g.a, nm = g.b - g.a;
@@ -387,8 +432,13 @@ __global__ void __launch_bounds__(256) dc_order_kernel(int level, int n, int nl,
 // element per thread: column col holds the normalised secular vector of a
 // root (rows of the kept poles) or the unit vector of a deflated pole.
 __global__ void __launch_bounds__(256) dc_vectors_kernel(int level, int n, int nl, const double *dv,
-                                                         const int *iv, const int *sv, double *U) {
-    const int q = blockIdx.z;
+                                                         const int *iv, const int *sv, double *U, int64_t zs) {
+    const int nmerge = nl >> level;
+    const int mb = blockIdx.z / nmerge, q = blockIdx.z - mb * nmerge;
+    dv = member_ptr(dv, zs, mb);
+    iv = member_ptr(iv, zs, mb);
+    sv = member_ptr(sv, zs, mb);
+    U = member_ptr(U, zs, mb);
     const MergeGeo g = merge_geo(level, q, n, nl);
     const int a = g.a, nm = g.b - g.a;
     const int k = sv[q * SCOUNT + SK];
@@ -415,7 +465,14 @@ __global__ void __launch_bounds__(256) dc_vectors_kernel(int level, int n, int n
 // Undo the deflating rotations (last first) on the rows of U, one column per
 // thread.
 __global__ void __launch_bounds__(256) dc_rotate_kernel(int level, int n, int nl, const double *dv, const int *iv,
-                                                        const int *sv, double *U) {
+                                                        const int *sv, double *U, int64_t zs) {
+    {
+        const int mb = blockIdx.z;
+        dv = member_ptr(dv, zs, mb);
+        iv = member_ptr(iv, zs, mb);
+        sv = member_ptr(sv, zs, mb);
+        U = member_ptr(U, zs, mb);
+    }
     const int q = blockIdx.y;
     const MergeGeo g = merge_geo(level, q, n, nl);
     const int a = g.a, nm = g.b - g.a;
@@ -462,7 +519,9 @@ hipError_t large_dc(LargeWs &w, hipStream_t st) {
     const int nl = dc_num_leaves(n);
     int64_t ldq = n;
     double *Qc = w.Q0, *Qn = w.Q1, *Dc = w.D0, *Dn = w.D1;
-    hipLaunchKernelGGL(dc_leaf_kernel, dim3(nl), dim3(64), 0, st, w.d, w.e, n, nl, Dc, Qc, ldq, w.ksel);
+    const int B = w.nmem;
+    const int64_t zs = w.zs;
+    hipLaunchKernelGGL(dc_leaf_kernel, dim3(nl, 1, B), dim3(64), 0, st, w.d, w.e, n, nl, Dc, Qc, ldq, w.ksel, zs);
     for (int level = 1; (1 << level) <= nl; ++level) {
         const int nmerge = nl >> level;
         int maxnm = 0, maxhalf = 0;
@@ -474,18 +533,18 @@ hipError_t large_dc(LargeWs &w, hipStream_t st) {
         }
         const int use_lds = maxnm <= PREP_LDS_MAX ? 1 : 0;
         const size_t prep_lds = use_lds ? (size_t)maxnm * 20 : 0;
-        hipLaunchKernelGGL(dc_prep_kernel, dim3(nmerge), dim3(256), prep_lds, st, level, n, nl, w.e, Dc, Qc, Qn,
-                           ldq, w.U, w.dcd, w.dci, w.dcs, w.gdesc, use_lds);
-        dim3 wgrid((maxnm + 3) / 4, nmerge);
-        dim3 tgrid((maxnm + 255) / 256, nmerge);
-        hipLaunchKernelGGL(dc_secular_kernel, wgrid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs);
-        hipLaunchKernelGGL(dc_lowner_kernel, wgrid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs);
-        hipLaunchKernelGGL(dc_norm_kernel, wgrid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs);
-        hipLaunchKernelGGL(dc_order_kernel, tgrid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs, Dn);
-        dim3 vgrid((maxnm + 63) / 64, (maxnm + 3) / 4, nmerge);
-        hipLaunchKernelGGL(dc_vectors_kernel, vgrid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs, w.U);
-        hipLaunchKernelGGL(dc_rotate_kernel, tgrid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs, w.U);
-        hipError_t e = gemm_launch_batched(w.gdesc, 2 * nmerge, maxhalf, maxnm, false, st);
+        hipLaunchKernelGGL(dc_prep_kernel, dim3(nmerge, 1, B), dim3(256), prep_lds, st, level, n, nl, w.e, Dc, Qc,
+                           Qn, ldq, w.U, w.dcd, w.dci, w.dcs, w.gdesc, use_lds, zs);
+        dim3 wgrid((maxnm + 3) / 4, nmerge, B);
+        dim3 tgrid((maxnm + 255) / 256, nmerge, B);
+        hipLaunchKernelGGL(dc_secular_kernel, wgrid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs, zs);
+        hipLaunchKernelGGL(dc_lowner_kernel, wgrid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs, zs);
+        hipLaunchKernelGGL(dc_norm_kernel, wgrid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs, zs);
+        hipLaunchKernelGGL(dc_order_kernel, tgrid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs, Dn, zs);
+        dim3 vgrid((maxnm + 63) / 64, (maxnm + 3) / 4, nmerge * B);
+        hipLaunchKernelGGL(dc_vectors_kernel, vgrid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs, w.U, zs);
+        hipLaunchKernelGGL(dc_rotate_kernel, tgrid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs, w.U, zs);
+        hipError_t e = gemm_launch_batched(w.gdesc, 2 * nmerge, maxhalf, maxnm, false, st, B, zs);
         if (e != hipSuccess) return e;
         std::swap(Qc, Qn);
         std::swap(Dc, Dn);

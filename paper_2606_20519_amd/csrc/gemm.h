@@ -56,15 +56,24 @@ struct GemmDesc {
     double diag_add;
     // EPI_SVEC: y = xscale*x + sign*acc (0 means 1, the default)
     double xscale;
+    // Lockstep group of nmem problems (0 or 1: a single one): problem b uses
+    // every pointer above moved by b * zs bytes, except y and xbase, which
+    // move by ioff[b] elements (ioff null: not at all).
+    int nmem;
+    int64_t zs;
+    const int64_t *ioff;
 };
 
 // Launch one GEMM described by `d` (grid sized from d) on stream st.
 hipError_t gemm_launch(const GemmDesc &d, bool complex_data, int epilogue, hipStream_t st);
 // Number of split-K slices gemm_launch uses for `d` (1 without kchunk).
-inline int gemm_kslices(const GemmDesc &d) { return d.kchunk > 0 ? (d.K + d.kchunk - 1) / d.kchunk : 1; }
+__host__ __device__ inline int gemm_kslices(const GemmDesc &d) {
+    return d.kchunk > 0 ? (d.K + d.kchunk - 1) / d.kchunk : 1;
+}
 // Launch `count` GEMMs whose descriptors live in device memory; every one
 // has M <= maxM, N <= maxN (grid sized from those bounds).
+// With nmem > 1 the descriptors of member b sit b * zs bytes after ddesc.
 hipError_t gemm_launch_batched(const GemmDesc *ddesc, int count, int maxM, int maxN, bool complex_data,
-                               hipStream_t st);
+                               hipStream_t st, int nmem = 1, int64_t zs = 0);
 
 }  // namespace psd

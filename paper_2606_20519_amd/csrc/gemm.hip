@@ -7,6 +7,8 @@
 //   A[i][k]: i = l % 16, k = l / 16;  B[k][j]: j = l % 16, k = l / 16;
 //   D[i][j] (4 values per lane): j = l % 16, i = l / 16 + 4 * v
 // (checked on gfx950 with one-hot inputs; the f32/bf16 forms differ).
+#include <algorithm>
+
 #include "common.h"
 #include "gemm.h"
 #include "gemm_tile.h"
@@ -21,19 +23,42 @@ using namespace gemmdev;
 template <typename T, int OPA, int OPB, int EPI>
 __global__ void __launch_bounds__(NT) gemm_kernel(GemmDesc d) {
     __shared__ GemmLds<T> L;
-    gemm_tile<T, OPA, OPB, EPI>(d, blockIdx.x, blockIdx.y, blockIdx.z, L);
+    int tz = blockIdx.z, b = 0;
+    if (d.nmem > 1) {
+        const int ks = gemm_kslices(d);
+        b = tz / ks;
+        tz -= b * ks;
+        d.A.p0 = member_ptr(d.A.p0, d.zs, b);
+        d.A.p1 = member_ptr(d.A.p1, d.zs, b);
+        d.A.kscale = member_ptr(d.A.kscale, d.zs, b);
+        d.B.p0 = member_ptr(d.B.p0, d.zs, b);
+        d.B.p1 = member_ptr(d.B.p1, d.zs, b);
+        d.B.kscale = member_ptr(d.B.kscale, d.zs, b);
+        d.C = member_ptr(d.C, d.zs, b);
+        d.lam = member_ptr(d.lam, d.zs, b);
+        d.dN = member_ptr(d.dN, d.zs, b);
+        d.dK = member_ptr(d.dK, d.zs, b);
+        d.dsign = member_ptr(d.dsign, d.zs, b);
+    }
+    if (d.ioff) {  // also for a group of one: its svec need not start at offset 0
+        const int64_t o = d.ioff[b];
+        if (d.y) d.y += o;
+        if (d.xbase) d.xbase += o;
+    }
+    gemm_tile<T, OPA, OPB, EPI>(d, blockIdx.x, blockIdx.y, tz, L);
 }
 
 template <typename T, int OPA, int OPB>
-__global__ void __launch_bounds__(NT) gemm_kernel_batched(const GemmDesc *ds) {
+__global__ void __launch_bounds__(NT) gemm_kernel_batched(const GemmDesc *ds, int count, int64_t zs) {
     __shared__ GemmLds<T> L;
-    const GemmDesc d = ds[blockIdx.z];
+    const int b = blockIdx.z / count;
+    const GemmDesc d = member_ptr(ds, zs, b)[blockIdx.z - b * count];
     gemm_tile<T, OPA, OPB, EPI_STORE>(d, blockIdx.x, blockIdx.y, 0, L);
 }
 
 template <typename T, int EPI>
 hipError_t launch_ops(const GemmDesc &d, hipStream_t st) {
-    dim3 grid((d.M + BM - 1) / BM, (d.N + BN - 1) / BN, gemm_kslices(d));
+    dim3 grid((d.M + BM - 1) / BM, (d.N + BN - 1) / BN, gemm_kslices(d) * std::max(1, d.nmem));
     const int key = d.A.op * 2 + d.B.op;
     switch (key) {
         case 0: hipLaunchKernelGGL((gemm_kernel<T, OP_N, OP_N, EPI>), grid, dim3(NT), 0, st, d); break;
@@ -60,22 +85,22 @@ hipError_t gemm_launch(const GemmDesc &d, bool complex_data, int epilogue, hipSt
         e = launch_ops<double, EPI_STORE>(d, st);
     }
     // algorithmic flops (upper bound when N or K is only known on the device)
-    double f = (complex_data ? 8.0 : 2.0) * (double)d.M * (double)d.N * (double)d.K;
+    double f = (complex_data ? 8.0 : 2.0) * (double)d.M * (double)d.N * (double)d.K * std::max(1, d.nmem);
     if (d.lower_only) f *= 0.5;
     timing_end(slot, st, f);
     return e;
 }
 
 hipError_t gemm_launch_batched(const GemmDesc *ddesc, int count, int maxM, int maxN, bool complex_data,
-                               hipStream_t st) {
+                               hipStream_t st, int nmem, int64_t zs) {
     if (count <= 0 || maxM <= 0 || maxN <= 0) return hipSuccess;
-    dim3 grid((maxM + BM - 1) / BM, (maxN + BN - 1) / BN, count);
+    dim3 grid((maxM + BM - 1) / BM, (maxN + BN - 1) / BN, count * std::max(1, nmem));
     // Batched problems use op(A) = N and op(B) = C (the divide-and-conquer
     // merge products Q_child * U^T with U stored row-major).
     if (complex_data)
-        hipLaunchKernelGGL((gemm_kernel_batched<cd, OP_N, OP_C>), grid, dim3(NT), 0, st, ddesc);
+        hipLaunchKernelGGL((gemm_kernel_batched<cd, OP_N, OP_C>), grid, dim3(NT), 0, st, ddesc, count, zs);
     else
-        hipLaunchKernelGGL((gemm_kernel_batched<double, OP_N, OP_C>), grid, dim3(NT), 0, st, ddesc);
+        hipLaunchKernelGGL((gemm_kernel_batched<double, OP_N, OP_C>), grid, dim3(NT), 0, st, ddesc, count, zs);
     return hipGetLastError();
 }
 

@@ -7,6 +7,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "gemm.h"
 #include "kernels.h"
 
@@ -52,6 +54,13 @@ struct LargeWs {
     double *Zfinal;     // n x n real eigenvectors of T (points at Q0 or Q1)
     int nchunk;         // split-K chunks for V^H Z
     double2 *B1;        // n x n (ld n) derivative scratch (full layouts only)
+    // lockstep group (every launch covers nmem blocks of this order; member b
+    // uses the workspace slot b * zs bytes on, svec offset ioff[b] and info
+    // record infoidx[b]); a single block: nmem = 1, zs = 0, null tables
+    int nmem;
+    int64_t zs;
+    const int64_t *ioff;
+    const int *infoidx;
 };
 
 // Bytes of a LargeWs for order n; carves it from `base` when non-null.
@@ -68,5 +77,17 @@ hipError_t large_reconstruct(const LargeWs &w, const double *x, double *y, int k
 hipError_t large_save(const LargeWs &w, double *saved, hipStream_t st);
 hipError_t large_load_saved(const LargeWs &w, const double *saved, hipStream_t st);
 hipError_t large_vjp_from_v(const LargeWs &w, const double *gy, double *gx, hipStream_t st);
+
+// Lockstep groups of same-order FP64 blocks (abi.hip): the large blocks of a
+// call split into groups; a group of c.blocks.size() members needs
+// group_ws_bytes(c) of workspace.
+struct GroupChunk {
+    int n;
+    std::vector<int> blocks;  // block indices, in member order
+};
+std::vector<GroupChunk> group_chunks(int nblocks, const int32_t *n);
+size_t group_ws_bytes(const GroupChunk &c);
+hipError_t project_group_ext(int n, int nmem, const double *x, double *y, const int64_t *ioff, const int *infoidx,
+                             psd_dev_info *infos, void *ws, hipStream_t s);
 
 }  // namespace psd

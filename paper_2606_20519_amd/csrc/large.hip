@@ -25,7 +25,8 @@ constexpr int KCHUNK = 256;
 
 inline size_t aup(size_t v) { return (v + 255) / 256 * 256; }
 
-__global__ void init_status_kernel(int *ksel) {
+__global__ void init_status_kernel(int *ksel, int64_t zs) {
+    ksel = member_ptr(ksel, zs, blockIdx.z);
     if (threadIdx.x < 4) ksel[threadIdx.x] = 0;
 }
 
@@ -33,7 +34,17 @@ __global__ void init_status_kernel(int *ksel) {
 __global__ void __launch_bounds__(256) select_kernel(const double *__restrict__ lam, const double *__restrict__ Z,
                                                      int n, int all_columns, double2 *Zc, int64_t lda,
                                                      double *lamsel, int *ksel, double *sgn,
-                                                     psd_dev_info *info) {
+                                                     psd_dev_info *info, int64_t zs, const int *infoidx) {
+    {
+        const int mb = blockIdx.z;
+        lam = member_ptr(lam, zs, mb);
+        Z = member_ptr(Z, zs, mb);
+        Zc = member_ptr(Zc, zs, mb);
+        lamsel = member_ptr(lamsel, zs, mb);
+        ksel = member_ptr(ksel, zs, mb);
+        sgn = member_ptr(sgn, zs, mb);
+        if (info) info += infoidx ? infoidx[mb] : mb;
+    }
     // first index with lambda > 0
     int lo = 0, hi = n;
     while (lo < hi) {
@@ -74,7 +85,14 @@ __global__ void __launch_bounds__(256) select_kernel(const double *__restrict__ 
 // W2 = T_b * sum_z partial_z  for columns c < k (8 columns per workgroup).
 __global__ void __launch_bounds__(256) bt_tw_kernel(const double2 *__restrict__ wpart, int nz, int64_t zstride,
                                                     const double2 *__restrict__ Tb, int kb, const int *ksel,
-                                                    double2 *W2) {
+                                                    double2 *W2, int64_t zs) {
+    {
+        const int mb = blockIdx.z;
+        wpart = member_ptr(wpart, zs, mb);
+        Tb = member_ptr(Tb, zs, mb);
+        ksel = member_ptr(ksel, zs, mb);
+        W2 = member_ptr(W2, zs, mb);
+    }
     __shared__ double2 Ts[NB][NB + 1];
     __shared__ double2 W1[NB][9];
     const int t = threadIdx.x, i = t & 31, cl = t >> 5;
@@ -180,20 +198,24 @@ size_t large_layout(int n, int flags, void *base, LargeWs *w) {
     L.B1 = full ? (double2 *)take(cdsz * (size_t)n * n) : nullptr;
     L.lam = L.D0;
     L.Zfinal = L.Q0;
+    L.nmem = 1;
+    L.zs = 0;
+    L.ioff = nullptr;
+    L.infoidx = nullptr;
     if (w) *w = L;
     return off;
 }
 
 hipError_t large_init(const LargeWs &w, hipStream_t st) {
-    hipLaunchKernelGGL(init_status_kernel, dim3(1), dim3(64), 0, st, w.ksel);
+    hipLaunchKernelGGL(init_status_kernel, dim3(1, 1, w.nmem), dim3(64), 0, st, w.ksel, w.zs);
     return hipGetLastError();
 }
 
 hipError_t large_select(const LargeWs &w, psd_dev_info *info, hipStream_t st, bool all_columns) {
     const int kcols = all_columns ? w.n : w.n / 2 + 1;
-    dim3 grid((w.n + 255) / 256, std::min(kcols, w.kmax));
+    dim3 grid((w.n + 255) / 256, std::min(kcols, w.kmax), w.nmem);
     hipLaunchKernelGGL(select_kernel, grid, dim3(256), 0, st, w.lam, w.Zfinal, w.n, all_columns ? 1 : 0, w.Zc,
-                       w.lda, w.lamsel, w.ksel, w.sgn, info);
+                       w.lda, w.lamsel, w.ksel, w.sgn, info, w.zs, w.infoidx);
     return hipGetLastError();
 }
 
@@ -213,12 +235,13 @@ hipError_t large_backtransform(const LargeWs &w, int ncols_max, hipStream_t st) 
         g.C = w.wpart; g.ldc = NB; g.alpha = 1.0; g.beta = 0.0;
         g.dN = w.ksel;
         g.kchunk = KCHUNK; g.c_zstride = zstride;
+        g.nmem = w.nmem; g.zs = w.zs;
         hipError_t e = gemm_launch(g, true, EPI_STORE, st);
         if (e != hipSuccess) return e;
         const int nz = gemm_kslices(g);
-        hipLaunchKernelGGL(bt_tw_kernel, dim3((ncols_max + 7) / 8), dim3(256), 0, st,
+        hipLaunchKernelGGL(bt_tw_kernel, dim3((ncols_max + 7) / 8, 1, w.nmem), dim3(256), 0, st,
                            reinterpret_cast<const double2 *>(w.wpart), nz, zstride, w.T + (int64_t)b * NB * NB, kb,
-                           w.ksel, w.W2);
+                           w.ksel, w.W2, w.zs);
         // Z[p0+1:, :] -= V_b W2
         GemmDesc u{};
         u.M = mr; u.N = ncols_max; u.K = kb;
@@ -226,6 +249,7 @@ hipError_t large_backtransform(const LargeWs &w, int ncols_max, hipStream_t st) 
         u.B = GemmOperand{w.W2, w.W2, NB, NB, kb, OP_N, nullptr};
         u.C = w.Zc + (p0 + 1); u.ldc = w.lda; u.alpha = -1.0; u.beta = 1.0;
         u.dN = w.ksel;
+        u.nmem = w.nmem; u.zs = w.zs;
         e = gemm_launch(u, true, EPI_STORE, st);
         if (e != hipSuccess) return e;
     }
@@ -242,6 +266,7 @@ hipError_t large_reconstruct(const LargeWs &w, const double *x, double *y, int k
     g.y = y; g.xbase = x; g.svec_n = w.n; g.sign = 1.0;
     g.dsign = w.sgn;
     g.dK = w.ksel;
+    g.nmem = w.nmem; g.zs = w.zs; g.ioff = w.ioff;
     return gemm_launch(g, true, EPI_SVEC, st);
 }
 

@@ -5,9 +5,10 @@
 //
 // The graph is captured on a stream the plan owns: a fork event, the
 // whole-block LDS kernel for every block of order <= 64 (one workgroup per
-// block), the large blocks spread round-robin over K side streams (each with
-// its own workspace slot, so K large blocks are in flight at once), and a
-// join.  Executing a plan whose buffers were already captured is one
+// block), the large-block jobs spread round-robin over K side streams (each
+// with its own workspace slot, so K jobs are in flight at once), and a join.
+// In FP64 mode a job is a lockstep group of same-order blocks (every launch
+// covers all its members); in the mixed modes a job is one block.  Executing a plan whose buffers were already captured is one
 // hipGraphLaunch on the caller's stream.  K is chosen by psd_plan_tune: it
 // replays the graph for each candidate, keeps the fastest and records it in a
 // small JSON-lines cache (PSD_TUNE_CACHE, default ./psdproj_tune.jsonl) keyed
@@ -95,6 +96,9 @@ struct psd_plan_s {
     size_t slot_bytes = 0;
     std::vector<SmallJob> small;
     SmallJob *dsmall = nullptr;
+    std::vector<GroupChunk> chunks;  // FP64 mode: lockstep groups
+    int64_t *dioff = nullptr;        // member svec offsets, chunk after chunk
+    int *didx = nullptr;             // member block indices
     hipStream_t cap = nullptr;
     hipStream_t side[kMaxConcurrency] = {};
     hipEvent_t fork = nullptr, join[kMaxConcurrency] = {};
@@ -113,14 +117,25 @@ hipError_t capture(psd_plan_s *p, const double *x, double *y, void *ws, psd_info
     for (int i = 0; i < K; ++i) chk(hipStreamWaitEvent(p->side[i], p->fork, 0));
     psd_dev_info *di = reinterpret_cast<psd_dev_info *>(infos);
     if (!p->small.empty()) chk(launch_small(p->dsmall, (int)p->small.size(), x, y, di, nullptr, p->cap));
-    int li = 0;
-    for (size_t b = 0; b < p->n.size(); ++b) {
-        if (p->n[b] <= 64) continue;
-        const int slot = li % K;
-        char *wsl = static_cast<char *>(ws) + (size_t)slot * p->slot_bytes;
-        chk(project_block_ext(p->n[b], x + p->off[b], y + p->off[b], p->mode, wsl, p->side[slot],
-                              di ? di + b : nullptr));
-        ++li;
+    if (p->mode == PSD_FP64_EIG) {
+        int pos = 0;
+        for (size_t ci = 0; ci < p->chunks.size(); ++ci) {
+            const int slot = (int)(ci % K), cnt = (int)p->chunks[ci].blocks.size();
+            char *wsl = static_cast<char *>(ws) + (size_t)slot * p->slot_bytes;
+            chk(project_group_ext(p->chunks[ci].n, cnt, x, y, p->dioff + pos, p->didx + pos, di, wsl,
+                                  p->side[slot]));
+            pos += cnt;
+        }
+    } else {
+        int li = 0;
+        for (size_t b = 0; b < p->n.size(); ++b) {
+            if (p->n[b] <= 64) continue;
+            const int slot = li % K;
+            char *wsl = static_cast<char *>(ws) + (size_t)slot * p->slot_bytes;
+            chk(project_block_ext(p->n[b], x + p->off[b], y + p->off[b], p->mode, wsl, p->side[slot],
+                                  di ? di + b : nullptr));
+            ++li;
+        }
     }
     for (int i = 0; i < K; ++i) {
         chk(hipEventRecord(p->join[i], p->side[i]));
@@ -163,6 +178,13 @@ psd_status psd_plan_create(int32_t nblocks, const int32_t *n, psd_mode mode, int
         }
         off += (int64_t)n[b] * n[b];
     }
+    if (mode == PSD_FP64_EIG) {
+        // jobs are lockstep groups
+        p->chunks = group_chunks(nblocks, n);
+        p->nlarge = (int)p->chunks.size();
+        p->slot_bytes = 0;
+        for (const auto &c : p->chunks) p->slot_bytes = std::max(p->slot_bytes, group_ws_bytes(c));
+    }
     p->slot_bytes = (p->slot_bytes + 255) / 256 * 256;
     int K = concurrency;
     if (K == 0) K = tune_lookup(tune_key(p->n, mode));
@@ -178,6 +200,19 @@ psd_status psd_plan_create(int32_t nblocks, const int32_t *n, psd_mode mode, int
         ok = hipMalloc(&p->dsmall, p->small.size() * sizeof(SmallJob)) == hipSuccess &&
              hipMemcpy(p->dsmall, p->small.data(), p->small.size() * sizeof(SmallJob), hipMemcpyHostToDevice) ==
                  hipSuccess;
+    }
+    if (ok && !p->chunks.empty()) {
+        std::vector<int64_t> hoff;
+        std::vector<int> hidx;
+        for (const auto &c : p->chunks)
+            for (int b : c.blocks) {
+                hoff.push_back(p->off[b]);
+                hidx.push_back(b);
+            }
+        ok = hipMalloc(&p->dioff, hoff.size() * sizeof(int64_t)) == hipSuccess &&
+             hipMalloc(&p->didx, hidx.size() * sizeof(int)) == hipSuccess &&
+             hipMemcpy(p->dioff, hoff.data(), hoff.size() * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(p->didx, hidx.data(), hidx.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
     }
     if (!ok) {
         psd_plan_destroy(p);
@@ -250,6 +285,8 @@ psd_status psd_plan_destroy(psd_plan p) {
     if (!p) return PSD_EINVAL;
     for (auto &g : p->graphs) (void)hipGraphExecDestroy(g.exec);
     if (p->dsmall) (void)hipFree(p->dsmall);
+    if (p->dioff) (void)hipFree(p->dioff);
+    if (p->didx) (void)hipFree(p->didx);
     if (p->cap) (void)hipStreamDestroy(p->cap);
     if (p->fork) (void)hipEventDestroy(p->fork);
     for (int i = 0; i < kMaxConcurrency; ++i) {

@@ -38,7 +38,11 @@ static_assert(TT == 64 && NB % 8 == 0 && (NB * NB) % 256 == 0, "staging layout")
 
 // svec -> lower triangle of M (M = conj X, see common.h); flags non-finite.
 __global__ void __launch_bounds__(256) unpack_kernel(const double *__restrict__ x, double2 *M, int64_t lda, int n,
-                                                     int *status) {
+                                                     int *status, int64_t zs, const int64_t *__restrict__ ioff) {
+    const int b = blockIdx.z;
+    M = member_ptr(M, zs, b);
+    status = member_ptr(status, zs, b);
+    if (ioff) x += ioff[b];
     const int j = blockIdx.y;
     const int i = j + blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
@@ -84,12 +88,14 @@ __device__ void norm_body(const double2 *__restrict__ M, int64_t lda, int n, int
 }
 
 __global__ void __launch_bounds__(512) norm_kernel(const double2 *__restrict__ M, int64_t lda, int n, int j,
-                                                   double *npart) {
-    norm_body(M, lda, n, j, npart);
+                                                   double *npart, int64_t zs) {
+    norm_body(member_ptr(M, zs, blockIdx.z), lda, n, j, member_ptr(npart, zs, blockIdx.z));
 }
 
 // Last diagonal entry of T.
-__global__ void final_kernel(const double2 *__restrict__ M, int64_t lda, int n, double *d) {
+__global__ void final_kernel(const double2 *__restrict__ M, int64_t lda, int n, double *d, int64_t zs) {
+    M = member_ptr(M, zs, blockIdx.z);
+    d = member_ptr(d, zs, blockIdx.z);
     if (threadIdx.x == 0) d[n - 1] = M[(n - 1) + (int64_t)(n - 1) * lda].x;
 }
 
@@ -228,8 +234,19 @@ __global__ void __launch_bounds__(256, 2) hemv_kernel(const double2 *__restrict_
                                                    int mt, const double *__restrict__ npart, int nparts,
                                                    double2 *vbuf, const double2 *__restrict__ W, int p0, int c,
                                                    double2 *P, double *tdot, double2 *pq, double2 *taus,
-                                                   double *d, double *e) {
+                                                   double *d, double *e, int64_t zs) {
     __shared__ HemvLds L;
+    const int b = blockIdx.z;
+    M = member_ptr(M, zs, b);
+    npart = member_ptr(npart, zs, b);
+    vbuf = member_ptr(vbuf, zs, b);
+    W = member_ptr(W, zs, b);
+    P = member_ptr(P, zs, b);
+    tdot = member_ptr(tdot, zs, b);
+    pq = member_ptr(pq, zs, b);
+    taus = member_ptr(taus, zs, b);
+    d = member_ptr(d, zs, b);
+    e = member_ptr(e, zs, b);
     hemv_tile(M, lda, n, j, mt, npart, nparts, vbuf, W, p0, c, P, tdot, pq, taus, d, e, blockIdx.x, L);
 }
 
@@ -422,14 +439,26 @@ __global__ void __launch_bounds__(256) w_kernel(double2 *M, int64_t lda, int n, 
                                                 const double2 *__restrict__ vbuf, double2 *W, int p0, int c,
                                                 int next_in_panel, const double2 *__restrict__ P,
                                                 const double *__restrict__ tdot, const double2 *__restrict__ pq,
-                                                const double2 *__restrict__ taus, double2 *Tb, double *npart) {
+                                                const double2 *__restrict__ taus, double2 *Tb, double *npart,
+                                                int64_t zs) {
     __shared__ WLds L;
+    const int b = blockIdx.z;
+    M = member_ptr(M, zs, b);
+    vbuf = member_ptr(vbuf, zs, b);
+    W = member_ptr(W, zs, b);
+    P = member_ptr(P, zs, b);
+    tdot = member_ptr(tdot, zs, b);
+    pq = member_ptr(pq, zs, b);
+    taus = member_ptr(taus, zs, b);
+    Tb = member_ptr(Tb, zs, b);
+    npart = member_ptr(npart, zs, b);
     w_rows(M, lda, n, j, mt, nt, vbuf, W, p0, c, next_in_panel, P, tdot, pq, taus, Tb, npart, blockIdx.x, L);
 }
 
 // Zero the upper triangle (incl. diagonal) of the reflector columns so that
 // column j of M is exactly v_j (v_j(j+1) = 1 is already stored).
-__global__ void __launch_bounds__(256) clean_kernel(double2 *M, int64_t lda, int n) {
+__global__ void __launch_bounds__(256) clean_kernel(double2 *M, int64_t lda, int n, int64_t zs) {
+    M = member_ptr(M, zs, blockIdx.z);
     const int j = blockIdx.y;
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i > j || j >= n) return;
@@ -440,8 +469,8 @@ __global__ void __launch_bounds__(256) clean_kernel(double2 *M, int64_t lda, int
 }  // namespace
 
 hipError_t large_unpack(const LargeWs &w, const double *x, hipStream_t st) {
-    dim3 grid((w.n + 255) / 256, w.n);
-    hipLaunchKernelGGL(unpack_kernel, grid, dim3(256), 0, st, x, w.M, w.lda, w.n, w.ksel);
+    dim3 grid((w.n + 255) / 256, w.n, w.nmem);
+    hipLaunchKernelGGL(unpack_kernel, grid, dim3(256), 0, st, x, w.M, w.lda, w.n, w.ksel, w.zs, w.ioff);
     return hipGetLastError();
 }
 
@@ -450,18 +479,18 @@ hipError_t large_tridiag(const LargeWs &w, hipStream_t st) {
     for (int p0 = 0; p0 < n - 1; p0 += NB) {
         const int kb = min(NB, n - 1 - p0);
         double2 *Tb = w.T + (int64_t)(p0 / NB) * NB * NB;
-        hipLaunchKernelGGL(norm_kernel, dim3(1), dim3(512), 0, st, w.M, w.lda, n, p0, w.npart);
+        hipLaunchKernelGGL(norm_kernel, dim3(1, 1, w.nmem), dim3(512), 0, st, w.M, w.lda, n, p0, w.npart, w.zs);
         int nparts = 1;
         for (int c = 0; c < kb; ++c) {
             const int j = p0 + c, m = n - j - 1;
             const int mt = (m + TT - 1) / TT, nt = mt * (mt + 1) / 2;
             const int slot = timing_begin(KF_HEMV, st);
-            hipLaunchKernelGGL(hemv_kernel, dim3(nt), dim3(256), 0, st, w.M, w.lda, n, j, mt, w.npart, nparts,
-                               w.vbuf, w.W, p0, c, w.P, w.tdot, w.pq, w.tau, w.d, w.e);
-            timing_end(slot, st, 8.0 * (double)m * (double)(m + 1));
+            hipLaunchKernelGGL(hemv_kernel, dim3(nt, 1, w.nmem), dim3(256), 0, st, w.M, w.lda, n, j, mt, w.npart,
+                               nparts, w.vbuf, w.W, p0, c, w.P, w.tdot, w.pq, w.tau, w.d, w.e, w.zs);
+            timing_end(slot, st, 8.0 * (double)m * (double)(m + 1) * w.nmem);
             const int next_in_panel = (c + 1 < kb) ? 1 : 0;
-            hipLaunchKernelGGL(w_kernel, dim3(mt), dim3(256), 0, st, w.M, w.lda, n, j, mt, nt, w.vbuf, w.W, p0,
-                               c, next_in_panel, w.P, w.tdot, w.pq, w.tau, Tb, w.npart);
+            hipLaunchKernelGGL(w_kernel, dim3(mt, 1, w.nmem), dim3(256), 0, st, w.M, w.lda, n, j, mt, nt, w.vbuf,
+                               w.W, p0, c, next_in_panel, w.P, w.tdot, w.pq, w.tau, Tb, w.npart, w.zs);
             nparts = mt;
         }
         const int t0 = p0 + kb;
@@ -476,17 +505,19 @@ hipError_t large_tridiag(const LargeWs &w, hipStream_t st) {
             g.ldc = w.lda;
             g.alpha = -1.0;
             g.beta = 1.0;
+            g.nmem = w.nmem;
+            g.zs = w.zs;
             hipError_t e = gemm_launch(g, true, EPI_STORE, st);
             if (e != hipSuccess) return e;
         }
     }
-    hipLaunchKernelGGL(final_kernel, dim3(1), dim3(64), 0, st, w.M, w.lda, n, w.d);
+    hipLaunchKernelGGL(final_kernel, dim3(1, 1, w.nmem), dim3(64), 0, st, w.M, w.lda, n, w.d, w.zs);
     return hipGetLastError();
 }
 
 hipError_t large_compute_T(const LargeWs &w, hipStream_t st) {
-    dim3 grid((w.n + 255) / 256, w.n);
-    hipLaunchKernelGGL(clean_kernel, grid, dim3(256), 0, st, w.M, w.lda, w.n);
+    dim3 grid((w.n + 255) / 256, w.n, w.nmem);
+    hipLaunchKernelGGL(clean_kernel, grid, dim3(256), 0, st, w.M, w.lda, w.n, w.zs);
     return hipGetLastError();
 }
 

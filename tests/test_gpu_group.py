@@ -1,0 +1,79 @@
+"""Lockstep groups of the FP64 large-block path: the same-order blocks of one
+batched call (the W blocks of a cone) go through every kernel launch of the
+path together, one workspace slot per member.  A member computes exactly what
+a single-block call computes, so every member is compared bitwise with the
+single-block result, and against the oracle (1e-10 relative Frobenius)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_20519_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2606_20519_amd as P
+    return P
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def check_against_single(P, parts, sizes, oracle_every=1):
+    y, infos = P.project_batched(dev(np.concatenate(parts)), sizes, info=True)
+    y = y.cpu().numpy()
+    off = 0
+    for i, (m, s, inf) in enumerate(zip(sizes, parts, infos)):
+        single, sinf = P.project(dev(s), m, info=True)
+        got = y[off:off + m * m]
+        assert np.array_equal(got, single.cpu().numpy()), (i, m)
+        assert (inf["status"], inf["n_pos"], inf["n_neg"]) == (sinf["status"], sinf["n_pos"], sinf["n_neg"]), i
+        assert inf["status"] == 0
+        if i % oracle_every == 0:
+            assert rel(got, oracle.project(s, m)) <= TOL, (i, m)
+        off += m * m
+
+
+def test_group_members_equal_single_blocks(P):
+    # groups {100 x 3}, {70 x 2}, {130}; the order-20 block takes the LDS kernel
+    sizes = [100, 70, 100, 130, 100, 70, 20]
+    parts = [W.gue(m, 7000 + i) for i, m in enumerate(sizes)]
+    check_against_single(P, parts, sizes)
+
+
+def test_group_members_select_different_sides(P):
+    # X and -X pick opposite sides (k+ <= k- vs k+ > k-) inside one group
+    n = 96
+    s, _, _ = W.constructed(n, 71, gap=1e-6)
+    t = W.gue(n, 72)
+    parts = [s, -s, t, -t]
+    check_against_single(P, parts, [n] * 4)
+
+
+def test_group_cap_splits_into_chunks(P):
+    # 40 blocks of one order: a group of 32 and one of 8
+    sizes = [65] * 40
+    parts = [W.gue(65, 7100 + i) for i in range(40)]
+    check_against_single(P, parts, sizes, oracle_every=7)
+
+
+def test_cone_blocks_grouped(P):
+    # a d = 3 cone: 4 instances x (W of order 81 + 8 Choi blocks of order 9)
+    x, sizes = W.cone(3, 4)
+    off, parts = 0, []
+    for m in sizes:
+        parts.append(x[off:off + m * m])
+        off += m * m
+    check_against_single(P, parts, sizes, oracle_every=9)

@@ -41,15 +41,22 @@ def blocks(x, sizes):
         off += m * m
 
 
+def cone_plus(d, inst, extra, seed):
+    """A cone plus extra large blocks of other orders (more FP64 jobs: the
+    same-order blocks form one lockstep group each)."""
+    x_np, sizes = W.cone(d, inst)
+    parts = [x_np] + [W.gue(m, seed + i) for i, m in enumerate(extra)]
+    return np.concatenate(parts), list(sizes) + list(extra)
+
+
 @pytest.mark.parametrize("concurrency", [1, 2, 3])
 def test_plan_replays_match_eager_and_oracle(P, concurrency):
     import torch
-    d, inst = 3, 3
-    x_np, sizes = W.cone(d, inst)
+    x_np, sizes = cone_plus(3, 3, [100, 120, 100], 8100)  # jobs: {81 x 3}, {100 x 2}, {120}
     x = dev(x_np)
     eager = P.project_batched(x, sizes).cpu().numpy()
     plan = P.Plan(sizes, "fp64", concurrency=concurrency)
-    assert plan.concurrency == min(concurrency, inst)
+    assert plan.concurrency == concurrency
     y = torch.empty_like(x)
     for rep in range(3):
         y.fill_(float("nan"))
@@ -89,7 +96,7 @@ def test_plan_tune_and_cache(P, tmp_path):
     import torch
     os.environ["PSD_TUNE_CACHE"] = str(tmp_path / "tune.jsonl")
     try:
-        x_np, sizes = W.cone(4, 4)
+        x_np, sizes = cone_plus(4, 4, [300, 200, 100], 8200)  # 4 FP64 jobs
         x = dev(x_np)
         y = torch.empty_like(x)
         plan = P.Plan(sizes, "fp64")
