@@ -19,10 +19,15 @@ Other workloads (one JSON line each, selected with --workload):
 
 The JSON line carries the roofline of the dominant kernel, timed live with
 HIP events recorded by the library on the kernel's own launch stream, and the
-CPU oracle timed on a bounded sample of the same workload.
+CPU oracle timed on a bounded sample of the same workload.  Its "traffic" is
+the HBM bytes per launch that rocprofv3 counters measured for that kernel
+(profiles/traffic_*.txt, scaled by the counters of a plain copy of known
+size, --copy-calibration); it is null when the kernel's source file no longer
+has the hash recorded with the counters.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c2]
 """
+import hashlib
 import argparse
 import json
 import os
@@ -52,6 +57,29 @@ def flops_ns(n: int, iters: int, corr: int) -> float:
     return iters * 2 * 4.0 * n ** 3 + corr * 2 * 8.0 * n ** 3 + 4.0 * n ** 3
 
 
+def measured_traffic(kernel, n, source):
+    """HBM bytes per launch of `kernel` at order n from the committed counter
+    summary, or None if there is none or the kernel source has changed."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_n{n}.txt")
+    src = os.path.join(ROOT, "paper_2606_20519_amd", "csrc", source)
+    if not (os.path.exists(path) and os.path.exists(src)):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    with open(src, "rb") as f:
+        digest = hashlib.sha256(f.read()).hexdigest()
+    if fields.get("source_sha256") != digest:
+        return None
+    try:
+        return round(float(fields["hbm_bytes_per_launch"]), 1)
+    except (KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,7 +90,12 @@ def main():
     ap.add_argument("--n", type=int, default=1296, help="order for c3")
     ap.add_argument("--d", type=int, default=5, help="local dimension for c4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=2, help="blocks projected by the CPU oracle")
+    ap.add_argument("--cpu-sample", type=int, default=10, help="blocks projected by the CPU oracle (bounded sample)")
+    ap.add_argument("--no-context", action="store_true",
+                    help="skip the context measurements after the timed region (counter runs)")
+    ap.add_argument("--blocks", type=int, default=50, help="blocks per step for c1 / c2 (counter runs use fewer)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 256 MiB device to device 3 times (counter calibration) and exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -72,6 +105,17 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        nbytes = 256 << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "device copy", "bytes_read_per_launch": nbytes,
+                          "bytes_written_per_launch": nbytes, "launches": 3}), flush=True)
+        return
 
     import paper_2606_20519_amd as P
     from paper_2606_20519_amd import _lib
@@ -88,14 +132,15 @@ def main():
     plan = None
     extra = {}
     if wl == "c2":
-        n, count = 625, 50
+        n, count = 625, args.blocks
         xs_np = W.warm_sequence(n, 1002, count)
-        desc = "d=5 warm-start sequence: 50 iterates of a 625x625 Hermitian block"
+        desc = (f"d=5 warm-start sequence: {count} iterates of a 625x625 Hermitian block, "
+                "projected one after another")
         sizes = [n] * count
     elif wl == "c1":
-        n, count = 16, 50
+        n, count = 16, args.blocks
         xs_np = [W.gue(n, 1001 + i) for i in range(count)]
-        desc = "d=2 process matrices: 50 blocks of order 16, one batched launch"
+        desc = f"d=2 process matrices: {count} blocks of order 16, one batched launch"
         sizes = [n] * count
     elif wl == "c3":
         n, count = args.n, 2
@@ -191,7 +236,8 @@ def main():
             achieved = timed[2] / (timed[0] * 1e-3) / 1e9
             roofline = {"kernel": "hemv_kernel (per-column Hermitian matrix-vector tiles, tridiagonalisation)",
                         "bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                        "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                        "frac": round(achieved / PEAK_HBM_GBS, 4),
+                        "traffic": measured_traffic("hemv_kernel", n, "tridiag.hip"),
                         "algorithmic_bytes_per_launch": round(timed[2] / timed[1], 1)}
         else:
             peak = PEAK_BF16_TFLOPS if mode == "mixed_bf16" else PEAK_FP32_TFLOPS
@@ -204,6 +250,19 @@ def main():
         roofline.update({"launches_timed": timed[1], "avg_launch_us": round(1e3 * avg_ms, 3),
                          "sample": "launches of the first projection in the timed region",
                          "share_of_step": round(timed[0] / ms_per_step, 4)})
+
+    if wl == "c2" and mode == "fp64" and not args.no_context:
+        # context only: the same iterates as independent blocks of one batched
+        # call (lockstep groups), which SCS cannot do with its own iterates
+        flat = X.reshape(-1)
+        yb = P.project_batched(flat, sizes, mode)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(2):
+            P.project_batched(flat, sizes, mode, out=yb)
+        torch.cuda.synchronize()
+        extra["independent_batch_proj_per_s"] = round(2 * count / (time.perf_counter() - t), 2)
+        extra["independent_batch_max_abs_diff"] = float((yb.reshape(Y.shape) - Y).abs().max())
 
     if wl == "c5":
         # derivative after the forward (eigen-pair saved by the forward)

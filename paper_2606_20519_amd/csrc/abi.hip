@@ -54,25 +54,34 @@ size_t large_ws_bytes(int n, int mode, int flags) {
     return b;
 }
 
-// Lockstep groups: FP64 blocks of one order n > 64 go through the path
-// together, at most group_cap(n) at a time (32, fewer where 32 workspace
-// slots would pass 4 GiB).
+bool is_mixed(int mode) { return mode == PSD_MIXED_BF16 || mode == PSD_MIXED_FP32; }
+
+int g_ns_iters = 40;
+int g_ns_corr = 2;
+
+// Lockstep groups: blocks of one order n > 64 go through the path (FP64 or
+// mixed) together, at most group_cap(n, mode) at a time (32, fewer where 32
+// workspace slots would pass 4 GiB).
 constexpr int kMaxGroup = 32;
 constexpr size_t kGroupBytes = size_t(4) << 30;
 
-int group_cap(int n) {
-    const size_t slot = large_layout(n, 0, nullptr, nullptr);
-    return (int)std::max<size_t>(1, std::min<size_t>(kMaxGroup, kGroupBytes / slot));
+// Workspace slot of one group member.
+size_t member_bytes(int n, int mode) {
+    return is_mixed(mode) ? mixed_layout(n, mode, nullptr, nullptr) : large_layout(n, 0, nullptr, nullptr);
 }
 
-// The large blocks of an FP64 call split into groups (same order, in order
-// of first appearance, each at most group_cap members).
-std::vector<psd::GroupChunk> make_chunks(int nblocks, const int32_t *n) {
+int group_cap(int n, int mode) {
+    return (int)std::max<size_t>(1, std::min<size_t>(kMaxGroup, kGroupBytes / member_bytes(n, mode)));
+}
+
+// The large blocks of a call split into groups (same order, in order of
+// first appearance, each at most group_cap members).
+std::vector<psd::GroupChunk> make_chunks(int nblocks, const int32_t *n, int mode) {
     std::vector<psd::GroupChunk> out;
     std::vector<int> done(nblocks, 0);
     for (int b = 0; b < nblocks; ++b) {
         if (n[b] <= 64 || done[b]) continue;
-        const int cap = group_cap(n[b]);
+        const int cap = group_cap(n[b], mode);
         psd::GroupChunk cur{n[b], {}};
         for (int c = b; c < nblocks; ++c) {
             if (n[c] != n[b] || done[c]) continue;
@@ -88,9 +97,7 @@ std::vector<psd::GroupChunk> make_chunks(int nblocks, const int32_t *n) {
     return out;
 }
 
-size_t chunk_ws_bytes(const psd::GroupChunk &c) {
-    return c.blocks.size() * large_layout(c.n, 0, nullptr, nullptr);
-}
+size_t chunk_ws_bytes(const psd::GroupChunk &c, int mode) { return c.blocks.size() * member_bytes(c.n, mode); }
 
 // Full FP64 eigen pipeline on one block: unpack, tridiagonalise, block
 // reflectors, divide and conquer.  Leaves w.lam / w.Zfinal set.
@@ -140,12 +147,21 @@ hipError_t large_project_group(int n, int nmem, const double *x, double *y, cons
     return large_reconstruct(w, x, y, w.kmax, s);
 }
 
+// A lockstep group in either precision form.
+hipError_t project_group(int n, int nmem, psd_mode mode, const double *x, double *y, const int64_t *ioff,
+                         const int *infoidx, psd_dev_info *infos, void *ws, hipStream_t s) {
+    if (!is_mixed(mode)) return large_project_group(n, nmem, x, y, ioff, infoidx, infos, ws, s);
+    MixedWs w;
+    const size_t slot = mixed_layout(n, mode, ws, &w);
+    w.nmem = nmem;
+    w.zs = (int64_t)slot;
+    w.ioff = ioff;
+    w.infoidx = infoidx;
+    return mixed_project(w, mode, x, y, infos, g_ns_iters, g_ns_corr, s);
+}
+
 psd_status status_of(hipError_t e) { return e == hipSuccess ? PSD_OK : PSD_EDEVICE; }
 
-int g_ns_iters = 40;
-int g_ns_corr = 2;
-
-bool is_mixed(int mode) { return mode == PSD_MIXED_BF16 || mode == PSD_MIXED_FP32; }
 
 // One block of order n > 64: the mixed path for mixed modes, else FP64.
 hipError_t project_block(int n, const double *x, double *y, psd_mode mode, void *ws, hipStream_t s,
@@ -162,19 +178,12 @@ hipError_t project_block(int n, const double *x, double *y, psd_mode mode, void 
 
 namespace psd {
 
-std::vector<GroupChunk> group_chunks(int nblocks, const int32_t *n) { return make_chunks(nblocks, n); }
-size_t group_ws_bytes(const GroupChunk &c) { return chunk_ws_bytes(c); }
-hipError_t project_group_ext(int n, int nmem, const double *x, double *y, const int64_t *ioff, const int *infoidx,
-                             psd_dev_info *infos, void *ws, hipStream_t s) {
-    return large_project_group(n, nmem, x, y, ioff, infoidx, infos, ws, s);
+std::vector<GroupChunk> group_chunks(int nblocks, const int32_t *n, int mode) { return make_chunks(nblocks, n, mode); }
+size_t group_ws_bytes(const GroupChunk &c, int mode) { return chunk_ws_bytes(c, mode); }
+hipError_t project_group_ext(int n, int nmem, psd_mode mode, const double *x, double *y, const int64_t *ioff,
+                             const int *infoidx, psd_dev_info *infos, void *ws, hipStream_t s) {
+    return project_group(n, nmem, mode, x, y, ioff, infoidx, infos, ws, s);
 }
-
-hipError_t project_block_ext(int n, const double *x, double *y, psd_mode mode, void *ws, hipStream_t s,
-                             psd_dev_info *info) {
-    return project_block(n, x, y, mode, ws, s, info, nullptr);
-}
-
-size_t block_ws_bytes(int n, psd_mode mode) { return large_ws_bytes(n, mode, 0); }
 
 hipError_t prepare_kernel_attributes() {
     hipError_t e = small_prepare();
@@ -224,10 +233,10 @@ psd_status psd_workspace_size(int32_t nblocks, const int32_t *n, psd_mode mode, 
         else large = std::max(large, large_ws_bytes(n[b], mode, flags));
     }
     size_t tables = 0;
-    if (nblocks > 1 && mode == PSD_FP64_EIG && !(flags & PSD_FLAG_SAVE)) {
+    if (nblocks > 1 && !(flags & PSD_FLAG_SAVE)) {
         // lockstep groups: member slots side by side, plus the offset and
         // info-index tables
-        for (const auto &c : make_chunks(nblocks, n)) large = std::max(large, chunk_ws_bytes(c));
+        for (const auto &c : make_chunks(nblocks, n, mode)) large = std::max(large, chunk_ws_bytes(c, mode));
         tables = align_up(sizeof(int64_t) * nblocks) + align_up(sizeof(int) * nblocks);
     }
     *bytes = align_up(small * sizeof(SmallJob)) + tables + large + kAlign;
@@ -283,7 +292,7 @@ psd_status psd_project_batched(int32_t nblocks, const int32_t *n, const double *
         off += (int64_t)n[b] * n[b];
     }
     psd_dev_info *dinfos = reinterpret_cast<psd_dev_info *>(infos);
-    const bool grouped = mode == PSD_FP64_EIG && nblocks > 1;
+    const bool grouped = nblocks > 1;
     Carve cv(ws);
     SmallJob *djobs = cv.take<SmallJob>(small.size());
     const size_t ioff_at = cv.used;
@@ -292,7 +301,7 @@ psd_status psd_project_batched(int32_t nblocks, const int32_t *n, const double *
     int *didx = grouped ? cv.take<int>(nblocks) : nullptr;
     void *lws = cv.base + cv.used;
     std::vector<GroupChunk> chunks;
-    if (grouped) chunks = make_chunks(nblocks, n);
+    if (grouped) chunks = make_chunks(nblocks, n, mode);
     // One host-to-device copy of the job and group tables.  Pageable source:
     // the copy is staged before hipMemcpyAsync returns.
     if (cv.used > 0 && (!small.empty() || grouped)) {
@@ -316,7 +325,7 @@ psd_status psd_project_batched(int32_t nblocks, const int32_t *n, const double *
         int pos = 0;
         for (const auto &c : chunks) {
             const int cnt = (int)c.blocks.size();
-            hipError_t e = large_project_group(c.n, cnt, x, y, dioff + pos, didx + pos, dinfos, lws, s);
+            hipError_t e = project_group(c.n, cnt, mode, x, y, dioff + pos, didx + pos, dinfos, lws, s);
             if (e != hipSuccess) return PSD_EDEVICE;
             pos += cnt;
         }

@@ -9,6 +9,7 @@
 
 #include <vector>
 
+#include "../../include/psdproj.h"
 #include "gemm.h"
 #include "kernels.h"
 
@@ -78,16 +79,16 @@ hipError_t large_save(const LargeWs &w, double *saved, hipStream_t st);
 hipError_t large_load_saved(const LargeWs &w, const double *saved, hipStream_t st);
 hipError_t large_vjp_from_v(const LargeWs &w, const double *gy, double *gx, hipStream_t st);
 
-// Lockstep groups of same-order FP64 blocks (abi.hip): the large blocks of a
-// call split into groups; a group of c.blocks.size() members needs
-// group_ws_bytes(c) of workspace.
+// Lockstep groups of same-order blocks (abi.hip): the large blocks of a call
+// split into groups; a group of c.blocks.size() members needs
+// group_ws_bytes(c, mode) of workspace.
 struct GroupChunk {
     int n;
     std::vector<int> blocks;  // block indices, in member order
 };
-std::vector<GroupChunk> group_chunks(int nblocks, const int32_t *n);
-size_t group_ws_bytes(const GroupChunk &c);
-hipError_t project_group_ext(int n, int nmem, const double *x, double *y, const int64_t *ioff, const int *infoidx,
-                             psd_dev_info *infos, void *ws, hipStream_t s);
+std::vector<GroupChunk> group_chunks(int nblocks, const int32_t *n, int mode);
+size_t group_ws_bytes(const GroupChunk &c, int mode);
+hipError_t project_group_ext(int n, int nmem, psd_mode mode, const double *x, double *y, const int64_t *ioff,
+                             const int *infoidx, psd_dev_info *infos, void *ws, hipStream_t s);
 
 }  // namespace psd

@@ -16,6 +16,13 @@ struct MixedWs {
     double2 *q, *qprev, *wv, *P;
     double *ab, *alpha, *red;
     int *status;
+    // lockstep group (as for the FP64 path: member b uses the slot b * zs
+    // bytes on, svec offset ioff[b], info record infoidx[b]); single block:
+    // nmem = 1, zs = 0, null tables
+    int nmem;
+    int64_t zs;
+    const int64_t *ioff;
+    const int *infoidx;
 };
 
 // mode: 1 = BF16, 2 = FP32 low-precision iterations.

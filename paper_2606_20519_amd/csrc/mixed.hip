@@ -51,8 +51,11 @@ __device__ inline double hash_unit(uint64_t x) {
     return (double)(x >> 11) * (1.0 / 9007199254740992.0) - 0.5;
 }
 
-__global__ void __launch_bounds__(1024) lz_init_kernel(int n, double2 *q, double2 *qprev, double *ab) {
+__global__ void __launch_bounds__(1024) lz_init_kernel(int n, double2 *q, double2 *qprev, double *ab, int64_t zs) {
     __shared__ double red[32];
+    q = member_ptr(q, zs, blockIdx.z);
+    qprev = member_ptr(qprev, zs, blockIdx.z);
+    ab = member_ptr(ab, zs, blockIdx.z);
     double part = 0.0;
     for (int r = threadIdx.x; r < n; r += blockDim.x) {
         const double2 v = cmk(hash_unit(2 * (uint64_t)r), hash_unit(2 * (uint64_t)r + 1));
@@ -67,8 +70,11 @@ __global__ void __launch_bounds__(1024) lz_init_kernel(int n, double2 *q, double
 
 // P[cs][row] = sum over the column chunk cs of M(row, col) q(col).
 __global__ void __launch_bounds__(256) lz_gemv_kernel(const double2 *__restrict__ M, int64_t lda, int n,
-                                                      const double2 *__restrict__ q, double2 *P) {
+                                                      const double2 *__restrict__ q, double2 *P, int64_t zs) {
     __shared__ double2 part[4][64];
+    M = member_ptr(M, zs, blockIdx.z);
+    q = member_ptr(q, zs, blockIdx.z);
+    P = member_ptr(P, zs, blockIdx.z);
     const int rb = blockIdx.x, cs = blockIdx.y, t = threadIdx.x, r = t & 63, g = t >> 6;
     const int row = rb * 64 + r;
     const int chunk = (n + LZ_SPLIT - 1) / LZ_SPLIT;
@@ -87,8 +93,13 @@ __global__ void __launch_bounds__(256) lz_gemv_kernel(const double2 *__restrict_
 // One Lanczos step on a single workgroup: y = sum P, a = Re q^H y,
 // w = y - a q - b_prev q_prev, b = ||w||, (q_prev, q) <- (q, w / b).
 __global__ void __launch_bounds__(1024) lz_step_kernel(int n, int step, const double2 *__restrict__ P, double2 *q,
-                                                       double2 *qprev, double2 *wv, double *ab) {
+                                                       double2 *qprev, double2 *wv, double *ab, int64_t zs) {
     __shared__ double red[32];
+    P = member_ptr(P, zs, blockIdx.z);
+    q = member_ptr(q, zs, blockIdx.z);
+    qprev = member_ptr(qprev, zs, blockIdx.z);
+    wv = member_ptr(wv, zs, blockIdx.z);
+    ab = member_ptr(ab, zs, blockIdx.z);
     if (ab[2 * LZ_STEPS + 2] != 0.0) return;  // broke down earlier
     double part = 0.0;
     for (int r = threadIdx.x; r < n; r += blockDim.x) {
@@ -124,8 +135,10 @@ __global__ void __launch_bounds__(1024) lz_step_kernel(int n, int step, const do
 }
 
 // alpha = 1.1 max |theta| over the Ritz values of the Lanczos tridiagonal.
-__global__ void __launch_bounds__(64) lz_final_kernel(const double *ab, double *alpha_out) {
+__global__ void __launch_bounds__(64) lz_final_kernel(const double *ab, double *alpha_out, int64_t zs) {
     __shared__ double d[64], e[64], Z[LZ_STEPS * LZ_STEPS], rc[64], rs[64];
+    ab = member_ptr(ab, zs, blockIdx.z);
+    alpha_out = member_ptr(alpha_out, zs, blockIdx.z);
     __shared__ int ri[64], nrot_s, done_s;
     const int k = (int)ab[2 * LZ_STEPS];
     const int t = threadIdx.x;
@@ -143,7 +156,10 @@ __global__ void __launch_bounds__(64) lz_final_kernel(const double *ab, double *
 // Full Hermitian matrix from the svec (M = conj X, see common.h); flags
 // non-finite entries.
 __global__ void __launch_bounds__(256) mx_unpack_kernel(const double *__restrict__ x, double2 *M, int64_t lda, int n,
-                                                        int *status) {
+                                                        int *status, int64_t zs, const int64_t *__restrict__ ioff) {
+    M = member_ptr(M, zs, blockIdx.z);
+    status = member_ptr(status, zs, blockIdx.z);
+    if (ioff) x += ioff[blockIdx.z];
     const int j = blockIdx.y;
     const int i = j + blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
@@ -160,7 +176,8 @@ __global__ void __launch_bounds__(256) mx_unpack_kernel(const double *__restrict
     M[i + (int64_t)j * lda] = v;
 }
 
-__global__ void mx_init_kernel(int *status) {
+__global__ void mx_init_kernel(int *status, int64_t zs) {
+    status = member_ptr(status, zs, blockIdx.z);
     if (threadIdx.x < 4) status[threadIdx.x] = 0;
 }
 
@@ -174,7 +191,11 @@ __device__ __forceinline__ float to_low<float>(float v) { return v; }
 // X0 = M / alpha in low precision, planar, ld = npad; zero padding.
 template <typename L>
 __global__ void __launch_bounds__(256) ns_scale_kernel(const double2 *__restrict__ M, int64_t lda, int n, int npad,
-                                                       const double *alpha, L *Xre, L *Xim) {
+                                                       const double *alpha, L *Xre, L *Xim, int64_t zs) {
+    M = member_ptr(M, zs, blockIdx.z);
+    alpha = member_ptr(alpha, zs, blockIdx.z);
+    Xre = member_ptr(Xre, zs, blockIdx.z);
+    Xim = member_ptr(Xim, zs, blockIdx.z);
     const int j = blockIdx.y;
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= npad) return;
@@ -201,8 +222,19 @@ enum { NS_EPI_T = 0, NS_EPI_HALF = 1, NS_EPI_F64 = 2 };
 template <typename L>
 __global__ void __launch_bounds__(256) ns_gemm_kernel(const L *__restrict__ Are, const L *__restrict__ Aim,
                                                       const L *__restrict__ Bre, const L *__restrict__ Bim, int npad,
-                                                      int epi, L *Cre, L *Cim, double2 *C64, int64_t ld64, int n) {
+                                                      int epi, L *Cre, L *Cim, double2 *C64, int64_t ld64, int n,
+                                                      int64_t zs) {
     constexpr bool BF = sizeof(L) == 2;
+    {
+        const int mb = blockIdx.z;
+        Are = member_ptr(Are, zs, mb);
+        Aim = member_ptr(Aim, zs, mb);
+        Bre = member_ptr(Bre, zs, mb);
+        Bim = member_ptr(Bim, zs, mb);
+        Cre = member_ptr(Cre, zs, mb);
+        Cim = member_ptr(Cim, zs, mb);
+        C64 = member_ptr(C64, zs, mb);
+    }
     constexpr int KP = 32 + (BF ? 8 : 4);  // padded k extent in LDS
     __shared__ __align__(16) L sAr[64][KP], sAi[64][KP], sBr[64][KP], sBi[64][KP];
     const int tb = blockIdx.x;
@@ -328,8 +360,11 @@ __global__ void __launch_bounds__(256) ns_gemm_kernel(const L *__restrict__ Are,
 constexpr int RES_COLS = 16;
 __global__ void __launch_bounds__(256) ns_residual_part_kernel(const double2 *__restrict__ T,
                                                                const double2 *__restrict__ S, int64_t lda, int n,
-                                                               double *red_out) {
+                                                               double *red_out, int64_t zs) {
     __shared__ double red[8];
+    T = member_ptr(T, zs, blockIdx.z);
+    S = member_ptr(S, zs, blockIdx.z);
+    red_out = member_ptr(red_out, zs, blockIdx.z);
     const int j0 = blockIdx.x * RES_COLS;
     double r2 = 0.0, tr = 0.0;
     for (int j = j0; j < min(n, j0 + RES_COLS); ++j)
@@ -345,8 +380,12 @@ __global__ void __launch_bounds__(256) ns_residual_part_kernel(const double2 *__
 
 __global__ void __launch_bounds__(256) ns_residual_final_kernel(const double *__restrict__ red_in, int nb, int n,
                                                                 int iters, const double *alpha, const int *status,
-                                                                psd_dev_info *info) {
+                                                                psd_dev_info *info, int64_t zs, const int *infoidx) {
     __shared__ double red[8];
+    red_in = member_ptr(red_in, zs, blockIdx.z);
+    alpha = member_ptr(alpha, zs, blockIdx.z);
+    status = member_ptr(status, zs, blockIdx.z);
+    if (info) info += infoidx ? infoidx[blockIdx.z] : blockIdx.z;
     double r2 = 0.0, tr = 0.0;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) { r2 += red_in[2 * b]; tr += red_in[2 * b + 1]; }
     r2 = block_sum(r2, red);
@@ -370,21 +409,23 @@ hipError_t ns_run(const MixedWs &w, const double *x, double *y, psd_dev_info *in
     const int n = w.n, npad = w.npad;
     const int64_t plane = (int64_t)npad * npad;
     L *X = reinterpret_cast<L *>(w.lo0), *T = reinterpret_cast<L *>(w.lo1), *X2 = reinterpret_cast<L *>(w.lo2);
-    dim3 sg((npad + 255) / 256, npad);
-    hipLaunchKernelGGL((ns_scale_kernel<L>), sg, dim3(256), 0, st, w.M, w.lda, n, npad, w.alpha, X, X + plane);
+    const int B = w.nmem;
+    const int64_t zs = w.zs;
+    dim3 sg((npad + 255) / 256, npad, B);
+    hipLaunchKernelGGL((ns_scale_kernel<L>), sg, dim3(256), 0, st, w.M, w.lda, n, npad, w.alpha, X, X + plane, zs);
     const int mt = npad / 64;
-    dim3 gg(mt * (mt + 1) / 2);
+    dim3 gg(mt * (mt + 1) / 2, 1, B);
     // complex multiply-adds of the lower tiles actually computed, 8 flops each
-    const double ns_flops = 8.0 * 64.0 * 64.0 * (double)npad * (double)(mt * (mt + 1) / 2);
+    const double ns_flops = 8.0 * 64.0 * 64.0 * (double)npad * (double)(mt * (mt + 1) / 2) * B;
     for (int k = 0; k < iters; ++k) {
         int slot = timing_begin(KF_NS, st);
         hipLaunchKernelGGL((ns_gemm_kernel<L>), gg, dim3(256), 0, st, X, X + plane, X, X + plane, npad, (int)NS_EPI_T,
-                           T, T + plane, (double2 *)nullptr, (int64_t)0, n);
+                           T, T + plane, (double2 *)nullptr, (int64_t)0, n, zs);
         timing_end(slot, st, ns_flops);
         const bool last = k == iters - 1;
         slot = timing_begin(KF_NS, st);
         hipLaunchKernelGGL((ns_gemm_kernel<L>), gg, dim3(256), 0, st, X, X + plane, T, T + plane, npad,
-                           last ? (int)NS_EPI_F64 : (int)NS_EPI_HALF, X2, X2 + plane, w.S, w.lda, n);
+                           last ? (int)NS_EPI_F64 : (int)NS_EPI_HALF, X2, X2 + plane, w.S, w.lda, n, zs);
         timing_end(slot, st, ns_flops);
         std::swap(X, X2);
     }
@@ -396,6 +437,7 @@ hipError_t ns_run(const MixedWs &w, const double *x, double *y, psd_dev_info *in
         a.A = GemmOperand{S, S, w.lda, w.lda, n, OP_N, nullptr};
         a.B = GemmOperand{S, S, w.lda, w.lda, n, OP_N, nullptr};
         a.C = w.T64; a.ldc = w.lda; a.alpha = -1.0; a.beta = 0.0; a.diag_add = 3.0;
+        a.nmem = B; a.zs = zs;
         hipError_t e = gemm_launch(a, true, EPI_STORE, st);
         if (e != hipSuccess) return e;
         GemmDesc b{};
@@ -403,6 +445,7 @@ hipError_t ns_run(const MixedWs &w, const double *x, double *y, psd_dev_info *in
         b.A = GemmOperand{S, S, w.lda, w.lda, n, OP_N, nullptr};
         b.B = GemmOperand{w.T64, w.T64, w.lda, w.lda, n, OP_N, nullptr};
         b.C = S2; b.ldc = w.lda; b.alpha = 0.5; b.beta = 0.0;
+        b.nmem = B; b.zs = zs;
         e = gemm_launch(b, true, EPI_STORE, st);
         if (e != hipSuccess) return e;
         std::swap(S, S2);
@@ -413,13 +456,14 @@ hipError_t ns_run(const MixedWs &w, const double *x, double *y, psd_dev_info *in
         a.A = GemmOperand{S, S, w.lda, w.lda, n, OP_N, nullptr};
         a.B = GemmOperand{S, S, w.lda, w.lda, n, OP_N, nullptr};
         a.C = w.T64; a.ldc = w.lda; a.alpha = -1.0; a.beta = 0.0; a.diag_add = 3.0;
+        a.nmem = B; a.zs = zs;
         hipError_t e = gemm_launch(a, true, EPI_STORE, st);
         if (e != hipSuccess) return e;
     }
     const int nrb = (n + RES_COLS - 1) / RES_COLS;
-    hipLaunchKernelGGL(ns_residual_part_kernel, dim3(nrb), dim3(256), 0, st, w.T64, S, w.lda, n, w.red);
-    hipLaunchKernelGGL(ns_residual_final_kernel, dim3(1), dim3(256), 0, st, w.red, nrb, n, iters, w.alpha, w.status,
-                       info);
+    hipLaunchKernelGGL(ns_residual_part_kernel, dim3(nrb, 1, B), dim3(256), 0, st, w.T64, S, w.lda, n, w.red, zs);
+    hipLaunchKernelGGL(ns_residual_final_kernel, dim3(1, 1, B), dim3(256), 0, st, w.red, nrb, n, iters, w.alpha,
+                       w.status, info, zs, w.infoidx);
     // Pi = X/2 + X S / 2, lower tiles, straight into the svec
     GemmDesc f{};
     f.M = f.N = f.K = n;
@@ -427,6 +471,7 @@ hipError_t ns_run(const MixedWs &w, const double *x, double *y, psd_dev_info *in
     f.A = GemmOperand{w.M, w.M, w.lda, w.lda, n, OP_N, nullptr};
     f.B = GemmOperand{S, S, w.lda, w.lda, n, OP_N, nullptr};
     f.y = y; f.xbase = x; f.svec_n = n; f.sign = 0.5; f.xscale = 0.5;
+    f.nmem = B; f.zs = zs; f.ioff = w.ioff;
     return gemm_launch(f, true, EPI_SVEC, st);
 }
 
@@ -462,6 +507,10 @@ size_t mixed_layout(int n, int mode, void *base, MixedWs *w) {
     W.alpha = (double *)take(sizeof(double));
     W.status = (int *)take(sizeof(int) * 4);
     W.red = (double *)take(sizeof(double) * 2 * ((size_t)(n + 15) / 16 + 1));
+    W.nmem = 1;
+    W.zs = 0;
+    W.ioff = nullptr;
+    W.infoidx = nullptr;
     if (w) *w = W;
     return off;
 }
@@ -470,16 +519,20 @@ hipError_t mixed_project(const MixedWs &w, int mode, const double *x, double *y,
                          int corr, hipStream_t st) {
     const int n = w.n;
     if (iters < 1) iters = 1;
-    hipLaunchKernelGGL(mx_init_kernel, dim3(1), dim3(64), 0, st, w.status);
-    hipLaunchKernelGGL(mx_unpack_kernel, dim3((n + 255) / 256, n), dim3(256), 0, st, x, w.M, w.lda, n, w.status);
+    const int B = w.nmem;
+    const int64_t zs = w.zs;
+    hipLaunchKernelGGL(mx_init_kernel, dim3(1, 1, B), dim3(64), 0, st, w.status, zs);
+    hipLaunchKernelGGL(mx_unpack_kernel, dim3((n + 255) / 256, n, B), dim3(256), 0, st, x, w.M, w.lda, n, w.status, zs,
+                       w.ioff);
     // spectral scale
-    hipLaunchKernelGGL(lz_init_kernel, dim3(1), dim3(1024), 0, st, n, w.q, w.qprev, w.ab);
+    hipLaunchKernelGGL(lz_init_kernel, dim3(1, 1, B), dim3(1024), 0, st, n, w.q, w.qprev, w.ab, zs);
     const int steps = std::min(LZ_STEPS, n);
     for (int s = 0; s < steps; ++s) {
-        hipLaunchKernelGGL(lz_gemv_kernel, dim3((n + 63) / 64, LZ_SPLIT), dim3(256), 0, st, w.M, w.lda, n, w.q, w.P);
-        hipLaunchKernelGGL(lz_step_kernel, dim3(1), dim3(1024), 0, st, n, s, w.P, w.q, w.qprev, w.wv, w.ab);
+        hipLaunchKernelGGL(lz_gemv_kernel, dim3((n + 63) / 64, LZ_SPLIT, B), dim3(256), 0, st, w.M, w.lda, n, w.q,
+                           w.P, zs);
+        hipLaunchKernelGGL(lz_step_kernel, dim3(1, 1, B), dim3(1024), 0, st, n, s, w.P, w.q, w.qprev, w.wv, w.ab, zs);
     }
-    hipLaunchKernelGGL(lz_final_kernel, dim3(1), dim3(64), 0, st, w.ab, w.alpha);
+    hipLaunchKernelGGL(lz_final_kernel, dim3(1, 1, B), dim3(64), 0, st, w.ab, w.alpha, zs);
     if (mode == 1) return ns_run<__bf16>(w, x, y, info, iters, corr, st);
     return ns_run<float>(w, x, y, info, iters, corr, st);
 }

@@ -7,8 +7,8 @@
 // whole-block LDS kernel for every block of order <= 64 (one workgroup per
 // block), the large-block jobs spread round-robin over K side streams (each
 // with its own workspace slot, so K jobs are in flight at once), and a join.
-// In FP64 mode a job is a lockstep group of same-order blocks (every launch
-// covers all its members); in the mixed modes a job is one block.  Executing a plan whose buffers were already captured is one
+// A job is a lockstep group of same-order blocks (every launch covers all its
+// members), in FP64 or mixed mode.  Executing a plan whose buffers were already captured is one
 // hipGraphLaunch on the caller's stream.  K is chosen by psd_plan_tune: it
 // replays the graph for each candidate, keeps the fastest and records it in a
 // small JSON-lines cache (PSD_TUNE_CACHE, default ./psdproj_tune.jsonl) keyed
@@ -30,9 +30,6 @@
 
 namespace psd {
 // defined in abi.hip
-hipError_t project_block_ext(int n, const double *x, double *y, psd_mode mode, void *ws, hipStream_t s,
-                             psd_dev_info *info);
-size_t block_ws_bytes(int n, psd_mode mode);
 hipError_t prepare_kernel_attributes();
 }  // namespace psd
 
@@ -96,7 +93,7 @@ struct psd_plan_s {
     size_t slot_bytes = 0;
     std::vector<SmallJob> small;
     SmallJob *dsmall = nullptr;
-    std::vector<GroupChunk> chunks;  // FP64 mode: lockstep groups
+    std::vector<GroupChunk> chunks;  // jobs: lockstep groups
     int64_t *dioff = nullptr;        // member svec offsets, chunk after chunk
     int *didx = nullptr;             // member block indices
     hipStream_t cap = nullptr;
@@ -117,25 +114,13 @@ hipError_t capture(psd_plan_s *p, const double *x, double *y, void *ws, psd_info
     for (int i = 0; i < K; ++i) chk(hipStreamWaitEvent(p->side[i], p->fork, 0));
     psd_dev_info *di = reinterpret_cast<psd_dev_info *>(infos);
     if (!p->small.empty()) chk(launch_small(p->dsmall, (int)p->small.size(), x, y, di, nullptr, p->cap));
-    if (p->mode == PSD_FP64_EIG) {
-        int pos = 0;
-        for (size_t ci = 0; ci < p->chunks.size(); ++ci) {
-            const int slot = (int)(ci % K), cnt = (int)p->chunks[ci].blocks.size();
-            char *wsl = static_cast<char *>(ws) + (size_t)slot * p->slot_bytes;
-            chk(project_group_ext(p->chunks[ci].n, cnt, x, y, p->dioff + pos, p->didx + pos, di, wsl,
-                                  p->side[slot]));
-            pos += cnt;
-        }
-    } else {
-        int li = 0;
-        for (size_t b = 0; b < p->n.size(); ++b) {
-            if (p->n[b] <= 64) continue;
-            const int slot = li % K;
-            char *wsl = static_cast<char *>(ws) + (size_t)slot * p->slot_bytes;
-            chk(project_block_ext(p->n[b], x + p->off[b], y + p->off[b], p->mode, wsl, p->side[slot],
-                                  di ? di + b : nullptr));
-            ++li;
-        }
+    int pos = 0;
+    for (size_t ci = 0; ci < p->chunks.size(); ++ci) {
+        const int slot = (int)(ci % K), cnt = (int)p->chunks[ci].blocks.size();
+        char *wsl = static_cast<char *>(ws) + (size_t)slot * p->slot_bytes;
+        chk(project_group_ext(p->chunks[ci].n, cnt, p->mode, x, y, p->dioff + pos, p->didx + pos, di, wsl,
+                              p->side[slot]));
+        pos += cnt;
     }
     for (int i = 0; i < K; ++i) {
         chk(hipEventRecord(p->join[i], p->side[i]));
@@ -172,19 +157,13 @@ psd_status psd_plan_create(int32_t nblocks, const int32_t *n, psd_mode mode, int
         p->n.push_back(n[b]);
         p->off.push_back(off);
         if (n[b] <= 64) p->small.push_back(SmallJob{off, 0, n[b], b});
-        else {
-            ++p->nlarge;
-            p->slot_bytes = std::max(p->slot_bytes, block_ws_bytes(n[b], mode));
-        }
         off += (int64_t)n[b] * n[b];
     }
-    if (mode == PSD_FP64_EIG) {
-        // jobs are lockstep groups
-        p->chunks = group_chunks(nblocks, n);
-        p->nlarge = (int)p->chunks.size();
-        p->slot_bytes = 0;
-        for (const auto &c : p->chunks) p->slot_bytes = std::max(p->slot_bytes, group_ws_bytes(c));
-    }
+    // jobs are lockstep groups
+    p->chunks = group_chunks(nblocks, n, mode);
+    p->nlarge = (int)p->chunks.size();
+    p->slot_bytes = 0;
+    for (const auto &c : p->chunks) p->slot_bytes = std::max(p->slot_bytes, group_ws_bytes(c, mode));
     p->slot_bytes = (p->slot_bytes + 255) / 256 * 256;
     int K = concurrency;
     if (K == 0) K = tune_lookup(tune_key(p->n, mode));

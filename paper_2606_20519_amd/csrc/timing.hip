@@ -47,7 +47,7 @@ psd_status psd_timing_start(int32_t family, int32_t max_launches) {
         return PSD_EINVAL;
     T.ev.assign(2 * (size_t)max_launches, nullptr);
     for (auto &e : T.ev)
-        if (hipEventCreate(&e) != hipSuccess) return PSD_EDEVICE;
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return PSD_EDEVICE;
     T.work.assign(max_launches, 0.0);
     T.max = max_launches;
     T.used = 0;

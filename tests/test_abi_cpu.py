@@ -58,18 +58,18 @@ def test_workspace_size_validation(L):
 
 
 def test_workspace_size_lockstep_groups(L):
-    """FP64 batched calls run same-order blocks in lockstep groups of at most
-    32, one workspace slot per member; the mixed modes keep one slot."""
+    """Batched calls run same-order blocks in lockstep groups of at most 32,
+    one workspace slot per member, in every mode."""
     lib = L.lib()
     out = ctypes.c_size_t(0)
-    assert lib.psd_workspace_size(1, L.int_array([625]), 0, 0, ctypes.byref(out)) == 0
-    one = out.value
-    assert lib.psd_workspace_size(32, L.int_array([625] * 32), 0, 0, ctypes.byref(out)) == 0
-    assert out.value >= 32 * (one - 512)
-    assert lib.psd_workspace_size(40, L.int_array([625] * 40), 0, 0, ctypes.byref(out)) == 0
-    assert out.value < 33 * one  # groups of at most 32 share the slots
-    assert lib.psd_workspace_size(32, L.int_array([625] * 32), 2, 0, ctypes.byref(out)) == 0
-    assert out.value < 2 * one
+    for mode in (0, 1, 2):
+        assert lib.psd_workspace_size(1, L.int_array([625]), mode, 0, ctypes.byref(out)) == 0
+        one = out.value
+        assert lib.psd_workspace_size(32, L.int_array([625] * 32), mode, 0, ctypes.byref(out)) == 0
+        assert out.value > 16 * one
+        g32 = out.value
+        assert lib.psd_workspace_size(40, L.int_array([625] * 40), mode, 0, ctypes.byref(out)) == 0
+        assert out.value < g32 + 4096  # groups of at most 32 share the slots
 
 
 def test_saved_size(L):

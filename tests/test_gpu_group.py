@@ -77,3 +77,23 @@ def test_cone_blocks_grouped(P):
         parts.append(x[off:off + m * m])
         off += m * m
     check_against_single(P, parts, sizes, oracle_every=9)
+
+
+@pytest.mark.parametrize("mode,tol", [("mixed_fp32", 3e-6), ("mixed_bf16", None)])
+def test_mixed_group_members_equal_single_blocks(P, mode, tol):
+    # the Newton-Schulz form grouped the same way: bitwise equal to single
+    # calls; error against the exact projection within the mixed bars
+    sizes = [96, 96, 80, 96]
+    parts = [W.constructed(m, 7200 + i, gap=1e-6)[0] for i, m in enumerate(sizes)]
+    y, infos = P.project_batched(dev(np.concatenate(parts)), sizes, mode, info=True)
+    y = y.cpu().numpy()
+    off = 0
+    for i, (m, s, inf) in enumerate(zip(sizes, parts, infos)):
+        single, sinf = P.project(dev(s), m, mode, info=True)
+        got = y[off:off + m * m]
+        assert np.array_equal(got, single.cpu().numpy()), (i, m)
+        assert inf == sinf, i
+        assert inf["status"] == 0
+        if tol is not None:
+            assert rel(got, oracle.project(s, m)) <= tol, (i, m)
+        off += m * m
