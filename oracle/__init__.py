@@ -207,35 +207,61 @@ def num_threads() -> int:
 # version of that recurrence (NumPy matmul as the only library step), used to
 # attribute the GPU mixed form's error to truncation versus rounding.
 
-def ns_scalar_map(t, iters: int):
+def ns_schedule(l0: float = 1e-6, tol: float = 1e-7, iters: int = None) -> list:
+    """Per-step scalings a_k of the scaled Newton-Schulz iteration
+    X_{k+1} = (a_k / 2) X_k (3I - a_k^2 X_k^2) (Chen and Chow, 2014).
+
+    The first step is unscaled (a_0 = 1): it maps any spectrum inside
+    (-sqrt 3, sqrt 3) into [-1, 1].  After it, with [l_k, 1] the bound on the
+    eigenvalue magnitudes (l_1 = f(l0), f(t) = (3t - t^3)/2),
+    a_k = sqrt(3 / (1 + l_k + l_k^2)) is the scaling for which f(a_k t) takes
+    the same value at both ends of the interval, and l_{k+1} = f(a_k l_k).
+    Without `iters` the schedule stops once 1 - l_k <= tol; with it, exactly
+    `iters` scalings are returned (a_k tends to 1 as l_k tends to 1)."""
+    def f(t):
+        return 0.5 * (3.0 * t - t ** 3)
+    a = [1.0]
+    lk = f(l0)
+    while (len(a) < iters) if iters is not None else (1.0 - lk > tol):
+        ak = float(np.sqrt(3.0 / (1.0 + lk + lk * lk)))
+        a.append(ak)
+        lk = f(ak * lk)
+    return a[:iters] if iters is not None else a
+
+
+def ns_scalar_map(t, iters: int, coeffs=None):
     """The scalar recurrence t <- 1.5 t - 0.5 t^3 applied `iters` times
-    (elementwise, float64)."""
+    (elementwise, float64); with `coeffs` (a_k, k < iters) the scaled step
+    t <- (3 a_k t - a_k^3 t^3) / 2."""
     t = np.asarray(t, dtype=np.float64).copy()
-    for _ in range(iters):
-        t = 1.5 * t - 0.5 * t ** 3
+    for k in range(iters):
+        a = 1.0 if coeffs is None else coeffs[k]
+        t = 0.5 * (3.0 * a * t - (a * t) ** 3)
     return t
 
 
-def ns_constructed_projection(u, lam, alpha: float, iters: int) -> np.ndarray:
+def ns_constructed_projection(u, lam, alpha: float, iters: int, coeffs=None) -> np.ndarray:
     """Exact-arithmetic Newton-Schulz projection of X = U diag(lam) U^H after
     `iters` steps: U diag((lam + lam p(lam/alpha))/2) U^H as svec, where p is
     the iterated scalar map.  Only per-eigenvalue arithmetic."""
     lam = np.asarray(lam, dtype=np.float64)
-    s = ns_scalar_map(lam / alpha, iters)
+    s = ns_scalar_map(lam / alpha, iters, coeffs)
     f = 0.5 * (lam + lam * s)
     u = np.asarray(u, dtype=np.complex128)
     return default().pack((u * f[None, :]) @ u.conj().T)
 
 
-def ns_matrix_projection(x_svec, n: int, alpha: float, iters: int) -> np.ndarray:
+def ns_matrix_projection(x_svec, n: int, alpha: float, iters: int, coeffs=None) -> np.ndarray:
     """FP64 Newton-Schulz projection by matrix products: X_0 = X/alpha,
-    X_{k+1} = X_k (3I - X_k^2)/2 for `iters` steps, then (X + X X_K)/2, whose
-    Hermitian part is returned as svec."""
+    X_{k+1} = (a_k/2) X_k (3I - a_k^2 X_k^2) for `iters` steps (a_k = 1
+    without `coeffs`), then (X + X X_K)/2, whose Hermitian part is returned
+    as svec."""
     x = default().unpack(x_svec, n)
     xk = x / alpha
     eye = np.eye(n)
-    for _ in range(iters):
-        xk = 0.5 * xk @ (3.0 * eye - xk @ xk)
+    for k in range(iters):
+        a = 1.0 if coeffs is None else coeffs[k]
+        xk = (0.5 * a) * xk @ (3.0 * eye - (a * a) * (xk @ xk))
     p = 0.5 * (x + x @ xk)
     return default().pack(0.5 * (p + p.conj().T))
 

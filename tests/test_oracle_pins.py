@@ -376,6 +376,65 @@ def test_ns_truncation_bounded_by_small_eigenvalues(orc):
         assert bound <= np.sqrt(np.sum(lam[np.abs(s) < 1 - 1e-12] ** 2)) + 1e-15
 
 
+def test_ns_schedule_equioscillation_and_start():
+    # a_0 = 1; afterwards each scaling makes f(a l) = f(a) (f(t) = (3t - t^3)/2)
+    # and the new lower bound is that common value
+    import oracle
+    a = oracle.ns_schedule(1e-6, 1e-7)
+    assert a[0] == 1.0
+    f = lambda t: 0.5 * (3.0 * t - t ** 3)
+    lk = f(1e-6)
+    for ak in a[1:]:
+        assert 1.0 <= ak <= np.sqrt(3.0)
+        assert abs(f(ak * lk) - f(ak)) <= 1e-15
+        lk = f(ak * lk)
+    assert 1.0 - lk <= 1e-7
+    # fewer than half the unscaled steps for the same resolution
+    t, k = 1e-6, 0
+    while 1.0 - t > 1e-7:
+        t, k = f(t), k + 1
+    assert len(a) <= k // 2
+    # explicit counts: the same prefix, then scalings tending to 1
+    assert oracle.ns_schedule(1e-6, iters=3) == a[:3]
+    long = oracle.ns_schedule(1e-6, iters=len(a) + 5)
+    assert long[:len(a)] == a and abs(long[-1] - 1.0) <= 1e-12
+
+
+def test_ns_schedule_maps_interval_brute_force():
+    # every magnitude in [l0, t*] ends within tol of 1 after the schedule and
+    # never above 1 + 1e-15; t* in (1, sqrt 3) solves f(t*) = f(l0), i.e.
+    # t*^2 + t* l0 + l0^2 = 3 (an alpha underestimated by up to t*)
+    import oracle
+    l0 = 1e-6
+    a = oracle.ns_schedule(l0, 1e-7)
+    tstar = 0.5 * (-l0 + np.sqrt(12.0 - 3.0 * l0 * l0))
+    t = np.concatenate([np.geomspace(l0, 1.0, 200001), np.linspace(1.0, tstar * (1 - 1e-12), 20001)])
+    s = oracle.ns_scalar_map(t, len(a), a)
+    assert s.min() >= 1.0 - 1e-7 and s.max() <= 1.0 + 1e-15
+    assert np.abs(oracle.ns_scalar_map(-t, len(a), a) + s).max() <= 1e-15  # odd map
+
+
+def test_ns_scaled_matrix_matches_scalar(orc):
+    # matrix products vs per-eigenvalue map (diagonal input and constructed U)
+    import oracle
+    a = oracle.ns_schedule(1e-6, iters=9)
+    d = np.array([0.9, -0.5, 1e-3, -2e-4, 0.3, 1.0])
+    n = len(d)
+    sx = orc.pack(np.diag(d).astype(complex))
+    got = orc.unpack(oracle.ns_matrix_projection(sx, n, 1.0, 9, a), n)
+    want = 0.5 * (d + d * oracle.ns_scalar_map(d, 9, a))
+    assert np.abs(np.diag(got).real - want).max() <= 1e-13 * np.abs(want).max()
+    assert np.abs(got - np.diag(np.diag(got))).max() == 0.0
+    sx, u, lam = W.constructed(24, 91, gap=1e-3)
+    for k in (4, 11):
+        ak = oracle.ns_schedule(1e-6, iters=k)
+        assert rel(oracle.ns_matrix_projection(sx, 24, 1.05, k, ak),
+                   oracle.ns_constructed_projection(u, lam, 1.05, k, ak)) <= 1e-12
+    full = oracle.ns_schedule(1e-6, 1e-7)
+    assert rel(oracle.ns_constructed_projection(u, lam, 1.05, len(full), full),
+               orc.constructed_projection(u, lam)) <= 1e-7
+
+
 def test_spectral_norm_pin(orc):
     import oracle
     sx, u, lam = W.constructed(20, 3)
