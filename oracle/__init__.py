@@ -207,25 +207,29 @@ def num_threads() -> int:
 # version of that recurrence (NumPy matmul as the only library step), used to
 # attribute the GPU mixed form's error to truncation versus rounding.
 
-def ns_schedule(l0: float = 1e-6, tol: float = 1e-7, iters: int = None) -> list:
+def ns_schedule(l0: float = 1e-6, tol: float = 1e-7, iters: int = None, amax: float = 1.5) -> list:
     """Per-step scalings a_k of the scaled Newton-Schulz iteration
-    X_{k+1} = (a_k / 2) X_k (3I - a_k^2 X_k^2) (Chen and Chow, 2014).
+    X_{k+1} = (a_k / 2) X_k (3I - a_k^2 X_k^2) (Chen and Chow, 2014), with
+    the scaling capped at `amax`.
 
     The first step is unscaled (a_0 = 1): it maps any spectrum inside
     (-sqrt 3, sqrt 3) into [-1, 1].  After it, with [l_k, 1] the bound on the
-    eigenvalue magnitudes (l_1 = f(l0), f(t) = (3t - t^3)/2),
-    a_k = sqrt(3 / (1 + l_k + l_k^2)) is the scaling for which f(a_k t) takes
-    the same value at both ends of the interval, and l_{k+1} = f(a_k l_k).
-    Without `iters` the schedule stops once 1 - l_k <= tol; with it, exactly
-    `iters` scalings are returned (a_k tends to 1 as l_k tends to 1)."""
+    eigenvalue magnitudes (l_1 = f(l0), f(t) = (3t - t^3)/2), the uncapped
+    choice sqrt(3 / (1 + l_k + l_k^2)) gives f(a t) equal values at both ends
+    of the interval; the cap keeps the top of the spectrum from being pushed
+    far down (f(sqrt 3) = 0), which in low precision costs accuracy when those
+    components grow back.  With a_k = min(amax, that value) the new bound is
+    l_{k+1} = min(f(a_k l_k), f(a_k)).  Without `iters` the schedule stops
+    once 1 - l_k <= tol; with it, exactly `iters` scalings are returned (a_k
+    tends to 1 as l_k tends to 1)."""
     def f(t):
         return 0.5 * (3.0 * t - t ** 3)
     a = [1.0]
     lk = f(l0)
     while (len(a) < iters) if iters is not None else (1.0 - lk > tol):
-        ak = float(np.sqrt(3.0 / (1.0 + lk + lk * lk)))
+        ak = min(amax, float(np.sqrt(3.0 / (1.0 + lk + lk * lk))))
         a.append(ak)
-        lk = f(ak * lk)
+        lk = min(f(ak * lk), f(ak))
     return a[:iters] if iters is not None else a
 
 

@@ -377,27 +377,38 @@ def test_ns_truncation_bounded_by_small_eigenvalues(orc):
 
 
 def test_ns_schedule_equioscillation_and_start():
-    # a_0 = 1; afterwards each scaling makes f(a l) = f(a) (f(t) = (3t - t^3)/2)
-    # and the new lower bound is that common value
+    # a_0 = 1; afterwards a_k = min(1.5, sqrt(3 / (1 + l + l^2))): below the
+    # cap f(a l) = f(a) (f(t) = (3t - t^3)/2), and the new lower bound is the
+    # smaller end value
     import oracle
     a = oracle.ns_schedule(1e-6, 1e-7)
     assert a[0] == 1.0
     f = lambda t: 0.5 * (3.0 * t - t ** 3)
     lk = f(1e-6)
     for ak in a[1:]:
-        assert 1.0 <= ak <= np.sqrt(3.0)
-        assert abs(f(ak * lk) - f(ak)) <= 1e-15
-        lk = f(ak * lk)
+        assert 1.0 <= ak <= 1.5
+        if ak < 1.5:
+            assert abs(f(ak * lk) - f(ak)) <= 1e-14  # f(sqrt 3) = 0: cancellation
+        else:
+            assert 1.5 <= np.sqrt(3.0 / (1.0 + lk + lk * lk))
+        lk = min(f(ak * lk), f(ak))
     assert 1.0 - lk <= 1e-7
-    # fewer than half the unscaled steps for the same resolution
+    # about half the unscaled steps for the same resolution
     t, k = 1e-6, 0
     while 1.0 - t > 1e-7:
         t, k = f(t), k + 1
-    assert len(a) <= k // 2
+    assert len(a) <= k // 2 + 2
     # explicit counts: the same prefix, then scalings tending to 1
     assert oracle.ns_schedule(1e-6, iters=3) == a[:3]
     long = oracle.ns_schedule(1e-6, iters=len(a) + 5)
     assert long[:len(a)] == a and abs(long[-1] - 1.0) <= 1e-12
+    # uncapped (amax >= sqrt 3): the pure equal-end scaling, fewer steps
+    un = oracle.ns_schedule(1e-6, 1e-7, amax=2.0)
+    lk = f(1e-6)
+    for ak in un[1:]:
+        assert abs(f(ak * lk) - f(ak)) <= 1e-14  # f(sqrt 3) = 0: cancellation
+        lk = min(f(ak * lk), f(ak))
+    assert len(un) < len(a)
 
 
 def test_ns_schedule_maps_interval_brute_force():
