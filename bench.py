@@ -51,9 +51,9 @@ def flops_eig(n: int, k: int) -> float:
 
 
 def flops_ns(n: int, iters: int, corr: int) -> float:
-    """Algorithmic real flops of one mixed projection: per iteration two
-    Hermitian products (lower half: 4 n^3 each), per FP64 correction two full
-    complex products (8 n^3 each), and the final product (lower half)."""
+    """Algorithmic real flops of one mixed projection: per Newton-Schulz step
+    two Hermitian products (lower half: 4 n^3 each), per FP64 correction two
+    full complex products (8 n^3 each), and the final product (lower half)."""
     return iters * 2 * 4.0 * n ** 3 + corr * 2 * 8.0 * n ** 3 + 4.0 * n ** 3
 
 
@@ -125,12 +125,18 @@ def main():
     stream = torch.cuda.current_stream(dev)
     wl = args.workload
     mode = args.mode or ("mixed_bf16" if wl == "c3" else "fp64")
-    iters, corr = 40, 2
-    P.set_ns_iterations(iters, corr)
+    extra = {}
+    corr = 2
+    P.set_ns_iterations(0, corr)  # automatic step count (scaled schedule)
+    iters = 0
+    if mode != "fp64":
+        _, inf = P.project(torch.from_numpy(W.gue(100, 1)).to(dev), 100, mode, info=True)
+        iters = inf["iters"]
+        extra["ns_steps"] = iters
+        extra["fp64_corrections"] = corr
 
     # ---- inputs (host, seeded) -> HBM
     plan = None
-    extra = {}
     if wl == "c2":
         n, count = 625, args.blocks
         xs_np = W.warm_sequence(n, 1002, count)

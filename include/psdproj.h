@@ -170,9 +170,13 @@ psd_status psd_timing_start(int32_t family, int32_t max_launches);
 psd_status psd_timing_stop(double *ms, int32_t *launches, double *work);
 
 /* Newton-Schulz settings of the mixed modes (process-wide; not
- * thread-safe): `iters` low-precision iterations (>= 1, default 40, enough for
- * eigenvalues down to about 1e-6 ||X||_2) and `corrections` FP64 correction
- * steps (>= 0, default 2).  Returns PSD_EINVAL outside 1..200 / 0..8. */
+ * thread-safe): `iters` low-precision steps of the scaled iteration
+ * X <- (a_k/2) X (3I - a_k^2 X^2) (a_0 = 1, then a_k = min(1.5,
+ * sqrt(3/(1+l+l^2))) for the current lower bound l of the scaled spectrum,
+ * starting from 1e-6); 0 (the default) = automatic, as many steps as bring l
+ * within 1e-7 of 1 (21): eigenvalues down to about 1e-6 ||X||_2 resolved.  `corrections`:
+ * FP64 correction steps (>= 0, default 2).  Returns PSD_EINVAL outside
+ * 0..200 / 0..8. */
 psd_status psd_set_ns_iterations(int32_t iters, int32_t corrections);
 
 /* Static description of a status code. */

@@ -27,8 +27,9 @@ _ws_cache: dict = {}
 INFO_WORDS = ctypes.sizeof(PsdInfo) // 4
 
 
-def set_ns_iterations(iters: int = 40, corrections: int = 2):
-    """Newton-Schulz iterations and FP64 correction steps of the mixed modes."""
+def set_ns_iterations(iters: int = 0, corrections: int = 2):
+    """Newton-Schulz steps (0: automatic, the scaled schedule's 21) and FP64
+    correction steps of the mixed modes."""
     _lib.set_ns_iterations(iters, corrections)
 
 

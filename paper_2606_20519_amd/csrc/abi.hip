@@ -56,7 +56,7 @@ size_t large_ws_bytes(int n, int mode, int flags) {
 
 bool is_mixed(int mode) { return mode == PSD_MIXED_BF16 || mode == PSD_MIXED_FP32; }
 
-int g_ns_iters = 40;
+int g_ns_iters = 0;  // automatic
 int g_ns_corr = 2;
 
 // Lockstep groups: blocks of one order n > 64 go through the path (FP64 or
@@ -198,7 +198,7 @@ extern "C" {
 const char *psd_version(void) { return "psdproj 0.1 (gfx950)"; }
 
 psd_status psd_set_ns_iterations(int32_t iters, int32_t corrections) {
-    if (iters < 1 || iters > 200 || corrections < 0 || corrections > 8) return PSD_EINVAL;
+    if (iters < 0 || iters > 200 || corrections < 0 || corrections > 8) return PSD_EINVAL;
     g_ns_iters = iters;
     g_ns_corr = corrections;
     return PSD_OK;

@@ -11,9 +11,13 @@
 //  * scale: alpha from a short FP64 Lanczos run (24 Hermitian mat-vecs, then
 //    the eigenvalues of the small tridiagonal by QL), alpha = 1.1 max|theta|;
 //  * X_0 = X/alpha rounded (RNE) to BF16 or FP32 planar complex;
-//  * K iterations, each two complex GEMMs on the MFMA cores with FP32
-//    accumulation: T = 3I - X_k^2, then X_{k+1} = X_k T / 2 (epilogues fused);
-//    the last product is kept in FP64;
+//  * K scaled iterations X_{k+1} = (a_k/2) X_k (3I - a_k^2 X_k^2) (Chen and
+//    Chow's scaled Newton-Schulz, scalings capped at 1.5: a_k from the known
+//    bound on the spectrum, 21 steps instead of 40 for the same resolution),
+//    each two complex GEMMs
+//    on the MFMA cores with FP32 accumulation: T = 3I - a_k^2 X_k^2, then
+//    X_{k+1} = (a_k/2) X_k T (scalings in the epilogues); the last product is
+//    kept in FP64;
 //  * c FP64 correction steps S <- S (3I - S^2)/2 (FP64 MFMA GEMMs), which
 //    square the error of every eigencomponent whose sign the low-precision
 //    iterations already resolved;
@@ -24,6 +28,8 @@
 // u ||X||: u = 2^-8 for BF16, 2^-24 for FP32) cannot be classified; their
 // contribution to the error is at most |lambda| each.
 #include <algorithm>
+#include <cmath>
+#include <vector>
 
 #include "common.h"
 #include "large.h"
@@ -222,8 +228,8 @@ enum { NS_EPI_T = 0, NS_EPI_HALF = 1, NS_EPI_F64 = 2 };
 template <typename L>
 __global__ void __launch_bounds__(256) ns_gemm_kernel(const L *__restrict__ Are, const L *__restrict__ Aim,
                                                       const L *__restrict__ Bre, const L *__restrict__ Bim, int npad,
-                                                      int epi, L *Cre, L *Cim, double2 *C64, int64_t ld64, int n,
-                                                      int64_t zs) {
+                                                      int epi, float c, L *Cre, L *Cim, double2 *C64, int64_t ld64,
+                                                      int n, int64_t zs) {
     constexpr bool BF = sizeof(L) == 2;
     {
         const int mb = blockIdx.z;
@@ -339,8 +345,8 @@ __global__ void __launch_bounds__(256) ns_gemm_kernel(const L *__restrict__ Are,
                 const int j = j0 + wn * 32 + b * 16 + (lane & 15);
                 if (i < j) continue;  // the mirror of (j, i) covers it
                 float re = accr[a][b][v], im = acci[a][b][v];
-                if (epi == NS_EPI_T) { re = (i == j ? 3.0f : 0.0f) - re; im = -im; }
-                else { re *= 0.5f; im *= 0.5f; }
+                if (epi == NS_EPI_T) { re = (i == j ? 3.0f : 0.0f) - c * re; im = -c * im; }
+                else { re *= c; im *= c; }
                 if (i == j) im = 0.0f;
                 if (epi != NS_EPI_F64) {
                     const L lr = to_low<L>(re), li = to_low<L>(im), lni = to_low<L>(-im);
@@ -403,9 +409,35 @@ __global__ void __launch_bounds__(256) ns_residual_final_kernel(const double *__
     }
 }
 
+// Scalings a_k of the scaled Newton-Schulz steps X <- (a/2) X (3I - a^2 X^2)
+// (Chen and Chow, 2014), capped at 1.5.  a_0 = 1 maps a spectrum inside
+// (-sqrt 3, sqrt 3) into [-1, 1]; then, with [l, 1] bounding the eigenvalue
+// magnitudes, a = min(1.5, sqrt(3 / (1 + l + l^2))) and
+// l <- min(f(a l), f(a)), f(t) = (3t - t^3)/2.  The uncapped value would
+// give f equal values at both ends, but it pushes the converged top of the
+// spectrum far down (f(sqrt 3) = 0), and its regrowth in low precision
+// amplifies rounding; the cap keeps the unscaled map's accuracy.  iters = 0:
+// as many steps as take l from 1e-6 to within 1e-7 of 1 (21, against 40
+// unscaled), i.e. eigenvalues down to 1e-6 alpha resolved.
+std::vector<double> ns_scalings(int iters) {
+    constexpr double l0 = 1e-6, tol = 1e-7, amax = 1.5;
+    auto cubic = [](double t) { return 0.5 * (3.0 * t - t * t * t); };
+    std::vector<double> a(1, 1.0);
+    double l = cubic(l0);
+    while (iters > 0 ? (int)a.size() < iters : (1.0 - l > tol && a.size() < 200)) {
+        const double s = std::min(amax, std::sqrt(3.0 / (1.0 + l + l * l)));
+        a.push_back(s);
+        l = std::min(cubic(s * l), cubic(s));
+    }
+    if (iters > 0) a.resize(iters);
+    return a;
+}
+
 template <typename L>
-hipError_t ns_run(const MixedWs &w, const double *x, double *y, psd_dev_info *info, int iters, int corr,
+hipError_t ns_run(const MixedWs &w, const double *x, double *y, psd_dev_info *info, int iters_req, int corr,
                   hipStream_t st) {
+    const std::vector<double> sc = ns_scalings(iters_req);
+    const int iters = (int)sc.size();
     const int n = w.n, npad = w.npad;
     const int64_t plane = (int64_t)npad * npad;
     L *X = reinterpret_cast<L *>(w.lo0), *T = reinterpret_cast<L *>(w.lo1), *X2 = reinterpret_cast<L *>(w.lo2);
@@ -420,12 +452,13 @@ hipError_t ns_run(const MixedWs &w, const double *x, double *y, psd_dev_info *in
     for (int k = 0; k < iters; ++k) {
         int slot = timing_begin(KF_NS, st);
         hipLaunchKernelGGL((ns_gemm_kernel<L>), gg, dim3(256), 0, st, X, X + plane, X, X + plane, npad, (int)NS_EPI_T,
-                           T, T + plane, (double2 *)nullptr, (int64_t)0, n, zs);
+                           (float)(sc[k] * sc[k]), T, T + plane, (double2 *)nullptr, (int64_t)0, n, zs);
         timing_end(slot, st, ns_flops);
         const bool last = k == iters - 1;
         slot = timing_begin(KF_NS, st);
         hipLaunchKernelGGL((ns_gemm_kernel<L>), gg, dim3(256), 0, st, X, X + plane, T, T + plane, npad,
-                           last ? (int)NS_EPI_F64 : (int)NS_EPI_HALF, X2, X2 + plane, w.S, w.lda, n, zs);
+                           last ? (int)NS_EPI_F64 : (int)NS_EPI_HALF, (float)(0.5 * sc[k]), X2, X2 + plane, w.S, w.lda,
+                           n, zs);
         timing_end(slot, st, ns_flops);
         std::swap(X, X2);
     }
@@ -518,7 +551,7 @@ size_t mixed_layout(int n, int mode, void *base, MixedWs *w) {
 hipError_t mixed_project(const MixedWs &w, int mode, const double *x, double *y, psd_dev_info *info, int iters,
                          int corr, hipStream_t st) {
     const int n = w.n;
-    if (iters < 1) iters = 1;
+    if (iters < 0) iters = 0;
     const int B = w.nmem;
     const int64_t zs = w.zs;
     hipLaunchKernelGGL(mx_init_kernel, dim3(1, 1, B), dim3(64), 0, st, w.status, zs);

@@ -32,7 +32,7 @@ def P():
     import torch
     assert torch.cuda.is_available()
     import paper_2606_20519_amd as P
-    P.set_ns_iterations(40, 2)
+    P.set_ns_iterations(0, 2)
     return P
 
 
@@ -45,16 +45,18 @@ def dev(a):
 @pytest.mark.parametrize("iters", [1, 2, 5])
 def test_ns_iterations_match_reference(P, mode, tol, iters):
     # No FP64 correction: the output is (X + X X_K)/2 with X_K from the
-    # low-precision iterations; the oracle runs the same recurrence in FP64
-    # with the same alpha (reported in info["scale"]).
+    # low-precision scaled iterations; the oracle runs the same recurrence
+    # (its own schedule of scalings) in FP64 with the same alpha (reported in
+    # info["scale"]).
     n = 96
     s = W.gue(n, 3500)
     P.set_ns_iterations(iters, 0)
     try:
         y, info = P.project(dev(s), n, mode=mode, info=True)
     finally:
-        P.set_ns_iterations(40, 2)
-    ref = oracle.ns_matrix_projection(s, n, info["scale"], iters)
+        P.set_ns_iterations(0, 2)
+    assert info["iters"] == iters
+    ref = oracle.ns_matrix_projection(s, n, info["scale"], iters, oracle.ns_schedule(iters=iters))
     err = rel(y.cpu().numpy(), ref)
     print(f"{mode} iters={iters}: rel err vs FP64 NS reference {err:.3e}", flush=True)
     assert err <= tol
