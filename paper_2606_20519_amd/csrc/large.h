@@ -54,6 +54,7 @@ struct LargeWs {
     double *lam;        // n final eigenvalues (ascending)
     double *Zfinal;     // n x n real eigenvectors of T (points at Q0 or Q1)
     int nchunk;         // split-K chunks for V^H Z
+    int kchunk;         // rows per chunk
     double2 *B1;        // n x n (ld n) derivative scratch (full layouts only)
     // lockstep group (every launch covers nmem blocks of this order; member b
     // uses the workspace slot b * zs bytes on, svec offset ioff[b] and info

@@ -21,7 +21,10 @@ namespace psd {
 namespace {
 
 constexpr int NB = LG_NB;
-constexpr int KCHUNK = 256;
+// Split-K chunk of V_b^H Z in the back-transform: 64 rows, more for large n
+// so that the partial sums stay at most 16 (the GEMM has only NB rows, so
+// the K split is where its parallelism comes from).
+inline int kchunk_for(int n) { return std::max(64, (n + 16 * 64 - 1) / (16 * 64) * 64); }
 
 inline size_t aup(size_t v) { return (v + 255) / 256 * 256; }
 
@@ -100,8 +103,14 @@ __global__ void __launch_bounds__(256) bt_tw_kernel(const double2 *__restrict__ 
     const int k = ksel[0];
     for (int idx = t; idx < NB * NB; idx += 256) Ts[idx % NB][idx / NB] = Tb[idx];
     double2 acc = cmk(0.0, 0.0);
-    if (c < k && i < kb)
-        for (int z = 0; z < nz; ++z) acc = cadd(acc, wpart[z * zstride + i + (int64_t)c * NB]);
+    if (c < k && i < kb) {
+        double2 pz[16];  // nz <= 16: every partial in flight at once
+#pragma unroll
+        for (int z = 0; z < 16; ++z) pz[z] = z < nz ? wpart[z * zstride + i + (int64_t)c * NB] : cmk(0.0, 0.0);
+#pragma unroll
+        for (int z = 0; z < 16; ++z) acc = cadd(acc, pz[z]);
+        for (int z = 16; z < nz; ++z) acc = cadd(acc, wpart[z * zstride + i + (int64_t)c * NB]);
+    }
     W1[i][cl] = acc;
     __syncthreads();
     if (c >= k) return;
@@ -167,7 +176,8 @@ size_t large_layout(int n, int flags, void *base, LargeWs *w) {
     L.npanel = (n - 1 + NB - 1) / NB;
     const bool full = (flags & 1) != 0;
     L.kmax = full ? n : n / 2 + 1;
-    L.nchunk = (n + KCHUNK - 1) / KCHUNK;
+    L.kchunk = kchunk_for(n);
+    L.nchunk = (n + L.kchunk - 1) / L.kchunk;
     const size_t cdsz = sizeof(double2), dsz = sizeof(double);
     L.M = (double2 *)take(cdsz * L.lda * n);
     L.W = (double2 *)take(cdsz * L.lda * NB);
@@ -234,7 +244,7 @@ hipError_t large_backtransform(const LargeWs &w, int ncols_max, hipStream_t st) 
         g.B = GemmOperand{w.Zc + (p0 + 1), w.Zc + (p0 + 1), w.lda, w.lda, mr, OP_N, nullptr};
         g.C = w.wpart; g.ldc = NB; g.alpha = 1.0; g.beta = 0.0;
         g.dN = w.ksel;
-        g.kchunk = KCHUNK; g.c_zstride = zstride;
+        g.kchunk = w.kchunk; g.c_zstride = zstride;
         g.nmem = w.nmem; g.zs = w.zs;
         hipError_t e = gemm_launch(g, true, EPI_STORE, st);
         if (e != hipSuccess) return e;
