@@ -72,7 +72,8 @@ typedef struct {
     int32_t iters;        /* NS iterations (mixed) or 0 */
     int32_t fallback;     /* 1 if a mixed request fell back to the FP64 path */
     int32_t reserved;
-    double est_rel_err;   /* mixed: ||I - S^2||_F / sqrt(n) of the sign estimate S; FP64: 0 */
+    double est_rel_err;   /* mixed: ||I - S^2||_F / sqrt(n) of the sign estimate S entering the
+                             last FP64 correction (the correction squares it); FP64: 0 */
     double scale;         /* mixed: spectral scale alpha (~1.1 ||X||_2); FP64: 0 */
 } psd_info;
 
@@ -173,10 +174,12 @@ psd_status psd_timing_stop(double *ms, int32_t *launches, double *work);
  * thread-safe): `iters` low-precision steps of the scaled iteration
  * X <- (a_k/2) X (3I - a_k^2 X^2) (a_0 = 1, then a_k = min(1.5,
  * sqrt(3/(1+l+l^2))) for the current lower bound l of the scaled spectrum,
- * starting from 1e-6); 0 (the default) = automatic, as many steps as bring l
- * within 1e-7 of 1 (21): eigenvalues down to about 1e-6 ||X||_2 resolved.  `corrections`:
- * FP64 correction steps (>= 0, default 2).  Returns PSD_EINVAL outside
- * 0..200 / 0..8. */
+ * starting from 1e-6); 0 (the default) = automatic, as many steps as bring
+ * l within 1e-7 of 1 (21): eigenvalues down to about 1e-6 ||X||_2 resolved.
+ * `corrections`: FP64 correction steps (>= 0, default 1: one squares the
+ * eigenvalue error of the resolved components to below the subspace error
+ * of the low-precision iterations, which no further step reduces).
+ * Returns PSD_EINVAL outside 0..200 / 0..8. */
 psd_status psd_set_ns_iterations(int32_t iters, int32_t corrections);
 
 /* Static description of a status code. */

@@ -27,7 +27,7 @@ _ws_cache: dict = {}
 INFO_WORDS = ctypes.sizeof(PsdInfo) // 4
 
 
-def set_ns_iterations(iters: int = 0, corrections: int = 2):
+def set_ns_iterations(iters: int = 0, corrections: int = 1):
     """Newton-Schulz steps (0: automatic, the scaled schedule's 21) and FP64
     correction steps of the mixed modes."""
     _lib.set_ns_iterations(iters, corrections)

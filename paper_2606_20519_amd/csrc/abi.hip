@@ -57,7 +57,7 @@ size_t large_ws_bytes(int n, int mode, int flags) {
 bool is_mixed(int mode) { return mode == PSD_MIXED_BF16 || mode == PSD_MIXED_FP32; }
 
 int g_ns_iters = 0;  // automatic
-int g_ns_corr = 2;
+int g_ns_corr = 1;
 
 // Lockstep groups: blocks of one order n > 64 go through the path (FP64 or
 // mixed) together, at most group_cap(n, mode) at a time (32, fewer where 32

@@ -56,6 +56,10 @@ struct GemmDesc {
     double diag_add;
     // EPI_SVEC: y = xscale*x + sign*acc (0 means 1, the default)
     double xscale;
+    // EPI_STORE of a Hermitian product (complex, lower_only, beta = 0): each
+    // lower entry is written with its conjugate mirror, diagonal imaginary
+    // parts zero, so the stored result is exactly Hermitian
+    int mirror;
     // Lockstep group of nmem problems (0 or 1: a single one): problem b uses
     // every pointer above moved by b * zs bytes, except y and xbase, which
     // move by ioff[b] elements (ioff null: not at all).

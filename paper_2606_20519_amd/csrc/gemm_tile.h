@@ -199,6 +199,13 @@ __device__ void gemm_tile(const GemmDesc &dd, int ti, int tj, int tz, GemmLds<T>
                 const int64_t idx = i + (int64_t)j * d.ldc;
                 if constexpr (CPLX) {
                     cd out = cmk(d.alpha * re + (i == j ? d.diag_add : 0.0), d.alpha * im);
+                    if (d.mirror) {
+                        if (i < j) continue;  // written as the mirror of (j, i)
+                        if (i == j) out.y = 0.0;
+                        *reinterpret_cast<cd *>(&C[idx]) = out;
+                        if (i != j) *reinterpret_cast<cd *>(&C[j + (int64_t)i * d.ldc]) = cconj(out);
+                        continue;
+                    }
                     if (d.beta != 0.0) {
                         const cd c0 = *reinterpret_cast<const cd *>(&C[idx]);
                         out = cmk(out.x + d.beta * c0.x, out.y + d.beta * c0.y);

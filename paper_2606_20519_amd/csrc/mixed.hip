@@ -18,9 +18,10 @@
 //    on the MFMA cores with FP32 accumulation: T = 3I - a_k^2 X_k^2, then
 //    X_{k+1} = (a_k/2) X_k T (scalings in the epilogues); the last product is
 //    kept in FP64;
-//  * c FP64 correction steps S <- S (3I - S^2)/2 (FP64 MFMA GEMMs), which
-//    square the error of every eigencomponent whose sign the low-precision
-//    iterations already resolved;
+//  * c FP64 correction steps S <- S (3I - S^2)/2 (FP64 MFMA GEMMs over the
+//    lower tiles, each written with its conjugate mirror: both products are
+//    Hermitian), which square the error of every eigencomponent whose sign
+//    the low-precision iterations already resolved;
 //  * Pi = X/2 + X S/2 by one FP64 GEMM over the lower tiles writing the svec;
 //    est_rel_err = ||I - S^2||_F / sqrt(n) of the S entering the last
 //    correction, n_pos from tr S.
@@ -445,21 +446,20 @@ hipError_t ns_run(const MixedWs &w, const double *x, double *y, psd_dev_info *in
     const int64_t zs = w.zs;
     dim3 sg((npad + 255) / 256, npad, B);
     hipLaunchKernelGGL((ns_scale_kernel<L>), sg, dim3(256), 0, st, w.M, w.lda, n, npad, w.alpha, X, X + plane, zs);
-    const int mt = npad / 64;
-    dim3 gg(mt * (mt + 1) / 2, 1, B);
+    const int mt = npad / 64, ntile = mt * (mt + 1) / 2;
+    dim3 gg(ntile, 1, B);
     // complex multiply-adds of the lower tiles actually computed, 8 flops each
-    const double ns_flops = 8.0 * 64.0 * 64.0 * (double)npad * (double)(mt * (mt + 1) / 2) * B;
+    const double ns_flops = 8.0 * 64.0 * 64.0 * (double)npad * (double)ntile * B;
+    auto product = [&](const L *A, const L *Bm, int epi, float cf, L *C, double2 *C64) {
+        const int slot = timing_begin(KF_NS, st);
+        hipLaunchKernelGGL((ns_gemm_kernel<L>), gg, dim3(256), 0, st, A, A + plane, Bm, Bm + plane, npad, epi, cf, C,
+                           C + plane, C64, w.lda, n, zs);
+        timing_end(slot, st, ns_flops);
+    };
     for (int k = 0; k < iters; ++k) {
-        int slot = timing_begin(KF_NS, st);
-        hipLaunchKernelGGL((ns_gemm_kernel<L>), gg, dim3(256), 0, st, X, X + plane, X, X + plane, npad, (int)NS_EPI_T,
-                           (float)(sc[k] * sc[k]), T, T + plane, (double2 *)nullptr, (int64_t)0, n, zs);
-        timing_end(slot, st, ns_flops);
+        product(X, X, (int)NS_EPI_T, (float)(sc[k] * sc[k]), T, (double2 *)nullptr);
         const bool last = k == iters - 1;
-        slot = timing_begin(KF_NS, st);
-        hipLaunchKernelGGL((ns_gemm_kernel<L>), gg, dim3(256), 0, st, X, X + plane, T, T + plane, npad,
-                           last ? (int)NS_EPI_F64 : (int)NS_EPI_HALF, (float)(0.5 * sc[k]), X2, X2 + plane, w.S, w.lda,
-                           n, zs);
-        timing_end(slot, st, ns_flops);
+        product(X, T, last ? (int)NS_EPI_F64 : (int)NS_EPI_HALF, (float)(0.5 * sc[k]), X2, w.S);
         std::swap(X, X2);
     }
     // FP64 corrections S <- S (3I - S^2) / 2
@@ -470,6 +470,7 @@ hipError_t ns_run(const MixedWs &w, const double *x, double *y, psd_dev_info *in
         a.A = GemmOperand{S, S, w.lda, w.lda, n, OP_N, nullptr};
         a.B = GemmOperand{S, S, w.lda, w.lda, n, OP_N, nullptr};
         a.C = w.T64; a.ldc = w.lda; a.alpha = -1.0; a.beta = 0.0; a.diag_add = 3.0;
+        a.lower_only = 1; a.mirror = 1;  // S^2 is Hermitian
         a.nmem = B; a.zs = zs;
         hipError_t e = gemm_launch(a, true, EPI_STORE, st);
         if (e != hipSuccess) return e;
@@ -478,6 +479,7 @@ hipError_t ns_run(const MixedWs &w, const double *x, double *y, psd_dev_info *in
         b.A = GemmOperand{S, S, w.lda, w.lda, n, OP_N, nullptr};
         b.B = GemmOperand{w.T64, w.T64, w.lda, w.lda, n, OP_N, nullptr};
         b.C = S2; b.ldc = w.lda; b.alpha = 0.5; b.beta = 0.0;
+        b.lower_only = 1; b.mirror = 1;  // S and 3I - S^2 commute: Hermitian product
         b.nmem = B; b.zs = zs;
         e = gemm_launch(b, true, EPI_STORE, st);
         if (e != hipSuccess) return e;
@@ -489,6 +491,7 @@ hipError_t ns_run(const MixedWs &w, const double *x, double *y, psd_dev_info *in
         a.A = GemmOperand{S, S, w.lda, w.lda, n, OP_N, nullptr};
         a.B = GemmOperand{S, S, w.lda, w.lda, n, OP_N, nullptr};
         a.C = w.T64; a.ldc = w.lda; a.alpha = -1.0; a.beta = 0.0; a.diag_add = 3.0;
+        a.lower_only = 1; a.mirror = 1;  // S^2 is Hermitian
         a.nmem = B; a.zs = zs;
         hipError_t e = gemm_launch(a, true, EPI_STORE, st);
         if (e != hipSuccess) return e;

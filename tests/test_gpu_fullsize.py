@@ -34,7 +34,7 @@ def P():
     import torch
     assert torch.cuda.is_available()
     import paper_2606_20519_amd as P
-    P.set_ns_iterations(0, 2)
+    P.set_ns_iterations(0, 1)
     return P
 
 

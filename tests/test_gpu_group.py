@@ -97,3 +97,20 @@ def test_mixed_group_members_equal_single_blocks(P, mode, tol):
         if tol is not None:
             assert rel(got, oracle.project(s, m)) <= tol, (i, m)
         off += m * m
+
+
+def test_mixed_bf16_group_big_tiles(P):
+    # 32 blocks of order 400 in BF16: the group's grid is large enough for the
+    # 128x128-tile product (a single block of this order takes the 64x64
+    # form, so here the members are checked against the closed form, not
+    # bitwise against single calls)
+    n, count = 400, 32
+    cons = [W.constructed(n, 7300 + i, gap=1e-3) for i in range(count)]
+    y, infos = P.project_batched(dev(np.concatenate([c[0] for c in cons])), [n] * count, "mixed_bf16", info=True)
+    y = y.cpu().numpy()
+    for i, ((s, u, lam), inf) in enumerate(zip(cons, infos)):
+        exact = oracle.constructed_projection(u, lam)
+        band = np.sqrt(np.sum(lam[np.abs(lam) < 0.03] ** 2))
+        err = np.linalg.norm(y[i * n * n:(i + 1) * n * n] - exact)
+        assert inf["status"] == 0, i
+        assert err <= 2.0 * band + 1e-9 * np.linalg.norm(exact), (i, err, band)

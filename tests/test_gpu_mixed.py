@@ -32,7 +32,7 @@ def P():
     import torch
     assert torch.cuda.is_available()
     import paper_2606_20519_amd as P
-    P.set_ns_iterations(0, 2)
+    P.set_ns_iterations(0, 1)
     return P
 
 
@@ -54,7 +54,7 @@ def test_ns_iterations_match_reference(P, mode, tol, iters):
     try:
         y, info = P.project(dev(s), n, mode=mode, info=True)
     finally:
-        P.set_ns_iterations(0, 2)
+        P.set_ns_iterations(0, 1)
     assert info["iters"] == iters
     ref = oracle.ns_matrix_projection(s, n, info["scale"], iters, oracle.ns_schedule(iters=iters))
     err = rel(y.cpu().numpy(), ref)
@@ -77,7 +77,9 @@ def test_mixed_fp32_gue(P, n):
     nrm2 = np.abs(lam).max()
     assert nrm2 <= info["scale"] <= 1.25 * nrm2
     assert info["n_pos"] == int((lam > 0).sum())
-    assert info["est_rel_err"] <= 1e-10
+    # ||I - S^2|| / sqrt(n) of the S entering the (one) FP64 correction: the
+    # FP32 iterate's residual; the correction squares it
+    assert info["est_rel_err"] <= 1e-5
 
 
 @pytest.mark.parametrize("n", [100, 200])
