@@ -55,6 +55,61 @@ struct GemmLds {
     T Bs[BK][BN + PAD];
 };
 
+// One k-slice of op(A) (rows i0.., BK columns from k0) and of op(B) (BK
+// rows from k0, columns j0..) into four registers per thread, zero outside
+// the problem; the matching stores put them in the LDS tiles As[k][i],
+// Bs[k][j].  The thread-to-element maps keep global reads coalesced.
+template <typename T, int OPA>
+__device__ __forceinline__ void gemm_load_a(const GemmDesc &d, int i0, int k0, T (&v)[4]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int i = OPA == OP_N ? (t & 63) : (t >> 4) + 16 * s;
+        const int k = OPA == OP_N ? (t >> 6) + 4 * s : (t & 15);
+        T x = zero_of(T());
+        if (i0 + i < d.M && k0 + k < d.K) {
+            x = op_elem<T, OPA, 1>(d.A, i0 + i, k0 + k);
+            if (d.A.kscale) x = scale_of(x, d.A.kscale[k0 + k]);
+        }
+        v[s] = x;
+    }
+}
+
+template <typename T, int OPA>
+__device__ __forceinline__ void gemm_store_a(T (&As)[BK][BM + PAD], const T (&v)[4]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int i = OPA == OP_N ? (t & 63) : (t >> 4) + 16 * s;
+        const int k = OPA == OP_N ? (t >> 6) + 4 * s : (t & 15);
+        As[k][i] = v[s];
+    }
+}
+
+template <typename T, int OPB>
+__device__ __forceinline__ void gemm_load_b(const GemmDesc &d, int j0, int k0, T (&v)[4]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int j = OPB == OP_N ? (t >> 4) + 16 * s : (t & 63);
+        const int k = OPB == OP_N ? (t & 15) : (t >> 6) + 4 * s;
+        T x = zero_of(T());
+        if (j0 + j < d.N && k0 + k < d.K) x = op_elem<T, OPB, 0>(d.B, k0 + k, j0 + j);
+        v[s] = x;
+    }
+}
+
+template <typename T, int OPB>
+__device__ __forceinline__ void gemm_store_b(T (&Bs)[BK][BN + PAD], const T (&v)[4]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int j = OPB == OP_N ? (t >> 4) + 16 * s : (t & 63);
+        const int k = OPB == OP_N ? (t & 15) : (t >> 6) + 4 * s;
+        Bs[k][j] = v[s];
+    }
+}
+
 template <typename T, int OPA, int OPB, int EPI>
 __device__ void gemm_tile(const GemmDesc &dd, int ti, int tj, int tz, GemmLds<T> &L) {
     auto &As = L.As;
@@ -84,54 +139,19 @@ __device__ void gemm_tile(const GemmDesc &dd, int ti, int tj, int tz, GemmLds<T>
             acc_i[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
         }
 
+    // The next k-slice is loaded into registers while the current one feeds
+    // the MFMAs, then stored to LDS: global latency overlaps the products.
+    T av[4], bv[4];
+    gemm_load_a<T, OPA>(d, i0, kbeg, av);
+    gemm_load_b<T, OPB>(d, j0, kbeg, bv);
     for (int k0 = kbeg; k0 < d.K; k0 += BK) {
-        // ---- A tile: op(A)[i0 + i][k0 + k]
-        if (OPA == OP_N) {
-            const int i = t & 63;
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int k = (t >> 6) + 4 * s;
-                T v = zero_of(T());
-                if (i0 + i < d.M && k0 + k < d.K) {
-                    v = op_elem<T, OP_N, 1>(d.A, i0 + i, k0 + k);
-                    if (d.A.kscale) v = scale_of(v, d.A.kscale[k0 + k]);
-                }
-                As[k][i] = v;
-            }
-        } else {
-            const int k = t & 15;
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int i = (t >> 4) + 16 * s;
-                T v = zero_of(T());
-                if (i0 + i < d.M && k0 + k < d.K) {
-                    v = op_elem<T, OP_C, 1>(d.A, i0 + i, k0 + k);
-                    if (d.A.kscale) v = scale_of(v, d.A.kscale[k0 + k]);
-                }
-                As[k][i] = v;
-            }
-        }
-        // ---- B tile: op(B)[k0 + k][j0 + j]
-        if (OPB == OP_N) {
-            const int k = t & 15;
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int j = (t >> 4) + 16 * s;
-                T v = zero_of(T());
-                if (j0 + j < d.N && k0 + k < d.K) v = op_elem<T, OP_N, 0>(d.B, k0 + k, j0 + j);
-                Bs[k][j] = v;
-            }
-        } else {
-            const int j = t & 63;
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int k = (t >> 6) + 4 * s;
-                T v = zero_of(T());
-                if (j0 + j < d.N && k0 + k < d.K) v = op_elem<T, OP_C, 0>(d.B, k0 + k, j0 + j);
-                Bs[k][j] = v;
-            }
-        }
+        gemm_store_a<T, OPA>(As, av);
+        gemm_store_b<T, OPB>(Bs, bv);
         __syncthreads();
+        if (k0 + BK < d.K) {
+            gemm_load_a<T, OPA>(d, i0, k0 + BK, av);
+            gemm_load_b<T, OPB>(d, j0, k0 + BK, bv);
+        }
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 4) {
             const int kr = ks + (lane >> 4), ii = lane & 15;
