@@ -215,6 +215,32 @@ __global__ void __launch_bounds__(256) ns_scale_kernel(const double2 *__restrict
 
 enum { NS_EPI_T = 0, NS_EPI_HALF = 1, NS_EPI_F64 = 2 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2), so workgroup g runs on XCD g % 8.  This maps the workgroups of each
+// XCD to a contiguous run of tiles (in the row-major lower-triangle order,
+// consecutive tiles share the A panel and nearby B panels), a bijection
+// onto 0..T-1: XCD x takes T/8 tiles (one more for x < T % 8).
+__device__ __forceinline__ int xcd_tile(int g, int T) {
+    const int per = T >> 3, rem = T & 7, x = g & 7, idx = g >> 3;
+    return x * per + min(x, rem) + idx;
+}
+
+// NQ 16-byte chunks of each plane of A (at ao) and B (at bo).
+template <typename L, int NQ>
+__device__ __forceinline__ void ns_load_chunks(const L *__restrict__ Are, const L *__restrict__ Aim,
+                                               const L *__restrict__ Bre, const L *__restrict__ Bim, int64_t ao,
+                                               int64_t bo, uint4 (&xr)[NQ], uint4 (&xi)[NQ], uint4 (&yr)[NQ],
+                                               uint4 (&yi)[NQ]) {
+    constexpr int E = 16 / (int)sizeof(L);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        xr[q] = *reinterpret_cast<const uint4 *>(Are + ao + q * E);
+        xi[q] = *reinterpret_cast<const uint4 *>(Aim + ao + q * E);
+        yr[q] = *reinterpret_cast<const uint4 *>(Bre + bo + q * E);
+        yi[q] = *reinterpret_cast<const uint4 *>(Bim + bo + q * E);
+    }
+}
+
 // C = A B for Hermitian A, B that commute (polynomials in the same X), so C
 // is Hermitian: only the lower tiles (ti >= tj) are computed, and each is
 // written together with its conjugate mirror, which keeps every iterate
@@ -244,7 +270,7 @@ __global__ void __launch_bounds__(256) ns_gemm_kernel(const L *__restrict__ Are,
     }
     constexpr int KP = 32 + (BF ? 8 : 4);  // padded k extent in LDS
     __shared__ __align__(16) L sAr[64][KP], sAi[64][KP], sBr[64][KP], sBi[64][KP];
-    const int tb = blockIdx.x;
+    const int tb = xcd_tile(blockIdx.x, gridDim.x);
     int ti = (int)((sqrt(8.0 * tb + 1.0) - 1.0) * 0.5);
     while ((ti + 1) * (ti + 2) / 2 <= tb) ++ti;
     while (ti * (ti + 1) / 2 > tb) --ti;
@@ -256,33 +282,42 @@ __global__ void __launch_bounds__(256) ns_gemm_kernel(const L *__restrict__ Are,
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) { accr[a][b] = v4f{0, 0, 0, 0}; acci[a][b] = v4f{0, 0, 0, 0}; }
-    // loader: thread t covers row (t/4) of the tile, k = 8*(t%4) .. +7
+    // loader: thread t covers row (t/4) of the tile, k = 8*(t%4) .. +7.
+    // BF16: one 16-byte chunk per plane, and the next k-slice is loaded into
+    // registers while the current one feeds the MFMAs.  FP32: loaded per
+    // slice (the prefetch spills registers there).
     const int lr = t >> 2, lk = (t & 3) * 8;
+    uint4 xr[1], xi[1], yr[1], yi[1];
+    if constexpr (BF)
+        ns_load_chunks<L, 1>(Are, Aim, Bre, Bim, (int64_t)lk + (int64_t)(i0 + lr) * npad,
+                             (int64_t)lk + (int64_t)(j0 + lr) * npad, xr, xi, yr, yi);
     for (int k0 = 0; k0 < npad; k0 += 32) {
-        {
+        if constexpr (BF) {
+            uint4 ai = xi[0];
+            ai.x ^= 0x80008000u; ai.y ^= 0x80008000u; ai.z ^= 0x80008000u; ai.w ^= 0x80008000u;  // conj
+            *reinterpret_cast<uint4 *>(&sAr[lr][lk]) = xr[0];
+            *reinterpret_cast<uint4 *>(&sAi[lr][lk]) = ai;
+            *reinterpret_cast<uint4 *>(&sBr[lr][lk]) = yr[0];
+            *reinterpret_cast<uint4 *>(&sBi[lr][lk]) = yi[0];
+        } else {
             const int64_t ao = (int64_t)(k0 + lk) + (int64_t)(i0 + lr) * npad;
             const int64_t bo = (int64_t)(k0 + lk) + (int64_t)(j0 + lr) * npad;
-            if constexpr (BF) {
-                const uint4 ar = *reinterpret_cast<const uint4 *>(Are + ao);
-                uint4 ai = *reinterpret_cast<const uint4 *>(Aim + ao);
-                ai.x ^= 0x80008000u; ai.y ^= 0x80008000u; ai.z ^= 0x80008000u; ai.w ^= 0x80008000u;  // conj
-                *reinterpret_cast<uint4 *>(&sAr[lr][lk]) = ar;
-                *reinterpret_cast<uint4 *>(&sAi[lr][lk]) = ai;
-                *reinterpret_cast<uint4 *>(&sBr[lr][lk]) = *reinterpret_cast<const uint4 *>(Bre + bo);
-                *reinterpret_cast<uint4 *>(&sBi[lr][lk]) = *reinterpret_cast<const uint4 *>(Bim + bo);
-            } else {
 #pragma unroll
-                for (int h = 0; h < 8; h += 4) {
-                    const float4 ar = *reinterpret_cast<const float4 *>(Are + ao + h);
-                    const float4 ai = *reinterpret_cast<const float4 *>(Aim + ao + h);
-                    *reinterpret_cast<float4 *>(&sAr[lr][lk + h]) = ar;
-                    *reinterpret_cast<float4 *>(&sAi[lr][lk + h]) = make_float4(-ai.x, -ai.y, -ai.z, -ai.w);
-                    *reinterpret_cast<float4 *>(&sBr[lr][lk + h]) = *reinterpret_cast<const float4 *>(Bre + bo + h);
-                    *reinterpret_cast<float4 *>(&sBi[lr][lk + h]) = *reinterpret_cast<const float4 *>(Bim + bo + h);
-                }
+            for (int h = 0; h < 8; h += 4) {
+                const float4 ar = *reinterpret_cast<const float4 *>(Are + ao + h);
+                const float4 ai = *reinterpret_cast<const float4 *>(Aim + ao + h);
+                *reinterpret_cast<float4 *>(&sAr[lr][lk + h]) = ar;
+                *reinterpret_cast<float4 *>(&sAi[lr][lk + h]) = make_float4(-ai.x, -ai.y, -ai.z, -ai.w);
+                *reinterpret_cast<float4 *>(&sBr[lr][lk + h]) = *reinterpret_cast<const float4 *>(Bre + bo + h);
+                *reinterpret_cast<float4 *>(&sBi[lr][lk + h]) = *reinterpret_cast<const float4 *>(Bim + bo + h);
             }
         }
         __syncthreads();
+        if constexpr (BF) {
+            const int kn = k0 + 32 < npad ? k0 + 32 : k0;  // the last slice again at the end: no branch
+            ns_load_chunks<L, 1>(Are, Aim, Bre, Bim, (int64_t)(kn + lk) + (int64_t)(i0 + lr) * npad,
+                                 (int64_t)(kn + lk) + (int64_t)(j0 + lr) * npad, xr, xi, yr, yi);
+        }
         const int ii = lane & 15, kg = lane >> 4;
         if constexpr (BF) {
             v8bf ar[2], ai[2], ain[2], br[2], bi[2];
