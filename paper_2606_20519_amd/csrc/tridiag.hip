@@ -283,8 +283,10 @@ __device__ void w_rows(double2 *M, int64_t lda, int n, int j, int mt, int nt, co
     const int r = t & 63, g = t >> 6;
     const int row = s + I * TT + r;
     const bool rowok = row < n;
-    // The global loads are issued in two groups ahead of their use (the
-    // stores below could alias them, so the compiler would not hoist them).
+    // Every global load is issued here, ahead of its use (the stores below
+    // could alias them, so the compiler would not hoist them): one memory
+    // round trip.  At most mt <= 64 workgroups run, so the registers this
+    // takes cost no occupancy.
     const double2 tj = taus[j];
     double2 pqv[NB / 2];  // p (q < c) / q (q >= c) partials of column q = g + 4k, row blocks on the lanes
 #pragma unroll
@@ -308,30 +310,6 @@ __device__ void w_rows(double2 *M, int64_t lda, int n, int j, int mt, int nt, co
         const int idx = t + 256 * k;
         tlv[k] = (I == 0 && idx < c * c) ? Tb[(idx % c) + (idx / c) * NB] : cmk(0.0, 0.0);
     }
-    // p = V^H v, q = W^H v
-    {
-        double pv[NB];  // {re, im} of column g + 4k at 2k, 2k + 1
-#pragma unroll
-        for (int k = 0; k < NB / 2; ++k) {
-            pv[2 * k] = pqv[k].x;
-            pv[2 * k + 1] = pqv[k].y;
-        }
-        const double sum = wave_sum_split(pv);  // lane l: value l / 2
-        const int q = g + 4 * (r >> 2);
-        if ((r & 1) == 0 && q < 2 * c)
-            (q < c ? reinterpret_cast<double *>(pS) + 2 * q : reinterpret_cast<double *>(qS) + 2 * (q - c))[(r >> 1) & 1] =
-                sum;
-    }
-    if (next_in_panel && t >= 64 && t < 64 + c) {
-        Ws[t - 64] = wsv;
-        Vs[t - 64] = vsv;
-    }
-#pragma unroll
-    for (int k = 0; k < NB * NB / 256; ++k) {
-        const int idx = t + 256 * k;
-        if (I == 0 && idx < c * c) Tl[idx % c][idx / c] = tlv[k];
-    }
-    __builtin_amdgcn_sched_barrier(0);  // second group of loads (one group would spill)
     // (fixed-length unrolled chunks: a loop with a data-dependent trip count
     // would wait for each load before issuing the next)
     double part = 0.0;  // 256 threads
@@ -368,6 +346,29 @@ __device__ void w_rows(double2 *M, int64_t lda, int n, int j, int mt, int nt, co
     if (t < TT && rowok) {
         vrow = vbuf[row];
         if (next_in_panel) mnext = M[row + (int64_t)(j + 1) * lda];
+    }
+    // p = V^H v, q = W^H v
+    {
+        double pv[NB];  // {re, im} of column g + 4k at 2k, 2k + 1
+#pragma unroll
+        for (int k = 0; k < NB / 2; ++k) {
+            pv[2 * k] = pqv[k].x;
+            pv[2 * k + 1] = pqv[k].y;
+        }
+        const double sum = wave_sum_split(pv);  // lane l: value l / 2
+        const int q = g + 4 * (r >> 2);
+        if ((r & 1) == 0 && q < 2 * c)
+            (q < c ? reinterpret_cast<double *>(pS) + 2 * q : reinterpret_cast<double *>(qS) + 2 * (q - c))[(r >> 1) & 1] =
+                sum;
+    }
+    if (next_in_panel && t >= 64 && t < 64 + c) {
+        Ws[t - 64] = wsv;
+        Vs[t - 64] = vsv;
+    }
+#pragma unroll
+    for (int k = 0; k < NB * NB / 256; ++k) {
+        const int idx = t + 256 * k;
+        if (I == 0 && idx < c * c) Tl[idx % c][idx / c] = tlv[k];
     }
     const double vAv = block_sum(part, red);  // barriers: pS/qS/Ws/Vs/Tl visible after it
     // Re q^H p: lanes over the panel columns (every wave, same order)
