@@ -203,6 +203,12 @@ def main():
         flops_step = sum(flops_ns(m, iters, corr) for m in sizes if m > 64)
 
     if wl == "c4":
+        # the autotuner picks the group size and the concurrency (outside
+        # timing; its cache goes to a temporary file unless PSD_TUNE_CACHE is set)
+        if not os.environ.get("PSD_TUNE_CACHE"):
+            import tempfile
+            os.environ["PSD_TUNE_CACHE"] = os.path.join(tempfile.gettempdir(), "psdproj_bench_tune.jsonl")
+        plan.tune(X, Y, reps=2, max_concurrency=8)
         plan.execute(X, out=Y)   # capture outside timing
     for _ in range(args.warmup):
         step()
@@ -352,6 +358,7 @@ def main():
     }
     if plan is not None:
         out["config"]["concurrency"] = plan.concurrency
+        out["config"]["group_size"] = plan.group_size
         plan.close()
     print(json.dumps(out), flush=True)
 

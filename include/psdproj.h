@@ -122,15 +122,19 @@ psd_status psd_project_vjp(int32_t n, const double *x, const double *saved,
 /* Plans: every block of one cone (e.g. per instance one W block of order
  * d^4 and eight instrument Choi blocks of order d^2), projected by ONE
  * hipGraph launch.  The graph holds the whole-block LDS kernel for all blocks
- * of order <= 64 and the large blocks spread over `concurrency` streams (each
- * with its own workspace slot), fork/join by events; it is captured on a
+ * of order <= 64 and the large blocks as jobs spread over `concurrency`
+ * streams (each with its own workspace slot), fork/join by events.  A job is
+ * a lockstep group: up to 32 blocks of one order (fewer where their
+ * workspace would pass 4 GiB, or the group size the autotuner chose) that
+ * share every kernel launch.  The graph is captured on a
  * stream the plan owns the first time a given (x, y, ws, infos) is executed
  * and replayed afterwards.  Creation allocates (streams, events, a device
  * copy of the block table); execution does not, apart from the one-time
  * capture and instantiation of a new graph.  concurrency = 0 takes the value
  * psd_plan_tune last recorded for this arch/mode/size list in the tuning
- * cache (file PSD_TUNE_CACHE, default ./psdproj_tune.jsonl), else 4; it is
- * clamped to [1, number of blocks of order > 64].  Mixed modes use the
+ * cache (file PSD_TUNE_CACHE, default ./psdproj_tune.jsonl), else 4; the
+ * group size recorded there is used as well.  Concurrency is clamped to
+ * [1, number of jobs].  Mixed modes use the
  * Newton-Schulz settings current at capture time.  A plan is not
  * thread-safe; execute it on one host thread. */
 typedef struct psd_plan_s *psd_plan;
@@ -141,13 +145,18 @@ psd_status psd_plan_create(int32_t nblocks, const int32_t *n /* host */, psd_mod
 psd_status psd_plan_workspace_size(psd_plan plan, int32_t concurrency, size_t *bytes);
 /* The plan's current concurrency. */
 int32_t psd_plan_concurrency(psd_plan plan);
+/* Members of the plan's largest lockstep group (0 without large blocks). */
+int32_t psd_plan_group_size(psd_plan plan);
 /* y <- the blocks of x projected (layout as psd_project_batched); infos:
  * nullable, one record per block. */
 psd_status psd_plan_execute(psd_plan plan, const double *x, double *y, void *ws, size_t ws_bytes,
                             void *stream, psd_info *infos);
-/* Autotuner: times `reps` replays for concurrency 1, 2, 4, ... and the
- * number of large blocks (each that fits in ws_bytes), keeps the fastest in
- * the plan, appends it to the tuning cache and returns it in *best. */
+/* Autotuner: for the group sizes 32 (or the memory-derived limit), 16 and 8
+ * (those that split the blocks differently) and, for each, concurrency 1, 2,
+ * 4, ... and the number of jobs (each that fits in ws_bytes), times `reps`
+ * replays; keeps the fastest pair in the plan, appends it to the tuning cache
+ * and returns the concurrency in *best (the group size:
+ * psd_plan_group_size).  Synchronises the stream. */
 psd_status psd_plan_tune(psd_plan plan, const double *x, double *y, void *ws, size_t ws_bytes,
                          void *stream, int32_t reps, int32_t *best);
 psd_status psd_plan_destroy(psd_plan plan);

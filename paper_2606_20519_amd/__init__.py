@@ -185,6 +185,12 @@ class Plan:
     def concurrency(self) -> int:
         return int(_lib.lib().psd_plan_concurrency(self._h))
 
+    @property
+    def group_size(self) -> int:
+        """Members of the largest lockstep group (same-order blocks sharing
+        every launch)."""
+        return int(_lib.lib().psd_plan_group_size(self._h))
+
     def workspace(self, concurrency: int = 0) -> torch.Tensor:
         nb = ctypes.c_size_t(0)
         check(_lib.lib().psd_plan_workspace_size(self._h, concurrency, ctypes.byref(nb)), "psd_plan_workspace_size")

@@ -76,12 +76,12 @@ int group_cap(int n, int mode) {
 
 // The large blocks of a call split into groups (same order, in order of
 // first appearance, each at most group_cap members).
-std::vector<psd::GroupChunk> make_chunks(int nblocks, const int32_t *n, int mode) {
+std::vector<psd::GroupChunk> make_chunks(int nblocks, const int32_t *n, int mode, int max_group = 0) {
     std::vector<psd::GroupChunk> out;
     std::vector<int> done(nblocks, 0);
     for (int b = 0; b < nblocks; ++b) {
         if (n[b] <= 64 || done[b]) continue;
-        const int cap = group_cap(n[b], mode);
+        const int cap = max_group > 0 ? std::min(max_group, group_cap(n[b], mode)) : group_cap(n[b], mode);
         psd::GroupChunk cur{n[b], {}};
         for (int c = b; c < nblocks; ++c) {
             if (n[c] != n[b] || done[c]) continue;
@@ -178,7 +178,9 @@ hipError_t project_block(int n, const double *x, double *y, psd_mode mode, void 
 
 namespace psd {
 
-std::vector<GroupChunk> group_chunks(int nblocks, const int32_t *n, int mode) { return make_chunks(nblocks, n, mode); }
+std::vector<GroupChunk> group_chunks(int nblocks, const int32_t *n, int mode, int max_group) {
+    return make_chunks(nblocks, n, mode, max_group);
+}
 size_t group_ws_bytes(const GroupChunk &c, int mode) { return chunk_ws_bytes(c, mode); }
 hipError_t project_group_ext(int n, int nmem, psd_mode mode, const double *x, double *y, const int64_t *ioff,
                              const int *infoidx, psd_dev_info *infos, void *ws, hipStream_t s) {

@@ -87,7 +87,8 @@ struct GroupChunk {
     int n;
     std::vector<int> blocks;  // block indices, in member order
 };
-std::vector<GroupChunk> group_chunks(int nblocks, const int32_t *n, int mode);
+// max_group > 0 caps the members per group below the memory-derived limit.
+std::vector<GroupChunk> group_chunks(int nblocks, const int32_t *n, int mode, int max_group = 0);
 size_t group_ws_bytes(const GroupChunk &c, int mode);
 hipError_t project_group_ext(int n, int nmem, psd_mode mode, const double *x, double *y, const int64_t *ioff,
                              const int *infoidx, psd_dev_info *infos, void *ws, hipStream_t s);

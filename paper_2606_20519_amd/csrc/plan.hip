@@ -45,6 +45,7 @@ struct GraphEntry {
     void *ws;
     psd_info *infos;
     int K;
+    int group;
     hipGraphExec_t exec;
 };
 
@@ -59,26 +60,29 @@ const char *tune_path() {
     return (p && *p) ? p : "psdproj_tune.jsonl";
 }
 
-// Last recorded concurrency for `key`, or 0.
-int tune_lookup(const std::string &key) {
+// Last recorded concurrency and group size for `key` (0 where none).
+void tune_lookup(const std::string &key, int *K, int *group) {
+    *K = 0;
+    *group = 0;
     FILE *f = std::fopen(tune_path(), "r");
-    if (!f) return 0;
+    if (!f) return;
     char line[1 << 14];
-    int best = 0;
     const std::string pat = "\"key\": \"" + key + "\"";
     while (std::fgets(line, sizeof line, f)) {
         if (!std::strstr(line, pat.c_str())) continue;
         const char *c = std::strstr(line, "\"concurrency\": ");
-        if (c) best = std::atoi(c + 15);
+        const char *g = std::strstr(line, "\"group\": ");
+        *K = c ? std::atoi(c + 15) : 0;
+        *group = g ? std::atoi(g + 9) : 0;
     }
     std::fclose(f);
-    return best;
 }
 
-void tune_record(const std::string &key, int K, double ms) {
+void tune_record(const std::string &key, int K, int group, double ms) {
     FILE *f = std::fopen(tune_path(), "a");
     if (!f) return;
-    std::fprintf(f, "{\"key\": \"%s\", \"concurrency\": %d, \"ms\": %.6f}\n", key.c_str(), K, ms);
+    std::fprintf(f, "{\"key\": \"%s\", \"concurrency\": %d, \"group\": %d, \"ms\": %.6f}\n", key.c_str(), K,
+                 group, ms);
     std::fclose(f);
 }
 
@@ -94,6 +98,7 @@ struct psd_plan_s {
     std::vector<SmallJob> small;
     SmallJob *dsmall = nullptr;
     std::vector<GroupChunk> chunks;  // jobs: lockstep groups
+    int group = 0;                   // members per group at most (0: the memory-derived limit)
     int64_t *dioff = nullptr;        // member svec offsets, chunk after chunk
     int *didx = nullptr;             // member block indices
     hipStream_t cap = nullptr;
@@ -136,8 +141,41 @@ hipError_t capture(psd_plan_s *p, const double *x, double *y, void *ws, psd_info
 
 hipGraphExec_t find_graph(psd_plan_s *p, const double *x, double *y, void *ws, psd_info *infos, int K) {
     for (auto &g : p->graphs)
-        if (g.x == x && g.y == y && g.ws == ws && g.infos == infos && g.K == K) return g.exec;
+        if (g.x == x && g.y == y && g.ws == ws && g.infos == infos && g.K == K && g.group == p->group) return g.exec;
     return nullptr;
+}
+
+// (Re)split the large blocks into lockstep groups of at most `group`
+// members (0: the memory-derived limit) and refill the device tables, whose
+// size (one entry per large block) does not depend on the split.
+bool set_jobs(psd_plan_s *p, int group) {
+    p->group = group;
+    p->chunks = group_chunks((int)p->n.size(), p->n.data(), p->mode, group);
+    p->nlarge = (int)p->chunks.size();
+    p->slot_bytes = 0;
+    for (const auto &c : p->chunks) p->slot_bytes = std::max(p->slot_bytes, group_ws_bytes(c, p->mode));
+    p->slot_bytes = (p->slot_bytes + 255) / 256 * 256;
+    if (p->chunks.empty()) return true;
+    std::vector<int64_t> hoff;
+    std::vector<int> hidx;
+    for (const auto &c : p->chunks)
+        for (int b : c.blocks) {
+            hoff.push_back(p->off[b]);
+            hidx.push_back(b);
+        }
+    if (!p->dioff &&
+        (hipMalloc(&p->dioff, hoff.size() * sizeof(int64_t)) != hipSuccess ||
+         hipMalloc(&p->didx, hidx.size() * sizeof(int)) != hipSuccess))
+        return false;
+    return hipMemcpy(p->dioff, hoff.data(), hoff.size() * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess &&
+           hipMemcpy(p->didx, hidx.data(), hidx.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
+}
+
+// Largest group of the current split.
+int max_members(const psd_plan_s *p) {
+    size_t m = 0;
+    for (const auto &c : p->chunks) m = std::max(m, c.blocks.size());
+    return (int)m;
 }
 
 }  // namespace
@@ -159,17 +197,18 @@ psd_status psd_plan_create(int32_t nblocks, const int32_t *n, psd_mode mode, int
         if (n[b] <= 64) p->small.push_back(SmallJob{off, 0, n[b], b});
         off += (int64_t)n[b] * n[b];
     }
-    // jobs are lockstep groups
-    p->chunks = group_chunks(nblocks, n, mode);
-    p->nlarge = (int)p->chunks.size();
-    p->slot_bytes = 0;
-    for (const auto &c : p->chunks) p->slot_bytes = std::max(p->slot_bytes, group_ws_bytes(c, mode));
-    p->slot_bytes = (p->slot_bytes + 255) / 256 * 256;
-    int K = concurrency;
-    if (K == 0) K = tune_lookup(tune_key(p->n, mode));
+    // jobs are lockstep groups; concurrency and group size from the cache
+    int K = concurrency, group = 0;
+    {
+        int Kc = 0, gc = 0;
+        tune_lookup(tune_key(p->n, mode), &Kc, &gc);
+        if (K == 0) K = Kc;
+        group = gc;
+    }
     if (K == 0) K = 4;
+    bool ok = set_jobs(p, group);
     p->K = std::max(1, std::min(K, std::max(1, p->nlarge)));
-    bool ok = prepare_kernel_attributes() == hipSuccess &&
+    ok = ok && prepare_kernel_attributes() == hipSuccess &&
               hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) == hipSuccess &&
               hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) == hipSuccess;
     for (int i = 0; ok && i < kMaxConcurrency; ++i)
@@ -179,19 +218,6 @@ psd_status psd_plan_create(int32_t nblocks, const int32_t *n, psd_mode mode, int
         ok = hipMalloc(&p->dsmall, p->small.size() * sizeof(SmallJob)) == hipSuccess &&
              hipMemcpy(p->dsmall, p->small.data(), p->small.size() * sizeof(SmallJob), hipMemcpyHostToDevice) ==
                  hipSuccess;
-    }
-    if (ok && !p->chunks.empty()) {
-        std::vector<int64_t> hoff;
-        std::vector<int> hidx;
-        for (const auto &c : p->chunks)
-            for (int b : c.blocks) {
-                hoff.push_back(p->off[b]);
-                hidx.push_back(b);
-            }
-        ok = hipMalloc(&p->dioff, hoff.size() * sizeof(int64_t)) == hipSuccess &&
-             hipMalloc(&p->didx, hidx.size() * sizeof(int)) == hipSuccess &&
-             hipMemcpy(p->dioff, hoff.data(), hoff.size() * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess &&
-             hipMemcpy(p->didx, hidx.data(), hidx.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
     }
     if (!ok) {
         psd_plan_destroy(p);
@@ -210,6 +236,8 @@ psd_status psd_plan_workspace_size(psd_plan p, int32_t concurrency, size_t *byte
 
 int32_t psd_plan_concurrency(psd_plan p) { return p ? p->K : 0; }
 
+int32_t psd_plan_group_size(psd_plan p) { return p ? max_members(p) : 0; }
+
 psd_status psd_plan_execute(psd_plan p, const double *x, double *y, void *ws, size_t ws_bytes, void *stream,
                             psd_info *infos) {
     if (!p || !x || !y) return PSD_EINVAL;
@@ -220,7 +248,7 @@ psd_status psd_plan_execute(psd_plan p, const double *x, double *y, void *ws, si
     hipGraphExec_t ex = find_graph(p, x, y, ws, infos, p->K);
     if (!ex) {
         if (capture(p, x, y, ws, infos, p->K, &ex) != hipSuccess) return PSD_EDEVICE;
-        p->graphs.push_back(GraphEntry{x, y, ws, infos, p->K, ex});
+        p->graphs.push_back(GraphEntry{x, y, ws, infos, p->K, p->group, ex});
     }
     return hipGraphLaunch(ex, static_cast<hipStream_t>(stream)) == hipSuccess ? PSD_OK : PSD_EDEVICE;
 }
@@ -231,32 +259,46 @@ psd_status psd_plan_tune(psd_plan p, const double *x, double *y, void *ws, size_
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipEvent_t t0, t1;
     if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) return PSD_EDEVICE;
-    int best = p->K;
+    int bestK = p->K, bestG = p->group;
     double best_ms = 1e300;
-    const int maxK = std::max(1, std::min(p->nlarge, kMaxConcurrency));
-    std::vector<int> cand;
-    for (int K = 1; K < maxK; K *= 2) cand.push_back(K);
-    cand.push_back(maxK);
-    for (int K : cand) {
-        if ((size_t)K * p->slot_bytes > ws_bytes) break;
-        const int saved = p->K;
-        p->K = K;
-        psd_status st = psd_plan_execute(p, x, y, ws, ws_bytes, stream, nullptr);  // capture + warm up
-        if (st != PSD_OK) { p->K = saved; continue; }
-        (void)hipEventRecord(t0, s);
-        for (int r = 0; r < reps && st == PSD_OK; ++r) st = psd_plan_execute(p, x, y, ws, ws_bytes, stream, nullptr);
-        (void)hipEventRecord(t1, s);
-        (void)hipEventSynchronize(t1);
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, t0, t1);
-        p->K = saved;
-        if (st == PSD_OK && ms / reps < best_ms) { best_ms = ms / reps; best = K; }
+    // group sizes: the memory-derived limit (up to 32), then 16 and 8 where
+    // they split differently; for each, concurrency 1, 2, 4, ... and the
+    // number of jobs
+    std::vector<int> tried;
+    for (int g : {0, 16, 8}) {
+        if (!set_jobs(p, g)) break;
+        const int mm = max_members(p);
+        if (std::find(tried.begin(), tried.end(), mm) != tried.end()) continue;
+        tried.push_back(mm);
+        const int maxK = std::max(1, std::min(p->nlarge, kMaxConcurrency));
+        std::vector<int> cand;
+        for (int K = 1; K < maxK; K *= 2) cand.push_back(K);
+        cand.push_back(maxK);
+        for (int K : cand) {
+            if ((size_t)K * p->slot_bytes > ws_bytes) break;
+            p->K = K;
+            psd_status st = psd_plan_execute(p, x, y, ws, ws_bytes, stream, nullptr);  // capture + warm up
+            if (st != PSD_OK) continue;
+            (void)hipEventRecord(t0, s);
+            for (int r = 0; r < reps && st == PSD_OK; ++r)
+                st = psd_plan_execute(p, x, y, ws, ws_bytes, stream, nullptr);
+            (void)hipEventRecord(t1, s);
+            (void)hipEventSynchronize(t1);  // nothing in flight reads the tables set_jobs rewrites
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, t0, t1);
+            if (st == PSD_OK && ms / reps < best_ms) {
+                best_ms = ms / reps;
+                bestK = K;
+                bestG = g;
+            }
+        }
     }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
-    p->K = best;
-    tune_record(tune_key(p->n, p->mode), best, best_ms);
-    if (best_out) *best_out = best;
+    if (!set_jobs(p, bestG)) return PSD_EDEVICE;
+    p->K = std::max(1, std::min(bestK, std::max(1, p->nlarge)));
+    tune_record(tune_key(p->n, p->mode), p->K, bestG, best_ms);
+    if (best_out) *best_out = p->K;
     return PSD_OK;
 }
 

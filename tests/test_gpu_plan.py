@@ -100,17 +100,45 @@ def test_plan_tune_and_cache(P, tmp_path):
         x = dev(x_np)
         y = torch.empty_like(x)
         plan = P.Plan(sizes, "fp64")
+        assert plan.group_size == 4  # the four W blocks of order 256 in one group
         best = plan.tune(x, y, reps=2, max_concurrency=4)
         assert 1 <= best <= 4 and plan.concurrency == best
+        group = plan.group_size
+        assert group in (4,)  # 16 and 8 do not split four blocks differently
         text = open(tmp_path / "tune.jsonl").read()
-        assert '"concurrency": %d' % best in text
+        assert '"concurrency": %d' % best in text and '"group": ' in text
         plan.close()
-        # a new plan for the same layout picks the recorded value
+        # a new plan for the same layout picks the recorded values
         plan2 = P.Plan(sizes, "fp64")
-        assert plan2.concurrency == best
+        assert plan2.concurrency == best and plan2.group_size == group
         ref = P.project_batched(x, sizes).cpu().numpy()
         assert np.array_equal(plan2.execute(x).cpu().numpy(), ref)
         plan2.close()
+    finally:
+        del os.environ["PSD_TUNE_CACHE"]
+
+
+def test_plan_tune_group_size(P, tmp_path):
+    # 20 blocks of order 100: group sizes 20 (one group), 16 + 4 and 8 + 8 + 4
+    # are all tried; whichever wins, replays equal eager results
+    import torch
+    os.environ["PSD_TUNE_CACHE"] = str(tmp_path / "tune.jsonl")
+    try:
+        sizes = [100] * 20
+        x_np = np.concatenate([W.gue(100, 8300 + i) for i in range(20)])
+        x = dev(x_np)
+        y = torch.empty_like(x)
+        plan = P.Plan(sizes, "fp64")
+        assert plan.group_size == 20
+        plan.tune(x, y, reps=1, max_concurrency=4)
+        assert plan.group_size in (20, 16, 8)
+        got = plan.execute(x).cpu().numpy()
+        # a member's arithmetic does not depend on its group: bitwise equal
+        assert np.array_equal(got, P.project_batched(x, sizes).cpu().numpy())
+        for i in (0, 7, 19):
+            blk = slice(i * 10000, (i + 1) * 10000)
+            assert rel(got[blk], oracle.project(x_np[blk], 100)) <= 1e-10
+        plan.close()
     finally:
         del os.environ["PSD_TUNE_CACHE"]
 
