@@ -1,5 +1,5 @@
-// Device-side body of the FP64 MFMA GEMM tile (see gemm.h), shared by the
-// GEMM kernels and by persistent kernels that run GEMM tiles as one phase.
+// Device-side body of the FP64 MFMA GEMM tile (see gemm.h), used by the
+// single and the batched GEMM kernels; the caller owns the LDS staging.
 //
 // Block tile 64x64x16, 256 threads = 4 waves in a 2x2 arrangement, each wave
 // owning a 32x32 sub-tile made of 2x2 v_mfma_f64_16x16x4 blocks.  Complex
