@@ -276,6 +276,26 @@ def main():
         extra["independent_batch_proj_per_s"] = round(2 * count / (time.perf_counter() - t), 2)
         extra["independent_batch_max_abs_diff"] = float((yb.reshape(Y.shape) - Y).abs().max())
 
+    if wl == "c1":
+        # context: one block of order 16 as a one-block plan, 10^4 graph replays
+        p1 = P.Plan([n], mode)
+        x1 = X[:n * n].clone()
+        y1 = p1.execute(x1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(10000):
+            p1.execute(x1, out=y1)
+        torch.cuda.synchronize()
+        extra["single_block_latency_us_graph"] = round((time.perf_counter() - t) / 10000 * 1e6, 2)
+        p1.close()
+        t = time.perf_counter()
+        for _ in range(10000):
+            P.project(x1, n, mode, out=y1)
+        torch.cuda.synchronize()
+        extra["single_block_latency_us_eager"] = round((time.perf_counter() - t) / 10000 * 1e6, 2)
+    if wl == "c4":
+        extra["block_projections_per_s"] = round(value * len(sizes), 1)
+
     if wl == "c5":
         # derivative after the forward (eigen-pair saved by the forward)
         sv = torch.empty(P.saved_numel(n), dtype=torch.float64, device=dev)
@@ -330,6 +350,14 @@ def main():
                 sample = f"first {m} of the {count} blocks (n={n}), cyclic Jacobi round-robin FP64, {dt:.1f} s"
                 value_cpu = m / dt
                 unit = "projections/s"
+            if wl == "c3" and mode != "fp64":
+                # truncation alone: the same scaled schedule in exact arithmetic
+                # per eigenvalue (the rest of the error is low-precision rounding)
+                _, inf0 = P.project(X[0], n, mode, info=True)
+                sched = oracle.ns_schedule(iters=inf0["iters"])
+                exact = oracle.constructed_projection(cons[0][1], cons[0][2])
+                trunc = oracle.ns_constructed_projection(cons[0][1], cons[0][2], inf0["scale"], inf0["iters"], sched)
+                extra["ns_truncation_rel_err"] = float(np.linalg.norm(trunc - exact) / np.linalg.norm(exact))
         cpu = {"value": round(value_cpu, 5) if value_cpu else None, "unit": unit, "cores": oracle.num_threads(),
                "kind": "oracle", "sample": sample}
 

@@ -115,8 +115,11 @@ hipError_t capture(psd_plan_s *p, const double *x, double *y, void *ws, psd_info
     if (e != hipSuccess) return e;
     hipError_t err = hipSuccess;
     auto chk = [&](hipError_t r) { if (err == hipSuccess && r != hipSuccess) err = r; };
-    chk(hipEventRecord(p->fork, p->cap));
-    for (int i = 0; i < K; ++i) chk(hipStreamWaitEvent(p->side[i], p->fork, 0));
+    const bool fork = !p->chunks.empty();  // only small blocks: one kernel node, no fork/join
+    if (fork) {
+        chk(hipEventRecord(p->fork, p->cap));
+        for (int i = 0; i < K; ++i) chk(hipStreamWaitEvent(p->side[i], p->fork, 0));
+    }
     psd_dev_info *di = reinterpret_cast<psd_dev_info *>(infos);
     if (!p->small.empty()) chk(launch_small(p->dsmall, (int)p->small.size(), x, y, di, nullptr, p->cap));
     int pos = 0;
@@ -127,7 +130,7 @@ hipError_t capture(psd_plan_s *p, const double *x, double *y, void *ws, psd_info
                               p->side[slot]));
         pos += cnt;
     }
-    for (int i = 0; i < K; ++i) {
+    for (int i = 0; fork && i < K; ++i) {
         chk(hipEventRecord(p->join[i], p->side[i]));
         chk(hipStreamWaitEvent(p->cap, p->join[i], 0));
     }
