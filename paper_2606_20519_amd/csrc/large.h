@@ -47,8 +47,10 @@ struct LargeWs {
     // back-transform and reconstruction
     double2 *Zc;        // lda x kmax selected eigenvectors (complex)
     double *lamsel;     // kmax selected eigenvalues
-    double *wpart;      // split-K partials of V^H Z: nchunk * NB * kmax complex
-    double2 *W2;        // NB x kmax
+    double *wpart;      // split-K partials of V^H Z: nchunk * 128 * kmax complex
+    double2 *W2;        // 128 x kmax
+    double2 *Sg;        // 128 x 128: V^H V of a group of four panels
+    double2 *spart;     // split-K partials of V^H V of a group: nchunk * 128 * 128
     int *ksel;          // [0] = k, [1] = n_pos, [2] = status
     double *sgn;        // reconstruction sign
     double *lam;        // n final eigenvalues (ascending)

@@ -1,10 +1,12 @@
 // Large-block FP64 path, stages after the tridiagonal eigensolver:
 //  * select: count the eigenvalues > 0 (lambda ascending) and pick the side
 //    with fewer columns, k = min(k+, k-);
-//  * back-transform: V = Q Z for those k columns, block reflector by block
-//    reflector (last panel first): Z <- Z - V_b (T_b (V_b^H Z)), with V_b^H Z
-//    as a split-K MFMA GEMM, the T_b product in LDS, and the update as an
-//    MFMA GEMM;
+//  * back-transform: V = Q Z for those k columns, four panels' reflectors
+//    at a time (last group first): Z <- Z - V_g (T_g (V_g^H Z)), with V_g^H Z
+//    as a split-K MFMA GEMM, the T_g product applied block by block from the
+//    panels' factors and V_g^H V_g (T_g itself is never formed), and the
+//    update as an MFMA GEMM (Z is read twice and written once per four
+//    panels);
 //  * reconstruction: Pi = V+ diag(lambda+) V+^H   (k+ <= k-), or
 //    Pi = X - V- diag(lambda-) V-^H (otherwise), one MFMA GEMM over the
 //    lower tiles whose epilogue writes the svec directly (App. D.2: zero the
@@ -21,6 +23,9 @@ namespace psd {
 namespace {
 
 constexpr int NB = LG_NB;
+constexpr int BG = 4;           // panels per back-transform group
+constexpr int GW = BG * NB;     // columns of a group's block reflector
+static_assert(GW == 128, "bt_tw_kernel puts two columns of GW rows on 256 threads");
 // Split-K chunk of V_b^H Z in the back-transform: 64 rows, more for large n
 // so that the partial sums stay at most 16 (the GEMM has only NB rows, so
 // the K split is where its parallelism comes from).
@@ -85,39 +90,85 @@ __global__ void __launch_bounds__(256) select_kernel(const double *__restrict__ 
     }
 }
 
-// W2 = T_b * sum_z partial_z  for columns c < k (8 columns per workgroup).
+// Block reflector of a group of up to BG consecutive panels (reflector
+// columns p0 .. p0 + G - 1): H_{b0} ... H_{b0+g-1} = I - V T V^H, where the
+// two-block identity (I - V1 T1 V1^H)(I - V2 T2 V2^H)
+//   = I - [V1 V2] [[T1, -T1 S12 T2], [0, T2]] [V1 V2]^H,   S = V^H V,
+// extends to g blocks with T upper triangular.  T is never formed: Y = T W
+// follows from the bottom block up, Y_j = T_j (W_j - sum_{l > j} S_jl Y_l).
+
+// S = sum of the split-K partials of V^H V (entries above the diagonal
+// blocks are the ones read).
+__global__ void __launch_bounds__(256) s_reduce_kernel(const double2 *__restrict__ spart, int nz, int64_t szstride,
+                                                       double2 *S, int64_t zs) {
+    spart = member_ptr(spart, zs, blockIdx.z);
+    S = member_ptr(S, zs, blockIdx.z);
+    const int idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= GW * GW) return;
+    double2 pz[16];  // nz <= 16: every partial in flight at once
+#pragma unroll
+    for (int z = 0; z < 16; ++z) pz[z] = z < nz ? spart[z * szstride + idx] : cmk(0.0, 0.0);
+    double2 acc = cmk(0.0, 0.0);
+#pragma unroll
+    for (int z = 0; z < 16; ++z) acc = cadd(acc, pz[z]);
+    for (int z = 16; z < nz; ++z) acc = cadd(acc, spart[z * szstride + idx]);
+    S[idx] = acc;
+}
+
+// W2 = T W, W = sum_z partial_z (G rows, ld GW), for columns c < k: two
+// columns per workgroup, the rows on the threads; T from the panels'
+// factors Tp (NB x NB each) and S as above.
 __global__ void __launch_bounds__(256) bt_tw_kernel(const double2 *__restrict__ wpart, int nz, int64_t zstride,
-                                                    const double2 *__restrict__ Tb, int kb, const int *ksel,
-                                                    double2 *W2, int64_t zs) {
+                                                    const double2 *__restrict__ Tp, const double2 *__restrict__ S,
+                                                    int G, const int *ksel, double2 *W2, int64_t zs) {
     {
         const int mb = blockIdx.z;
         wpart = member_ptr(wpart, zs, mb);
-        Tb = member_ptr(Tb, zs, mb);
+        Tp = member_ptr(Tp, zs, mb);
+        S = member_ptr(S, zs, mb);
         ksel = member_ptr(ksel, zs, mb);
         W2 = member_ptr(W2, zs, mb);
     }
-    __shared__ double2 Ts[NB][NB + 1];
-    __shared__ double2 W1[NB][9];
-    const int t = threadIdx.x, i = t & 31, cl = t >> 5;
-    const int c = blockIdx.x * 8 + cl;
+    __shared__ double2 Wl[GW][3];  // W, then the block's right-hand side
+    __shared__ double2 Yl[GW][3];  // Y
+    const int t = threadIdx.x, i = t % GW, cl = t / GW;
+    const int c = blockIdx.x * 2 + cl;
     const int k = ksel[0];
-    for (int idx = t; idx < NB * NB; idx += 256) Ts[idx % NB][idx / NB] = Tb[idx];
+    const bool live = c < k && i < G;
     double2 acc = cmk(0.0, 0.0);
-    if (c < k && i < kb) {
-        double2 pz[16];  // nz <= 16: every partial in flight at once
+    if (live) {
+        double2 pz[16];
 #pragma unroll
-        for (int z = 0; z < 16; ++z) pz[z] = z < nz ? wpart[z * zstride + i + (int64_t)c * NB] : cmk(0.0, 0.0);
+        for (int z = 0; z < 16; ++z) pz[z] = z < nz ? wpart[z * zstride + i + (int64_t)c * GW] : cmk(0.0, 0.0);
 #pragma unroll
         for (int z = 0; z < 16; ++z) acc = cadd(acc, pz[z]);
-        for (int z = 16; z < nz; ++z) acc = cadd(acc, wpart[z * zstride + i + (int64_t)c * NB]);
+        for (int z = 16; z < nz; ++z) acc = cadd(acc, wpart[z * zstride + i + (int64_t)c * GW]);
     }
-    W1[i][cl] = acc;
+    Wl[i][cl] = acc;
+    Yl[i][cl] = cmk(0.0, 0.0);
     __syncthreads();
-    if (c >= k) return;
-    double2 out = cmk(0.0, 0.0);
-    if (i < kb)
-        for (int l = i; l < kb; ++l) out = cfma(Ts[i][l], W1[l][cl], out);
-    W2[i + (int64_t)c * NB] = out;
+    const int g = (G + NB - 1) / NB, bj = i / NB, r = i % NB;
+    for (int j = g - 1; j >= 0; --j) {
+        const int kbj = min(NB, G - j * NB);
+        // right-hand side W_j - sum_{l > j} S_jl Y_l
+        if (bj == j && live) {
+            double2 rhs = Wl[i][cl];
+#pragma unroll 8
+            for (int m = (j + 1) * NB; m < G; ++m) rhs = csub(rhs, cmul(S[i + (int64_t)m * GW], Yl[m][cl]));
+            Wl[i][cl] = rhs;
+        }
+        __syncthreads();
+        // Y_j = T_j (right-hand side), T_j upper triangular
+        if (bj == j && live) {
+            const double2 *Tj = Tp + (int64_t)j * NB * NB;
+            double2 y = cmk(0.0, 0.0);
+#pragma unroll 8
+            for (int m = r; m < kbj; ++m) y = cfma(Tj[r + (int64_t)m * NB], Wl[j * NB + m][cl], y);
+            Yl[i][cl] = y;
+        }
+        __syncthreads();
+    }
+    if (live) W2[i + (int64_t)c * GW] = Yl[i][cl];
 }
 
 __global__ void __launch_bounds__(256) save_kernel(const double *__restrict__ lam, const double2 *__restrict__ Zc,
@@ -201,8 +252,10 @@ size_t large_layout(int n, int flags, void *base, LargeWs *w) {
     L.gdesc = (GemmDesc *)take(sizeof(GemmDesc) * (size_t)(n + 2));
     L.Zc = (double2 *)take(cdsz * L.lda * L.kmax);
     L.lamsel = (double *)take(dsz * L.kmax);
-    L.wpart = (double *)take(cdsz * (size_t)L.nchunk * NB * L.kmax);
-    L.W2 = (double2 *)take(cdsz * (size_t)NB * L.kmax);
+    L.wpart = (double *)take(cdsz * (size_t)L.nchunk * GW * L.kmax);
+    L.W2 = (double2 *)take(cdsz * (size_t)GW * L.kmax);
+    L.Sg = (double2 *)take(cdsz * (size_t)GW * GW);
+    L.spart = (double2 *)take(cdsz * (size_t)L.nchunk * GW * GW);
     L.ksel = (int *)take(sizeof(int) * 4);
     L.sgn = (double *)take(dsz);
     L.B1 = full ? (double2 *)take(cdsz * (size_t)n * n) : nullptr;
@@ -231,37 +284,51 @@ hipError_t large_select(const LargeWs &w, psd_dev_info *info, hipStream_t st, bo
 
 hipError_t large_backtransform(const LargeWs &w, int ncols_max, hipStream_t st) {
     const int n = w.n;
-    const int64_t zstride = (int64_t)NB * w.kmax;
-    for (int b = w.npanel - 1; b >= 0; --b) {
-        const int p0 = b * NB;
-        const int kb = std::min(NB, n - 1 - p0);
+    const int64_t zstride = (int64_t)GW * w.kmax, szstride = (int64_t)GW * GW;
+    const int ngroup = (w.npanel + BG - 1) / BG;
+    for (int gi = ngroup - 1; gi >= 0; --gi) {
+        const int b0 = gi * BG, b1 = std::min(w.npanel, b0 + BG), g = b1 - b0;
+        const int p0 = b0 * NB;
+        const int G = std::min(n - 1, b1 * NB) - p0;  // reflector columns of the group
         const int mr = n - 1 - p0;
-        const double2 *Vb = w.M + (p0 + 1) + (int64_t)p0 * w.lda;
-        // partials of V_b^H Z over row chunks
-        GemmDesc g{};
-        g.M = kb; g.N = ncols_max; g.K = mr;
-        g.A = GemmOperand{Vb, Vb, w.lda, w.lda, mr, OP_C, nullptr};
-        g.B = GemmOperand{w.Zc + (p0 + 1), w.Zc + (p0 + 1), w.lda, w.lda, mr, OP_N, nullptr};
-        g.C = w.wpart; g.ldc = NB; g.alpha = 1.0; g.beta = 0.0;
-        g.dN = w.ksel;
-        g.kchunk = w.kchunk; g.c_zstride = zstride;
-        g.nmem = w.nmem; g.zs = w.zs;
-        hipError_t e = gemm_launch(g, true, EPI_STORE, st);
-        if (e != hipSuccess) return e;
-        const int nz = gemm_kslices(g);
-        hipLaunchKernelGGL(bt_tw_kernel, dim3((ncols_max + 7) / 8, 1, w.nmem), dim3(256), 0, st,
-                           reinterpret_cast<const double2 *>(w.wpart), nz, zstride, w.T + (int64_t)b * NB * NB, kb,
-                           w.ksel, w.W2, w.zs);
-        // Z[p0+1:, :] -= V_b W2
+        const double2 *Vg = w.M + (p0 + 1) + (int64_t)p0 * w.lda;
+        hipError_t e;
+        // S = V^H V (its blocks above the diagonal couple the panels)
+        if (g > 1) {
+            GemmDesc sg{};
+            sg.M = sg.N = G; sg.K = mr;
+            sg.A = GemmOperand{Vg, Vg, w.lda, w.lda, mr, OP_C, nullptr};
+            sg.B = GemmOperand{Vg, Vg, w.lda, w.lda, mr, OP_N, nullptr};
+            sg.C = w.spart; sg.ldc = GW; sg.alpha = 1.0; sg.beta = 0.0;
+            sg.kchunk = w.kchunk; sg.c_zstride = szstride;
+            sg.nmem = w.nmem; sg.zs = w.zs;
+            if ((e = gemm_launch(sg, true, EPI_STORE, st)) != hipSuccess) return e;
+            hipLaunchKernelGGL(s_reduce_kernel, dim3(GW * GW / 256, 1, w.nmem), dim3(256), 0, st,
+                               reinterpret_cast<const double2 *>(w.spart), gemm_kslices(sg), szstride, w.Sg, w.zs);
+        }
+        // partials of V^H Z over row chunks
+        GemmDesc gm{};
+        gm.M = G; gm.N = ncols_max; gm.K = mr;
+        gm.A = GemmOperand{Vg, Vg, w.lda, w.lda, mr, OP_C, nullptr};
+        gm.B = GemmOperand{w.Zc + (p0 + 1), w.Zc + (p0 + 1), w.lda, w.lda, mr, OP_N, nullptr};
+        gm.C = w.wpart; gm.ldc = GW; gm.alpha = 1.0; gm.beta = 0.0;
+        gm.dN = w.ksel;
+        gm.kchunk = w.kchunk; gm.c_zstride = zstride;
+        gm.nmem = w.nmem; gm.zs = w.zs;
+        if ((e = gemm_launch(gm, true, EPI_STORE, st)) != hipSuccess) return e;
+        const int nz = gemm_kslices(gm);
+        hipLaunchKernelGGL(bt_tw_kernel, dim3((ncols_max + 1) / 2, 1, w.nmem), dim3(256), 0, st,
+                           reinterpret_cast<const double2 *>(w.wpart), nz, zstride, w.T + (int64_t)b0 * NB * NB, w.Sg,
+                           G, w.ksel, w.W2, w.zs);
+        // Z[p0+1:, :] -= V W2
         GemmDesc u{};
-        u.M = mr; u.N = ncols_max; u.K = kb;
-        u.A = GemmOperand{Vb, Vb, w.lda, w.lda, kb, OP_N, nullptr};
-        u.B = GemmOperand{w.W2, w.W2, NB, NB, kb, OP_N, nullptr};
+        u.M = mr; u.N = ncols_max; u.K = G;
+        u.A = GemmOperand{Vg, Vg, w.lda, w.lda, G, OP_N, nullptr};
+        u.B = GemmOperand{w.W2, w.W2, GW, GW, G, OP_N, nullptr};
         u.C = w.Zc + (p0 + 1); u.ldc = w.lda; u.alpha = -1.0; u.beta = 1.0;
         u.dN = w.ksel;
         u.nmem = w.nmem; u.zs = w.zs;
-        e = gemm_launch(u, true, EPI_STORE, st);
-        if (e != hipSuccess) return e;
+        if ((e = gemm_launch(u, true, EPI_STORE, st)) != hipSuccess) return e;
     }
     return hipGetLastError();
 }
