@@ -254,8 +254,11 @@ def main():
         else:
             peak = PEAK_BF16_TFLOPS if mode == "mixed_bf16" else PEAK_FP32_TFLOPS
             achieved = timed[2] / (timed[0] * 1e-3) / 1e12
-            roofline = {"kernel": f"ns_gemm_kernel<{'bf16' if mode == 'mixed_bf16' else 'f32'}> "
-                                  "(Hermitian-half complex GEMM, Newton-Schulz)",
+            npad = (n + 63) // 64 * 64
+            kname = ("ns_gemm128_kernel (128x128 tiles, direct global-to-LDS loads; split tail summed by "
+                     "ns128_tail_kernel)" if mode == "mixed_bf16" and npad >= 2048 else
+                     f"ns_gemm_kernel<{'bf16' if mode == 'mixed_bf16' else 'f32'}> (64x64 tiles)")
+            roofline = {"kernel": kname + ", Hermitian-half complex GEMM of the Newton-Schulz steps",
                         "bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                         "frac": round(achieved / peak, 4), "traffic": None,
                         "algorithmic_flops_per_launch": round(timed[2] / timed[1], 1)}

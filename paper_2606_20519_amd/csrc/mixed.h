@@ -15,6 +15,7 @@ struct MixedWs {
     void *lo0, *lo1, *lo2;   // two planes (re, im) each
     double2 *q, *qprev, *wv, *P;
     double *ab, *alpha, *red;
+    float *part;        // split partial sums of the BF16 128x128 product (large npad)
     int *status;
     // lockstep group (as for the FP64 path: member b uses the slot b * zs
     // bytes on, svec offset ioff[b], info record infoidx[b]); single block:

@@ -396,6 +396,261 @@ __global__ void __launch_bounds__(256) ns_gemm_kernel(const L *__restrict__ Are,
             }
 }
 
+// ---- BF16 product of the large blocks: 128x128 tiles fed by direct
+// global->LDS loads.
+//
+// The 64x64 tile above stages its operands through registers; at large n its
+// MFMAs wait on the loads of the next k-slice.  Here each wave streams one
+// operand plane (Re A, Im A, Re B, Im B) straight into LDS with
+// global_load_lds_dwordx4 (no registers, no LDS store instructions), into a
+// two-deep ring: slice s + 1 is in flight while slice s feeds the MFMAs.
+// 4 waves in 2x2 own 64x64 each (4x4 blocks of 16x16x32 MFMA); LDS rows are
+// 64 bytes unpadded, the 16-byte chunk q of row r at position q ^ f(r),
+// f(r) = ((r >> 2) ^ (r >> 1)) & 3, which keeps every fragment read free of
+// bank conflicts (16 lanes over 64 banks or 8 lanes over 32).  Two
+// workgroups fit on a CU (64 KiB of LDS, at most 256 registers each).
+//
+// Tile count: the lower tiles of an npad x npad product, T = m (m + 1) / 2
+// with m = npad / 128 rounded up.  When T slightly exceeds the resident
+// workgroups (NS_SLOTS), the last T mod NS_SLOTS tiles would run alone in a
+// second round; instead each is split along k into `split` parts written
+// as raw FP32 partials, summed in part order (deterministic) by a second
+// kernel that applies the same epilogue.
+constexpr int NS_SLOTS = 512;  // 256 CUs x 2 resident workgroups
+constexpr int NS_BIG = 2048;   // npad from which the 128x128 path is used
+constexpr int NS_PART_FLOATS = 32768;  // raw accumulators of one tile part
+
+// Tail split of the 128x128 path for an npad x npad product (per block:
+// independent of the group size, so group members match single calls).
+void ns_tail_plan(int npad, int *ntile, int *tfull, int *rem, int *split) {
+    const int m = (npad + 127) / 128, T = m * (m + 1) / 2;
+    int r = T > NS_SLOTS ? T % NS_SLOTS : 0;
+    if (r > NS_SLOTS / 4) r = 0;
+    *ntile = T;
+    *rem = r;
+    *split = r ? std::min(16, NS_SLOTS / r) : 1;
+    *tfull = T - r;
+}
+
+// One 16-byte chunk per lane from g into LDS at lds + 16 * lane.  Issued as
+// inline assembly so that the compiler does not hold every LDS read behind
+// it (it cannot tell the ring slots apart); the waits are explicit: WAIT_VM
+// on this wave's own loads, then a barrier for everyone's.
+__device__ __forceinline__ void dma16(const void *g, unsigned lds) {
+    asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g), "s"(lds) : "memory", "m0");
+}
+#define NS_WAIT_VM0() __builtin_amdgcn_s_waitcnt((0x7 << 4) | (0xF << 8))
+
+__device__ __forceinline__ void ns_tile_ij(int tb, int &ti, int &tj) {
+    ti = (int)((sqrt(8.0 * tb + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= tb) ++ti;
+    while (ti * (ti + 1) / 2 > tb) --ti;
+    tj = tb - ti * (ti + 1) / 2;
+}
+
+// Epilogue of one 16x16 block at (ib, jb) as in ns_gemm_kernel: the lower
+// part with its conjugate mirror; blocks strictly below the diagonal write
+// four consecutive rows per lane as one 8-byte store.
+__device__ __forceinline__ void ns128_store_block(const v4f &accr, const v4f &acci, int ib, int jb, int lane, int npad,
+                                                  int epi, float c, __bf16 *Cre, __bf16 *Cim, double2 *C64,
+                                                  int64_t ld64, int n) {
+    if (ib < jb || ib >= npad) return;
+    const int ir = ib + 4 * (lane >> 4), j = jb + (lane & 15);
+    if (epi != NS_EPI_F64 && ib > jb) {
+        union { __bf16 h[4]; uint2 u; } pr, pi, pn;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            float re = accr[v], im = acci[v];
+            if (epi == NS_EPI_T) { re = -c * re; im = -c * im; }
+            else { re *= c; im *= c; }
+            pr.h[v] = (__bf16)re;
+            pi.h[v] = (__bf16)im;
+            pn.h[v] = (__bf16)(-im);
+        }
+        const int64_t o = (int64_t)ir + (int64_t)j * npad;
+        *reinterpret_cast<uint2 *>(Cre + o) = pr.u;
+        *reinterpret_cast<uint2 *>(Cim + o) = pi.u;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t om = (int64_t)j + (int64_t)(ir + v) * npad;
+            Cre[om] = pr.h[v];
+            Cim[om] = pn.h[v];
+        }
+        return;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = ir + v;
+        if (i < j) continue;
+        float re = accr[v], im = acci[v];
+        if (epi == NS_EPI_T) { re = (i == j ? 3.0f : 0.0f) - c * re; im = -c * im; }
+        else { re *= c; im *= c; }
+        if (i == j) im = 0.0f;
+        if (epi != NS_EPI_F64) {
+            const __bf16 lr = (__bf16)re, li = (__bf16)im, lni = (__bf16)(-im);
+            const int64_t o = (int64_t)i + (int64_t)j * npad, om = (int64_t)j + (int64_t)i * npad;
+            Cre[o] = lr; Cim[o] = li;
+            Cre[om] = lr; Cim[om] = lni;
+        } else if (i < n && j < n) {
+            C64[i + (int64_t)j * ld64] = cmk((double)re, (double)im);
+            C64[j + (int64_t)i * ld64] = cmk((double)re, -(double)im);
+        }
+    }
+}
+
+// Workgroups g < tfull: whole tiles (XCD-aware order); the rest: part
+// (g - tfull) % split of tail tile tfull + (g - tfull) / split.
+__global__ void __launch_bounds__(256, 2) ns_gemm128_kernel(const __bf16 *Are, const __bf16 *Aim, const __bf16 *Bre,
+                                                            const __bf16 *Bim, int npad, int epi, float c, __bf16 *Cre,
+                                                            __bf16 *Cim, double2 *C64, int64_t ld64, int n, int tfull,
+                                                            int split, float *part, int64_t zs) {
+    {
+        const int mb = blockIdx.z;
+        Are = member_ptr(Are, zs, mb);
+        Aim = member_ptr(Aim, zs, mb);
+        Bre = member_ptr(Bre, zs, mb);
+        Bim = member_ptr(Bim, zs, mb);
+        Cre = member_ptr(Cre, zs, mb);
+        Cim = member_ptr(Cim, zs, mb);
+        C64 = member_ptr(C64, zs, mb);
+        part = member_ptr(part, zs, mb);
+    }
+    // [slot][plane: Re A, Im A, Re B, Im B][128 rows x 64 bytes, swizzled]
+    __shared__ __align__(16) char lds[2][4][8192];
+    const int g = blockIdx.x;
+    const int q = g < tfull ? -1 : g - tfull;
+    const int tb = q < 0 ? xcd_tile(g, tfull) : tfull + q / split;
+    int ti, tj;
+    ns_tile_ij(tb, ti, tj);
+    const int i0 = ti * 128, j0 = tj * 128;
+    const int t = threadIdx.x, lane = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6), wm = w & 1, wn = w >> 1;
+    const bool idle = ti == tj && wm == 0 && wn == 1;  // wave tile above the diagonal
+    v4f accr[4][4], acci[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) { accr[a][b] = v4f{0, 0, 0, 0}; acci[a][b] = v4f{0, 0, 0, 0}; }
+    // wave w streams plane w: lane l fills slot 64 p + l of the plane (row
+    // 16 p + l / 4, position l % 4) with the chunk that the swizzle puts
+    // there.  Rows past npad (the last tile row when npad % 128 == 64) read
+    // row npad - 1 instead: they only feed outputs that are not stored.
+    const __bf16 *src = w == 0 ? Are : w == 1 ? Aim : w == 2 ? Bre : Bim;
+    const int r0 = w < 2 ? i0 : j0;
+    const int cg = (lane & 3) ^ (((lane >> 4) ^ (lane >> 3)) & 3);
+    int64_t goff[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) goff[p] = (int64_t)min(r0 + p * 16 + (lane >> 2), npad - 1) * npad + cg * 8;
+    const int nkall = npad / 32;
+    int kbeg = 0, kend = nkall;
+    if (q >= 0) {
+        const int kc = (nkall + split - 1) / split;
+        kbeg = min(nkall, (q % split) * kc);
+        kend = min(nkall, kbeg + kc);
+    }
+    const unsigned lds0 = (unsigned)(size_t)(__attribute__((address_space(3))) char *)&lds[0][w][0];
+#define NS128_ISSUE(ST)                                                          \
+    {                                                                            \
+        const unsigned dst = lds0 + (unsigned)((ST) & 1) * (4 * 8192);           \
+        const __bf16 *s0 = src + (ST) * 32;                                      \
+        _Pragma("unroll") for (int p = 0; p < 8; ++p) dma16(s0 + goff[p], dst + p * 1024); \
+    }
+    if (kbeg < kend) NS128_ISSUE(kbeg)
+    const int ii = lane & 15, kg = lane >> 4;
+    const int rsw = (kg ^ (((ii >> 2) ^ (ii >> 1)) & 3)) * 16;
+    for (int s = kbeg; s < kend; ++s) {
+        NS_WAIT_VM0();
+        asm volatile("s_barrier" ::: "memory");
+        if (s + 1 < kend) NS128_ISSUE(s + 1)
+        if (!idle) {
+            const char *bA = &lds[s & 1][0][0];
+            v8bf br[4], bi[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int off = (wn * 64 + b * 16 + ii) * 64 + rsw;
+                br[b] = *reinterpret_cast<const v8bf *>(bA + 2 * 8192 + off);
+                bi[b] = *reinterpret_cast<const v8bf *>(bA + 3 * 8192 + off);
+            }
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const int off = (wm * 64 + a * 16 + ii) * 64 + rsw;
+                const v8bf ar = *reinterpret_cast<const v8bf *>(bA + off);
+                // Im of the stored column is -Im A(i, k) (A(i,k) = conj of the
+                // stored (k, i)): ai enters Re C with +, its negation Im C
+                uint4 u = *reinterpret_cast<const uint4 *>(bA + 8192 + off);
+                const v8bf ai = *reinterpret_cast<const v8bf *>(&u);
+                u.x ^= 0x80008000u; u.y ^= 0x80008000u; u.z ^= 0x80008000u; u.w ^= 0x80008000u;
+                const v8bf ain = *reinterpret_cast<const v8bf *>(&u);
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    accr[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, br[b], accr[a][b], 0, 0, 0);
+                    accr[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai, bi[b], accr[a][b], 0, 0, 0);
+                    acci[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, bi[b], acci[a][b], 0, 0, 0);
+                    acci[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ain, br[b], acci[a][b], 0, 0, 0);
+                }
+            }
+        }
+    }
+#undef NS128_ISSUE
+    if (idle) return;
+    if (q >= 0) {
+        // raw partial sums, register order with the lane fastest
+        float *pp = part + (int64_t)q * NS_PART_FLOATS;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int idx = ((w * 16 + a * 4 + b) * 4 + v) * 64 + lane;
+                    pp[idx] = accr[a][b][v];
+                    pp[NS_PART_FLOATS / 2 + idx] = acci[a][b][v];
+                }
+        return;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            ns128_store_block(accr[a][b], acci[a][b], i0 + wm * 64 + a * 16, j0 + wn * 64 + b * 16, lane, npad, epi, c,
+                              Cre, Cim, C64, ld64, n);
+}
+
+// Tail tile tfull + blockIdx.x: its split partials summed in part order,
+// then the epilogue; workgroup y covers the block row a = y of every wave.
+__global__ void __launch_bounds__(256) ns128_tail_kernel(const float *__restrict__ part, int tfull, int split, int npad,
+                                                         int epi, float c, __bf16 *Cre, __bf16 *Cim, double2 *C64,
+                                                         int64_t ld64, int n, int64_t zs) {
+    {
+        const int mb = blockIdx.z;
+        part = member_ptr(part, zs, mb);
+        Cre = member_ptr(Cre, zs, mb);
+        Cim = member_ptr(Cim, zs, mb);
+        C64 = member_ptr(C64, zs, mb);
+    }
+    const int a = blockIdx.y;
+    int ti, tj;
+    ns_tile_ij(tfull + (int)blockIdx.x, ti, tj);
+    const int i0 = ti * 128, j0 = tj * 128;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w & 1, wn = w >> 1;
+    if (ti == tj && wm == 0 && wn == 1) return;
+    const float *pp = part + (int64_t)blockIdx.x * split * NS_PART_FLOATS;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        v4f re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+        for (int p = 0; p < split; ++p) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int idx = ((w * 16 + a * 4 + b) * 4 + v) * 64 + lane;
+                re[v] += pp[(int64_t)p * NS_PART_FLOATS + idx];
+                im[v] += pp[(int64_t)p * NS_PART_FLOATS + NS_PART_FLOATS / 2 + idx];
+            }
+        }
+        ns128_store_block(re, im, i0 + wm * 64 + a * 16, j0 + wn * 64 + b * 16, lane, npad, epi, c, Cre, Cim, C64, ld64,
+                          n);
+    }
+}
+
 // ||T - 2I||_F^2 (T = 3I - S^2, so T - 2I = I - S^2) and tr S: partials per
 // column block (one workgroup per 16 columns), then one workgroup writes the
 // info record.
@@ -481,14 +736,32 @@ hipError_t ns_run(const MixedWs &w, const double *x, double *y, psd_dev_info *in
     const int64_t zs = w.zs;
     dim3 sg((npad + 255) / 256, npad, B);
     hipLaunchKernelGGL((ns_scale_kernel<L>), sg, dim3(256), 0, st, w.M, w.lda, n, npad, w.alpha, X, X + plane, zs);
-    const int mt = npad / 64, ntile = mt * (mt + 1) / 2;
-    dim3 gg(ntile, 1, B);
-    // complex multiply-adds of the lower tiles actually computed, 8 flops each
-    const double ns_flops = 8.0 * 64.0 * 64.0 * (double)npad * (double)ntile * B;
+    // BF16 at npad >= NS_BIG: 128x128 tiles with a split tail; otherwise the
+    // 64x64 tile (the choice depends on npad only, so that group members
+    // match single-block calls bit for bit)
+    const bool big = sizeof(L) == 2 && npad >= NS_BIG;
+    int ntile, tfull, rem, split;
+    if (big) ns_tail_plan(npad, &ntile, &tfull, &rem, &split);
+    else { const int mt = npad / 64; ntile = mt * (mt + 1) / 2; tfull = ntile; rem = 0; split = 1; }
+    // algorithmic count: the n (n + 1) / 2 lower entries of an order-n
+    // Hermitian product, n complex multiply-adds (8 flops) each
+    const double ns_flops = 8.0 * (double)n * (double)n * (double)(n + 1) / 2.0 * B;
     auto product = [&](const L *A, const L *Bm, int epi, float cf, L *C, double2 *C64) {
         const int slot = timing_begin(KF_NS, st);
-        hipLaunchKernelGGL((ns_gemm_kernel<L>), gg, dim3(256), 0, st, A, A + plane, Bm, Bm + plane, npad, epi, cf, C,
-                           C + plane, C64, w.lda, n, zs);
+        if constexpr (sizeof(L) == 2) {
+            if (big) {
+                hipLaunchKernelGGL(ns_gemm128_kernel, dim3(tfull + rem * split, 1, B), dim3(256), 0, st, A, A + plane,
+                                   Bm, Bm + plane, npad, epi, cf, C, C + plane, C64, w.lda, n, tfull, split, w.part,
+                                   zs);
+                if (rem)
+                    hipLaunchKernelGGL(ns128_tail_kernel, dim3(rem, 4, B), dim3(256), 0, st, w.part, tfull, split, npad,
+                                       epi, cf, C, C + plane, C64, w.lda, n, zs);
+                timing_end(slot, st, ns_flops);
+                return;
+            }
+        }
+        hipLaunchKernelGGL((ns_gemm_kernel<L>), dim3(ntile, 1, B), dim3(256), 0, st, A, A + plane, Bm, Bm + plane, npad,
+                           epi, cf, C, C + plane, C64, w.lda, n, zs);
         timing_end(slot, st, ns_flops);
     };
     for (int k = 0; k < iters; ++k) {
@@ -578,6 +851,12 @@ size_t mixed_layout(int n, int mode, void *base, MixedWs *w) {
     W.alpha = (double *)take(sizeof(double));
     W.status = (int *)take(sizeof(int) * 4);
     W.red = (double *)take(sizeof(double) * 2 * ((size_t)(n + 15) / 16 + 1));
+    W.part = nullptr;
+    if (mode == 1 && W.npad >= NS_BIG) {
+        int ntile, tfull, rem, split;
+        ns_tail_plan(W.npad, &ntile, &tfull, &rem, &split);
+        if (rem) W.part = (float *)take(sizeof(float) * NS_PART_FLOATS * (size_t)rem * split);
+    }
     W.nmem = 1;
     W.zs = 0;
     W.ioff = nullptr;

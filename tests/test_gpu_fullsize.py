@@ -12,7 +12,9 @@ bench.py times.
 * one d = 5 cone (32 W blocks of order 625 and 256 Choi blocks) by one plan
   launch: the W blocks of instances 0 and 31 and every Choi block against the
   oracle, and the Moreau identity on every block.
-* n = 4200, past 64 row blocks (the longest trailing loops): invariants."""
+* n = 4200, past 64 row blocks (the longest trailing loops): invariants.
+* n = 4000 in BF16 (the 128x128-tile product with the split tail): against
+  the closed form, within the BF16 band bound."""
 import numpy as np
 import pytest
 
@@ -77,6 +79,23 @@ def test_constructed_full_size_all_modes(P, n):
             assert err <= FP32_FULL_TOL
         else:
             assert err * nrm <= 2.0 * band + 1e-9 * nrm
+
+
+def test_constructed_4000_mixed_bf16(P):
+    # BF16 at an order past 3969: the 128x128-tile product with its split
+    # tail (528 tiles, the last 16 in 16 k-parts) and a ragged last tile row
+    # (npad = 4032); against the closed form, within the BF16 band bound
+    n = 4000
+    s, u, lam = W.constructed(n, 1008, gap=1e-6)
+    exact = oracle.constructed_projection(u, lam)
+    nrm = np.linalg.norm(exact)
+    band = np.sqrt(np.sum(lam[np.abs(lam) < 0.03] ** 2))
+    y, info = P.project(dev(s), n, "mixed_bf16", info=True)
+    err = np.linalg.norm(y.cpu().numpy() - exact)
+    print(f"n={n} mixed_bf16: rel err vs closed form {err / nrm:.2e} (band {band / nrm:.2e})", flush=True)
+    assert info["status"] == 0
+    assert abs(info["n_pos"] - int((lam > 0).sum())) <= int((np.abs(lam) < 0.03).sum())
+    assert err <= 2.0 * band + 1e-9 * nrm
 
 
 def _invariants(P, s, n):

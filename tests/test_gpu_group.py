@@ -99,11 +99,10 @@ def test_mixed_group_members_equal_single_blocks(P, mode, tol):
         off += m * m
 
 
-def test_mixed_bf16_group_big_tiles(P):
-    # 32 blocks of order 400 in BF16: the group's grid is large enough for the
-    # 128x128-tile product (a single block of this order takes the 64x64
-    # form, so here the members are checked against the closed form, not
-    # bitwise against single calls)
+def test_mixed_bf16_group_many_members(P):
+    # 32 blocks of order 400 in BF16 in one group (the 64x64-tile product, as
+    # for a single block of this order): against the closed form, and the
+    # first members bitwise against single calls
     n, count = 400, 32
     cons = [W.constructed(n, 7300 + i, gap=1e-3) for i in range(count)]
     y, infos = P.project_batched(dev(np.concatenate([c[0] for c in cons])), [n] * count, "mixed_bf16", info=True)
@@ -111,6 +110,26 @@ def test_mixed_bf16_group_big_tiles(P):
     for i, ((s, u, lam), inf) in enumerate(zip(cons, infos)):
         exact = oracle.constructed_projection(u, lam)
         band = np.sqrt(np.sum(lam[np.abs(lam) < 0.03] ** 2))
-        err = np.linalg.norm(y[i * n * n:(i + 1) * n * n] - exact)
+        got = y[i * n * n:(i + 1) * n * n]
+        err = np.linalg.norm(got - exact)
         assert inf["status"] == 0, i
         assert err <= 2.0 * band + 1e-9 * np.linalg.norm(exact), (i, err, band)
+        if i < 2:
+            assert np.array_equal(got, P.project(dev(s), n, "mixed_bf16").cpu().numpy()), i
+
+
+def test_mixed_bf16_group_large_orders(P):
+    # orders on the 128x128-tile product: two members of order 4000 (split
+    # tail, ragged last tile row) and one of 2100, each bitwise equal to its
+    # single-block call (the tile form depends on the order only)
+    sizes = [4000, 2100, 4000]
+    parts = [W.gue(m, 7400 + i) for i, m in enumerate(sizes)]
+    y, infos = P.project_batched(dev(np.concatenate(parts)), sizes, "mixed_bf16", info=True)
+    y = y.cpu().numpy()
+    off = 0
+    for i, (m, s, inf) in enumerate(zip(sizes, parts, infos)):
+        single, sinf = P.project(dev(s), m, "mixed_bf16", info=True)
+        assert np.array_equal(y[off:off + m * m], single.cpu().numpy()), (i, m)
+        assert inf == sinf, i
+        assert inf["status"] == 0
+        off += m * m
