@@ -268,7 +268,10 @@ __global__ void __launch_bounds__(256) ns_gemm_kernel(const L *__restrict__ Are,
         Cim = member_ptr(Cim, zs, mb);
         C64 = member_ptr(C64, zs, mb);
     }
-    constexpr int KP = 32 + (BF ? 8 : 4);  // padded k extent in LDS
+    // LDS rows: BF16 64 bytes unpadded, the 16-byte chunk q of row r at
+    // position q ^ f(r), f(r) = ((r >> 2) ^ (r >> 1)) & 3 (conflict-free
+    // stores and fragment reads); FP32 padded by 4
+    constexpr int KP = 32 + (BF ? 0 : 4);
     __shared__ __align__(16) L sAr[64][KP], sAi[64][KP], sBr[64][KP], sBi[64][KP];
     const int tb = xcd_tile(blockIdx.x, gridDim.x);
     int ti = (int)((sqrt(8.0 * tb + 1.0) - 1.0) * 0.5);
@@ -287,6 +290,7 @@ __global__ void __launch_bounds__(256) ns_gemm_kernel(const L *__restrict__ Are,
     // registers while the current one feeds the MFMAs.  FP32: loaded per
     // slice (the prefetch spills registers there).
     const int lr = t >> 2, lk = (t & 3) * 8;
+    const int lks = BF ? (((t & 3) ^ (((lr >> 2) ^ (lr >> 1)) & 3)) * 8) : lk;  // swizzled store position
     uint4 xr[1], xi[1], yr[1], yi[1];
     if constexpr (BF)
         ns_load_chunks<L, 1>(Are, Aim, Bre, Bim, (int64_t)lk + (int64_t)(i0 + lr) * npad,
@@ -295,10 +299,10 @@ __global__ void __launch_bounds__(256) ns_gemm_kernel(const L *__restrict__ Are,
         if constexpr (BF) {
             uint4 ai = xi[0];
             ai.x ^= 0x80008000u; ai.y ^= 0x80008000u; ai.z ^= 0x80008000u; ai.w ^= 0x80008000u;  // conj
-            *reinterpret_cast<uint4 *>(&sAr[lr][lk]) = xr[0];
-            *reinterpret_cast<uint4 *>(&sAi[lr][lk]) = ai;
-            *reinterpret_cast<uint4 *>(&sBr[lr][lk]) = yr[0];
-            *reinterpret_cast<uint4 *>(&sBi[lr][lk]) = yi[0];
+            *reinterpret_cast<uint4 *>(&sAr[lr][lks]) = xr[0];
+            *reinterpret_cast<uint4 *>(&sAi[lr][lks]) = ai;
+            *reinterpret_cast<uint4 *>(&sBr[lr][lks]) = yr[0];
+            *reinterpret_cast<uint4 *>(&sBi[lr][lks]) = yi[0];
         } else {
             const int64_t ao = (int64_t)(k0 + lk) + (int64_t)(i0 + lr) * npad;
             const int64_t bo = (int64_t)(k0 + lk) + (int64_t)(j0 + lr) * npad;
@@ -320,18 +324,20 @@ __global__ void __launch_bounds__(256) ns_gemm_kernel(const L *__restrict__ Are,
         }
         const int ii = lane & 15, kg = lane >> 4;
         if constexpr (BF) {
+            const int ks = (kg ^ (((ii >> 2) ^ (ii >> 1)) & 3)) * 8;  // rows 16 apart share f
             v8bf ar[2], ai[2], ain[2], br[2], bi[2];
 #pragma unroll
             for (int a = 0; a < 2; ++a) {
-                ar[a] = *reinterpret_cast<const v8bf *>(&sAr[wm * 32 + a * 16 + ii][kg * 8]);
-                ai[a] = *reinterpret_cast<const v8bf *>(&sAi[wm * 32 + a * 16 + ii][kg * 8]);
-                v8s neg = *reinterpret_cast<const v8s *>(&ai[a]) ^ (short)0x8000;
-                ain[a] = *reinterpret_cast<const v8bf *>(&neg);
+                ar[a] = *reinterpret_cast<const v8bf *>(&sAr[wm * 32 + a * 16 + ii][ks]);
+                uint4 u = *reinterpret_cast<const uint4 *>(&sAi[wm * 32 + a * 16 + ii][ks]);
+                ai[a] = *reinterpret_cast<const v8bf *>(&u);
+                u.x ^= 0x80008000u; u.y ^= 0x80008000u; u.z ^= 0x80008000u; u.w ^= 0x80008000u;
+                ain[a] = *reinterpret_cast<const v8bf *>(&u);
             }
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
-                br[b] = *reinterpret_cast<const v8bf *>(&sBr[wn * 32 + b * 16 + ii][kg * 8]);
-                bi[b] = *reinterpret_cast<const v8bf *>(&sBi[wn * 32 + b * 16 + ii][kg * 8]);
+                br[b] = *reinterpret_cast<const v8bf *>(&sBr[wn * 32 + b * 16 + ii][ks]);
+                bi[b] = *reinterpret_cast<const v8bf *>(&sBi[wn * 32 + b * 16 + ii][ks]);
             }
 #pragma unroll
             for (int a = 0; a < 2; ++a)
