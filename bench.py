@@ -18,7 +18,10 @@ Other workloads (one JSON line each, selected with --workload):
       after it (--mode fp64 | mixed_*)
 
 The JSON line carries the roofline of the dominant kernel, timed live with
-HIP events recorded by the library on the kernel's own launch stream, and the
+HIP events recorded by the library on the kernel's own launch stream (FP64:
+the tridiagonalisation's HEMV; mixed: the Newton-Schulz products or the FP64
+correction products, whichever takes more of a projection in an untimed
+probe, with the other as context), and the
 CPU oracle timed on a bounded sample of the same workload.  Its "traffic" is
 the HBM bytes per launch that rocprofv3 counters measured for that kernel
 (profiles/traffic_*.txt, scaled by the counters of a plain copy of known
@@ -78,6 +81,27 @@ def measured_traffic(kernel, n, source):
         return round(float(fields["hbm_bytes_per_launch"]), 1)
     except (KeyError, ValueError):
         return None
+
+
+def mfma_roofline(fp64_gemm, mode, n, timed):
+    """Roofline entry of an MFMA kernel family from (ms, launches, flops):
+    the FP64 GEMM or the Newton-Schulz products."""
+    achieved = timed[2] / (timed[0] * 1e-3) / 1e12
+    if fp64_gemm:
+        return {"kernel": "gemm_kernel<cd,...> (FP64 complex GEMM, 64x64 tiles: the FP64 corrections and "
+                          "the final product X S of the mixed form)",
+                "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                "algorithmic_flops_per_launch": round(timed[2] / timed[1], 1)}
+    peak = PEAK_BF16_TFLOPS if mode == "mixed_bf16" else PEAK_FP32_TFLOPS
+    npad = (n + 63) // 64 * 64
+    kname = ("ns_gemm128_kernel (128x128 tiles, direct global-to-LDS loads; split tail summed by "
+             "ns128_tail_kernel)" if mode == "mixed_bf16" and npad >= 2048 else
+             f"ns_gemm_kernel<{'bf16' if mode == 'mixed_bf16' else 'f32'}> (64x64 tiles)")
+    return {"kernel": kname + ", Hermitian-half complex GEMM of the Newton-Schulz steps",
+            "bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None,
+            "algorithmic_flops_per_launch": round(timed[2] / timed[1], 1)}
 
 
 def main():
@@ -218,10 +242,24 @@ def main():
     # Newton-Schulz GEMMs (mixed); the library brackets its launches with HIP
     # events on their launch stream -- the first projection's launches
     fam = None
+    other = None
     if mode == "fp64" and n > 64 and wl != "c4":
         fam, sample = _lib.KF_HEMV, n - 1
     elif mode != "fp64" and wl != "c4":
-        fam, sample = _lib.KF_NS, 2 * iters
+        # the Newton-Schulz products or the FP64 products (corrections and
+        # the final X S) -- whichever family takes more of one projection,
+        # from an untimed probe of each (the other is kept as context)
+        probe = {}
+        for f in (_lib.KF_NS, _lib.KF_GEMM):
+            _lib.timing_start(f, 4096)
+            P.project(X[0], n, mode, out=Y[0])
+            torch.cuda.synchronize()
+            probe[f] = _lib.timing_stop()
+        fam = max(probe, key=lambda f: probe[f][0])
+        sample = probe[fam][1]
+        o = _lib.KF_GEMM if fam == _lib.KF_NS else _lib.KF_NS
+        if probe[o][1] > 0:
+            other = (o, probe[o])
     if fam:
         _lib.timing_start(fam, sample)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -252,16 +290,14 @@ def main():
                         "traffic": measured_traffic("hemv_kernel", n, "tridiag.hip"),
                         "algorithmic_bytes_per_launch": round(timed[2] / timed[1], 1)}
         else:
-            peak = PEAK_BF16_TFLOPS if mode == "mixed_bf16" else PEAK_FP32_TFLOPS
-            achieved = timed[2] / (timed[0] * 1e-3) / 1e12
-            npad = (n + 63) // 64 * 64
-            kname = ("ns_gemm128_kernel (128x128 tiles, direct global-to-LDS loads; split tail summed by "
-                     "ns128_tail_kernel)" if mode == "mixed_bf16" and npad >= 2048 else
-                     f"ns_gemm_kernel<{'bf16' if mode == 'mixed_bf16' else 'f32'}> (64x64 tiles)")
-            roofline = {"kernel": kname + ", Hermitian-half complex GEMM of the Newton-Schulz steps",
-                        "bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                        "frac": round(achieved / peak, 4), "traffic": None,
-                        "algorithmic_flops_per_launch": round(timed[2] / timed[1], 1)}
+            roofline = mfma_roofline(fam == _lib.KF_GEMM, mode, n, timed)
+            if other:
+                o, pr = other
+                ctx = mfma_roofline(o == _lib.KF_GEMM, mode, n, pr)
+                ctx.update({"avg_launch_us": round(1e3 * pr[0] / pr[1], 3), "launches": pr[1],
+                            "share_of_projection_ms": round(pr[0], 3),
+                            "sample": "untimed probe projection (HIP events)"})
+                roofline["other_mfma_kernel"] = ctx
         roofline.update({"launches_timed": timed[1], "avg_launch_us": round(1e3 * avg_ms, 3),
                          "sample": "launches of the first projection in the timed region",
                          "share_of_step": round(timed[0] / ms_per_step, 4)})

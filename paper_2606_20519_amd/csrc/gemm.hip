@@ -21,7 +21,7 @@ namespace {
 using namespace gemmdev;
 
 template <typename T, int OPA, int OPB, int EPI>
-__global__ void __launch_bounds__(NT) gemm_kernel(GemmDesc d) {
+__global__ void __launch_bounds__(NT, 3) gemm_kernel(GemmDesc d) {
     __shared__ GemmLds<T> L;
     int tz = blockIdx.z, b = 0;
     if (d.nmem > 1) {
