@@ -600,18 +600,17 @@ __global__ void __launch_bounds__(256, 2) ns_gemm128_kernel(const __bf16 *Are, c
 #undef NS128_ISSUE
     if (idle) return;
     if (q >= 0) {
-        // raw partial sums, register order with the lane fastest
+        // raw partial sums: per (wave, block) 64 lanes x 4 values, one
+        // 16-byte store per lane and plane
         float *pp = part + (int64_t)q * NS_PART_FLOATS;
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int idx = ((w * 16 + a * 4 + b) * 4 + v) * 64 + lane;
-                    pp[idx] = accr[a][b][v];
-                    pp[NS_PART_FLOATS / 2 + idx] = acci[a][b][v];
-                }
+            for (int b = 0; b < 4; ++b) {
+                const int idx = ((w * 16 + a * 4 + b) * 64 + lane) * 4;
+                *reinterpret_cast<v4f *>(pp + idx) = accr[a][b];
+                *reinterpret_cast<v4f *>(pp + NS_PART_FLOATS / 2 + idx) = acci[a][b];
+            }
         return;
     }
 #pragma unroll
@@ -623,7 +622,8 @@ __global__ void __launch_bounds__(256, 2) ns_gemm128_kernel(const __bf16 *Are, c
 }
 
 // Tail tile tfull + blockIdx.x: its split partials summed in part order,
-// then the epilogue; workgroup y covers the block row a = y of every wave.
+// then the epilogue; workgroup y covers the 16x16 block (a, b) = (y / 4,
+// y % 4) of every wave.
 __global__ void __launch_bounds__(256) ns128_tail_kernel(const float *__restrict__ part, int tfull, int split, int npad,
                                                          int epi, float c, __bf16 *Cre, __bf16 *Cim, double2 *C64,
                                                          int64_t ld64, int n, int64_t zs) {
@@ -634,27 +634,19 @@ __global__ void __launch_bounds__(256) ns128_tail_kernel(const float *__restrict
         Cim = member_ptr(Cim, zs, mb);
         C64 = member_ptr(C64, zs, mb);
     }
-    const int a = blockIdx.y;
+    const int a = blockIdx.y >> 2, b = blockIdx.y & 3;
     int ti, tj;
     ns_tile_ij(tfull + (int)blockIdx.x, ti, tj);
     const int i0 = ti * 128, j0 = tj * 128;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w & 1, wn = w >> 1;
     if (ti == tj && wm == 0 && wn == 1) return;
-    const float *pp = part + (int64_t)blockIdx.x * split * NS_PART_FLOATS;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        v4f re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
-        for (int p = 0; p < split; ++p) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int idx = ((w * 16 + a * 4 + b) * 4 + v) * 64 + lane;
-                re[v] += pp[(int64_t)p * NS_PART_FLOATS + idx];
-                im[v] += pp[(int64_t)p * NS_PART_FLOATS + NS_PART_FLOATS / 2 + idx];
-            }
-        }
-        ns128_store_block(re, im, i0 + wm * 64 + a * 16, j0 + wn * 64 + b * 16, lane, npad, epi, c, Cre, Cim, C64, ld64,
-                          n);
+    const float *pp = part + (int64_t)blockIdx.x * split * NS_PART_FLOATS + ((w * 16 + a * 4 + b) * 64 + lane) * 4;
+    v4f re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+    for (int p = 0; p < split; ++p) {
+        re += *reinterpret_cast<const v4f *>(pp + (int64_t)p * NS_PART_FLOATS);
+        im += *reinterpret_cast<const v4f *>(pp + (int64_t)p * NS_PART_FLOATS + NS_PART_FLOATS / 2);
     }
+    ns128_store_block(re, im, i0 + wm * 64 + a * 16, j0 + wn * 64 + b * 16, lane, npad, epi, c, Cre, Cim, C64, ld64, n);
 }
 
 // ||T - 2I||_F^2 (T = 3I - S^2, so T - 2I = I - S^2) and tr S: partials per
@@ -760,7 +752,7 @@ hipError_t ns_run(const MixedWs &w, const double *x, double *y, psd_dev_info *in
                                    Bm, Bm + plane, npad, epi, cf, C, C + plane, C64, w.lda, n, tfull, split, w.part,
                                    zs);
                 if (rem)
-                    hipLaunchKernelGGL(ns128_tail_kernel, dim3(rem, 4, B), dim3(256), 0, st, w.part, tfull, split, npad,
+                    hipLaunchKernelGGL(ns128_tail_kernel, dim3(rem, 16, B), dim3(256), 0, st, w.part, tfull, split, npad,
                                        epi, cf, C, C + plane, C64, w.lda, n, zs);
                 timing_end(slot, st, ns_flops);
                 return;
