@@ -298,9 +298,11 @@ def main():
                             "share_of_projection_ms": round(pr[0], 3),
                             "sample": "untimed probe projection (HIP events)"})
                 roofline["other_mfma_kernel"] = ctx
+        # the timed launches belong to the first projection of the step
+        per_proj_ms = ms_per_step / (1 if wl == "c4" else blocks_per_step)
         roofline.update({"launches_timed": timed[1], "avg_launch_us": round(1e3 * avg_ms, 3),
                          "sample": "launches of the first projection in the timed region",
-                         "share_of_step": round(timed[0] / ms_per_step, 4)})
+                         "share_of_projection": round(timed[0] / per_proj_ms, 4)})
 
     if wl == "c2" and mode == "fp64" and not args.no_context:
         # context only: the same iterates as independent blocks of one batched
