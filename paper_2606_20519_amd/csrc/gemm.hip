@@ -45,7 +45,20 @@ __global__ void __launch_bounds__(NT, 3) gemm_kernel(GemmDesc d) {
         if (d.y) d.y += o;
         if (d.xbase) d.xbase += o;
     }
-    gemm_tile<T, OPA, OPB, EPI>(d, blockIdx.x, blockIdx.y, tz, L);
+    int ti = blockIdx.x, tj = blockIdx.y;
+    if (d.lower_only) {
+        // compact grid over the lower tiles only (M == N): column by column,
+        // longest column first, rows consecutive within a column (the order
+        // of the full grid, without the workgroups that would exit at once)
+        const int mt = (d.M + BM - 1) / BM;
+        const int t = mt * (mt + 1) / 2 - 1 - (int)blockIdx.x;
+        int u = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+        while ((u + 1) * (u + 2) / 2 <= t) ++u;
+        while (u * (u + 1) / 2 > t) --u;
+        tj = mt - 1 - u;
+        ti = mt - 1 - (t - u * (u + 1) / 2);
+    }
+    gemm_tile<T, OPA, OPB, EPI>(d, ti, tj, tz, L);
 }
 
 template <typename T, int OPA, int OPB>
@@ -59,6 +72,11 @@ __global__ void __launch_bounds__(NT) gemm_kernel_batched(const GemmDesc *ds, in
 template <typename T, int EPI>
 hipError_t launch_ops(const GemmDesc &d, hipStream_t st) {
     dim3 grid((d.M + BM - 1) / BM, (d.N + BN - 1) / BN, gemm_kslices(d) * std::max(1, d.nmem));
+    if (d.lower_only) {
+        const int mt = (d.M + BM - 1) / BM;
+        grid.x = mt * (mt + 1) / 2;
+        grid.y = 1;
+    }
     const int key = d.A.op * 2 + d.B.op;
     switch (key) {
         case 0: hipLaunchKernelGGL((gemm_kernel<T, OP_N, OP_N, EPI>), grid, dim3(NT), 0, st, d); break;
@@ -73,6 +91,7 @@ hipError_t launch_ops(const GemmDesc &d, hipStream_t st) {
 
 hipError_t gemm_launch(const GemmDesc &d, bool complex_data, int epilogue, hipStream_t st) {
     if (d.M <= 0 || d.N <= 0) return hipSuccess;
+    if (d.lower_only && d.M != d.N) return hipErrorInvalidValue;  // the lower-tile grid assumes a square output
     const int slot = timing_begin(KF_GEMM, st);
     hipError_t e;
     if (complex_data) {
