@@ -105,19 +105,24 @@ __global__ void final_kernel(const double2 *__restrict__ M, int64_t lda, int n, 
 //   direct part  A_IJ v_J      -> P[I][slot J]
 //   adjoint part A_IJ^H v_I    -> P[J][slot I]     (I > J only)
 //   tdot[tile]  = w * Re(v_I^H A_IJ v_J), w = 1 (diagonal) or 2
+// The tile stays in registers (thread: row = lane, columns g + 4k): the row
+// sums are per-thread partials over 16 columns summed over the 4 waves, the
+// column sums a split butterfly over the 64 lanes of the wave that owns the
+// column.  A diagonal tile holds its stored lower part L + D (D real), and
+// H v = (L + D) v + L^H v: the direct part over the lower part, the adjoint
+// part over the strict lower part added to the same rows.  Only the short
+// vectors pass through LDS, so three workgroups fit on a CU.
 // Diagonal-tile workgroups write v for their rows into vbuf and produce
 // p = V^H v and q = W^H v over their 64 rows for the c panel columns done.
 struct HemvLds {
-    double2 tile[TT * (TT + 1)];
     double2 vI[TT], vJ[TT];
-    double2 rowp[4][TT], colp[4][TT];
+    double2 rowp[4][TT], colp[TT];
 };
 
 __device__ void hemv_tile(const double2 *__restrict__ M, int64_t lda, int n, int j, int mt,
                           const double *__restrict__ npart, int nparts, double2 *vbuf,
                           const double2 *__restrict__ W, int p0, int c, double2 *P, double *tdot, double2 *pq,
                           double2 *taus, double *d, double *e, int b, HemvLds &L) {
-    auto &tile = L.tile;
     auto &vI = L.vI;
     auto &vJ = L.vJ;
     auto &rowp = L.rowp;
@@ -132,13 +137,12 @@ __device__ void hemv_tile(const double2 *__restrict__ M, int64_t lda, int n, int
     const double2 *colj = M + (int64_t)j * lda;
     const bool diag = I == J;
     const bool rowok = r0 + lane < n;
-    // The global loads of the tile are issued in two groups ahead of their
-    // use: two memory round trips per tile instead of a chain of them.
+    // every global load of the tile issued at once: one memory round trip
     double sp = 0.0;  // sigma: every wave reduces the same partials in the same lane order
     for (int k = lane; k < nparts; k += 64) sp += npart[k];
     const double2 alpha = colj[s];
     const double djj = (b == 0 && t == 0) ? colj[j].x : 0.0;
-    double2 tv[TT / 4];  // tile column g + 4k, row lane
+    double2 tv[TT / 4];  // tile column g + 4k, row lane (diagonal tile: lower part only)
 #pragma unroll
     for (int k = 0; k < TT / 4; ++k) {
         const int cc = g + 4 * k, col = c0 + cc;
@@ -148,18 +152,41 @@ __device__ void hemv_tile(const double2 *__restrict__ M, int64_t lda, int n, int
     const double2 cv = (t < 2 * TT && vrow < n && vrow != s) ? colj[vrow] : cmk(0.0, 0.0);
     const double sigma = warp_sum(sp);
     const Refl h = make_refl(alpha, sigma);
-#pragma unroll
-    for (int k = 0; k < TT / 4; ++k) tile[(g + 4 * k) * (TT + 1) + lane] = tv[k];
     if (t < 2 * TT) {
         double2 v = cmk(0.0, 0.0);
         if (vrow == s) v = cmk(1.0, 0.0);
         else if (vrow < n) v = cmul(cv, h.scale);
         if (t < TT) vI[t] = v; else vJ[t - TT] = v;
     }
-    // second group of loads, in flight while the strips are summed (issuing
-    // them with the first group would spill registers)
+    __syncthreads();
+    if (b == 0 && t == 0) {
+        d[j] = djj;
+        e[j] = h.beta;
+        taus[j] = h.tau;
+    }
+    // direct part: this thread's row over its 16 columns; adjoint part: the
+    // 16 column terms of this row, summed over the lanes below
+    const double2 vl = vI[lane];
+    double2 racc = cmk(0.0, 0.0);
+    double pv[TT / 2];  // {re, im} of column g + 4k at 2k, 2k + 1
+#pragma unroll
+    for (int k = 0; k < TT / 4; ++k) {
+        const int cc = g + 4 * k;
+        double2 a = tv[k];
+        if (diag && lane == cc) a.y = 0.0;  // the diagonal is real
+        racc = cfma(a, vJ[cc], racc);
+        const double2 z = (diag && lane == cc) ? cmk(0.0, 0.0) : cmulc(tv[k], vl);  // conj(A) v_I
+        pv[2 * k] = z.x;
+        pv[2 * k + 1] = z.y;
+    }
+    rowp[g][lane] = racc;
+    {
+        const double sum = wave_sum_split(pv);  // lane l: value l / 2
+        if ((lane & 1) == 0) reinterpret_cast<double *>(&colp[g + 4 * (lane >> 2)])[(lane >> 1) & 1] = sum;
+    }
+    // diagonal tiles: rows of the panel's V (q < c) and W (q >= c) columns,
+    // q = g + 4k (after the tile's registers are free)
     __builtin_amdgcn_sched_barrier(0);
-    // diagonal tiles: rows of the panel's V (q < c) and W (q >= c) columns, q = g + 4k
     double2 xq[TT / 4];
 #pragma unroll
     for (int k = 0; k < TT / 4; ++k) {
@@ -170,46 +197,17 @@ __device__ void hemv_tile(const double2 *__restrict__ M, int64_t lda, int n, int
             xq[k] = col[r0 + lane];
         }
     }
-    __syncthreads();
-    if (b == 0 && t == 0) {
-        d[j] = djj;
-        e[j] = h.beta;
-        taus[j] = h.tau;
-    }
-    // partial row sums (direct) and column sums (adjoint) over 16-wide strips
-    {
-        double2 racc = cmk(0.0, 0.0), cacc = cmk(0.0, 0.0);
-        const int k0 = 16 * g;
-        if (I == J) {
-#pragma unroll 4
-            for (int cc = k0; cc < k0 + 16; ++cc) {
-                double2 a;
-                if (cc < lane) a = tile[cc * (TT + 1) + lane];
-                else if (cc == lane) a = cmk(tile[cc * (TT + 1) + lane].x, 0.0);
-                else a = cconj(tile[lane * (TT + 1) + cc]);
-                racc = cfma(a, vI[cc], racc);
-            }
-        } else {
-#pragma unroll 4
-            for (int cc = k0; cc < k0 + 16; ++cc) racc = cfma(tile[cc * (TT + 1) + lane], vJ[cc], racc);
-#pragma unroll 4
-            for (int rr = k0; rr < k0 + 16; ++rr) cacc = cfmac(tile[lane * (TT + 1) + rr], vI[rr], cacc);
-        }
-        rowp[g][lane] = racc;
-        colp[g][lane] = cacc;
-    }
     // diagonal tiles: p = V^H v, q = W^H v over these rows, 2c columns,
     // column q on wave q % 4 with the 64 rows on the lanes
     if (diag && c > 0) {
-        const double2 vl = vI[lane];
-        double pv[TT / 2];  // {re, im} of column g + 4k at 2k, 2k + 1
+        double pw[TT / 2];
 #pragma unroll
         for (int k = 0; k < TT / 4; ++k) {
             const double2 pr = cmulc(xq[k], vl);
-            pv[2 * k] = pr.x;
-            pv[2 * k + 1] = pr.y;
+            pw[2 * k] = pr.x;
+            pw[2 * k + 1] = pr.y;
         }
-        const double sum = wave_sum_split(pv);  // lane l: value l / 2
+        const double sum = wave_sum_split(pw);  // lane l: value l / 2
         const int q = g + 4 * (lane >> 2);
         if ((lane & 1) == 0 && q < 2 * c)
             reinterpret_cast<double *>(pq)[2 * (((int64_t)I * 2 + (q < c ? 0 : 1)) * NB + (q < c ? q : q - c)) +
@@ -217,20 +215,20 @@ __device__ void hemv_tile(const double2 *__restrict__ M, int64_t lda, int n, int
     }
     __syncthreads();
     if (t < TT) {
-        const double2 y = cadd(cadd(rowp[0][t], rowp[1][t]), cadd(rowp[2][t], rowp[3][t]));
+        double2 y = cadd(cadd(rowp[0][t], rowp[1][t]), cadd(rowp[2][t], rowp[3][t]));
+        if (diag) y = cadd(y, colp[t]);
         P[((int64_t)I * mt + J) * TT + t] = y;
-        if (I == J && r0 + t < n) vbuf[r0 + t] = vI[t];
+        if (diag && r0 + t < n) vbuf[r0 + t] = vI[t];
         const double dv = warp_sum(cmulc(vI[t], y).x);
-        if (t == 0) tdot[b] = (I == J) ? dv : 2.0 * dv;
-    } else if (t < 2 * TT && I != J) {
+        if (t == 0) tdot[b] = diag ? dv : 2.0 * dv;
+    } else if (t < 2 * TT && !diag) {
         const int cc = t - TT;
-        const double2 z = cadd(cadd(colp[0][cc], colp[1][cc]), cadd(colp[2][cc], colp[3][cc]));
-        P[((int64_t)J * mt + I) * TT + cc] = z;
+        P[((int64_t)J * mt + I) * TT + cc] = colp[cc];
     }
     __syncthreads();  // LDS reuse by a following call in the same workgroup
 }
 
-__global__ void __launch_bounds__(256, 2) hemv_kernel(const double2 *__restrict__ M, int64_t lda, int n, int j,
+__global__ void __launch_bounds__(256, 3) hemv_kernel(const double2 *__restrict__ M, int64_t lda, int n, int j,
                                                    int mt, const double *__restrict__ npart, int nparts,
                                                    double2 *vbuf, const double2 *__restrict__ W, int p0, int c,
                                                    double2 *P, double *tdot, double2 *pq, double2 *taus,
