@@ -158,14 +158,90 @@ __global__ void __launch_bounds__(256) dc_prep_kernel(int level, int n, int nl, 
         for (int i = t; i < nm; i += blockDim.x) { zl[i] = z[i]; dl[i] = dd[i]; }
     }
     __syncthreads();
+    // Fast path, in parallel: merge the two ascending halves by ranks (ties:
+    // the first half first), split the merged order into deflated (small z)
+    // and kept entries, and test every consecutive kept pair for the
+    // close-pair rotation with the scan's own expression.  When no pair
+    // qualifies (and both halves are ascending) nothing rotates, and this is
+    // exactly what the sequential scan below produces; otherwise the scan
+    // runs from scratch.
+    __shared__ int fast_ok;
+    __shared__ int kcnt[256];
+    const double tol = 8.0 * EPS * fmax(dmax, rho * zmax);
+    if (t == 0) fast_ok = 1;
+    __syncthreads();
+    for (int i = t; i + 1 < nm; i += blockDim.x)
+        if (i + 1 != n1 && dl[i + 1] < dl[i]) fast_ok = 0;
+    for (int i = t; i < nm; i += blockDim.x) {
+        const double v = dl[i];
+        int pos;
+        if (i < n1) {  // second-half values strictly below v
+            int lo = n1, hi = nm;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (dl[mid] < v) lo = mid + 1; else hi = mid;
+            }
+            pos = i + (lo - n1);
+        } else {  // first-half values at or below v
+            int lo = 0, hi = n1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (dl[mid] <= v) lo = mid + 1; else hi = mid;
+            }
+            pos = (i - n1) + lo;
+        }
+        pl[pos] = i;  // in range whatever the data; overwritten by the scan if unsorted
+    }
+    __syncthreads();
+    const int chunk = (nm + 255) / 256;
+    const int cb0 = min(nm, t * chunk), cb1 = min(nm, cb0 + chunk);
+    {
+        int nk = 0;
+        for (int idx = cb0; idx < cb1; ++idx) nk += (rho * fabs(zl[pl[idx]]) <= tol) ? 0 : 1;
+        kcnt[t] = nk;
+    }
+    __syncthreads();
     if (t == 0) {
+        int acc = 0;
+        for (int u = 0; u < 256; ++u) {
+            const int cu = kcnt[u];
+            kcnt[u] = acc;
+            acc += cu;
+        }
+        red_k = acc;
+    }
+    __syncthreads();
+    {
+        int kk = kcnt[t], nd0 = cb0 - kcnt[t];
+        for (int idx = cb0; idx < cb1; ++idx) {
+            const int p = pl[idx];
+            if (rho * fabs(zl[p]) <= tol) defl[nd0++] = p;
+            else keep[kk++] = p;
+        }
+    }
+    __syncthreads();
+    {
+        const int kt = red_k;
+        for (int i = 1 + t; i < kt; i += blockDim.x) {
+            const int prev = keep[i - 1], p = keep[i];
+            const double tz = hypot(zl[prev], zl[p]);
+            const double c = zl[p] / tz, s = -zl[prev] / tz;
+            const double tt = dl[p] - dl[prev];
+            if (fabs(tt * c * s) <= tol) fast_ok = 0;
+        }
+    }
+    __syncthreads();
+    if (t == 0 && fast_ok) {
+        red_nd = nm - red_k;
+        red_nr = 0;
+    }
+    if (t == 0 && !fast_ok) {
         // merge the two ascending halves into one ascending order
         int i1 = 0, i2 = n1, o = 0;
         while (i1 < n1 && i2 < nm) pl[o++] = (dl[i2] < dl[i1]) ? i2++ : i1++;
         while (i1 < n1) pl[o++] = i1++;
         while (i2 < nm) pl[o++] = i2++;
         // deflation
-        const double tol = 8.0 * EPS * fmax(dmax, rho * zmax);
         int k = 0, nd = 0, nr = 0, prev = -1;
         for (int idx = 0; idx < nm; ++idx) {
             const int p = pl[idx];
