@@ -85,6 +85,20 @@ def test_large_degenerate_spectrum(P):
     assert rel(y, oracle.project(s, n)) <= TOL
 
 
+def test_large_clustered_and_distinct_spectrum(P):
+    # clusters (close-pair deflation by rotation: the sequential merge scan)
+    # next to distinct eigenvalues (the parallel merge), n = 301
+    n = 301
+    rng = np.random.default_rng(11)
+    u = W.haar_unitary(n, rng)
+    lam = np.concatenate([np.repeat([-1.5, 0.75], 60), np.full(40, 1e-9), rng.uniform(-3.0, 3.0, n - 160)])
+    x = (u * lam) @ u.conj().T
+    s = W.upper_pack((x + x.conj().T) / 2)
+    y = P.project(dev(s), n).cpu().numpy()
+    assert rel(y, oracle.constructed_projection(u, lam)) <= 1e-12
+    assert rel(y, oracle.project(s, n)) <= TOL
+
+
 def test_large_special_inputs(P):
     n = 80
     d = np.linspace(-3.0, 5.0, n)
