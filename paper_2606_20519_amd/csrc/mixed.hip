@@ -241,6 +241,62 @@ __device__ __forceinline__ void ns_load_chunks(const L *__restrict__ Are, const 
     }
 }
 
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+// Epilogue of one 32x32 block at (ib, jb), BF16 planes (as ns_gemm_kernel's
+// 16x16 one: the lower part with its conjugate mirror).  32x32x16 output
+// layout: D[i][j] in lane j + 32 ((i / 4) % 2), element 4 (i / 8) + i % 4.
+__device__ __forceinline__ void ns_store_block32(const v16f &accr, const v16f &acci, int ib, int jb, int lane, int npad,
+                                                 int epi, float c, __bf16 *Cre, __bf16 *Cim, double2 *C64,
+                                                 int64_t ld64, int n) {
+    if (ib < jb || ib >= npad) return;
+    const int j = jb + (lane & 31), ih = 4 * (lane >> 5);
+    if (epi != NS_EPI_F64 && ib > jb) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int ir = ib + 8 * g + ih;
+            union { __bf16 h[4]; uint2 u; } pr, pi, pn;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                float re = accr[4 * g + v], im = acci[4 * g + v];
+                if (epi == NS_EPI_T) { re = -c * re; im = -c * im; }
+                else { re *= c; im *= c; }
+                pr.h[v] = (__bf16)re;
+                pi.h[v] = (__bf16)im;
+                pn.h[v] = (__bf16)(-im);
+            }
+            const int64_t o = (int64_t)ir + (int64_t)j * npad;
+            *reinterpret_cast<uint2 *>(Cre + o) = pr.u;
+            *reinterpret_cast<uint2 *>(Cim + o) = pi.u;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t om = (int64_t)j + (int64_t)(ir + v) * npad;
+                Cre[om] = pr.h[v];
+                Cim[om] = pn.h[v];
+            }
+        }
+        return;
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = ib + 8 * (r >> 2) + ih + (r & 3);
+        if (i < j) continue;
+        float re = accr[r], im = acci[r];
+        if (epi == NS_EPI_T) { re = (i == j ? 3.0f : 0.0f) - c * re; im = -c * im; }
+        else { re *= c; im *= c; }
+        if (i == j) im = 0.0f;
+        if (epi != NS_EPI_F64) {
+            const __bf16 lr = (__bf16)re, li = (__bf16)im, lni = (__bf16)(-im);
+            const int64_t o = (int64_t)i + (int64_t)j * npad, om = (int64_t)j + (int64_t)i * npad;
+            Cre[o] = lr; Cim[o] = li;
+            Cre[om] = lr; Cim[om] = lni;
+        } else if (i < n && j < n) {
+            C64[i + (int64_t)j * ld64] = cmk((double)re, (double)im);
+            C64[j + (int64_t)i * ld64] = cmk((double)re, -(double)im);
+        }
+    }
+}
+
 // C = A B for Hermitian A, B that commute (polynomials in the same X), so C
 // is Hermitian: only the lower tiles (ti >= tj) are computed, and each is
 // written together with its conjugate mirror, which keeps every iterate
@@ -280,11 +336,18 @@ __global__ void __launch_bounds__(256) ns_gemm_kernel(const L *__restrict__ Are,
     const int tj = tb - ti * (ti + 1) / 2;
     const int i0 = ti * 64, j0 = tj * 64;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w & 1, wn = w >> 1;
+    // FP32: 2x2 blocks of 16x16x4 per wave; BF16: one 32x32x16 block per wave
+    // (two accumulators: with one wave per SIMD, as for a single block of
+    // order ~1300, the 32x32 form keeps the MFMA pipe far busier)
     v4f accr[2][2], acci[2][2];
+    v16f accr32, acci32;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) { accr[a][b] = v4f{0, 0, 0, 0}; acci[a][b] = v4f{0, 0, 0, 0}; }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) { accr32[r] = 0.0f; acci32[r] = 0.0f; }
+    const bool idle = ti == tj && wm == 0 && wn == 1;  // wave tile above the diagonal
     // loader: thread t covers row (t/4) of the tile, k = 8*(t%4) .. +7.
     // BF16: one 16-byte chunk per plane, and the next k-slice is loaded into
     // registers while the current one feeds the MFMAs.  FP32: loaded per
@@ -324,30 +387,27 @@ __global__ void __launch_bounds__(256) ns_gemm_kernel(const L *__restrict__ Are,
         }
         const int ii = lane & 15, kg = lane >> 4;
         if constexpr (BF) {
-            const int ks = (kg ^ (((ii >> 2) ^ (ii >> 1)) & 3)) * 8;  // rows 16 apart share f
-            v8bf ar[2], ai[2], ain[2], br[2], bi[2];
+            // 32x32x16 operands: row lane % 32 of the wave's 32 rows, k chunk
+            // 2h + lane / 32 (rows 32 apart share the swizzle)
+            const int rl = lane & 31, kh = lane >> 5;
+            const int fsw = ((rl >> 2) ^ (rl >> 1)) & 3;
+            if (!idle) {
 #pragma unroll
-            for (int a = 0; a < 2; ++a) {
-                ar[a] = *reinterpret_cast<const v8bf *>(&sAr[wm * 32 + a * 16 + ii][ks]);
-                uint4 u = *reinterpret_cast<const uint4 *>(&sAi[wm * 32 + a * 16 + ii][ks]);
-                ai[a] = *reinterpret_cast<const v8bf *>(&u);
-                u.x ^= 0x80008000u; u.y ^= 0x80008000u; u.z ^= 0x80008000u; u.w ^= 0x80008000u;
-                ain[a] = *reinterpret_cast<const v8bf *>(&u);
-            }
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                br[b] = *reinterpret_cast<const v8bf *>(&sBr[wn * 32 + b * 16 + ii][ks]);
-                bi[b] = *reinterpret_cast<const v8bf *>(&sBi[wn * 32 + b * 16 + ii][ks]);
-            }
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    accr[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar[a], br[b], accr[a][b], 0, 0, 0);
-                    accr[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ain[a], bi[b], accr[a][b], 0, 0, 0);
-                    acci[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar[a], bi[b], acci[a][b], 0, 0, 0);
-                    acci[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai[a], br[b], acci[a][b], 0, 0, 0);
+                for (int h = 0; h < 2; ++h) {
+                    const int pos = ((2 * h + kh) ^ fsw) * 8;
+                    const v8bf ar = *reinterpret_cast<const v8bf *>(&sAr[wm * 32 + rl][pos]);
+                    uint4 u = *reinterpret_cast<const uint4 *>(&sAi[wm * 32 + rl][pos]);  // -Im of the stored column
+                    const v8bf ai = *reinterpret_cast<const v8bf *>(&u);
+                    u.x ^= 0x80008000u; u.y ^= 0x80008000u; u.z ^= 0x80008000u; u.w ^= 0x80008000u;
+                    const v8bf ain = *reinterpret_cast<const v8bf *>(&u);
+                    const v8bf br = *reinterpret_cast<const v8bf *>(&sBr[wn * 32 + rl][pos]);
+                    const v8bf bi = *reinterpret_cast<const v8bf *>(&sBi[wn * 32 + rl][pos]);
+                    accr32 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar, br, accr32, 0, 0, 0);
+                    acci32 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar, bi, acci32, 0, 0, 0);
+                    accr32 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ain, bi, accr32, 0, 0, 0);
+                    acci32 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ai, br, acci32, 0, 0, 0);
                 }
+            }
         } else {
 #pragma unroll
             for (int ks = 0; ks < 32; ks += 4) {
@@ -374,6 +434,11 @@ __global__ void __launch_bounds__(256) ns_gemm_kernel(const L *__restrict__ Are,
             }
         }
         __syncthreads();
+    }
+    if constexpr (BF) {
+        if (!idle)
+            ns_store_block32(accr32, acci32, i0 + wm * 32, j0 + wn * 32, lane, npad, epi, c, Cre, Cim, C64, ld64, n);
+        return;
     }
     // epilogue; f32-accumulating 16x16 MFMA layout: D[i][j] in lane
     // j + 16*(i/4), element i % 4
