@@ -35,7 +35,6 @@
 #include "common.h"
 #include "large.h"
 #include "mixed.h"
-#include "ql.h"
 #include "timing.h"
 
 namespace psd {
@@ -142,20 +141,64 @@ __global__ void __launch_bounds__(1024) lz_step_kernel(int n, int step, const do
 }
 
 // alpha = 1.1 max |theta| over the Ritz values of the Lanczos tridiagonal.
+// Eigenvalues of the real symmetric tridiagonal (d, e) of order k below x
+// (Sturm count: negative pivots of T - xI = L D L^T).
+__device__ __forceinline__ int lz_sturm(const double *d, const double *e, int k, double x) {
+    int cnt = 0;
+    double q = 1.0;
+    for (int i = 0; i < k; ++i) {
+        const double off = i > 0 ? e[i - 1] * e[i - 1] / q : 0.0;
+        q = d[i] - x - off;
+        if (q == 0.0) q = -1e-300;  // a zero pivot counts as negative (x at an eigenvalue)
+        cnt += q < 0.0 ? 1 : 0;
+    }
+    return cnt;
+}
+
+// alpha = 1.1 max |theta| over the Ritz values theta of the k-step Lanczos
+// tridiagonal: its largest and smallest eigenvalues by multisection, the 64
+// lanes testing 64 shifts of the current interval per step (the interval
+// shrinks 65-fold), from the Gershgorin bounds until it is below 1e-14 of
+// its magnitude; the interval's outer end bounds |theta| from above.
 __global__ void __launch_bounds__(64) lz_final_kernel(const double *ab, double *alpha_out, int64_t zs) {
-    __shared__ double d[64], e[64], Z[LZ_STEPS * LZ_STEPS], rc[64], rs[64];
+    __shared__ double d[LZ_STEPS], e[LZ_STEPS];
     ab = member_ptr(ab, zs, blockIdx.z);
     alpha_out = member_ptr(alpha_out, zs, blockIdx.z);
-    __shared__ int ri[64], nrot_s, done_s;
     const int k = (int)ab[2 * LZ_STEPS];
     const int t = threadIdx.x;
     if (t < k) { d[t] = ab[t]; e[t] = t < k - 1 ? ab[LZ_STEPS + t] : 0.0; }
-    for (int idx = t; idx < k * k; idx += blockDim.x) Z[idx] = (idx % k == idx / k) ? 1.0 : 0.0;
     __syncthreads();
-    if (k > 0) ql_implicit(d, e, Z, k, k, rc, rs, ri, &nrot_s, &done_s);
+    if (k <= 0) {
+        if (t == 0) *alpha_out = 1.0;
+        return;
+    }
+    double glo = 0.0, ghi = 0.0;
+    for (int i = 0; i < k; ++i) {
+        const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < k - 1 ? fabs(e[i]) : 0.0);
+        glo = i == 0 ? d[i] - r : fmin(glo, d[i] - r);
+        ghi = i == 0 ? d[i] + r : fmax(ghi, d[i] + r);
+    }
+    double bound[2];
+    for (int side = 0; side < 2; ++side) {
+        // side 0: largest eigenvalue (count(x) == k iff x > it);
+        // side 1: smallest (count(x) >= 1 iff x > it)
+        double lo = glo - 1e-300, hi = ghi + 1e-300;
+        for (int it = 0; it < 20 && hi - lo > 1e-14 * fmax(fabs(lo), fabs(hi)); ++it) {
+            const double x = lo + (hi - lo) * (double)(t + 1) / 65.0;
+            const int cnt = lz_sturm(d, e, k, x);
+            const bool above = side == 0 ? cnt == k : cnt >= 1;
+            // the first lane whose shift lies above the eigenvalue
+            const unsigned long long mask = __ballot(above);
+            const int first = mask ? __ffsll(mask) - 1 : 64;
+            const double nhi = first < 64 ? lo + (hi - lo) * (double)(first + 1) / 65.0 : hi;
+            const double nlo = first > 0 ? lo + (hi - lo) * (double)first / 65.0 : lo;
+            lo = nlo;
+            hi = nhi;
+        }
+        bound[side] = side == 0 ? hi : lo;
+    }
     if (t == 0) {
-        double m = 0.0;
-        for (int i = 0; i < k; ++i) m = fmax(m, fabs(d[i]));
+        const double m = fmax(fabs(bound[0]), fabs(bound[1]));
         *alpha_out = m > 0.0 ? 1.1 * m : 1.0;
     }
 }
