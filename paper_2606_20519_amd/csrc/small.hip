@@ -5,146 +5,141 @@
 //
 // Steps, all in LDS (M = conj X, column-major, see common.h):
 //   1. unpack the svec block (App. D.1 vec_R) into the full Hermitian M;
-//   2. Householder reduction M = Q T Q^H to a real symmetric tridiagonal T
-//      (reflectors H_j = I - tau_j v_j v_j^H with real subdiagonal beta_j);
-//   3. implicit-shift QL iteration on T, accumulating the rotations into Z
-//      (T = Z diag(lambda) Z^T);
-//   4. back-transform V = Q Z for the smaller sign side only;
-//   5. Pi = V+ diag(lambda+) V+^H, or X + V- diag(|lambda-|) V-^H when fewer
+//   2. two-sided Jacobi M <- U^H M U, V <- V U, until M is diagonal: each
+//      step applies n/2 disjoint plane rotations at once (round-robin
+//      pairing, every pair once per sweep), each a phase on index q that
+//      makes M(p,q) real followed by the real rotation that zeroes it;
+//      rotations below the relative threshold eps sqrt(|M(p,p)| |M(q,q)|)
+//      are skipped, and the iteration stops after a sweep without one;
+//   3. Pi = V+ diag(lambda+) V+^H, or X + V- diag(|lambda-|) V-^H when fewer
 //      eigenvalues are non-positive (App. D.2: eigendecompose, zero the
 //      negative eigenvalues), written straight back as svec.
+// Every step is n/2 independent rotations over the 256 threads: a few
+// dozen barrier-separated steps per sweep, where a tridiagonal QL computes
+// its rotations one after another.
 #include "common.h"
 #include "kernels.h"
-#include "ql.h"
 
 namespace psd {
 
-constexpr int SB_MAX = 64;   // largest order served
-constexpr int SB_LD = 64;    // LDS leading dimension
-constexpr int SB_NT = 256;   // threads per workgroup
-constexpr int SB_KMAX = 32;  // max columns back-transformed at once
+constexpr int SB_MAX = 64;     // largest order served
+constexpr int SB_LD = 64;      // LDS leading dimension
+constexpr int SB_NT = 256;     // threads per workgroup
+constexpr int SB_SWEEPS = 40;  // sweeps before reporting non-convergence
 
 struct SmallLds {
-    cd A[SB_LD * SB_MAX];       // M, then reflectors below the subdiagonal
-    double Z[SB_LD * SB_MAX];   // tridiagonal eigenvectors
-    cd Vs[SB_LD * SB_KMAX];     // back-transformed columns
-    cd part[4 * SB_MAX];        // partial row sums
-    cd w[SB_MAX];
-    cd tau[SB_MAX];
-    double d[SB_MAX], e[SB_MAX], lam[SB_MAX];
-    double rc[SB_MAX], rs[SB_MAX];
-    double scal[SB_KMAX];
+    cd A[SB_LD * SB_MAX];  // M, rotated towards diagonal form
+    cd V[SB_LD * SB_MAX];  // accumulated rotations: eigenvectors in the columns
+    // rotation of pair k of the current step: columns p, q, cosine, sine,
+    // phase e^{i phi} of M(p, q), and the new diagonal entries
+    int rp[SB_MAX / 2 + 1], rq[SB_MAX / 2 + 1];
+    double rc[SB_MAX / 2 + 1], rs[SB_MAX / 2 + 1], rdp[SB_MAX / 2 + 1], rdq[SB_MAX / 2 + 1];
+    cd rph[SB_MAX / 2 + 1];
+    int ract[SB_MAX / 2 + 1];
+    double lam[SB_MAX], scal[SB_MAX];
     int perm[SB_MAX];
-    int sel[SB_KMAX];
-    double red[SB_NT / 64 * 2];
-    int nrot, done, status, ksel, sgn;
+    int sel[SB_MAX];
+    int rotated, status, ksel, sgn;
 };
 
-__device__ void small_ql(SmallLds &S, int n) {
-    int st = ql_implicit(S.d, S.e, S.Z, SB_LD, n, S.rc, S.rs, S.perm, &S.nrot, &S.done);
-    if (threadIdx.x == 0 && st != ST_OK && S.status == ST_OK) S.status = st;
-    __syncthreads();
+// Pair k of round r of the round-robin over m (even) indices: index m - 1 is
+// fixed, the others turn; every pair occurs once in rounds 0 .. m-2.
+__device__ __forceinline__ void rr_pair(int m, int r, int k, int &p, int &q) {
+    int a, b;
+    if (k == 0) {
+        a = r;
+        b = m - 1;
+    } else {
+        a = (r + k) % (m - 1);
+        b = (r - k + (m - 1)) % (m - 1);
+    }
+    p = min(a, b);
+    q = max(a, b);
 }
 
-// Householder reduction of the Hermitian matrix in S.A (order n) to real
-// tridiagonal form (d, e), reflectors stored below the diagonal with the unit
-// leading entry written explicitly.
-__device__ void small_tridiag(SmallLds &S, int n) {
+// Two-sided Jacobi of the Hermitian S.A (order n), V = I on entry.
+__device__ void small_jacobi(SmallLds &S, int n) {
     const int t = threadIdx.x;
-    for (int j = 0; j + 1 < n; ++j) {
-        const int m = n - j - 1;  // trailing order
-        // sigma = sum |x_r|^2 for r >= j+2
-        double part = 0.0;
-        for (int r = j + 2 + t; r < n; r += SB_NT) part += cabs2(S.A[r + j * SB_LD]);
-        const double sigma = block_sum(part, S.red);
-        const cd alpha = S.A[(j + 1) + j * SB_LD];
-        cd tau, scale;
-        double beta;
-        if (sigma == 0.0 && alpha.y == 0.0) {
-            tau = cmk(0.0, 0.0); beta = alpha.x; scale = cmk(0.0, 0.0);
-        } else {
-            beta = -copysign(sqrt(cabs2(alpha) + sigma), alpha.x);
-            tau = cmk((beta - alpha.x) / beta, -alpha.y / beta);
-            scale = cdiv(cmk(1.0, 0.0), cmk(alpha.x - beta, alpha.y));
-        }
+    const double eps = 2.220446049250313e-16;
+    const int m = n + (n & 1);  // an odd order gets a dummy index n that never rotates
+    const int npairs = m / 2;
+    int sweep = 0;
+    for (; sweep < SB_SWEEPS; ++sweep) {
+        if (t == 0) S.rotated = 0;
         __syncthreads();
-        for (int r = j + 2 + t; r < n; r += SB_NT) S.A[r + j * SB_LD] = cmul(S.A[r + j * SB_LD], scale);
-        if (t == 0) {
-            S.A[(j + 1) + j * SB_LD] = cmk(1.0, 0.0);
-            S.d[j] = S.A[j + j * SB_LD].x;
-            S.e[j] = beta;
-            S.tau[j] = tau;
-        }
-        __syncthreads();
-        if (tau.x == 0.0 && tau.y == 0.0) continue;
-        // w = tau * A' v  over the trailing block (rows/cols j+1..n-1)
-        {
-            const int r = t & 63, q = t >> 6;
-            cd acc = cmk(0.0, 0.0);
-            if (r < m) {
-                for (int c = q; c < m; c += 4)
-                    acc = cfma(S.A[(j + 1 + r) + (j + 1 + c) * SB_LD], S.A[(j + 1 + c) + j * SB_LD], acc);
+        for (int r = 0; r + 1 < m; ++r) {
+            // 1. rotation parameters, one thread per pair, from the current M
+            if (t < npairs) {
+                int p, q;
+                rr_pair(m, r, t, p, q);
+                S.rp[t] = p;
+                S.rq[t] = q;
+                int act = 0;
+                if (q < n) {
+                    const cd apq = S.A[p + q * SB_LD];
+                    const double app = S.A[p + p * SB_LD].x, aqq = S.A[q + q * SB_LD].x;
+                    const double rr = sqrt(cabs2(apq));
+                    if (rr > 0.0 && rr > eps * sqrt(fabs(app) * fabs(aqq))) {
+                        act = 1;
+                        const cd ph = cmk(apq.x / rr, apq.y / rr);  // e^{i phi}
+                        const double tau = (aqq - app) / (2.0 * rr);
+                        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        const double c = 1.0 / sqrt(1.0 + tt * tt);
+                        S.rc[t] = c;
+                        S.rs[t] = tt * c;
+                        S.rph[t] = ph;
+                        S.rdp[t] = app - tt * rr;
+                        S.rdq[t] = aqq + tt * rr;
+                        S.rotated = 1;  // benign race: all writers store 1
+                    }
+                }
+                S.ract[t] = act;
             }
-            S.part[q * SB_MAX + r] = acc;
+            __syncthreads();
+            // 2. rows p, q of every active pair: (U^H M) with U = D J,
+            //    D = diag(1, conj(ph)) on q, J = [[c, s], [-s, c]]
+            for (int idx = t; idx < npairs * n; idx += SB_NT) {
+                const int k = idx / n, col = idx % n;
+                if (!S.ract[k]) continue;
+                const int p = S.rp[k], q = S.rq[k];
+                const double c = S.rc[k], sn = S.rs[k];
+                const cd ph = S.rph[k];
+                const cd ap = S.A[p + col * SB_LD], aq = cmul(ph, S.A[q + col * SB_LD]);
+                S.A[p + col * SB_LD] = cmk(c * ap.x - sn * aq.x, c * ap.y - sn * aq.y);
+                S.A[q + col * SB_LD] = cmk(sn * ap.x + c * aq.x, sn * ap.y + c * aq.y);
+            }
+            __syncthreads();
+            // 3. columns p, q of M and V: (M U), (V U); the 2x2 block of each
+            //    pair set to its exact diagonal form
+            for (int idx = t; idx < npairs * n; idx += SB_NT) {
+                const int k = idx / n, row = idx % n;
+                if (!S.ract[k]) continue;
+                const int p = S.rp[k], q = S.rq[k];
+                const double c = S.rc[k], sn = S.rs[k];
+                const cd phc = cconj(S.rph[k]);
+                {
+                    const cd ap = S.A[row + p * SB_LD], aq = cmul(phc, S.A[row + q * SB_LD]);
+                    cd np = cmk(c * ap.x - sn * aq.x, c * ap.y - sn * aq.y);
+                    cd nq = cmk(sn * ap.x + c * aq.x, sn * ap.y + c * aq.y);
+                    if (row == p) { np = cmk(S.rdp[k], 0.0); nq = cmk(0.0, 0.0); }
+                    if (row == q) { np = cmk(0.0, 0.0); nq = cmk(S.rdq[k], 0.0); }
+                    S.A[row + p * SB_LD] = np;
+                    S.A[row + q * SB_LD] = nq;
+                }
+                {
+                    const cd vp = S.V[row + p * SB_LD], vq = cmul(phc, S.V[row + q * SB_LD]);
+                    S.V[row + p * SB_LD] = cmk(c * vp.x - sn * vq.x, c * vp.y - sn * vq.y);
+                    S.V[row + q * SB_LD] = cmk(sn * vp.x + c * vq.x, sn * vp.y + c * vq.y);
+                }
+            }
+            __syncthreads();
         }
+        const int any = S.rotated;
         __syncthreads();
-        cd wv = cmk(0.0, 0.0);  // conj(w_r) v_r partial
-        if (t < m) {
-            cd y = cadd(cadd(S.part[t], S.part[SB_MAX + t]), cadd(S.part[2 * SB_MAX + t], S.part[3 * SB_MAX + t]));
-            cd w = cmul(tau, y);
-            S.w[t] = w;
-            wv = cmulc(w, S.A[(j + 1 + t) + j * SB_LD]);
-        }
-        const double wvr = block_sum(wv.x, S.red);
-        const double wvi = block_sum(wv.y, S.red + SB_NT / 64);
-        // alpha2 = -1/2 tau (w^H v);  w += alpha2 v
-        const cd a2 = cscale(cmul(tau, cmk(wvr, wvi)), -0.5);
-        if (t < m) S.w[t] = cfma(a2, S.A[(j + 1 + t) + j * SB_LD], S.w[t]);
-        __syncthreads();
-        // A' -= v w^H + w v^H
-        for (int idx = t; idx < m * m; idx += SB_NT) {
-            const int r = idx % m, c = idx / m;
-            const cd vr = S.A[(j + 1 + r) + j * SB_LD], vc = S.A[(j + 1 + c) + j * SB_LD];
-            const cd wr = S.w[r], wc = S.w[c];
-            cd a = S.A[(j + 1 + r) + (j + 1 + c) * SB_LD];
-            a = csub(a, cmul(vr, cconj(wc)));
-            a = csub(a, cmul(wr, cconj(vc)));
-            S.A[(j + 1 + r) + (j + 1 + c) * SB_LD] = a;
-        }
-        __syncthreads();
+        if (!any) break;
     }
-    if (t == 0) S.d[n - 1] = S.A[(n - 1) + (n - 1) * SB_LD].x;
+    if (t == 0 && sweep == SB_SWEEPS && S.status == ST_OK) S.status = ST_ENOCONV;
     __syncthreads();
-}
-
-// Vs[:, 0:k] = Q Z[:, cols] with Q = H_0 H_1 ... H_{n-2}; cols given by
-// column indices colidx[0..k) of Z.  k <= SB_KMAX.
-__device__ void small_backtransform(SmallLds &S, int n, int k, const int *colidx) {
-    const int t = threadIdx.x;
-    for (int idx = t; idx < n * k; idx += SB_NT) {
-        const int r = idx % n, c = idx / n;
-        S.Vs[r + c * SB_LD] = cmk(S.Z[r + colidx[c] * SB_LD], 0.0);
-    }
-    __syncthreads();
-    // 8 lanes per column: lane group g = t/8 handles column g (k <= 32)
-    const int c = t >> 3, sub = t & 7;
-    for (int j = n - 2; j >= 0; --j) {
-        const cd tj = S.tau[j];
-        if (tj.x == 0.0 && tj.y == 0.0) continue;  // uniform across the block
-        cd acc = cmk(0.0, 0.0);
-        if (c < k)
-            for (int r = j + 1 + sub; r < n; r += 8) acc = cfmac(S.A[r + j * SB_LD], S.Vs[r + c * SB_LD], acc);
-#pragma unroll
-        for (int o = 1; o < 8; o <<= 1) {
-            acc.x += __shfl_xor(acc.x, o, 64);
-            acc.y += __shfl_xor(acc.y, o, 64);
-        }
-        const cd f = cmul(tj, acc);
-        if (c < k)
-            for (int r = j + 1 + sub; r < n; r += 8)
-                S.Vs[r + c * SB_LD] = csub(S.Vs[r + c * SB_LD], cmul(S.A[r + j * SB_LD], f));
-        __syncthreads();
-    }
 }
 
 __global__ void __launch_bounds__(SB_NT)
@@ -179,7 +174,7 @@ small_project_kernel(const SmallJob *jobs, SmallJob single, const double *__rest
     }
     for (int idx = t; idx < n * n; idx += SB_NT) {
         const int i = idx % n, j = idx / n;
-        S.Z[i + j * SB_LD] = (i == j) ? 1.0 : 0.0;
+        S.V[i + j * SB_LD] = cmk((i == j) ? 1.0 : 0.0, 0.0);
     }
     if (bad) S.status = ST_ENONFINITE;  // benign race: all writers store the same value
     __syncthreads();
@@ -199,20 +194,19 @@ small_project_kernel(const SmallJob *jobs, SmallJob single, const double *__rest
         return;
     }
 
-    // 2-3. tridiagonalise, then QL
-    small_tridiag(S, n);
-    small_ql(S, n);
+    // 2. Jacobi
+    small_jacobi(S, n);
 
-    // ascending order of the eigenvalues
+    // ascending order of the eigenvalues (the diagonal of the rotated M)
     if (t < n) {
-        const double v = S.d[t];
+        const double v = S.A[t + t * SB_LD].x;
         int rank = 0;
         for (int q = 0; q < n; ++q) {
-            const double u = S.d[q];
+            const double u = S.A[q + q * SB_LD].x;
             rank += (u < v) || (u == v && q < t);
         }
         S.lam[rank] = v;
-        S.perm[rank] = t;  // column of Z
+        S.perm[rank] = t;  // column of V
     }
     __syncthreads();
     if (t == 0) {
@@ -234,27 +228,20 @@ small_project_kernel(const SmallJob *jobs, SmallJob single, const double *__rest
     }
     __syncthreads();
 
-    // optional: full eigenvectors for a later derivative
+    // optional: full eigenvectors (ascending eigenvalues) for a later derivative
     if (saved_all) {
         double *sv = saved_all + job.saved_offset;
         if (t < n) sv[t] = S.lam[t];
         cd *V = reinterpret_cast<cd *>(sv + n);
-        for (int c0 = 0; c0 < n; c0 += SB_KMAX) {
-            const int kc = min(SB_KMAX, n - c0);
-            small_backtransform(S, n, kc, S.perm + c0);
-            for (int idx = t; idx < n * kc; idx += SB_NT) {
-                const int r = idx % n, c = idx / n;
-                V[r + (long)(c0 + c) * n] = S.Vs[r + c * SB_LD];
-            }
-            __syncthreads();
+        for (int idx = t; idx < n * n; idx += SB_NT) {
+            const int r = idx % n, c = idx / n;
+            V[r + (long)c * n] = S.V[r + S.perm[c] * SB_LD];
         }
     }
 
-    // 4. back-transform the selected side
     const int k = S.ksel;
-    small_backtransform(S, n, k, S.sel);
 
-    // 5. reconstruct the lower triangle and pack.  Each thread reads x and
+    // 3. reconstruct the lower triangle and pack.  Each thread reads x and
     //    writes y at the same svec positions, so y may alias x.
     //    sgn>0: Pi = sum_{lambda>0} lambda v v^H;
     //    sgn<0: Pi = X - sum_{lambda<=0} lambda v v^H.
@@ -265,8 +252,10 @@ small_project_kernel(const SmallJob *jobs, SmallJob single, const double *__rest
         const int i = idx % n, j = idx / n;
         if (i < j) continue;
         cd acc = cmk(0.0, 0.0);
-        for (int c = 0; c < k; ++c)
-            acc = cfma(cscale(S.Vs[i + c * SB_LD], S.scal[c]), cconj(S.Vs[j + c * SB_LD]), acc);
+        for (int c = 0; c < k; ++c) {
+            const int col = S.sel[c];
+            acc = cfma(cscale(S.V[i + col * SB_LD], S.scal[c]), cconj(S.V[j + col * SB_LD]), acc);
+        }
         if (i == j) {
             const long o = svec_col_start(n, j);
             const double base = sgn > 0 ? 0.0 : x[o];
