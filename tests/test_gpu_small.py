@@ -57,6 +57,23 @@ def test_small_constructed_and_sides(P, n):
         assert rel(y, oracle.constructed_projection(u, lam_s)) <= 1e-12
 
 
+def test_small_clustered_and_wide_spectra(P):
+    # repeated eigenvalues and exact zeros at an odd order, +-1 each of
+    # multiplicity 32, and a spectrum over sixteen decades: against the
+    # closed form and the oracle
+    rng = np.random.default_rng(17)
+    cases = [(33, np.concatenate([np.repeat([-2.0, 0.0, 1.5], 10), [3.0, -4.0, 0.25]])),
+             (64, np.repeat([-1.0, 1.0], 32)),
+             (48, np.concatenate([np.logspace(-8, 8, 24), -np.logspace(-8, 8, 24)]))]
+    for n, lam in cases:
+        u = W.haar_unitary(n, rng)
+        x = (u * lam) @ u.conj().T
+        s = W.upper_pack((x + x.conj().T) / 2)
+        y = P.project(dev(s), n).cpu().numpy()
+        assert rel(y, oracle.constructed_projection(u, lam)) <= 1e-12, n
+        assert rel(y, oracle.project(s, n)) <= TOL, n
+
+
 def test_small_special_inputs(P):
     n = 12
     rng = np.random.default_rng(3)
