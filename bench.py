@@ -428,6 +428,7 @@ def main():
     if plan is not None:
         out["config"]["concurrency"] = plan.concurrency
         out["config"]["group_size"] = plan.group_size
+        out["config"]["ns_tile_threshold"] = plan.ns_tile_threshold
         plan.close()
     print(json.dumps(out), flush=True)
 

@@ -147,15 +147,24 @@ psd_status psd_plan_workspace_size(psd_plan plan, int32_t concurrency, size_t *b
 int32_t psd_plan_concurrency(psd_plan plan);
 /* Members of the plan's largest lockstep group (0 without large blocks). */
 int32_t psd_plan_group_size(psd_plan plan);
+/* Padded order from which the plan's BF16 Newton-Schulz products use
+ * 128x128 tiles (2048 by default, as for psd_project and
+ * psd_project_batched; 1024 when the autotuner found that form faster for
+ * the plan's groups).  The two forms sum in different orders: the results of
+ * a plan at 1024 differ from eager calls by FP32 rounding in the
+ * low-precision iterations (both within the BF16 form's error bound). */
+int32_t psd_plan_ns_tile_threshold(psd_plan plan);
 /* y <- the blocks of x projected (layout as psd_project_batched); infos:
  * nullable, one record per block. */
 psd_status psd_plan_execute(psd_plan plan, const double *x, double *y, void *ws, size_t ws_bytes,
                             void *stream, psd_info *infos);
 /* Autotuner: for the group sizes 32 (or the memory-derived limit), 16 and 8
  * (those that split the blocks differently) and, for each, concurrency 1, 2,
- * 4, ... and the number of jobs (each that fits in ws_bytes), times `reps`
- * replays; keeps the fastest pair in the plan, appends it to the tuning cache
- * and returns the concurrency in *best (the group size:
+ * 4, ... and the number of jobs (each that fits in ws_bytes) -- and for BF16
+ * plans with a block of padded order 1024..2047 also for both tile forms of
+ * the Newton-Schulz product (psd_plan_ns_tile_threshold) -- times `reps`
+ * replays; keeps the fastest combination in the plan, appends it to the
+ * tuning cache and returns the concurrency in *best (the group size:
  * psd_plan_group_size).  Synchronises the stream. */
 psd_status psd_plan_tune(psd_plan plan, const double *x, double *y, void *ws, size_t ws_bytes,
                          void *stream, int32_t reps, int32_t *best);

@@ -191,6 +191,12 @@ class Plan:
         every launch)."""
         return int(_lib.lib().psd_plan_group_size(self._h))
 
+    @property
+    def ns_tile_threshold(self) -> int:
+        """Padded order from which the plan's BF16 Newton-Schulz products use
+        128x128 tiles (2048 by default; 1024 if the autotuner chose it)."""
+        return int(_lib.lib().psd_plan_ns_tile_threshold(self._h))
+
     def workspace(self, concurrency: int = 0) -> torch.Tensor:
         nb = ctypes.c_size_t(0)
         check(_lib.lib().psd_plan_workspace_size(self._h, concurrency, ctypes.byref(nb)), "psd_plan_workspace_size")

@@ -20,7 +20,7 @@ PSD_FLAG_SAVE = 1
 # Every symbol include/psdproj.h declares.
 EXPORTS = ("psd_workspace_size", "psd_saved_size", "psd_project", "psd_project_batched",
            "psd_project_vjp", "psd_plan_create", "psd_plan_workspace_size", "psd_plan_concurrency",
-           "psd_plan_group_size",
+           "psd_plan_group_size", "psd_plan_ns_tile_threshold",
            "psd_plan_execute", "psd_plan_tune", "psd_plan_destroy", "psd_timing_start", "psd_timing_stop",
            "psd_set_ns_iterations", "psd_status_string", "psd_version")
 KF_HEMV, KF_GEMM, KF_NS = 1, 2, 3
@@ -72,6 +72,8 @@ def lib():
     L.psd_plan_concurrency.restype = i32
     L.psd_plan_group_size.argtypes = [vp]
     L.psd_plan_group_size.restype = i32
+    L.psd_plan_ns_tile_threshold.argtypes = [vp]
+    L.psd_plan_ns_tile_threshold.restype = i32
     L.psd_plan_execute.argtypes = [vp, vp, vp, vp, sz, vp, vp]
     L.psd_plan_execute.restype = i32
     L.psd_plan_tune.argtypes = [vp, vp, vp, vp, sz, vp, i32, ctypes.POINTER(i32)]

@@ -149,10 +149,12 @@ hipError_t large_project_group(int n, int nmem, const double *x, double *y, cons
 
 // A lockstep group in either precision form.
 hipError_t project_group(int n, int nmem, psd_mode mode, const double *x, double *y, const int64_t *ioff,
-                         const int *infoidx, psd_dev_info *infos, void *ws, hipStream_t s) {
+                         const int *infoidx, psd_dev_info *infos, void *ws, hipStream_t s,
+                         int ns_big = NS_BIG_DEFAULT) {
     if (!is_mixed(mode)) return large_project_group(n, nmem, x, y, ioff, infoidx, infos, ws, s);
     MixedWs w;
     const size_t slot = mixed_layout(n, mode, ws, &w);
+    w.ns_big = ns_big;
     w.nmem = nmem;
     w.zs = (int64_t)slot;
     w.ioff = ioff;
@@ -183,8 +185,8 @@ std::vector<GroupChunk> group_chunks(int nblocks, const int32_t *n, int mode, in
 }
 size_t group_ws_bytes(const GroupChunk &c, int mode) { return chunk_ws_bytes(c, mode); }
 hipError_t project_group_ext(int n, int nmem, psd_mode mode, const double *x, double *y, const int64_t *ioff,
-                             const int *infoidx, psd_dev_info *infos, void *ws, hipStream_t s) {
-    return project_group(n, nmem, mode, x, y, ioff, infoidx, infos, ws, s);
+                             const int *infoidx, psd_dev_info *infos, void *ws, hipStream_t s, int ns_big) {
+    return project_group(n, nmem, mode, x, y, ioff, infoidx, infos, ws, s, ns_big);
 }
 
 hipError_t prepare_kernel_attributes() {

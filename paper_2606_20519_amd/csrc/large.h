@@ -92,7 +92,8 @@ struct GroupChunk {
 // max_group > 0 caps the members per group below the memory-derived limit.
 std::vector<GroupChunk> group_chunks(int nblocks, const int32_t *n, int mode, int max_group = 0);
 size_t group_ws_bytes(const GroupChunk &c, int mode);
+// ns_big: npad from which the BF16 Newton-Schulz product uses 128x128 tiles.
 hipError_t project_group_ext(int n, int nmem, psd_mode mode, const double *x, double *y, const int64_t *ioff,
-                             const int *infoidx, psd_dev_info *infos, void *ws, hipStream_t s);
+                             const int *infoidx, psd_dev_info *infos, void *ws, hipStream_t s, int ns_big);
 
 }  // namespace psd

@@ -16,6 +16,7 @@ struct MixedWs {
     double2 *q, *qprev, *wv, *P;
     double *ab, *alpha, *red;
     float *part;        // split partial sums of the BF16 128x128 product (large npad)
+    int ns_big;         // npad from which the BF16 product uses 128x128 tiles
     int *status;
     // lockstep group (as for the FP64 path: member b uses the slot b * zs
     // bytes on, svec offset ioff[b], info record infoidx[b]); single block:
@@ -25,6 +26,13 @@ struct MixedWs {
     const int64_t *ioff;
     const int *infoidx;
 };
+
+// The BF16 Newton-Schulz product takes 128x128 tiles from this npad on (64x64
+// below): the default of single calls and eager groups; a plan may lower it
+// to NS_BIG_MIN (its autotuner times both).  Below 2048 the 128x128 form
+// never splits its tail, so the workspace is the same either way.
+constexpr int NS_BIG_DEFAULT = 2048;
+constexpr int NS_BIG_MIN = 1024;
 
 // mode: 1 = BF16, 2 = FP32 low-precision iterations.
 size_t mixed_layout(int n, int mode, void *base, MixedWs *w);

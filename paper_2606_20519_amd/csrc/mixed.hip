@@ -531,7 +531,7 @@ __global__ void __launch_bounds__(256) ns_gemm_kernel(const L *__restrict__ Are,
 // as raw FP32 partials, summed in part order (deterministic) by a second
 // kernel that applies the same epilogue.
 constexpr int NS_SLOTS = 512;  // 256 CUs x 2 resident workgroups
-constexpr int NS_BIG = 2048;   // npad from which the 128x128 path is used
+constexpr int NS_BIG = NS_BIG_DEFAULT;  // npad from which the 128x128 path is used by default
 constexpr int NS_PART_FLOATS = 32768;  // raw accumulators of one tile part
 
 // Tail split of the 128x128 path for an npad x npad product (per block:
@@ -842,10 +842,11 @@ hipError_t ns_run(const MixedWs &w, const double *x, double *y, psd_dev_info *in
     const int64_t zs = w.zs;
     dim3 sg((npad + 255) / 256, npad, B);
     hipLaunchKernelGGL((ns_scale_kernel<L>), sg, dim3(256), 0, st, w.M, w.lda, n, npad, w.alpha, X, X + plane, zs);
-    // BF16 at npad >= NS_BIG: 128x128 tiles with a split tail; otherwise the
-    // 64x64 tile (the choice depends on npad only, so that group members
-    // match single-block calls bit for bit)
-    const bool big = sizeof(L) == 2 && npad >= NS_BIG;
+    // BF16 at npad >= w.ns_big: 128x128 tiles with a split tail; otherwise
+    // the 64x64 tile (the choice depends on npad and the threshold only, so
+    // that group members match single-block calls bit for bit under the
+    // same threshold)
+    const bool big = sizeof(L) == 2 && npad >= w.ns_big;
     int ntile, tfull, rem, split;
     if (big) ns_tail_plan(npad, &ntile, &tfull, &rem, &split);
     else { const int mt = npad / 64; ntile = mt * (mt + 1) / 2; tfull = ntile; rem = 0; split = 1; }
@@ -958,6 +959,7 @@ size_t mixed_layout(int n, int mode, void *base, MixedWs *w) {
     W.status = (int *)take(sizeof(int) * 4);
     W.red = (double *)take(sizeof(double) * 2 * ((size_t)(n + 15) / 16 + 1));
     W.part = nullptr;
+    W.ns_big = NS_BIG;
     if (mode == 1 && W.npad >= NS_BIG) {
         int ntile, tfull, rem, split;
         ns_tail_plan(W.npad, &ntile, &tfull, &rem, &split);

@@ -9,11 +9,13 @@
 // with its own workspace slot, so K jobs are in flight at once), and a join.
 // A job is a lockstep group of same-order blocks (every launch covers all its
 // members), in FP64 or mixed mode.  Executing a plan whose buffers were already captured is one
-// hipGraphLaunch on the caller's stream.  K is chosen by psd_plan_tune: it
-// replays the graph for each candidate, keeps the fastest and records it in a
-// small JSON-lines cache (PSD_TUNE_CACHE, default ./psdproj_tune.jsonl) keyed
-// by the device architecture, the mode and the block sizes; psd_plan_create
-// reads that cache.
+// hipGraphLaunch on the caller's stream.  K, the group size and, for BF16
+// plans with blocks of padded order 1024..2047, the tile form of the
+// Newton-Schulz product (64x64, or 128x128 from padded order 1024 on) are
+// chosen by psd_plan_tune: it replays the graph for each candidate, keeps the
+// fastest and records it in a small JSON-lines cache (PSD_TUNE_CACHE, default
+// ./psdproj_tune.jsonl) keyed by the device architecture, the mode and the
+// block sizes; psd_plan_create reads that cache.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -46,6 +48,7 @@ struct GraphEntry {
     psd_info *infos;
     int K;
     int group;
+    int ns_big;
     hipGraphExec_t exec;
 };
 
@@ -60,10 +63,12 @@ const char *tune_path() {
     return (p && *p) ? p : "psdproj_tune.jsonl";
 }
 
-// Last recorded concurrency and group size for `key` (0 where none).
-void tune_lookup(const std::string &key, int *K, int *group) {
+// Last recorded concurrency, group size and Newton-Schulz tile threshold
+// for `key` (0 where none).
+void tune_lookup(const std::string &key, int *K, int *group, int *ns_big) {
     *K = 0;
     *group = 0;
+    *ns_big = 0;
     FILE *f = std::fopen(tune_path(), "r");
     if (!f) return;
     char line[1 << 14];
@@ -72,17 +77,19 @@ void tune_lookup(const std::string &key, int *K, int *group) {
         if (!std::strstr(line, pat.c_str())) continue;
         const char *c = std::strstr(line, "\"concurrency\": ");
         const char *g = std::strstr(line, "\"group\": ");
+        const char *b = std::strstr(line, "\"ns_big\": ");
         *K = c ? std::atoi(c + 15) : 0;
         *group = g ? std::atoi(g + 9) : 0;
+        *ns_big = b ? std::atoi(b + 10) : 0;
     }
     std::fclose(f);
 }
 
-void tune_record(const std::string &key, int K, int group, double ms) {
+void tune_record(const std::string &key, int K, int group, int ns_big, double ms) {
     FILE *f = std::fopen(tune_path(), "a");
     if (!f) return;
-    std::fprintf(f, "{\"key\": \"%s\", \"concurrency\": %d, \"group\": %d, \"ms\": %.6f}\n", key.c_str(), K,
-                 group, ms);
+    std::fprintf(f, "{\"key\": \"%s\", \"concurrency\": %d, \"group\": %d, \"ns_big\": %d, \"ms\": %.6f}\n",
+                 key.c_str(), K, group, ns_big, ms);
     std::fclose(f);
 }
 
@@ -99,6 +106,7 @@ struct psd_plan_s {
     SmallJob *dsmall = nullptr;
     std::vector<GroupChunk> chunks;  // jobs: lockstep groups
     int group = 0;                   // members per group at most (0: the memory-derived limit)
+    int ns_big = NS_BIG_DEFAULT;     // padded order from which BF16 products use 128x128 tiles
     int64_t *dioff = nullptr;        // member svec offsets, chunk after chunk
     int *didx = nullptr;             // member block indices
     hipStream_t cap = nullptr;
@@ -127,7 +135,7 @@ hipError_t capture(psd_plan_s *p, const double *x, double *y, void *ws, psd_info
         const int slot = (int)(ci % K), cnt = (int)p->chunks[ci].blocks.size();
         char *wsl = static_cast<char *>(ws) + (size_t)slot * p->slot_bytes;
         chk(project_group_ext(p->chunks[ci].n, cnt, p->mode, x, y, p->dioff + pos, p->didx + pos, di, wsl,
-                              p->side[slot]));
+                              p->side[slot], p->ns_big));
         pos += cnt;
     }
     for (int i = 0; fork && i < K; ++i) {
@@ -144,7 +152,9 @@ hipError_t capture(psd_plan_s *p, const double *x, double *y, void *ws, psd_info
 
 hipGraphExec_t find_graph(psd_plan_s *p, const double *x, double *y, void *ws, psd_info *infos, int K) {
     for (auto &g : p->graphs)
-        if (g.x == x && g.y == y && g.ws == ws && g.infos == infos && g.K == K && g.group == p->group) return g.exec;
+        if (g.x == x && g.y == y && g.ws == ws && g.infos == infos && g.K == K && g.group == p->group &&
+            g.ns_big == p->ns_big)
+            return g.exec;
     return nullptr;
 }
 
@@ -203,10 +213,11 @@ psd_status psd_plan_create(int32_t nblocks, const int32_t *n, psd_mode mode, int
     // jobs are lockstep groups; concurrency and group size from the cache
     int K = concurrency, group = 0;
     {
-        int Kc = 0, gc = 0;
-        tune_lookup(tune_key(p->n, mode), &Kc, &gc);
+        int Kc = 0, gc = 0, bc = 0;
+        tune_lookup(tune_key(p->n, mode), &Kc, &gc, &bc);
         if (K == 0) K = Kc;
         group = gc;
+        if (bc == NS_BIG_MIN || bc == NS_BIG_DEFAULT) p->ns_big = bc;
     }
     if (K == 0) K = 4;
     bool ok = set_jobs(p, group);
@@ -241,6 +252,8 @@ int32_t psd_plan_concurrency(psd_plan p) { return p ? p->K : 0; }
 
 int32_t psd_plan_group_size(psd_plan p) { return p ? max_members(p) : 0; }
 
+int32_t psd_plan_ns_tile_threshold(psd_plan p) { return p ? p->ns_big : 0; }
+
 psd_status psd_plan_execute(psd_plan p, const double *x, double *y, void *ws, size_t ws_bytes, void *stream,
                             psd_info *infos) {
     if (!p || !x || !y) return PSD_EINVAL;
@@ -251,7 +264,7 @@ psd_status psd_plan_execute(psd_plan p, const double *x, double *y, void *ws, si
     hipGraphExec_t ex = find_graph(p, x, y, ws, infos, p->K);
     if (!ex) {
         if (capture(p, x, y, ws, infos, p->K, &ex) != hipSuccess) return PSD_EDEVICE;
-        p->graphs.push_back(GraphEntry{x, y, ws, infos, p->K, p->group, ex});
+        p->graphs.push_back(GraphEntry{x, y, ws, infos, p->K, p->group, p->ns_big, ex});
     }
     return hipGraphLaunch(ex, static_cast<hipStream_t>(stream)) == hipSuccess ? PSD_OK : PSD_EDEVICE;
 }
@@ -262,11 +275,24 @@ psd_status psd_plan_tune(psd_plan p, const double *x, double *y, void *ws, size_
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipEvent_t t0, t1;
     if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) return PSD_EDEVICE;
-    int bestK = p->K, bestG = p->group;
+    int bestK = p->K, bestG = p->group, bestB = p->ns_big;
     double best_ms = 1e300;
+    // tile forms of the BF16 Newton-Schulz product: the default, and 128x128
+    // tiles from padded order 1024 when a block falls in 1024..2047
+    std::vector<int> forms{NS_BIG_DEFAULT};
+    if (p->mode == PSD_MIXED_BF16)
+        for (int m : p->n) {
+            const int npad = (m + 63) / 64 * 64;
+            if (m > 64 && npad >= NS_BIG_MIN && npad < NS_BIG_DEFAULT) {
+                forms.push_back(NS_BIG_MIN);
+                break;
+            }
+        }
     // group sizes: the memory-derived limit (up to 32), then 16 and 8 where
     // they split differently; for each, concurrency 1, 2, 4, ... and the
     // number of jobs
+    for (int form : forms) {
+    p->ns_big = form;
     std::vector<int> tried;
     for (int g : {0, 16, 8}) {
         if (!set_jobs(p, g)) break;
@@ -293,14 +319,17 @@ psd_status psd_plan_tune(psd_plan p, const double *x, double *y, void *ws, size_
                 best_ms = ms / reps;
                 bestK = K;
                 bestG = g;
+                bestB = form;
             }
         }
+    }
     }
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
     if (!set_jobs(p, bestG)) return PSD_EDEVICE;
+    p->ns_big = bestB;
     p->K = std::max(1, std::min(bestK, std::max(1, p->nlarge)));
-    tune_record(tune_key(p->n, p->mode), p->K, bestG, best_ms);
+    tune_record(tune_key(p->n, p->mode), p->K, bestG, bestB, best_ms);
     if (best_out) *best_out = p->K;
     return PSD_OK;
 }

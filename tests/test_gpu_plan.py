@@ -157,3 +157,53 @@ def test_plan_mixed_matches_eager(P):
         tol = 1e-10 if m <= 64 else 3e-6
         assert rel(eager[off:off + m * m], oracle.project(s, m)) <= tol
     plan.close()
+
+
+def test_plan_bf16_tile_form(P, tmp_path):
+    # BF16 plan whose large blocks have padded order 1152 (1024..2047): the
+    # Newton-Schulz product may run in 128x128 tiles there.  A recorded
+    # threshold of 1024 forces that form: replays are bitwise stable and every
+    # block is within the BF16 band bound of its closed form; the default
+    # form equals eager calls bit for bit; tuning records a threshold that a
+    # new plan picks up.
+    import torch
+    path = tmp_path / "tune.jsonl"
+    os.environ["PSD_TUNE_CACHE"] = str(path)
+    try:
+        n, count = 1100, 3
+        cons = [W.constructed(n, 8400 + i, gap=1e-3) for i in range(count)]
+        x_np = np.concatenate([c[0] for c in cons] + [W.gue(25, 8500 + i) for i in range(4)])
+        sizes = [n] * count + [25] * 4
+        x = dev(x_np)
+        eager = P.project_batched(x, sizes, "mixed_bf16").cpu().numpy()
+        plan = P.Plan(sizes, "mixed_bf16")
+        assert plan.ns_tile_threshold == 2048
+        assert np.array_equal(plan.execute(x).cpu().numpy(), eager)
+        plan.close()
+        key = "gfx950:mode1:" + ",".join(str(m) for m in sizes)
+        with open(path, "a") as f:
+            f.write('{"key": "%s", "concurrency": 1, "group": 0, "ns_big": 1024, "ms": 1.0}\n' % key)
+        plan = P.Plan(sizes, "mixed_bf16")
+        assert plan.ns_tile_threshold == 1024
+        first = plan.execute(x).cpu().numpy()
+        for _ in range(2):
+            P.project_batched(x, sizes, "mixed_bf16")  # eager work between replays
+            torch.cuda.synchronize()
+            assert np.array_equal(plan.execute(x).cpu().numpy(), first)
+        for i, (s, u, lam) in enumerate(cons):
+            exact = oracle.constructed_projection(u, lam)
+            band = np.sqrt(np.sum(lam[np.abs(lam) < 0.03] ** 2))
+            err = np.linalg.norm(first[i * n * n:(i + 1) * n * n] - exact)
+            assert err <= 2.0 * band + 1e-9 * np.linalg.norm(exact), (i, err, band)
+        off = count * n * n
+        assert np.array_equal(first[off:], eager[off:])  # the small blocks do not depend on it
+        y = torch.empty_like(x)
+        plan.tune(x, y, reps=1, max_concurrency=2)
+        chosen = plan.ns_tile_threshold
+        assert chosen in (1024, 2048)
+        plan.close()
+        plan = P.Plan(sizes, "mixed_bf16")
+        assert plan.ns_tile_threshold == chosen
+        plan.close()
+    finally:
+        del os.environ["PSD_TUNE_CACHE"]
