@@ -112,8 +112,10 @@ __global__ void final_kernel(const double2 *__restrict__ M, int64_t lda, int n, 
 // H v = (L + D) v + L^H v: the direct part over the lower part, the adjoint
 // part over the strict lower part added to the same rows.  Only the short
 // vectors pass through LDS, so three workgroups fit on a CU.
-// Diagonal-tile workgroups write v for their rows into vbuf and produce
-// p = V^H v and q = W^H v over their 64 rows for the c panel columns done.
+// Diagonal-tile workgroups write v for their rows into vbuf.  The panel dot
+// products p = V^H v and q = W^H v (c panel columns done) are summed per
+// block row by workgroups of their own (hemv_pq), so that no workgroup of
+// the launch waits on a second memory round trip.
 struct HemvLds {
     double2 vI[TT], vJ[TT];
     double2 rowp[4][TT], colp[TT];
@@ -184,35 +186,6 @@ __device__ void hemv_tile(const double2 *__restrict__ M, int64_t lda, int n, int
         const double sum = wave_sum_split(pv);  // lane l: value l / 2
         if ((lane & 1) == 0) reinterpret_cast<double *>(&colp[g + 4 * (lane >> 2)])[(lane >> 1) & 1] = sum;
     }
-    // diagonal tiles: rows of the panel's V (q < c) and W (q >= c) columns,
-    // q = g + 4k (after the tile's registers are free)
-    __builtin_amdgcn_sched_barrier(0);
-    double2 xq[TT / 4];
-#pragma unroll
-    for (int k = 0; k < TT / 4; ++k) {
-        const int q = g + 4 * k;
-        xq[k] = cmk(0.0, 0.0);
-        if (diag && q < 2 * c && rowok) {
-            const double2 *col = (q < c) ? (M + (int64_t)(p0 + q) * lda) : (W + (int64_t)(q - c) * lda);
-            xq[k] = col[r0 + lane];
-        }
-    }
-    // diagonal tiles: p = V^H v, q = W^H v over these rows, 2c columns,
-    // column q on wave q % 4 with the 64 rows on the lanes
-    if (diag && c > 0) {
-        double pw[TT / 2];
-#pragma unroll
-        for (int k = 0; k < TT / 4; ++k) {
-            const double2 pr = cmulc(xq[k], vl);
-            pw[2 * k] = pr.x;
-            pw[2 * k + 1] = pr.y;
-        }
-        const double sum = wave_sum_split(pw);  // lane l: value l / 2
-        const int q = g + 4 * (lane >> 2);
-        if ((lane & 1) == 0 && q < 2 * c)
-            reinterpret_cast<double *>(pq)[2 * (((int64_t)I * 2 + (q < c ? 0 : 1)) * NB + (q < c ? q : q - c)) +
-                                           ((lane >> 1) & 1)] = sum;
-    }
     __syncthreads();
     if (t < TT) {
         double2 y = cadd(cadd(rowp[0][t], rowp[1][t]), cadd(rowp[2][t], rowp[3][t]));
@@ -228,6 +201,53 @@ __device__ void hemv_tile(const double2 *__restrict__ M, int64_t lda, int n, int
     __syncthreads();  // LDS reuse by a following call in the same workgroup
 }
 
+// p = V^H v and q = W^H v over the 64 rows of block row I (2c columns,
+// column q on wave q % 4 with the rows on the lanes): the reflector is
+// rebuilt from the sigma partials as by the tiles, and every load is issued
+// at once.
+__device__ void hemv_pq(const double2 *__restrict__ M, int64_t lda, int n, int j, const double *__restrict__ npart,
+                        int nparts, const double2 *__restrict__ W, int p0, int c, double2 *pq, int I) {
+    const int s = j + 1;
+    const int t = threadIdx.x, lane = t & 63, g = t >> 6;
+    const int r0 = s + I * TT;
+    const int row = r0 + lane;
+    const bool rowok = row < n;
+    const double2 *colj = M + (int64_t)j * lda;
+    double sp = 0.0;
+    for (int k = lane; k < nparts; k += 64) sp += npart[k];
+    const double2 alpha = colj[s];
+    const double2 cv = (rowok && row != s) ? colj[row] : cmk(0.0, 0.0);
+    double2 xq[TT / 4];
+#pragma unroll
+    for (int k = 0; k < TT / 4; ++k) {
+        const int q = g + 4 * k;
+        xq[k] = cmk(0.0, 0.0);
+        if (q < 2 * c && rowok) {
+            const double2 *col = (q < c) ? (M + (int64_t)(p0 + q) * lda) : (W + (int64_t)(q - c) * lda);
+            xq[k] = col[row];
+        }
+    }
+    const double sigma = warp_sum(sp);
+    const Refl h = make_refl(alpha, sigma);
+    double2 vl = cmk(0.0, 0.0);
+    if (row == s) vl = cmk(1.0, 0.0);
+    else if (rowok) vl = cmul(cv, h.scale);
+    double pw[TT / 2];  // {re, im} of column g + 4k at 2k, 2k + 1
+#pragma unroll
+    for (int k = 0; k < TT / 4; ++k) {
+        const double2 pr = cmulc(xq[k], vl);
+        pw[2 * k] = pr.x;
+        pw[2 * k + 1] = pr.y;
+    }
+    const double sum = wave_sum_split(pw);  // lane l: value l / 2
+    const int q = g + 4 * (lane >> 2);
+    if ((lane & 1) == 0 && q < 2 * c)
+        reinterpret_cast<double *>(pq)[2 * (((int64_t)I * 2 + (q < c ? 0 : 1)) * NB + (q < c ? q : q - c)) +
+                                       ((lane >> 1) & 1)] = sum;
+}
+
+// Workgroups 0 .. nt-1: the tiles; nt .. nt+mt-1 (when c > 0): the panel dot
+// products of block row blockIdx.x - nt.
 __global__ void __launch_bounds__(256, 3) hemv_kernel(const double2 *__restrict__ M, int64_t lda, int n, int j,
                                                    int mt, const double *__restrict__ npart, int nparts,
                                                    double2 *vbuf, const double2 *__restrict__ W, int p0, int c,
@@ -245,6 +265,11 @@ __global__ void __launch_bounds__(256, 3) hemv_kernel(const double2 *__restrict_
     taus = member_ptr(taus, zs, b);
     d = member_ptr(d, zs, b);
     e = member_ptr(e, zs, b);
+    const int nt = mt * (mt + 1) / 2;
+    if ((int)blockIdx.x >= nt) {
+        hemv_pq(M, lda, n, j, npart, nparts, W, p0, c, pq, (int)blockIdx.x - nt);
+        return;
+    }
     hemv_tile(M, lda, n, j, mt, npart, nparts, vbuf, W, p0, c, P, tdot, pq, taus, d, e, blockIdx.x, L);
 }
 
@@ -484,7 +509,7 @@ hipError_t large_tridiag(const LargeWs &w, hipStream_t st) {
             const int j = p0 + c, m = n - j - 1;
             const int mt = (m + TT - 1) / TT, nt = mt * (mt + 1) / 2;
             const int slot = timing_begin(KF_HEMV, st);
-            hipLaunchKernelGGL(hemv_kernel, dim3(nt, 1, w.nmem), dim3(256), 0, st, w.M, w.lda, n, j, mt, w.npart,
+            hipLaunchKernelGGL(hemv_kernel, dim3(nt + (c > 0 ? mt : 0), 1, w.nmem), dim3(256), 0, st, w.M, w.lda, n, j, mt, w.npart,
                                nparts, w.vbuf, w.W, p0, c, w.P, w.tdot, w.pq, w.tau, w.d, w.e, w.zs);
             timing_end(slot, st, 8.0 * (double)m * (double)(m + 1) * w.nmem);
             const int next_in_panel = (c + 1 < kb) ? 1 : 0;
