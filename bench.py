@@ -232,7 +232,7 @@ def main():
         if not os.environ.get("PSD_TUNE_CACHE"):
             import tempfile
             os.environ["PSD_TUNE_CACHE"] = os.path.join(tempfile.gettempdir(), "psdproj_bench_tune.jsonl")
-        plan.tune(X, Y, reps=2, max_concurrency=8)
+        plan.tune(X, Y, reps=3 if args.d <= 6 else 2, max_concurrency=8)
         plan.execute(X, out=Y)   # capture outside timing
     for _ in range(args.warmup):
         step()

@@ -162,10 +162,12 @@ psd_status psd_plan_execute(psd_plan plan, const double *x, double *y, void *ws,
  * (those that split the blocks differently) and, for each, concurrency 1, 2,
  * 4, ... and the number of jobs (each that fits in ws_bytes) -- and for BF16
  * plans with a block of padded order 1024..2047 also for both tile forms of
- * the Newton-Schulz product (psd_plan_ns_tile_threshold) -- times `reps`
- * replays; keeps the fastest combination in the plan, appends it to the
- * tuning cache and returns the concurrency in *best (the group size:
- * psd_plan_group_size).  Synchronises the stream. */
+ * the Newton-Schulz product (psd_plan_ns_tile_threshold) -- replays the
+ * graph once untimed, then `reps` times, each timed on its own, and scores
+ * the combination by its fastest replay (two untimed replays of the plan as
+ * it stands come first); keeps the fastest combination in the plan, appends
+ * it to the tuning cache and returns the concurrency in *best (the group
+ * size: psd_plan_group_size).  Synchronises the stream. */
 psd_status psd_plan_tune(psd_plan plan, const double *x, double *y, void *ws, size_t ws_bytes,
                          void *stream, int32_t reps, int32_t *best);
 psd_status psd_plan_destroy(psd_plan plan);

@@ -140,8 +140,10 @@ __device__ void hemv_tile(const double2 *__restrict__ M, int64_t lda, int n, int
     const bool diag = I == J;
     const bool rowok = r0 + lane < n;
     // every global load of the tile issued at once: one memory round trip
-    double sp = 0.0;  // sigma: every wave reduces the same partials in the same lane order
-    for (int k = lane; k < nparts; k += 64) sp += npart[k];
+    // (a loop that sums loaded values waits for its loads before anything
+    // after it is issued, so only the rare partials beyond 64 are looped over,
+    // after the tile's loads)
+    double sp = lane < nparts ? npart[lane] : 0.0;  // sigma: every wave sums the same partials in the same order
     const double2 alpha = colj[s];
     const double djj = (b == 0 && t == 0) ? colj[j].x : 0.0;
     double2 tv[TT / 4];  // tile column g + 4k, row lane (diagonal tile: lower part only)
@@ -152,6 +154,7 @@ __device__ void hemv_tile(const double2 *__restrict__ M, int64_t lda, int n, int
     }
     const int vrow = (t < TT ? r0 : c0) + lane;  // threads < 2*TT: entries of v_I, v_J
     const double2 cv = (t < 2 * TT && vrow < n && vrow != s) ? colj[vrow] : cmk(0.0, 0.0);
+    for (int k = lane + 64; k < nparts; k += 64) sp += npart[k];
     const double sigma = warp_sum(sp);
     const Refl h = make_refl(alpha, sigma);
     if (t < 2 * TT) {
@@ -213,8 +216,7 @@ __device__ void hemv_pq(const double2 *__restrict__ M, int64_t lda, int n, int j
     const int row = r0 + lane;
     const bool rowok = row < n;
     const double2 *colj = M + (int64_t)j * lda;
-    double sp = 0.0;
-    for (int k = lane; k < nparts; k += 64) sp += npart[k];
+    double sp = lane < nparts ? npart[lane] : 0.0;  // as in hemv_tile
     const double2 alpha = colj[s];
     const double2 cv = (rowok && row != s) ? colj[row] : cmk(0.0, 0.0);
     double2 xq[TT / 4];
@@ -227,6 +229,7 @@ __device__ void hemv_pq(const double2 *__restrict__ M, int64_t lda, int n, int j
             xq[k] = col[row];
         }
     }
+    for (int k = lane + 64; k < nparts; k += 64) sp += npart[k];
     const double sigma = warp_sum(sp);
     const Refl h = make_refl(alpha, sigma);
     double2 vl = cmk(0.0, 0.0);
@@ -308,19 +311,18 @@ __device__ void w_rows(double2 *M, int64_t lda, int n, int j, int mt, int nt, co
     const bool rowok = row < n;
     // Every global load is issued here, ahead of its use (the stores below
     // could alias them, so the compiler would not hoist them): one memory
-    // round trip.  At most mt <= 64 workgroups run, so the registers this
-    // takes cost no occupancy.
+    // round trip.  A loop that sums loaded values waits for its loads before
+    // anything after it is issued, so the first chunk of each sum is loaded
+    // here and only the chunks beyond it (n > 4096) are looped over, after
+    // every first load.  At most mt <= 64 workgroups run, so the registers
+    // this takes cost no occupancy.
     const double2 tj = taus[j];
     double2 pqv[NB / 2];  // p (q < c) / q (q >= c) partials of column q = g + 4k, row blocks on the lanes
 #pragma unroll
     for (int k = 0; k < NB / 2; ++k) {
         const int q = g + 4 * k;
-        pqv[k] = cmk(0.0, 0.0);
-        if (q < 2 * c) {
-            const double2 *src = pq + (q < c ? q : NB + q - c);  // row block bb at src[bb * 2 * NB]
-            if (r < mt) pqv[k] = src[(int64_t)r * 2 * NB];
-            for (int bb = r + 64; bb < mt; bb += 64) pqv[k] = cadd(pqv[k], src[(int64_t)bb * 2 * NB]);  // n > 4097
-        }
+        const double2 *src = pq + (q < c ? q : NB + q - c);  // row block bb at src[bb * 2 * NB]
+        pqv[k] = (q < 2 * c && r < mt) ? src[(int64_t)r * 2 * NB] : cmk(0.0, 0.0);
     }
     double2 wsv = cmk(0.0, 0.0), vsv = cmk(0.0, 0.0);
     if (next_in_panel && t >= 64 && t < 64 + c) {
@@ -333,25 +335,15 @@ __device__ void w_rows(double2 *M, int64_t lda, int n, int j, int mt, int nt, co
         const int idx = t + 256 * k;
         tlv[k] = (I == 0 && idx < c * c) ? Tb[(idx % c) + (idx / c) * NB] : cmk(0.0, 0.0);
     }
-    // (fixed-length unrolled chunks: a loop with a data-dependent trip count
-    // would wait for each load before issuing the next)
-    double part = 0.0;  // 256 threads
-    for (int base = t; base < nt; base += 8 * 256) {
-        double tv[8];
+    // tile terms v_I^H A v_J (256 threads, chunks of 8 x 256) and the
+    // partials of y = A v for this row (4 groups, chunks of 16 x 4)
+    double tv[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) tv[u] = (base + 256 * u < nt) ? tdot[base + 256 * u] : 0.0;
+    for (int u = 0; u < 8; ++u) tv[u] = (t + 256 * u < nt) ? tdot[t + 256 * u] : 0.0;
+    double2 yv[16];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) part += tv[u];
-    }
-    double2 y = cmk(0.0, 0.0);
-    for (int base = g; base < mt; base += 64) {
-        double2 yv[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u)
-            yv[u] = (base + 4 * u < mt) ? P[((int64_t)I * mt + base + 4 * u) * TT + r] : cmk(0.0, 0.0);
-#pragma unroll
-        for (int u = 0; u < 16; ++u) y = cadd(y, yv[u]);
-    }
+    for (int u = 0; u < 16; ++u)
+        yv[u] = (g + 4 * u < mt) ? P[((int64_t)I * mt + g + 4 * u) * TT + r] : cmk(0.0, 0.0);
     double2 vr[NB / 4], wr[NB / 4];  // panel columns g + 4k of V and W at this row
 #pragma unroll
     for (int k = 0; k < NB / 4; ++k) {
@@ -360,16 +352,43 @@ __device__ void w_rows(double2 *M, int64_t lda, int n, int j, int mt, int nt, co
         vr[k] = ok ? M[row + (int64_t)(p0 + cc) * lda] : cmk(0.0, 0.0);
         wr[k] = ok ? W[row + (int64_t)cc * lda] : cmk(0.0, 0.0);
     }
-    double2 ys = cmk(0.0, 0.0);
-    if (next_in_panel && g == 0) {
-        if (r < mt) ys = P[(int64_t)r * TT];
-        for (int sl = r + 64; sl < mt; sl += 64) ys = cadd(ys, P[(int64_t)sl * TT]);  // n > 4097
-    }
+    double2 ys = (next_in_panel && g == 0 && r < mt) ? P[(int64_t)r * TT] : cmk(0.0, 0.0);
     double2 vrow = cmk(0.0, 0.0), mnext = cmk(0.0, 0.0);
     if (t < TT && rowok) {
         vrow = vbuf[row];
         if (next_in_panel) mnext = M[row + (int64_t)(j + 1) * lda];
     }
+    // the chunks beyond the first (n > 4096), after every first load
+#pragma unroll
+    for (int k = 0; k < NB / 2; ++k) {
+        const int q = g + 4 * k;
+        const double2 *src = pq + (q < c ? q : NB + q - c);
+        if (q < 2 * c)
+            for (int bb = r + 64; bb < mt; bb += 64) pqv[k] = cadd(pqv[k], src[(int64_t)bb * 2 * NB]);
+    }
+    // (sums start from their first term: an added constant zero would be
+    // moved into the predicated load and wait for it there)
+    double part = tv[0];
+#pragma unroll
+    for (int u = 1; u < 8; ++u) part += tv[u];
+    for (int base = t + 8 * 256; base < nt; base += 8 * 256) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) tv[u] = (base + 256 * u < nt) ? tdot[base + 256 * u] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) part += tv[u];
+    }
+    double2 y = yv[0];
+#pragma unroll
+    for (int u = 1; u < 16; ++u) y = cadd(y, yv[u]);
+    for (int base = g + 64; base < mt; base += 64) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            yv[u] = (base + 4 * u < mt) ? P[((int64_t)I * mt + base + 4 * u) * TT + r] : cmk(0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < 16; ++u) y = cadd(y, yv[u]);
+    }
+    if (next_in_panel && g == 0)
+        for (int sl = r + 64; sl < mt; sl += 64) ys = cadd(ys, P[(int64_t)sl * TT]);
     // p = V^H v, q = W^H v
     {
         double pv[NB];  // {re, im} of column g + 4k at 2k, 2k + 1
