@@ -13,6 +13,10 @@
 // After the panel, the trailing matrix gets the rank-2NB update
 // A -= V W^H + W V^H as one FP64 MFMA GEMM (lower tiles only).
 //
+// Once the trailing matrix from a panel boundary has order <= LG_TAIL, one
+// workgroup per block finishes the reduction in LDS (tail_kernel): the
+// launches of those columns would cost far more than their work.
+//
 // Per column two launches: the tiled HEMV over the lower triangle (one
 // workgroup per 64x64 tile; each first rebuilds the column's reflector from
 // the sigma partials, identically), and the w/next-column step (one workgroup
@@ -32,6 +36,7 @@ namespace {
 
 constexpr int TT = LG_TILE;
 constexpr int NB = LG_NB;
+constexpr int TAIL = LG_TAIL;
 // per-wave register staging below: 2c < 4 * (NB / 2) panel columns, c*c <= NB*NB
 // T-factor entries over 256 threads, TT / 4 tile columns per wave
 static_assert(TT == 64 && NB % 8 == 0 && (NB * NB) % 256 == 0, "staging layout");
@@ -90,13 +95,6 @@ __device__ void norm_body(const double2 *__restrict__ M, int64_t lda, int n, int
 __global__ void __launch_bounds__(512) norm_kernel(const double2 *__restrict__ M, int64_t lda, int n, int j,
                                                    double *npart, int64_t zs) {
     norm_body(member_ptr(M, zs, blockIdx.z), lda, n, j, member_ptr(npart, zs, blockIdx.z));
-}
-
-// Last diagonal entry of T.
-__global__ void final_kernel(const double2 *__restrict__ M, int64_t lda, int n, double *d, int64_t zs) {
-    M = member_ptr(M, zs, blockIdx.z);
-    d = member_ptr(d, zs, blockIdx.z);
-    if (threadIdx.x == 0) d[n - 1] = M[(n - 1) + (int64_t)(n - 1) * lda].x;
 }
 
 // Reflector of column j (recomputed identically by every workgroup from the
@@ -498,6 +496,177 @@ __global__ void __launch_bounds__(256) w_kernel(double2 *M, int64_t lda, int n, 
     w_rows(M, lda, n, j, mt, nt, vbuf, W, p0, c, next_in_panel, P, tdot, pq, taus, Tb, npart, blockIdx.x, L);
 }
 
+// The last columns in one workgroup.  The lower triangle of the trailing
+// matrix A = M[p0:, p0:] (order m0 = n - p0 <= TAIL; every earlier panel is
+// already applied) is held in LDS packed by rows, and the unblocked steps of
+// the same reduction run there, column k after column k-1:
+//   v from column k (make_refl), y = A22 v, w = tau y - 1/2 |tau|^2 (v^H y) v,
+//   A22 -= v w^H + w v^H
+// (the panel formulas with no earlier panel columns), each v overwriting the
+// column it came from.  Then the block-reflector factor of every panel of the
+// tail follows from the Gram matrix G = V^H V of its reflectors:
+//   T(c, c) = tau_c,  T(0:c, c) = -tau_c T(0:c, 0:c) G(0:c, c),
+// the recurrence the per-column step applies with p = V^H v_c = G(0:c, c).
+// One workgroup of 1024 threads per block (grid z: group member).
+struct TailLds {
+    double2 A[TAIL * (TAIL + 1) / 2];  // row i at i(i+1)/2, columns 0..i
+    double2 v[TAIL], w[TAIL];           // w: y = A22 v of the current column
+    double2 tau[TAIL];
+    double2 G[NB * NB], Tf[NB * NB];    // column-major, leading dimension NB
+};
+
+__device__ __forceinline__ int tpk(int i, int l) { return i * (i + 1) / 2 + l; }
+
+__global__ void __launch_bounds__(1024) tail_kernel(double2 *M, int64_t lda, int n, int p0, double2 *taus,
+                                                    double *d, double *e, double2 *T, int64_t zs) {
+    __shared__ TailLds L;
+    const int b = blockIdx.z;
+    M = member_ptr(M, zs, b);
+    taus = member_ptr(taus, zs, b);
+    d = member_ptr(d, zs, b);
+    e = member_ptr(e, zs, b);
+    T = member_ptr(T, zs, b);
+    const int m0 = n - p0;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int ri = t >> 3, sub = t & 7;  // phases over rows: 8 threads per row
+    // lower triangle of A, column-major in HBM: all loads issued, then stored
+    {
+        constexpr int CH = (TAIL * TAIL + 1023) / 1024;
+        double2 buf[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int idx = t + 1024 * u, l = idx / m0, i = idx - l * m0;
+            buf[u] = (idx < m0 * m0 && i >= l) ? M[(p0 + i) + (int64_t)(p0 + l) * lda] : cmk(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int idx = t + 1024 * u, l = idx / m0, i = idx - l * m0;
+            if (idx < m0 * m0 && i >= l) L.A[tpk(i, l)] = buf[u];
+        }
+    }
+    __syncthreads();
+    for (int k = 0; k < m0 - 1; ++k) {
+        const int k1 = k + 1;
+        // reflector of column k and v (wave 0)
+        if (wv == 0) {
+            double sp = 0.0;
+            for (int r = k + 2 + lane; r < m0; r += 64) sp += cabs2(L.A[tpk(r, k)]);
+            const double sigma = warp_sum(sp);
+            const Refl h = make_refl(L.A[tpk(k1, k)], sigma);
+            for (int r = k1 + lane; r < m0; r += 64) {
+                const double2 vr = (r == k1) ? cmk(1.0, 0.0) : cmul(L.A[tpk(r, k)], h.scale);
+                L.v[r] = vr;
+                L.A[tpk(r, k)] = vr;
+            }
+            if (lane == 0) {
+                L.tau[k] = h.tau;
+                d[p0 + k] = L.A[tpk(k, k)].x;
+                e[p0 + k] = h.beta;
+                taus[p0 + k] = h.tau;
+            }
+        }
+        __syncthreads();
+        // y = A22 v: row i over columns k1 + sub + 8q (the diagonal is real),
+        // eight loads issued per chunk before they are used
+        {
+            const int i = k1 + ri;
+            double2 acc = cmk(0.0, 0.0);
+            if (i < m0) {
+                const int rowb = tpk(i, 0);
+                for (int l0 = k1 + sub; l0 < m0; l0 += 64) {
+                    double2 av[8], vv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int l = l0 + 8 * u;
+                        av[u] = cmk(0.0, 0.0);
+                        vv[u] = cmk(0.0, 0.0);
+                        if (l < m0) {
+                            vv[u] = L.v[l];
+                            if (l < i) av[u] = L.A[rowb + l];
+                            else if (l == i) av[u] = cmk(L.A[rowb + l].x, 0.0);
+                            else av[u] = cconj(L.A[tpk(l, i)]);
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) acc = cfma(av[u], vv[u], acc);
+                }
+            }
+#pragma unroll
+            for (int o = 1; o < 8; o <<= 1) acc = cadd(acc, cmk(__shfl_xor(acc.x, o, 64), __shfl_xor(acc.y, o, 64)));
+            if (sub == 0 && i < m0) L.w[i] = acc;
+        }
+        __syncthreads();
+        // a2 = -1/2 |tau|^2 v^H A v (every wave, the same sum), then
+        // A22 -= v w^H + w v^H over the lower triangle with w = tau y + a2 v
+        // formed where it is needed
+        {
+            double pv = 0.0;
+            for (int r = k1 + lane; r < m0; r += 64) pv += cmulc(L.v[r], L.w[r]).x;
+            const double vAv = warp_sum(pv);
+            const double2 tk = L.tau[k];
+            const double2 a2 = cmk(-0.5 * cabs2(tk) * vAv, 0.0);
+            const int i = k1 + ri;
+            if (i < m0) {
+                const double2 vi = L.v[i], wi = cfma(a2, vi, cmul(tk, L.w[i]));
+                const int rowb = tpk(i, 0);
+                for (int l0 = k1 + sub; l0 <= i; l0 += 32) {
+                    double2 av[4], vv[4], yy[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int l = l0 + 8 * u;
+                        av[u] = vv[u] = yy[u] = cmk(0.0, 0.0);
+                        if (l <= i) {
+                            av[u] = L.A[rowb + l];
+                            vv[u] = L.v[l];
+                            yy[u] = L.w[l];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int l = l0 + 8 * u;
+                        const double2 wl = cfma(a2, vv[u], cmul(tk, yy[u]));
+                        if (l <= i) L.A[rowb + l] = csub(av[u], cadd(cmul(vi, cconj(wl)), cmul(wi, cconj(vv[u]))));
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (t == 0) d[n - 1] = L.A[tpk(m0 - 1, m0 - 1)].x;
+    // reflectors to M (column p0 + k, rows below the diagonal)
+    for (int idx = t; idx < m0 * m0; idx += 1024) {
+        const int k = idx / m0, r = idx - k * m0;
+        if (r > k && k < m0 - 1) M[(p0 + r) + (int64_t)(p0 + k) * lda] = L.A[tpk(r, k)];
+    }
+    // block-reflector factors of the tail's panels
+    for (int pp = p0; pp < n - 1; pp += NB) {
+        const int kb = min(NB, n - 1 - pp), kc0 = pp - p0;
+        {
+            const int a = t % NB, c = t / NB;  // NB * NB == 1024 pairs: one each
+            if (c < kb && a < c) {
+                double2 g = cmk(0.0, 0.0);
+                for (int r = kc0 + c + 1; r < m0; ++r) g = cfma(cconj(L.A[tpk(r, kc0 + a)]), L.A[tpk(r, kc0 + c)], g);
+                L.G[a + c * NB] = g;
+            }
+        }
+        __syncthreads();
+        // row a of T on lane a of wave 0, column by column (each entry needs
+        // only the same row's earlier entries)
+        if (wv == 0 && lane < kb) {
+            const int a = lane;
+            for (int c = a; c < kb; ++c) {
+                double2 z = cmk(0.0, 0.0);
+                for (int l = a; l < c; ++l) z = cfma(L.Tf[a + l * NB], L.G[l + c * NB], z);
+                const double2 tc = L.tau[kc0 + c];
+                const double2 val = (c == a) ? tc : cscale(cmul(tc, z), -1.0);
+                L.Tf[a + c * NB] = val;
+                T[(int64_t)(pp / NB) * NB * NB + a + c * NB] = val;
+            }
+        }
+        __syncthreads();  // G and Tf reuse by the next panel
+    }
+}
+
 // Zero the upper triangle (incl. diagonal) of the reflector columns so that
 // column j of M is exactly v_j (v_j(j+1) = 1 is already stored).
 __global__ void __launch_bounds__(256) clean_kernel(double2 *M, int64_t lda, int n, int64_t zs) {
@@ -519,7 +688,10 @@ hipError_t large_unpack(const LargeWs &w, const double *x, hipStream_t st) {
 
 hipError_t large_tridiag(const LargeWs &w, hipStream_t st) {
     const int n = w.n;
-    for (int p0 = 0; p0 < n - 1; p0 += NB) {
+    // panels up to ptail by the per-column launches; from ptail (the first
+    // panel boundary with n - ptail <= TAIL) one workgroup finishes in LDS
+    const int ptail = n <= TAIL ? 0 : (n - TAIL + NB - 1) / NB * NB;
+    for (int p0 = 0; p0 < ptail; p0 += NB) {
         const int kb = min(NB, n - 1 - p0);
         double2 *Tb = w.T + (int64_t)(p0 / NB) * NB * NB;
         hipLaunchKernelGGL(norm_kernel, dim3(1, 1, w.nmem), dim3(512), 0, st, w.M, w.lda, n, p0, w.npart, w.zs);
@@ -554,7 +726,8 @@ hipError_t large_tridiag(const LargeWs &w, hipStream_t st) {
             if (e != hipSuccess) return e;
         }
     }
-    hipLaunchKernelGGL(final_kernel, dim3(1, 1, w.nmem), dim3(64), 0, st, w.M, w.lda, n, w.d, w.zs);
+    hipLaunchKernelGGL(tail_kernel, dim3(1, 1, w.nmem), dim3(1024), 0, st, w.M, w.lda, n, ptail, w.tau, w.d, w.e,
+                       w.T, w.zs);
     return hipGetLastError();
 }
 

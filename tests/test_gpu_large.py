@@ -113,6 +113,53 @@ def test_large_special_inputs(P):
     assert np.abs(P.project(dev(-psd), n).cpu().numpy()).max() <= 1e-11 * np.abs(psd).max()
 
 
+@pytest.mark.parametrize("n", [120, 121, 152, 153])
+def test_large_tail_boundaries(P, n):
+    # the last columns are reduced by one workgroup in LDS from the first
+    # panel boundary p0 (a multiple of 32) with n - p0 <= 120: n = 120 has no
+    # blocked panel, 121 and 153 the shortest tail (89), 152 the longest (120)
+    s = W.gue(n, 3100 + n)
+    print(f"large tail boundary n={n}", flush=True)
+    y, lam, v = saved_pair(P, s, n)
+    m = oracle.unpack(s, n).conj()
+    ref = np.linalg.eigvalsh(m)
+    assert np.max(np.abs(lam - ref)) <= 1e-12 * np.abs(ref).max()
+    assert np.linalg.norm(m @ v - v * lam) <= 1e-11 * np.linalg.norm(m)
+    assert np.linalg.norm(v.conj().T @ v - np.eye(n)) <= 1e-11
+    assert rel(y, oracle.project(s, n)) <= TOL
+
+
+def test_large_tail_structured_columns(P):
+    # n = 152: blocked panels, then a tail of order 120 holding (a) a complex
+    # tridiagonal stretch, where reflectors only rotate a phase (sigma = 0,
+    # alpha complex), and (b) a zero column, where the reflector is the
+    # identity (tau = 0)
+    n = 152
+    rng = np.random.default_rng(3152)
+    a = W.cn01(rng, (n, n))
+    a = (a + a.conj().T) / 2
+    t0 = 90
+    a[t0:, t0:] = 0.0
+    for i in range(t0, n):
+        a[i, i] = rng.standard_normal()
+        if i + 1 < n:
+            a[i + 1, i] = W.cn01(rng, ())
+            a[i, i + 1] = np.conj(a[i + 1, i])
+    a[:t0, t0:] = 0.0
+    a[t0:, :t0] = 0.0
+    z = 130
+    a[z, :] = 0.0
+    a[:, z] = 0.0
+    s = oracle.pack(a)
+    print("large tail structured n=152", flush=True)
+    y, lam, v = saved_pair(P, s, n)
+    m = oracle.unpack(s, n).conj()
+    ref = np.linalg.eigvalsh(m)
+    assert np.max(np.abs(lam - ref)) <= 1e-12 * np.abs(ref).max()
+    assert np.linalg.norm(m @ v - v * lam) <= 1e-11 * np.linalg.norm(m)
+    assert rel(y, oracle.project(s, n)) <= TOL
+
+
 def test_large_invariants_in_place_determinism(P):
     n = 190
     s = W.gue(n, 33)
