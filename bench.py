@@ -244,7 +244,18 @@ def main():
     fam = None
     other = None
     if mode == "fp64" and n > 64 and wl != "c4":
-        fam, sample = _lib.KF_HEMV, n - 1
+        # one projection's HEMV launches (the columns before the LDS tail),
+        # counted by an untimed probe
+        _lib.timing_start(_lib.KF_HEMV, n)
+        P.project(X[0], n, mode, out=Y[0])
+        torch.cuda.synchronize()
+        fam, sample = _lib.KF_HEMV, _lib.timing_stop()[1]
+        # the per-column w / next-column step between the HEMV launches
+        # (latency bound: no roofline, its launches kept as context)
+        _lib.timing_start(_lib.KF_WSTEP, n)
+        P.project(X[0], n, mode, out=Y[0])
+        torch.cuda.synchronize()
+        other = (_lib.KF_WSTEP, _lib.timing_stop())
     elif mode != "fp64" and wl != "c4":
         # the Newton-Schulz products or the FP64 products (corrections and
         # the final X S) -- whichever family takes more of one projection,
@@ -289,6 +300,12 @@ def main():
                         "frac": round(achieved / PEAK_HBM_GBS, 4),
                         "traffic": measured_traffic("hemv_kernel", n, "tridiag.hip"),
                         "algorithmic_bytes_per_launch": round(timed[2] / timed[1], 1)}
+            if other and other[1][1] > 0:
+                pr = other[1]
+                roofline["other_kernel"] = {
+                    "kernel": "w_kernel (per-column w / next-column step, tridiagonalisation)", "bound": "latency",
+                    "avg_launch_us": round(1e3 * pr[0] / pr[1], 3), "launches": pr[1],
+                    "share_of_projection_ms": round(pr[0], 3), "sample": "untimed probe projection (HIP events)"}
         else:
             roofline = mfma_roofline(fam == _lib.KF_GEMM, mode, n, timed)
             if other:

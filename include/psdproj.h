@@ -180,12 +180,13 @@ psd_status psd_plan_destroy(psd_plan plan);
  * number of launches timed and their algorithmic work: bytes of the matrix
  * read for PSD_KF_HEMV (the lower triangle of the trailing matrix, 16 bytes
  * per complex entry), real flops for PSD_KF_GEMM (8 per complex
- * multiply-add).  Not thread-safe; meant for benchmarks and tests.  The
+ * multiply-add), none for PSD_KF_WSTEP.  Not thread-safe; meant for benchmarks and tests.  The
  * events are created by psd_timing_start and destroyed by psd_timing_stop. */
 typedef enum {
     PSD_KF_HEMV = 1,   /* per-column Hermitian matrix-vector tiles of the tridiagonalisation */
     PSD_KF_GEMM = 2,   /* FP64 MFMA GEMMs */
-    PSD_KF_NS = 3      /* low-precision Newton-Schulz GEMMs (flops of the lower tiles computed) */
+    PSD_KF_NS = 3,     /* low-precision Newton-Schulz GEMMs (flops of the lower tiles computed) */
+    PSD_KF_WSTEP = 4   /* per-column w / next-column step of the tridiagonalisation (latency bound) */
 } psd_kernel_family;
 psd_status psd_timing_start(int32_t family, int32_t max_launches);
 psd_status psd_timing_stop(double *ms, int32_t *launches, double *work);

@@ -23,7 +23,7 @@ EXPORTS = ("psd_workspace_size", "psd_saved_size", "psd_project", "psd_project_b
            "psd_plan_group_size", "psd_plan_ns_tile_threshold",
            "psd_plan_execute", "psd_plan_tune", "psd_plan_destroy", "psd_timing_start", "psd_timing_stop",
            "psd_set_ns_iterations", "psd_status_string", "psd_version")
-KF_HEMV, KF_GEMM, KF_NS = 1, 2, 3
+KF_HEMV, KF_GEMM, KF_NS, KF_WSTEP = 1, 2, 3, 4
 
 
 class PsdError(RuntimeError):

@@ -4,7 +4,7 @@
 
 namespace psd {
 
-enum { KF_HEMV = 1, KF_GEMM = 2, KF_NS = 3 };
+enum { KF_HEMV = 1, KF_GEMM = 2, KF_NS = 3, KF_WSTEP = 4 };
 
 // Records the start event of a timed launch of `family` on `st`; returns the
 // slot to close with timing_end, or -1 if this launch is not timed.

@@ -43,7 +43,7 @@ extern "C" {
 psd_status psd_timing_start(int32_t family, int32_t max_launches) {
     using namespace psd;
     TimingState &T = g_timing;
-    if (family < KF_HEMV || family > KF_NS || max_launches < 1 || T.family != 0)
+    if (family < KF_HEMV || family > KF_WSTEP || max_launches < 1 || T.family != 0)
         return PSD_EINVAL;
     T.ev.assign(2 * (size_t)max_launches, nullptr);
     for (auto &e : T.ev)

@@ -704,8 +704,10 @@ hipError_t large_tridiag(const LargeWs &w, hipStream_t st) {
                                nparts, w.vbuf, w.W, p0, c, w.P, w.tdot, w.pq, w.tau, w.d, w.e, w.zs);
             timing_end(slot, st, 8.0 * (double)m * (double)(m + 1) * w.nmem);
             const int next_in_panel = (c + 1 < kb) ? 1 : 0;
+            const int wslot = timing_begin(KF_WSTEP, st);
             hipLaunchKernelGGL(w_kernel, dim3(mt, 1, w.nmem), dim3(256), 0, st, w.M, w.lda, n, j, mt, nt, w.vbuf,
                                w.W, p0, c, next_in_panel, w.P, w.tdot, w.pq, w.tau, Tb, w.npart, w.zs);
+            timing_end(wslot, st, 0.0);
             nparts = mt;
         }
         const int t0 = p0 + kb;

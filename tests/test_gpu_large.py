@@ -129,6 +129,24 @@ def test_large_tail_boundaries(P, n):
     assert rel(y, oracle.project(s, n)) <= TOL
 
 
+@pytest.mark.parametrize("n,launches", [(100, 0), (120, 0), (121, 32), (200, 96)])
+def test_tail_switch_launch_counts(P, n, launches):
+    # per-column launches (HEMV and w step, counted by the timing hooks) run
+    # up to the first panel boundary p0 with n - p0 <= 120; the rest is one
+    # LDS launch
+    from paper_2606_20519_amd import _lib
+    import torch
+    x = dev(W.gue(n, 77))
+    for fam in (_lib.KF_HEMV, _lib.KF_WSTEP):
+        _lib.timing_start(fam, 4 * n)
+        P.project(x, n)
+        torch.cuda.synchronize()
+        ms, cnt, work = _lib.timing_stop()
+        assert cnt == launches
+        if fam == _lib.KF_HEMV:
+            assert work == sum(8.0 * m * (m + 1) for m in range(n - 1, n - 1 - launches, -1))
+
+
 def test_large_tail_structured_columns(P):
     # n = 152: blocked panels, then a tail of order 120 holding (a) a complex
     # tridiagonal stretch, where reflectors only rotate a phase (sigma = 0,
