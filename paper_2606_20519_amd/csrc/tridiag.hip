@@ -447,8 +447,10 @@ __device__ void w_rows(double2 *M, int64_t lda, int n, int j, int mt, int nt, co
     if (next_in_panel && g == 0) {
         // y(s) - (V q)(s) - (W p)(s), the panel columns on the lanes
         if (r < c) ys = csub(ys, cadd(cmul(Vs[r], qS[r]), cmul(Ws[r], pS[r])));
-        ys = cmk(warp_sum(ys.x), warp_sum(ys.y));
-        if (r == 0) wsh = cadd(cmul(tj, ys), cmk(a2, 0.0));  // v[s] = 1
+        double yv[2] = {ys.x, ys.y};
+        const double ysum = wave_sum_split(yv);  // lanes 0..31: re, 32..63: im
+        const double2 yt = cmk(__shfl(ysum, 0, 64), __shfl(ysum, 32, 64));
+        if (r == 0) wsh = cadd(cmul(tj, yt), cmk(a2, 0.0));  // v[s] = 1
     }
     __syncthreads();
     double nrm = 0.0;
@@ -469,11 +471,11 @@ __device__ void w_rows(double2 *M, int64_t lda, int n, int j, int mt, int nt, co
             if (row > j + 2) nrm = cabs2(a);
         }
     }
-    if (next_in_panel) {
-        const double sum = block_sum(nrm, red);
+    // sigma partial of column j+1 over these rows: only wave 0 holds rows
+    if (next_in_panel && g == 0) {
+        const double sum = warp_sum(nrm);
         if (t == 0) npart[I] = sum;
     }
-    __syncthreads();  // LDS reuse by a following call in the same workgroup
 }
 
 __global__ void __launch_bounds__(256) w_kernel(double2 *M, int64_t lda, int n, int j, int mt, int nt,
