@@ -27,18 +27,18 @@ __device__ __forceinline__ cd conj_of(cd v) { return cconj(v); }
 __device__ __forceinline__ double scale_of(double v, double s) { return v * s; }
 __device__ __forceinline__ cd scale_of(cd v, double s) { return cscale(v, s); }
 
-// op(X)[r][c] where for A (r, c) = (i, k) and for B (r, c) = (k, j).
-// `kdim` tells which of r/c is the K index (0: r, 1: c).
+// The stored element behind op(X)[r][c] (not yet conjugated for OP_C),
+// where for A (r, c) = (i, k) and for B (r, c) = (k, j).  `kdim` tells
+// which of r/c is the K index (0: r, 1: c).
 template <typename T, int OP, int KDIM>
-__device__ __forceinline__ T op_elem(const GemmOperand &o, int r, int c) {
+__device__ __forceinline__ T op_raw(const GemmOperand &o, int r, int c) {
     const int k = KDIM == 0 ? r : c;
     const bool second = k >= o.ksplit;
     const T *p = static_cast<const T *>(second ? o.p1 : o.p0);
     const int64_t ld = second ? o.ld1 : o.ld0;
     const int kk = second ? k - o.ksplit : k;
     const int rr = KDIM == 0 ? kk : r, cc = KDIM == 0 ? c : kk;
-    T v = (OP == OP_N) ? p[rr + (int64_t)cc * ld] : conj_of(p[cc + (int64_t)rr * ld]);
-    return v;
+    return (OP == OP_N) ? p[rr + (int64_t)cc * ld] : p[cc + (int64_t)rr * ld];
 }
 
 __device__ __forceinline__ double gamma_dk(double a, double b) {
@@ -58,55 +58,75 @@ struct GemmLds {
 // One k-slice of op(A) (rows i0.., BK columns from k0) and of op(B) (BK
 // rows from k0, columns j0..) into four registers per thread, zero outside
 // the problem; the matching stores put them in the LDS tiles As[k][i],
-// Bs[k][j].  The thread-to-element maps keep global reads coalesced.
+// Bs[k][j].  The thread-to-element maps keep global reads coalesced.  The
+// loads only fetch, at indices clamped into the problem (M, N, K >= 1 where
+// they run), every element unconditionally, with the k-scales of A and a
+// mask of the elements inside the problem; the zeroing outside it, the
+// conjugation and the scaling are applied by the stores, one k-slice later.
+// No load then waits where it is issued (a load under a branch, or one
+// whose value is used at once, waits for its round trip there).
+struct KSlice {
+    double ks[4];
+    unsigned ok;
+};
+
 template <typename T, int OPA>
-__device__ __forceinline__ void gemm_load_a(const GemmDesc &d, int i0, int k0, T (&v)[4]) {
+__device__ __forceinline__ void gemm_load_a(const GemmDesc &d, int i0, int k0, T (&v)[4], KSlice &m) {
+    const int t = threadIdx.x;
+    m.ok = 0u;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int i = OPA == OP_N ? (t & 63) : (t >> 4) + 16 * s;
+        const int k = OPA == OP_N ? (t >> 6) + 4 * s : (t & 15);
+        const bool in = i0 + i < d.M && k0 + k < d.K;
+        const int ic = min(i0 + i, d.M - 1), kc = min(k0 + k, d.K - 1);
+        v[s] = op_raw<T, OPA, 1>(d.A, ic, kc);
+        m.ks[s] = d.A.kscale ? d.A.kscale[kc] : 1.0;
+        m.ok |= in ? 1u << s : 0u;
+    }
+}
+
+template <typename T, int OPA>
+__device__ __forceinline__ void gemm_store_a(const GemmDesc &d, T (&As)[BK][BM + PAD], const T (&v)[4],
+                                             const KSlice &m) {
     const int t = threadIdx.x;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const int i = OPA == OP_N ? (t & 63) : (t >> 4) + 16 * s;
         const int k = OPA == OP_N ? (t >> 6) + 4 * s : (t & 15);
-        T x = zero_of(T());
-        if (i0 + i < d.M && k0 + k < d.K) {
-            x = op_elem<T, OPA, 1>(d.A, i0 + i, k0 + k);
-            if (d.A.kscale) x = scale_of(x, d.A.kscale[k0 + k]);
-        }
-        v[s] = x;
-    }
-}
-
-template <typename T, int OPA>
-__device__ __forceinline__ void gemm_store_a(T (&As)[BK][BM + PAD], const T (&v)[4]) {
-    const int t = threadIdx.x;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int i = OPA == OP_N ? (t & 63) : (t >> 4) + 16 * s;
-        const int k = OPA == OP_N ? (t >> 6) + 4 * s : (t & 15);
-        As[k][i] = v[s];
+        const bool in = (m.ok >> s) & 1u;
+        T x = v[s];
+        if (OPA == OP_C) x = conj_of(x);
+        if (d.A.kscale) x = scale_of(x, m.ks[s]);
+        As[k][i] = in ? x : zero_of(T());
     }
 }
 
 template <typename T, int OPB>
-__device__ __forceinline__ void gemm_load_b(const GemmDesc &d, int j0, int k0, T (&v)[4]) {
+__device__ __forceinline__ void gemm_load_b(const GemmDesc &d, int j0, int k0, T (&v)[4], unsigned &ok) {
+    const int t = threadIdx.x;
+    ok = 0u;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int j = OPB == OP_N ? (t >> 4) + 16 * s : (t & 63);
+        const int k = OPB == OP_N ? (t & 15) : (t >> 6) + 4 * s;
+        const bool in = j0 + j < d.N && k0 + k < d.K;
+        v[s] = op_raw<T, OPB, 0>(d.B, min(k0 + k, d.K - 1), min(j0 + j, d.N - 1));
+        ok |= in ? 1u << s : 0u;
+    }
+}
+
+template <typename T, int OPB>
+__device__ __forceinline__ void gemm_store_b(T (&Bs)[BK][BN + PAD], const T (&v)[4], unsigned ok) {
     const int t = threadIdx.x;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const int j = OPB == OP_N ? (t >> 4) + 16 * s : (t & 63);
         const int k = OPB == OP_N ? (t & 15) : (t >> 6) + 4 * s;
-        T x = zero_of(T());
-        if (j0 + j < d.N && k0 + k < d.K) x = op_elem<T, OPB, 0>(d.B, k0 + k, j0 + j);
-        v[s] = x;
-    }
-}
-
-template <typename T, int OPB>
-__device__ __forceinline__ void gemm_store_b(T (&Bs)[BK][BN + PAD], const T (&v)[4]) {
-    const int t = threadIdx.x;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const int j = OPB == OP_N ? (t >> 4) + 16 * s : (t & 63);
-        const int k = OPB == OP_N ? (t & 15) : (t >> 6) + 4 * s;
-        Bs[k][j] = v[s];
+        const bool in = (ok >> s) & 1u;
+        T x = v[s];
+        if (OPB == OP_C) x = conj_of(x);
+        Bs[k][j] = in ? x : zero_of(T());
     }
 }
 
@@ -142,15 +162,19 @@ __device__ void gemm_tile(const GemmDesc &dd, int ti, int tj, int tz, GemmLds<T>
     // The next k-slice is loaded into registers while the current one feeds
     // the MFMAs, then stored to LDS: global latency overlaps the products.
     T av[4], bv[4];
-    gemm_load_a<T, OPA>(d, i0, kbeg, av);
-    gemm_load_b<T, OPB>(d, j0, kbeg, bv);
+    KSlice am;
+    unsigned bok;
+    if (kbeg < d.K) {  // (a split-K slice past a device-side K has no products)
+        gemm_load_a<T, OPA>(d, i0, kbeg, av, am);
+        gemm_load_b<T, OPB>(d, j0, kbeg, bv, bok);
+    }
     for (int k0 = kbeg; k0 < d.K; k0 += BK) {
-        gemm_store_a<T, OPA>(As, av);
-        gemm_store_b<T, OPB>(Bs, bv);
+        gemm_store_a<T, OPA>(d, As, av, am);
+        gemm_store_b<T, OPB>(Bs, bv, bok);
         __syncthreads();
         if (k0 + BK < d.K) {
-            gemm_load_a<T, OPA>(d, i0, k0 + BK, av);
-            gemm_load_b<T, OPB>(d, j0, k0 + BK, bv);
+            gemm_load_a<T, OPA>(d, i0, k0 + BK, av, am);
+            gemm_load_b<T, OPB>(d, j0, k0 + BK, bv, bok);
         }
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 4) {
@@ -183,6 +207,25 @@ __device__ void gemm_tile(const GemmDesc &dd, int ti, int tj, int tz, GemmLds<T>
 
     // ---- epilogue
     const double rt2 = 1.41421356237309504880;
+    // C for beta != 0: every value this thread adds to is loaded before the
+    // first store (a load placed after a store to the same array would wait
+    // for that store, one memory round trip per element)
+    T cold[2][2][4];
+    if constexpr (EPI != EPI_SVEC) {
+        if (d.beta != 0.0 && !(CPLX && d.mirror)) {
+            const T *C = static_cast<const T *>(d.C);
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = i0 + wm * 32 + a * 16 + (lane >> 4) + 4 * v;
+                        const int j = j0 + wn * 32 + b * 16 + (lane & 15);
+                        if (i < d.M && j < d.N) cold[a][b][v] = C[i + (int64_t)j * d.ldc];
+                    }
+        }
+    }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -227,13 +270,13 @@ __device__ void gemm_tile(const GemmDesc &dd, int ti, int tj, int tz, GemmLds<T>
                         continue;
                     }
                     if (d.beta != 0.0) {
-                        const cd c0 = *reinterpret_cast<const cd *>(&C[idx]);
+                        const cd c0 = *reinterpret_cast<const cd *>(&cold[a][b][v]);
                         out = cmk(out.x + d.beta * c0.x, out.y + d.beta * c0.y);
                     }
                     *reinterpret_cast<cd *>(&C[idx]) = out;
                 } else {
                     double out = d.alpha * re + (i == j ? d.diag_add : 0.0);
-                    if (d.beta != 0.0) out += d.beta * *reinterpret_cast<const double *>(&C[idx]);
+                    if (d.beta != 0.0) out += d.beta * *reinterpret_cast<const double *>(&cold[a][b][v]);
                     *reinterpret_cast<double *>(&C[idx]) = out;
                 }
             }
