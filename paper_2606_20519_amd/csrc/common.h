@@ -57,6 +57,34 @@ __device__ __forceinline__ double warp_sum(double v) {
     return v;
 }
 
+// Sum of one double over the 64 lanes of a wave whose lanes are all active,
+// the same value in every lane, without LDS traffic: inside each row of 16
+// lanes four DPP exchanges (the quad permutations 1,0,3,2 and 2,3,0,1, then
+// the half-row and the row mirrors), each pairing a lane with one that holds
+// a disjoint partial, so every lane of a row ends with the row's sum (a + b
+// and b + a round alike); then the four row sums, read from lanes 0, 16, 32
+// and 48, added in that order.
+template <int CTRL>
+__device__ __forceinline__ double dpp_double(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xF, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double readlane_double(double v, int l) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+    v += dpp_double<0xB1>(v);   // quad_perm(1, 0, 3, 2): lane ^ 1
+    v += dpp_double<0x4E>(v);   // quad_perm(2, 3, 0, 1): lane ^ 2
+    v += dpp_double<0x141>(v);  // row_half_mirror: lane 7 - i within 8
+    v += dpp_double<0x140>(v);  // row_mirror: lane 15 - i within 16
+    return ((readlane_double(v, 0) + readlane_double(v, 16)) + readlane_double(v, 32)) + readlane_double(v, 48);
+}
+
 // Sums K doubles (K a power of two, 2 <= K <= 32) over the 64 lanes of a
 // wave.  Each exchange stage sends half of the live values to the partner
 // lane and keeps the other half, so the K sums cost K - 1 + log2(64 / K)

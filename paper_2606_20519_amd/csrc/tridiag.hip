@@ -153,7 +153,7 @@ __device__ void hemv_tile(const double2 *__restrict__ M, int64_t lda, int n, int
     const int vrow = (t < TT ? r0 : c0) + lane;  // threads < 2*TT: entries of v_I, v_J
     const double2 cv = (t < 2 * TT && vrow < n && vrow != s) ? colj[vrow] : cmk(0.0, 0.0);
     for (int k = lane + 64; k < nparts; k += 64) sp += npart[k];
-    const double sigma = warp_sum(sp);
+    const double sigma = wave_sum_dpp(sp);
     const Refl h = make_refl(alpha, sigma);
     if (t < 2 * TT) {
         double2 v = cmk(0.0, 0.0);
@@ -193,7 +193,7 @@ __device__ void hemv_tile(const double2 *__restrict__ M, int64_t lda, int n, int
         if (diag) y = cadd(y, colp[t]);
         P[((int64_t)I * mt + J) * TT + t] = y;
         if (diag && r0 + t < n) vbuf[r0 + t] = vI[t];
-        const double dv = warp_sum(cmulc(vI[t], y).x);
+        const double dv = wave_sum_dpp(cmulc(vI[t], y).x);  // wave 0, every lane
         if (t == 0) tdot[b] = diag ? dv : 2.0 * dv;
     } else if (t < 2 * TT && !diag) {
         const int cc = t - TT;
@@ -228,7 +228,7 @@ __device__ void hemv_pq(const double2 *__restrict__ M, int64_t lda, int n, int j
         }
     }
     for (int k = lane + 64; k < nparts; k += 64) sp += npart[k];
-    const double sigma = warp_sum(sp);
+    const double sigma = wave_sum_dpp(sp);
     const Refl h = make_refl(alpha, sigma);
     double2 vl = cmk(0.0, 0.0);
     if (row == s) vl = cmk(1.0, 0.0);
@@ -410,9 +410,16 @@ __device__ void w_rows(double2 *M, int64_t lda, int n, int j, int mt, int nt, co
         const int idx = t + 256 * k;
         if (I == 0 && idx < c * c) Tl[idx % c][idx / c] = tlv[k];
     }
-    const double vAv = block_sum(part, red);  // barriers: pS/qS/Ws/Vs/Tl visible after it
+    // v^H A v: per-wave sums, then the four in order (the barrier also makes
+    // pS/qS/Ws/Vs/Tl visible)
+    part = wave_sum_dpp(part);
+    if (r == 0) red[g] = part;
+    __syncthreads();
+    double vAv = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) vAv += red[k];
     // Re q^H p: lanes over the panel columns (every wave, same order)
-    const double qp = warp_sum(r < c ? cmulc(qS[r], pS[r]).x : 0.0);
+    const double qp = wave_sum_dpp(r < c ? cmulc(qS[r], pS[r]).x : 0.0);
     const double a2 = -0.5 * cabs2(tj) * (vAv - 2.0 * qp);
     // block-reflector factor, column c: row i on the 8 lanes 8i..8i+7
     if (I == 0) {
@@ -473,7 +480,7 @@ __device__ void w_rows(double2 *M, int64_t lda, int n, int j, int mt, int nt, co
     }
     // sigma partial of column j+1 over these rows: only wave 0 holds rows
     if (next_in_panel && g == 0) {
-        const double sum = warp_sum(nrm);
+        const double sum = wave_sum_dpp(nrm);
         if (t == 0) npart[I] = sum;
     }
 }
@@ -553,7 +560,7 @@ __global__ void __launch_bounds__(1024) tail_kernel(double2 *M, int64_t lda, int
         if (wv == 0) {
             double sp = 0.0;
             for (int r = k + 2 + lane; r < m0; r += 64) sp += cabs2(L.A[tpk(r, k)]);
-            const double sigma = warp_sum(sp);
+            const double sigma = wave_sum_dpp(sp);
             const Refl h = make_refl(L.A[tpk(k1, k)], sigma);
             for (int r = k1 + lane; r < m0; r += 64) {
                 const double2 vr = (r == k1) ? cmk(1.0, 0.0) : cmul(L.A[tpk(r, k)], h.scale);
@@ -604,7 +611,7 @@ __global__ void __launch_bounds__(1024) tail_kernel(double2 *M, int64_t lda, int
         {
             double pv = 0.0;
             for (int r = k1 + lane; r < m0; r += 64) pv += cmulc(L.v[r], L.w[r]).x;
-            const double vAv = warp_sum(pv);
+            const double vAv = wave_sum_dpp(pv);
             const double2 tk = L.tau[k];
             const double2 a2 = cmk(-0.5 * cabs2(tk) * vAv, 0.0);
             const int i = k1 + ri;
