@@ -60,12 +60,13 @@ def flops_ns(n: int, iters: int, corr: int) -> float:
     return iters * 2 * 4.0 * n ** 3 + corr * 2 * 8.0 * n ** 3 + 4.0 * n ** 3
 
 
-def measured_traffic(kernel, n, source):
+def measured_traffic(kernel, n, sources):
     """HBM bytes per launch of `kernel` at order n from the committed counter
-    summary, or None if there is none or the kernel source has changed."""
+    summary, or None if there is none or the kernel's sources have changed
+    (sha256 over the files in `sources`, concatenated in that order)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_n{n}.txt")
-    src = os.path.join(ROOT, "paper_2606_20519_amd", "csrc", source)
-    if not (os.path.exists(path) and os.path.exists(src)):
+    srcs = [os.path.join(ROOT, "paper_2606_20519_amd", "csrc", f) for f in sources]
+    if not (os.path.exists(path) and all(os.path.exists(f) for f in srcs)):
         return None
     fields = {}
     with open(path) as f:
@@ -73,8 +74,11 @@ def measured_traffic(kernel, n, source):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
-    with open(src, "rb") as f:
-        digest = hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for f in srcs:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    digest = h.hexdigest()
     if fields.get("source_sha256") != digest:
         return None
     try:
@@ -298,7 +302,7 @@ def main():
             roofline = {"kernel": "hemv_kernel (per-column Hermitian matrix-vector tiles, tridiagonalisation)",
                         "bound": "hbm", "achieved": round(achieved, 2), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                         "frac": round(achieved / PEAK_HBM_GBS, 4),
-                        "traffic": measured_traffic("hemv_kernel", n, "tridiag.hip"),
+                        "traffic": measured_traffic("hemv_kernel", n, ("tridiag.hip", "common.h")),
                         "algorithmic_bytes_per_launch": round(timed[2] / timed[1], 1)}
             if other and other[1][1] > 0:
                 pr = other[1]

@@ -85,32 +85,92 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
     return ((readlane_double(v, 0) + readlane_double(v, 16)) + readlane_double(v, 32)) + readlane_double(v, 48);
 }
 
+// Exchange of a pair of doubles between lane l and lane l ^ O for O = 32
+// (the halves of the wave) or O = 16 (even and odd rows of 16 lanes) by the
+// lane-swap instructions, without LDS traffic: on return `a` and `b` hold
+// the lane's own a and the partner's a where (l & O) == 0, and the
+// partner's b and the lane's own b where (l & O) != 0.
+template <int O>
+__device__ __forceinline__ void lane_swap_pair(double &a, double &b) {
+    static_assert(O == 32 || O == 16, "swap distance");
+    const unsigned long long ua = (unsigned long long)__double_as_longlong(a);
+    const unsigned long long ub = (unsigned long long)__double_as_longlong(b);
+    unsigned alo = (unsigned)ua, ahi = (unsigned)(ua >> 32), blo = (unsigned)ub, bhi = (unsigned)(ub >> 32);
+    if constexpr (O == 32) {
+        const auto lo = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+        alo = lo[0]; blo = lo[1]; ahi = hi[0]; bhi = hi[1];
+    } else {
+        const auto lo = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+        alo = lo[0]; blo = lo[1]; ahi = hi[0]; bhi = hi[1];
+    }
+    a = __longlong_as_double((long long)(((unsigned long long)ahi << 32) | alo));
+    b = __longlong_as_double((long long)(((unsigned long long)bhi << 32) | blo));
+}
+
+// x of lane l ^ O (every lane of the wave active): lane swaps for 32 and
+// 16, DPP quad permutations for 2 and 1, ds_bpermute otherwise.
+template <int O>
+__device__ __forceinline__ double xor_lane(double x, int lane) {
+    if constexpr (O == 32 || O == 16) {
+        double a = x, b = x;
+        lane_swap_pair<O>(a, b);
+        return (lane & O) ? a : b;
+    } else if constexpr (O == 2) {
+        return dpp_double<0x4E>(x);
+    } else if constexpr (O == 1) {
+        return dpp_double<0xB1>(x);
+    } else {
+        return __shfl_xor(x, O, 64);
+    }
+}
+
 // Sums K doubles (K a power of two, 2 <= K <= 32) over the 64 lanes of a
-// wave.  Each exchange stage sends half of the live values to the partner
-// lane and keeps the other half, so the K sums cost K - 1 + log2(64 / K)
-// shuffles instead of K * 6.  Lane l returns the total of value l / (64 / K).
+// wave whose lanes are all active.  Each exchange stage sends half of the
+// live values to the partner lane l ^ O and keeps the other half, so the K
+// sums cost K - 1 + log2(64 / K) exchanges instead of K * 6; the exchanges
+// across 32 and 16 lanes are lane swaps of a kept/sent pair, those across 2
+// and 1 DPP, only those across 8 and 4 go through LDS.  Lane l returns the
+// total of value l / (64 / K).
 template <int CNT, int O, int K>
 __device__ __forceinline__ void wave_split_stage(double (&v)[K], int lane) {
     if constexpr (CNT > 1) {
         const bool up = (lane & O) != 0;
 #pragma unroll
         for (int i = 0; i < CNT / 2; ++i) {
-            const double send = up ? v[i] : v[i + CNT / 2];
-            const double keep = up ? v[i + CNT / 2] : v[i];
-            v[i] = keep + __shfl_xor(send, O, 64);
+            if constexpr (O == 32 || O == 16) {
+                // lower lanes keep v[i] and receive the partner's v[i];
+                // upper lanes keep v[i + CNT/2] and receive the partner's
+                double a = v[i], b = v[i + CNT / 2];
+                lane_swap_pair<O>(a, b);
+                v[i] = up ? b + a : a + b;
+            } else {
+                const double send = up ? v[i] : v[i + CNT / 2];
+                const double keep = up ? v[i + CNT / 2] : v[i];
+                v[i] = keep + xor_lane<O>(send, lane);
+            }
         }
         wave_split_stage<CNT / 2, O / 2, K>(v, lane);
+    }
+}
+
+template <int O>
+__device__ __forceinline__ double wave_tail_sum(double r, int lane) {
+    if constexpr (O > 0) {
+        r += xor_lane<O>(r, lane);
+        return wave_tail_sum<O / 2>(r, lane);
+    } else {
+        return r;
     }
 }
 
 template <int K>
 __device__ __forceinline__ double wave_sum_split(double (&v)[K]) {
     static_assert(K >= 2 && K <= 32 && (K & (K - 1)) == 0, "K");
-    wave_split_stage<K, 32, K>(v, threadIdx.x & 63);
-    double r = v[0];
-#pragma unroll
-    for (int o = 32 / K; o > 0; o >>= 1) r += __shfl_xor(r, o, 64);
-    return r;
+    const int lane = threadIdx.x & 63;
+    wave_split_stage<K, 32, K>(v, lane);
+    return wave_tail_sum<32 / K>(v[0], lane);
 }
 
 // Block-wide sum of one double; `red` is LDS scratch of >= blockDim/64 doubles.
