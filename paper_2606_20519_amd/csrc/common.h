@@ -109,20 +109,28 @@ __device__ __forceinline__ void lane_swap_pair(double &a, double &b) {
     b = __longlong_as_double((long long)(((unsigned long long)bhi << 32) | blo));
 }
 
-// x of lane l ^ O (every lane of the wave active): lane swaps for 32 and
-// 16, DPP quad permutations for 2 and 1, ds_bpermute otherwise.
+// x of lane l ^ O (every lane of the wave active), without LDS traffic:
+// lane swaps for 32 and 16; inside a row of 16 lanes DPP: the rotation by 8
+// (row_ror:8 is l ^ 8), the shifts by 4 chosen by bit 2 of the lane
+// (row_shl:4 reads lane l + 4, row_shr:4 lane l - 4), the quad permutations
+// for 2 and 1.
 template <int O>
 __device__ __forceinline__ double xor_lane(double x, int lane) {
+    static_assert(O == 32 || O == 16 || O == 8 || O == 4 || O == 2 || O == 1, "xor distance");
     if constexpr (O == 32 || O == 16) {
         double a = x, b = x;
         lane_swap_pair<O>(a, b);
         return (lane & O) ? a : b;
+    } else if constexpr (O == 8) {
+        return dpp_double<0x128>(x);
+    } else if constexpr (O == 4) {
+        const double from_above = dpp_double<0x104>(x);  // row_shl:4
+        const double from_below = dpp_double<0x114>(x);  // row_shr:4
+        return (lane & 4) ? from_below : from_above;
     } else if constexpr (O == 2) {
         return dpp_double<0x4E>(x);
-    } else if constexpr (O == 1) {
-        return dpp_double<0xB1>(x);
     } else {
-        return __shfl_xor(x, O, 64);
+        return dpp_double<0xB1>(x);
     }
 }
 
@@ -130,9 +138,8 @@ __device__ __forceinline__ double xor_lane(double x, int lane) {
 // wave whose lanes are all active.  Each exchange stage sends half of the
 // live values to the partner lane l ^ O and keeps the other half, so the K
 // sums cost K - 1 + log2(64 / K) exchanges instead of K * 6; the exchanges
-// across 32 and 16 lanes are lane swaps of a kept/sent pair, those across 2
-// and 1 DPP, only those across 8 and 4 go through LDS.  Lane l returns the
-// total of value l / (64 / K).
+// across 32 and 16 lanes are lane swaps of a kept/sent pair, the others DPP
+// (none goes through LDS).  Lane l returns the total of value l / (64 / K).
 template <int CNT, int O, int K>
 __device__ __forceinline__ void wave_split_stage(double (&v)[K], int lane) {
     if constexpr (CNT > 1) {
