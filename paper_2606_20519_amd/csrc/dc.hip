@@ -302,10 +302,20 @@ __global__ void __launch_bounds__(256) dc_prep_kernel(int level, int n, int nl, 
     }
 }
 
+// Product of one double over a wave whose lanes are all active, the same in
+// every lane: the exchange pattern of wave_sum_dpp with products.
+__device__ __forceinline__ double wave_prod_dpp(double v) {
+    v *= dpp_double<0xB1>(v);
+    v *= dpp_double<0x4E>(v);
+    v *= dpp_double<0x141>(v);
+    v *= dpp_double<0x140>(v);
+    return ((readlane_double(v, 0) * readlane_double(v, 16)) * readlane_double(v, 32)) * readlane_double(v, 48);
+}
+
 // Root j of 1 + rho sum_i zh_i^2 / (dh_i - lambda) = 0 (dh ascending, gaps
-// > 0), solved by one wave: the lanes split every sum over i and the wave-wide
-// butterfly sums give all lanes the same totals, so all lanes take the same
-// steps.  Returns the origin pole o and tau with lambda = dh[o] + tau.
+// > 0), solved by one wave (every lane active): the lanes split every sum
+// over i and the wave-wide DPP sums give all lanes the same totals, so all
+// lanes take the same steps.  Returns the origin pole o and tau with lambda = dh[o] + tau.
 __device__ void secular_root_wave(const double *dh, const double *zh, int k, double rho, int j, int *o_out,
                                   double *tau_out) {
     const int lane = threadIdx.x & 63;
@@ -315,13 +325,13 @@ __device__ void secular_root_wave(const double *dh, const double *zh, int k, dou
         const double gap = dh[j + 1] - dh[j];
         double f = 0.0;
         for (int i = lane; i < k; i += 64) f += rho * zh[i] * zh[i] / ((dh[i] - dh[j]) - 0.5 * gap);
-        f = 1.0 + warp_sum(f);
+        f = 1.0 + wave_sum_dpp(f);
         if (f > 0.0) { o = j; lo = 0.0; hi = 0.5 * gap; }
         else { o = j + 1; lo = -0.5 * gap; hi = 0.0; }
     } else {
         double zz = 0.0;
         for (int i = lane; i < k; i += 64) zz += zh[i] * zh[i];
-        zz = warp_sum(zz);
+        zz = wave_sum_dpp(zz);
         o = j; lo = 0.0; hi = rho * zz;
     }
     const double dO = dh[o];
@@ -336,8 +346,8 @@ __device__ void secular_root_wave(const double *dh, const double *zh, int k, dou
             if (i <= j) { psi += term; dpsi += term / diff; }
             else { phi += term; dphi += term / diff; }
         }
-        psi = warp_sum(psi); phi = warp_sum(phi);
-        dpsi = warp_sum(dpsi); dphi = warp_sum(dphi); sabs = warp_sum(sabs);
+        psi = wave_sum_dpp(psi); phi = wave_sum_dpp(phi);
+        dpsi = wave_sum_dpp(dpsi); dphi = wave_sum_dpp(dphi); sabs = wave_sum_dpp(sabs);
         const double f = 1.0 + psi + phi;
         if (f < 0.0) lo = tau; else hi = tau;
         if (f == 0.0 || fabs(f) <= 8.0 * EPS * (1.0 + sabs)) break;
@@ -400,12 +410,6 @@ __global__ void __launch_bounds__(256) dc_secular_kernel(int level, int n, int n
     }
 }
 
-__device__ __forceinline__ double warp_prod(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v *= __shfl_xor(v, o, 64);
-    return v;
-}
-
 // zhat_i^2 = prod_j (lambda_j - d_i) / (rho prod_{l != i} (d_l - d_i)), paired
 // so that every factor is a ratio in (0, 1] (interlacing).
 __global__ void __launch_bounds__(256) dc_lowner_kernel(int level, int n, int nl, double *dv, const int *iv,
@@ -435,7 +439,7 @@ __global__ void __launch_bounds__(256) dc_lowner_kernel(int level, int n, int nl
         const double den = (jj < i) ? (dh[jj] - di) : (dh[jj + 1] - di);
         prod *= num / den;
     }
-    prod = warp_prod(prod) * (((dh[org[k - 1]] - di) + tau[k - 1]) / rho);
+    prod = wave_prod_dpp(prod) * (((dh[org[k - 1]] - di) + tau[k - 1]) / rho);
     if (lane == 0) dv[(int64_t)DZHAT * n + a + i] = copysign(sqrt(fmax(prod, 0.0)), zh[i]);
 }
 
@@ -463,7 +467,7 @@ __global__ void __launch_bounds__(256) dc_norm_kernel(int level, int n, int nl, 
         const double u = zhat[i] / ((dh[i] - dO) - tj);
         s2 += u * u;
     }
-    s2 = warp_sum(s2);
+    s2 = wave_sum_dpp(s2);
     if (lane == 0) dv[(int64_t)DNRM * n + a + j] = 1.0 / sqrt(s2);
 }
 
