@@ -88,8 +88,15 @@ __device__ void norm_body(const double2 *__restrict__ M, int64_t lda, int n, int
     const double2 *col = M + (int64_t)j * lda;
     double part = 0.0;
     for (int r = j + 2 + threadIdx.x; r < n; r += blockDim.x) part += cabs2(col[r]);
-    const double sum = block_sum(part, red);
-    if (threadIdx.x == 0) npart[0] = sum;
+    // wave sums (every lane active), then the waves' in order
+    part = wave_sum_dpp(part);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sum = 0.0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) sum += red[k];
+        npart[0] = sum;
+    }
 }
 
 __global__ void __launch_bounds__(512) norm_kernel(const double2 *__restrict__ M, int64_t lda, int n, int j,
@@ -427,8 +434,10 @@ __device__ void w_rows(double2 *M, int64_t lda, int n, int j, int mt, int nt, co
         double2 z = cmk(0.0, 0.0);
         if (ti < c)
             for (int l = ti + ch; l < c; l += 8) z = cfma(Tl[ti][l], pS[l], z);
-#pragma unroll
-        for (int o = 1; o < 8; o <<= 1) z = cadd(z, cmk(__shfl_xor(z.x, o, 64), __shfl_xor(z.y, o, 64)));
+        // sum over the 8 lanes of row ti (every lane of the workgroup active)
+        z = cadd(z, cmk(xor_lane<1>(z.x, t & 63), xor_lane<1>(z.y, t & 63)));
+        z = cadd(z, cmk(xor_lane<2>(z.x, t & 63), xor_lane<2>(z.y, t & 63)));
+        z = cadd(z, cmk(xor_lane<4>(z.x, t & 63), xor_lane<4>(z.y, t & 63)));
         if (ch == 0 && ti <= c) Tb[ti + c * NB] = (ti == c) ? tj : cscale(cmul(tj, z), -1.0);
     }
     // V q + W p and (for column j+1) the panel terms, split over 4 groups
@@ -456,7 +465,7 @@ __device__ void w_rows(double2 *M, int64_t lda, int n, int j, int mt, int nt, co
         if (r < c) ys = csub(ys, cadd(cmul(Vs[r], qS[r]), cmul(Ws[r], pS[r])));
         double yv[2] = {ys.x, ys.y};
         const double ysum = wave_sum_split(yv);  // lanes 0..31: re, 32..63: im
-        const double2 yt = cmk(__shfl(ysum, 0, 64), __shfl(ysum, 32, 64));
+        const double2 yt = cmk(readlane_double(ysum, 0), readlane_double(ysum, 32));
         if (r == 0) wsh = cadd(cmul(tj, yt), cmk(a2, 0.0));  // v[s] = 1
     }
     __syncthreads();
@@ -600,8 +609,9 @@ __global__ void __launch_bounds__(1024) tail_kernel(double2 *M, int64_t lda, int
                     for (int u = 0; u < 8; ++u) acc = cfma(av[u], vv[u], acc);
                 }
             }
-#pragma unroll
-            for (int o = 1; o < 8; o <<= 1) acc = cadd(acc, cmk(__shfl_xor(acc.x, o, 64), __shfl_xor(acc.y, o, 64)));
+            acc = cadd(acc, cmk(xor_lane<1>(acc.x, lane), xor_lane<1>(acc.y, lane)));
+            acc = cadd(acc, cmk(xor_lane<2>(acc.x, lane), xor_lane<2>(acc.y, lane)));
+            acc = cadd(acc, cmk(xor_lane<4>(acc.x, lane), xor_lane<4>(acc.y, lane)));
             if (sub == 0 && i < m0) L.w[i] = acc;
         }
         __syncthreads();
