@@ -18,7 +18,7 @@ namespace psd {
 constexpr int LG_NB = 32;      // panel width of the tridiagonalisation
 constexpr int LG_TILE = 64;    // HEMV tile
 constexpr int LG_TAIL = 120;   // largest trailing order reduced by one workgroup in LDS
-constexpr int DC_LEAF = 4;     // largest leaf of the divide and conquer
+constexpr int DC_LEAF = 16;    // largest leaf of the divide and conquer
 
 struct LargeWs {
     int n;
