@@ -32,8 +32,15 @@
  * a workspace, partially overlapping x/y) are returned synchronously and
  * nothing is enqueued.  Conditions found on the device (non-finite input,
  * non-convergence) are written to `info` asynchronously; synchronise the
- * stream before reading it.  No call prints, throws or allocates.  Calls on
- * different streams with different workspaces may run concurrently.
+ * stream before reading it.  No call prints, throws or allocates, and none
+ * synchronises the stream except a mixed-mode psd_project while the FP64
+ * fallback is enabled (psd_set_mixed_fallback).  Calls on different streams
+ * with different workspaces may run concurrently.
+ *
+ * Failure policy: a block whose input holds a NaN or an infinity gets
+ * status PSD_ENONFINITE and an all-NaN output; a tridiagonal or secular
+ * iteration that hits its cap gets PSD_ENOCONV (the output is the last
+ * iterate's).
  */
 #ifndef PSDPROJ_H
 #define PSDPROJ_H
@@ -72,8 +79,10 @@ typedef struct {
     int32_t iters;        /* NS iterations (mixed) or 0 */
     int32_t fallback;     /* 1 if a mixed request fell back to the FP64 path */
     int32_t reserved;
-    double est_rel_err;   /* mixed: ||I - S^2||_F / sqrt(n) of the sign estimate S entering the
-                             last FP64 correction (the correction squares it); FP64: 0 */
+    double est_rel_err;   /* mixed: first-order estimate of ||y - Pi(X)||_F / ||Pi(X)||_F,
+                             ||[X, S]||_F / (4 ||y||_F) for the sign estimate S (the
+                             commutator vanishes for the exact sign; relative to ||X||_F
+                             when y = 0); FP64: 0 */
     double scale;         /* mixed: spectral scale alpha (~1.1 ||X||_2); FP64: 0 */
 } psd_info;
 
@@ -130,7 +139,9 @@ psd_status psd_project_vjp(int32_t n, const double *x, const double *saved,
  * stream the plan owns the first time a given (x, y, ws, infos) is executed
  * and replayed afterwards.  Creation allocates (streams, events, a device
  * copy of the block table); execution does not, apart from the one-time
- * capture and instantiation of a new graph.  concurrency = 0 takes the value
+ * capture and instantiation of a new graph (a plan keeps the graphs of its
+ * last 8 buffer sets; capturing a ninth synchronises `stream` and drops the
+ * oldest).  concurrency = 0 takes the value
  * psd_plan_tune last recorded for this arch/mode/size list in the tuning
  * cache (file PSD_TUNE_CACHE, default ./psdproj_tune.jsonl), else 4; the
  * group size recorded there is used as well.  Concurrency is clamped to
@@ -202,6 +213,17 @@ psd_status psd_timing_stop(double *ms, int32_t *launches, double *work);
  * of the low-precision iterations, which no further step reduces).
  * Returns PSD_EINVAL outside 0..200 / 0..8. */
 psd_status psd_set_ns_iterations(int32_t iters, int32_t corrections);
+
+/* FP64 fallback of the mixed modes (process-wide; not thread-safe):
+ * with max_rel_err > 0, psd_project in a mixed mode writes the mixed run's
+ * record to its workspace, synchronises the stream and, if that record
+ * reports PSD_ENOCONV or an est_rel_err above max_rel_err (or not a number),
+ * projects the block again by the FP64 path; the caller's info then holds
+ * the FP64 record with fallback = 1.  A non-finite input is not retried.
+ * Applies to single blocks outside graph capture (not to psd_project_batched
+ * or plans).  0 (the default) disables it.  Returns PSD_EINVAL for a
+ * negative or NaN bound. */
+psd_status psd_set_mixed_fallback(double max_rel_err);
 
 /* Static description of a status code. */
 const char *psd_status_string(psd_status status);

@@ -18,6 +18,8 @@ Contents (each function cites the passage it follows):
   which is what back-propagation through the projection needs (App. E).
 * ``constructed_projection`` -- the closed form U diag(max(lam,0)) U^H for an
   input built as U diag(lam) U^H (matmul as a library step).
+* ``constructed_vjp`` -- the closed form U (Gamma o U^H G U) U^H of the
+  derivative for such an input (App. E; Daleckii-Krein divided differences).
 """
 from __future__ import annotations
 
@@ -157,6 +159,27 @@ class Oracle:
         p = (u * lp[None, :]) @ u.conj().T
         return self.pack(p)
 
+    def constructed_vjp(self, u, lam, gy) -> np.ndarray:
+        """Closed form of the Daleckii-Krein derivative (App. E needs the
+        derivative of Pi) for X = U diag(lam) U^H with U unitary:
+        DPi(X)[G] = U (Gamma o (U^H G U)) U^H, G = mat_R(gy), with the divided
+        differences of f(t) = max(t, 0),
+            Gamma_ij = (f(lam_i) - f(lam_j)) / (lam_i - lam_j)  for opposite signs,
+                       1 if both are > 0, 0 if both are <= 0,
+        returned as svec (matmul as the library step)."""
+        u = np.asarray(u, dtype=np.complex128)
+        lam = np.asarray(lam, dtype=np.float64)
+        n = lam.size
+        g = self.unpack(gy, n)
+        pos = lam > 0.0
+        f = np.maximum(lam, 0.0)
+        den = lam[:, None] - lam[None, :]
+        mixed = pos[:, None] != pos[None, :]
+        gam = np.where(pos[:, None] & pos[None, :], 1.0, 0.0)
+        gam[mixed] = (f[:, None] - f[None, :])[mixed] / den[mixed]
+        m = u.conj().T @ g @ u
+        return self.pack(u @ (gam * m) @ u.conj().T)
+
     def num_threads(self) -> int:
         return int(self.lib.or_num_threads())
 
@@ -186,6 +209,7 @@ def project(s, n, mode=1): return default().project(s, n, mode)
 def reconstruct(lam, v): return default().reconstruct(lam, v)
 def vjp(s, gy, n, mode=1): return default().vjp(s, gy, n, mode)
 def constructed_projection(u, lam): return default().constructed_projection(u, lam)
+def constructed_vjp(u, lam, gy): return default().constructed_vjp(u, lam, gy)
 
 
 def num_threads() -> int:

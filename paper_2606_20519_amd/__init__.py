@@ -21,6 +21,7 @@ from . import _lib
 from ._lib import MODES, PSD_FLAG_SAVE, PsdError, PsdInfo, check  # noqa: F401
 
 __all__ = ["project", "project_batched", "vjp", "PSDProject", "Plan", "workspace", "set_ns_iterations",
+           "set_mixed_fallback",
            "PsdError", "MODES"]
 
 _ws_cache: dict = {}
@@ -31,6 +32,12 @@ def set_ns_iterations(iters: int = 0, corrections: int = 1):
     """Newton-Schulz steps (0: automatic, the scaled schedule's 21) and FP64
     correction steps of the mixed modes."""
     _lib.set_ns_iterations(iters, corrections)
+
+
+def set_mixed_fallback(max_rel_err: float = 0.0):
+    """FP64 re-run of a mixed-mode `project` whose error estimate exceeds
+    `max_rel_err` (0 disables it; the call then synchronises its stream)."""
+    _lib.set_mixed_fallback(max_rel_err)
 
 
 def _mode(mode) -> int:
@@ -91,6 +98,15 @@ def _info_dict(t: torch.Tensor) -> dict:
     return {f: getattr(rec, f) for f, _ in PsdInfo._fields_}
 
 
+def info_records(t: torch.Tensor, count: int) -> list:
+    """The first `count` psd_info records of an int32 tensor (device or host)
+    as dicts (synchronises)."""
+    raw = t.cpu().numpy().tobytes()
+    k = ctypes.sizeof(PsdInfo)
+    recs = [PsdInfo.from_buffer_copy(raw[i * k:(i + 1) * k]) for i in range(count)]
+    return [{f: getattr(r, f) for f, _ in PsdInfo._fields_} for r in recs]
+
+
 def project_batched(x: torch.Tensor, sizes, mode="fp64", out: torch.Tensor = None, info: bool = False):
     """Projects consecutive svec blocks of orders `sizes` independently."""
     sizes = [int(s) for s in sizes]
@@ -105,10 +121,7 @@ def project_batched(x: torch.Tensor, sizes, mode="fp64", out: torch.Tensor = Non
                                         ws.numel(), ctypes.c_void_p(_stream_ptr(x.device)), _ptr(inf_t))
     check(st, "psd_project_batched")
     if info:
-        raw = inf_t.cpu().numpy().tobytes()
-        k = ctypes.sizeof(PsdInfo)
-        recs = [PsdInfo.from_buffer_copy(raw[i * k:(i + 1) * k]) for i in range(len(sizes))]
-        return y, [{f: getattr(r, f) for f, _ in PsdInfo._fields_} for r in recs]
+        return y, info_records(inf_t, len(sizes))
     return y
 
 

@@ -22,7 +22,7 @@ EXPORTS = ("psd_workspace_size", "psd_saved_size", "psd_project", "psd_project_b
            "psd_project_vjp", "psd_plan_create", "psd_plan_workspace_size", "psd_plan_concurrency",
            "psd_plan_group_size", "psd_plan_ns_tile_threshold",
            "psd_plan_execute", "psd_plan_tune", "psd_plan_destroy", "psd_timing_start", "psd_timing_stop",
-           "psd_set_ns_iterations", "psd_status_string", "psd_version")
+           "psd_set_ns_iterations", "psd_set_mixed_fallback", "psd_status_string", "psd_version")
 KF_HEMV, KF_GEMM, KF_NS, KF_WSTEP = 1, 2, 3, 4
 
 
@@ -82,6 +82,8 @@ def lib():
     L.psd_plan_destroy.restype = i32
     L.psd_set_ns_iterations.argtypes = [i32, i32]
     L.psd_set_ns_iterations.restype = i32
+    L.psd_set_mixed_fallback.argtypes = [ctypes.c_double]
+    L.psd_set_mixed_fallback.restype = i32
     L.psd_timing_start.argtypes = [i32, i32]
     L.psd_timing_start.restype = i32
     L.psd_timing_stop.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
@@ -131,3 +133,7 @@ def timing_stop():
 
 def set_ns_iterations(iters: int, corrections: int):
     check(lib().psd_set_ns_iterations(iters, corrections), "psd_set_ns_iterations")
+
+
+def set_mixed_fallback(max_rel_err: float):
+    check(lib().psd_set_mixed_fallback(float(max_rel_err)), "psd_set_mixed_fallback")

@@ -1,6 +1,7 @@
 // Host runtime behind the C ABI declared in include/psdproj.h: argument
-// validation, workspace layout and kernel dispatch.  No call allocates,
-// prints or synchronises; all device work goes on the caller's stream.
+// validation, workspace layout and kernel dispatch.  No call allocates or
+// prints; all device work goes on the caller's stream, and only a mixed
+// psd_project with the FP64 fallback enabled synchronises it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -46,11 +47,15 @@ struct Carve {
     }
 };
 
-// Workspace of one FP64 large-block computation of order n.
+// Workspace of one large-block computation of order n.  Mixed modes also
+// reserve, after the larger of the two paths' layouts, an svec copy of the
+// input and one info record for the FP64 fallback (psd_set_mixed_fallback).
 size_t large_ws_bytes(int n, int mode, int flags) {
     size_t b = large_layout(n, flags, nullptr, nullptr);
-    if ((mode == PSD_MIXED_BF16 || mode == PSD_MIXED_FP32) && !(flags & PSD_FLAG_SAVE))
-        b = std::max(b, mixed_layout(n, mode, nullptr, nullptr));
+    if ((mode == PSD_MIXED_BF16 || mode == PSD_MIXED_FP32) && !(flags & PSD_FLAG_SAVE)) {
+        b = align_up(std::max(b, mixed_layout(n, mode, nullptr, nullptr)));
+        b += align_up(sizeof(double) * (size_t)n * (size_t)n) + align_up(sizeof(psd_info));
+    }
     return b;
 }
 
@@ -58,6 +63,32 @@ bool is_mixed(int mode) { return mode == PSD_MIXED_BF16 || mode == PSD_MIXED_FP3
 
 int g_ns_iters = 0;  // automatic
 int g_ns_corr = 1;
+double g_fallback_bound = 0.0;  // 0: no FP64 fallback of the mixed modes
+
+// Marks a record written by the FP64 path as the fallback of a mixed call.
+__global__ void mark_fallback_kernel(psd_dev_info *info) { info->fallback = 1; }
+
+// Host tables reach the device as kernel arguments, copied by value at the
+// launch: no staging buffer outlives the call, and a captured graph holds
+// its own copy of the values.
+constexpr int kArgWords = 512;
+struct ArgChunk {
+    uint32_t w[kArgWords];
+};
+__global__ void __launch_bounds__(256) upload_kernel(ArgChunk c, int nwords, uint32_t *dst) {
+    for (int i = threadIdx.x; i < nwords; i += blockDim.x) dst[i] = c.w[i];
+}
+hipError_t upload_table(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    const size_t words = (bytes + 3) / 4;
+    const uint32_t *sw = static_cast<const uint32_t *>(src);
+    for (size_t off = 0; off < words; off += kArgWords) {
+        ArgChunk c;
+        const int nw = (int)std::min<size_t>(kArgWords, words - off);
+        std::memcpy(c.w, sw + off, sizeof(uint32_t) * nw);
+        hipLaunchKernelGGL(upload_kernel, dim3(1), dim3(256), 0, s, c, nw, static_cast<uint32_t *>(dst) + off);
+    }
+    return hipGetLastError();
+}
 
 // Lockstep groups: blocks of one order n > 64 go through the path (FP64 or
 // mixed) together, at most group_cap(n, mode) at a time (32, fewer where 32
@@ -165,10 +196,46 @@ hipError_t project_group(int n, int nmem, psd_mode mode, const double *x, double
 psd_status status_of(hipError_t e) { return e == hipSuccess ? PSD_OK : PSD_EDEVICE; }
 
 
+// Mixed projection of one block with the FP64 fallback: the record of the
+// mixed run goes to the workspace, the stream is synchronised, and when the
+// run reports a failed status or an error estimate above the bound (or not a
+// number) the block is projected again by the FP64 path, whose record is
+// marked fallback = 1.  A non-finite input is not retried (FP64 would fail
+// the same way).  The input is copied first when the call is in place.
+hipError_t mixed_with_fallback(int n, const double *x, double *y, psd_mode mode, void *ws, hipStream_t s,
+                               psd_dev_info *info) {
+    MixedWs w;
+    const size_t base = align_up(std::max(large_layout(n, 0, nullptr, nullptr), mixed_layout(n, mode, nullptr, nullptr)));
+    mixed_layout(n, mode, ws, &w);
+    const size_t nb = sizeof(double) * (size_t)n * (size_t)n;
+    double *xcopy = reinterpret_cast<double *>(static_cast<char *>(ws) + base);
+    psd_dev_info *winfo = reinterpret_cast<psd_dev_info *>(static_cast<char *>(ws) + base + align_up(nb));
+    hipError_t e;
+    const double *xin = x;
+    if (x == y) {
+        if ((e = hipMemcpyAsync(xcopy, x, nb, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+        xin = xcopy;
+    }
+    if ((e = mixed_project(w, mode, x, y, winfo, g_ns_iters, g_ns_corr, s)) != hipSuccess) return e;
+    psd_dev_info h{};
+    if ((e = hipMemcpyAsync(&h, winfo, sizeof(h), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    const bool accept = h.status == PSD_ENONFINITE || (h.status == PSD_OK && h.est_rel_err <= g_fallback_bound);
+    if (accept) return info ? hipMemcpyAsync(info, winfo, sizeof(h), hipMemcpyDefault, s) : hipSuccess;
+    if ((e = large_project(n, xin, y, ws, s, info, nullptr)) != hipSuccess) return e;
+    if (info) hipLaunchKernelGGL(mark_fallback_kernel, dim3(1), dim3(1), 0, s, info);
+    return hipGetLastError();
+}
+
 // One block of order n > 64: the mixed path for mixed modes, else FP64.
 hipError_t project_block(int n, const double *x, double *y, psd_mode mode, void *ws, hipStream_t s,
-                         psd_dev_info *info, double *saved) {
+                         psd_dev_info *info, double *saved, bool allow_fallback = false) {
     if (is_mixed(mode) && !saved) {
+        if (allow_fallback && g_fallback_bound > 0.0) {
+            hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+            if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone)
+                return mixed_with_fallback(n, x, y, mode, ws, s, info);
+        }
         MixedWs w;
         mixed_layout(n, mode, ws, &w);
         return mixed_project(w, mode, x, y, info, g_ns_iters, g_ns_corr, s);
@@ -205,6 +272,12 @@ psd_status psd_set_ns_iterations(int32_t iters, int32_t corrections) {
     if (iters < 0 || iters > 200 || corrections < 0 || corrections > 8) return PSD_EINVAL;
     g_ns_iters = iters;
     g_ns_corr = corrections;
+    return PSD_OK;
+}
+
+psd_status psd_set_mixed_fallback(double max_rel_err) {
+    if (!(max_rel_err >= 0.0)) return PSD_EINVAL;
+    g_fallback_bound = max_rel_err;
     return PSD_OK;
 }
 
@@ -264,7 +337,7 @@ psd_status psd_project(int32_t n, const double *x, double *y, psd_mode mode, voi
         SmallJob job{0, 0, n, 0};
         return status_of(launch_small_one(job, x, y, dinfo, saved, s));
     }
-    return status_of(project_block(n, x, y, mode, ws, s, dinfo, saved));
+    return status_of(project_block(n, x, y, mode, ws, s, dinfo, saved, true));
 }
 
 psd_status psd_project_batched(int32_t nblocks, const int32_t *n, const double *x, double *y,
@@ -306,10 +379,9 @@ psd_status psd_project_batched(int32_t nblocks, const int32_t *n, const double *
     void *lws = cv.base + cv.used;
     std::vector<GroupChunk> chunks;
     if (grouped) chunks = make_chunks(nblocks, n, mode);
-    // One host-to-device copy of the job and group tables.  Pageable source:
-    // the copy is staged before hipMemcpyAsync returns.
+    // The job and group tables, uploaded as kernel arguments.
     if (cv.used > 0 && (!small.empty() || grouped)) {
-        std::vector<char> host(cv.used, 0);
+        std::vector<char> host((cv.used + 3) / 4 * 4, 0);
         if (!small.empty()) std::memcpy(host.data(), small.data(), small.size() * sizeof(SmallJob));
         if (grouped) {
             int64_t *hoff = reinterpret_cast<int64_t *>(host.data() + ioff_at);
@@ -322,7 +394,7 @@ psd_status psd_project_batched(int32_t nblocks, const int32_t *n, const double *
                     ++pos;
                 }
         }
-        hipError_t e = hipMemcpyAsync(ws, host.data(), cv.used, hipMemcpyHostToDevice, s);
+        hipError_t e = upload_table(ws, host.data(), cv.used, s);
         if (e != hipSuccess) return PSD_EDEVICE;
     }
     if (grouped) {

@@ -58,12 +58,16 @@ __global__ void __launch_bounds__(256) dc_leaf_kernel(const double *__restrict__
     __shared__ int nrot_s, done_s;
     const int q = blockIdx.x, t = threadIdx.x;
     const int a = leaf_bound(q, n, nl), b = leaf_bound(q + 1, n, nl), sz = b - a;
+    // A block whose input held a NaN or an infinity is solved as the zero
+    // matrix (its output is overwritten with NaN at the end): every index the
+    // merges derive from the data then stays well defined.
+    const bool flagged = status[2] == ST_ENONFINITE;
     if (t < sz) {
-        double dv = d[a + t];
-        if (t == 0 && a > 0) dv -= fabs(e[a - 1]);
-        if (t == sz - 1 && b < n) dv -= fabs(e[b - 1]);
+        double dv = flagged ? 0.0 : d[a + t];
+        if (!flagged && t == 0 && a > 0) dv -= fabs(e[a - 1]);
+        if (!flagged && t == sz - 1 && b < n) dv -= fabs(e[b - 1]);
         dl[t] = dv;
-        el[t] = (t < sz - 1) ? e[a + t] : 0.0;
+        el[t] = (!flagged && t < sz - 1) ? e[a + t] : 0.0;
     }
     for (int idx = t; idx < sz * sz; idx += blockDim.x) Z[idx] = (idx % sz == idx / sz) ? 1.0 : 0.0;
     __syncthreads();
@@ -74,7 +78,22 @@ __global__ void __launch_bounds__(256) dc_leaf_kernel(const double *__restrict__
         int rank = 0;
         for (int k = 0; k < sz; ++k) rank += (dl[k] < v) || (dl[k] == v && k < t);
         rankv[t] = rank;
-        D[a + rank] = v;
+    }
+    __syncthreads();
+    // Ranks are a permutation only if every value compares (no NaN, which a
+    // finite input can still produce by overflow): otherwise keep the order.
+    __shared__ int perm_ok;
+    if (t == 0) {
+        unsigned long long bits = 0;  // sz <= LEAF_MAX = 64 rows
+        for (int k = 0; k < sz; ++k) bits |= 1ull << rankv[k];
+        const bool perm = (sz == 64) ? (bits == ~0ull) : (bits == ((1ull << sz) - 1));
+        perm_ok = perm ? 1 : 0;
+        if (!perm && status[2] == ST_OK) status[2] = ST_ENONFINITE;
+    }
+    __syncthreads();
+    if (t < sz) {
+        if (!perm_ok) rankv[t] = t;
+        D[a + rankv[t]] = dl[t];
     }
     __syncthreads();
     for (int idx = t; idx < sz * sz; idx += blockDim.x) {
@@ -97,9 +116,11 @@ __device__ inline MergeGeo merge_geo(int level, int q, int n, int nl) {
 __global__ void __launch_bounds__(256) dc_prep_kernel(int level, int n, int nl, const double *__restrict__ e,
                                                       const double *__restrict__ Dcur, const double *Qcur,
                                                       double *Qnext, int64_t ldq, double *U, double *dv,
-                                                      int *iv, int *sv, GemmDesc *gd, int use_lds, int64_t zs) {
+                                                      int *iv, int *sv, GemmDesc *gd, int use_lds, int *status,
+                                                      int64_t zs) {
     {
         const int mb = blockIdx.z;
+        status = member_ptr(status, zs, mb);
         e = member_ptr(e, zs, mb);
         Dcur = member_ptr(Dcur, zs, mb);
         Qcur = member_ptr(Qcur, zs, mb);
@@ -114,8 +135,9 @@ __global__ void __launch_bounds__(256) dc_prep_kernel(int level, int n, int nl, 
     const int q = blockIdx.x, t = threadIdx.x;
     const MergeGeo g = merge_geo(level, q, n, nl);
     const int a = g.a, n1 = g.m - g.a, n2 = g.b - g.m, nm = g.b - g.a;
-    const double beta = e[g.m - 1];
-    const double rho = 2.0 * fabs(beta);
+    const bool flagged = status[2] == ST_ENONFINITE;
+    const double beta = flagged ? 0.0 : e[g.m - 1];
+    double rho = 2.0 * fabs(beta);
     const double sgn = beta < 0.0 ? -1.0 : 1.0;
     const double rs2 = 0.70710678118654752440;
     double *z = dv + (int64_t)DZ * n + a, *Dm = dv + (int64_t)DDM * n + a, *dd = dv + (int64_t)DDD * n + a;
@@ -124,16 +146,31 @@ __global__ void __launch_bounds__(256) dc_prep_kernel(int level, int n, int nl, 
     int *perm = iv + (int64_t)IPERM * n + a, *keep = iv + (int64_t)IKEEP * n + a;
     int *defl = iv + (int64_t)IDEFL * n + a, *rp = iv + (int64_t)IRP * n + a, *rn = iv + (int64_t)IRN * n + a;
     int *rowk = iv + (int64_t)IROWK * n + a;
-    double zmax = 0.0, dmax = 0.0;
+    // Every value must compare for the ranks and the deflation below to index
+    // correctly; a merge that meets a NaN or an infinity (flagged input, or
+    // overflow) is carried out on zeros instead and the block is flagged, so
+    // the rest of the solver stays in bounds (the output becomes NaN).
+    bool finite = isfinite(rho);
     for (int i = t; i < nm; i += blockDim.x) {
         const double zi = (i < n1) ? Qcur[(g.m - 1) + (int64_t)(a + i) * ldq] * rs2
                                    : sgn * Qcur[g.m + (int64_t)(g.m + i - n1) * ldq] * rs2;
-        z[i] = zi;
         const double di = Dcur[a + i];
+        finite = finite && isfinite(zi) && isfinite(di);
+        z[i] = zi;
         Dm[i] = di;
         dd[i] = di;
-        zmax = fmax(zmax, fabs(zi));
-        dmax = fmax(dmax, fabs(di));
+    }
+    const bool sane = __syncthreads_and(finite ? 1 : 0) != 0;
+    if (!sane) {
+        rho = 0.0;
+        for (int i = t; i < nm; i += blockDim.x) { z[i] = 0.0; Dm[i] = 0.0; dd[i] = 0.0; }
+        if (t == 0 && status[2] == ST_OK) status[2] = ST_ENONFINITE;
+        __syncthreads();
+    }
+    double zmax = 0.0, dmax = 0.0;
+    for (int i = t; i < nm; i += blockDim.x) {
+        zmax = fmax(zmax, fabs(z[i]));
+        dmax = fmax(dmax, fabs(dd[i]));
     }
     // block max via the sum helper on a two-pass scheme
     {
@@ -316,7 +353,7 @@ __device__ __forceinline__ double wave_prod_dpp(double v) {
 // > 0), solved by one wave (every lane active): the lanes split every sum
 // over i and the wave-wide DPP sums give all lanes the same totals, so all
 // lanes take the same steps.  Returns the origin pole o and tau with lambda = dh[o] + tau.
-__device__ void secular_root_wave(const double *dh, const double *zh, int k, double rho, int j, int *o_out,
+__device__ bool secular_root_wave(const double *dh, const double *zh, int k, double rho, int j, int *o_out,
                                   double *tau_out) {
     const int lane = threadIdx.x & 63;
     int o;
@@ -336,6 +373,7 @@ __device__ void secular_root_wave(const double *dh, const double *zh, int k, dou
     }
     const double dO = dh[o];
     double tau = 0.5 * (lo + hi);
+    bool converged = false;
     for (int it = 0; it < 100; ++it) {
         double psi = 0.0, phi = 0.0, dpsi = 0.0, dphi = 0.0, sabs = 0.0;
         for (int i = lane; i < k; i += 64) {
@@ -350,8 +388,8 @@ __device__ void secular_root_wave(const double *dh, const double *zh, int k, dou
         dpsi = wave_sum_dpp(dpsi); dphi = wave_sum_dpp(dphi); sabs = wave_sum_dpp(sabs);
         const double f = 1.0 + psi + phi;
         if (f < 0.0) lo = tau; else hi = tau;
-        if (f == 0.0 || fabs(f) <= 8.0 * EPS * (1.0 + sabs)) break;
-        if (hi - lo <= 2.0 * EPS * fmax(fabs(lo), fabs(hi))) break;
+        if (f == 0.0 || fabs(f) <= 8.0 * EPS * (1.0 + sabs)) { converged = true; break; }
+        if (hi - lo <= 2.0 * EPS * fmax(fabs(lo), fabs(hi))) { converged = true; break; }
         const double a_ = (dh[j] - dO) - tau;
         double tn;
         bool ok = false;
@@ -376,18 +414,20 @@ __device__ void secular_root_wave(const double *dh, const double *zh, int k, dou
             ok = c > 0.0;
         }
         if (!ok || !(tn > lo && tn < hi)) tn = 0.5 * (lo + hi);
-        if (fabs(tn - tau) <= 2.0 * EPS * fabs(tn)) { tau = tn; break; }
+        if (fabs(tn - tau) <= 2.0 * EPS * fabs(tn)) { tau = tn; converged = true; break; }
         tau = tn;
     }
     *o_out = o;
     *tau_out = tau;
+    return converged;
 }
 
 // One wave per root: 4 roots per 256-thread workgroup.
 __global__ void __launch_bounds__(256) dc_secular_kernel(int level, int n, int nl, double *dv, int *iv,
-                                                         const int *sv, int64_t zs) {
+                                                         const int *sv, int *status, int64_t zs) {
     {
         const int mb = blockIdx.z;
+        status = member_ptr(status, zs, mb);
         dv = member_ptr(dv, zs, mb);
         iv = member_ptr(iv, zs, mb);
         sv = member_ptr(sv, zs, mb);
@@ -402,8 +442,9 @@ __global__ void __launch_bounds__(256) dc_secular_kernel(int level, int n, int n
     const double *dh = dv + (int64_t)DDH * n + a, *zh = dv + (int64_t)DZH * n + a;
     int o;
     double tau;
-    secular_root_wave(dh, zh, k, rho, j, &o, &tau);
+    const bool converged = secular_root_wave(dh, zh, k, rho, j, &o, &tau);
     if ((threadIdx.x & 63) == 0) {
+        if (!converged && status[2] == ST_OK) status[2] = ST_ENOCONV;
         iv[(int64_t)IORG * n + a + j] = o;
         dv[(int64_t)DTAU * n + a + j] = tau;
         dv[(int64_t)DLAM * n + a + j] = dh[o] + tau;
@@ -614,10 +655,11 @@ hipError_t large_dc(LargeWs &w, hipStream_t st) {
         const int use_lds = maxnm <= PREP_LDS_MAX ? 1 : 0;
         const size_t prep_lds = use_lds ? (size_t)maxnm * 20 : 0;
         hipLaunchKernelGGL(dc_prep_kernel, dim3(nmerge, 1, B), dim3(256), prep_lds, st, level, n, nl, w.e, Dc, Qc,
-                           Qn, ldq, w.U, w.dcd, w.dci, w.dcs, w.gdesc, use_lds, zs);
+                           Qn, ldq, w.U, w.dcd, w.dci, w.dcs, w.gdesc, use_lds, w.ksel, zs);
         dim3 wgrid((maxnm + 3) / 4, nmerge, B);
         dim3 tgrid((maxnm + 255) / 256, nmerge, B);
-        hipLaunchKernelGGL(dc_secular_kernel, wgrid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs, zs);
+        hipLaunchKernelGGL(dc_secular_kernel, wgrid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs, w.ksel,
+                           zs);
         hipLaunchKernelGGL(dc_lowner_kernel, wgrid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs, zs);
         hipLaunchKernelGGL(dc_norm_kernel, wgrid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs, zs);
         hipLaunchKernelGGL(dc_order_kernel, tgrid, dim3(256), 0, st, level, n, nl, w.dcd, w.dci, w.dcs, Dn, zs);

@@ -48,6 +48,9 @@ struct GemmDesc {
     const int *dK;
     // EPI_SVEC: sign read from the device (base x used iff sign < 0).
     const double *dsign;
+    // EPI_SVEC: status word of the problem (nullable); when it reports a
+    // non-finite input every output entry is NaN.
+    const int *dstatus;
     // Split-K: blockIdx.z handles K range [z*kchunk, (z+1)*kchunk) and
     // writes its partial product to C + z*c_zstride (beta must be 0).
     int kchunk;

@@ -39,6 +39,7 @@ __global__ void __launch_bounds__(NT, 3) gemm_kernel(GemmDesc d) {
         d.dN = member_ptr(d.dN, d.zs, b);
         d.dK = member_ptr(d.dK, d.zs, b);
         d.dsign = member_ptr(d.dsign, d.zs, b);
+        d.dstatus = member_ptr(d.dstatus, d.zs, b);
     }
     if (d.ioff) {  // also for a group of one: its svec need not start at offset 0
         const int64_t o = d.ioff[b];

@@ -238,6 +238,7 @@ __device__ void gemm_tile(const GemmDesc &dd, int ti, int tj, int tz, GemmLds<T>
                 double re = acc_r[a][b][v], im = CPLX ? acc_i[a][b][v] : 0.0;
                 if (EPI == EPI_SVEC) {
                     if (i < j) continue;
+                    if (d.dstatus && *d.dstatus == ST_ENONFINITE) re = im = __builtin_nan("");
                     const int64_t n = d.svec_n;
                     const double sgn = d.dsign ? *d.dsign : d.sign;
                     const double *xb = (d.dsign && sgn > 0.0) ? nullptr : d.xbase;

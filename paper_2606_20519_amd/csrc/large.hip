@@ -343,6 +343,7 @@ hipError_t large_reconstruct(const LargeWs &w, const double *x, double *y, int k
     g.y = y; g.xbase = x; g.svec_n = w.n; g.sign = 1.0;
     g.dsign = w.sgn;
     g.dK = w.ksel;
+    g.dstatus = w.ksel + 2;
     g.nmem = w.nmem; g.zs = w.zs; g.ioff = w.ioff;
     return gemm_launch(g, true, EPI_SVEC, st);
 }
@@ -392,6 +393,7 @@ hipError_t large_vjp_from_v(const LargeWs &w, const double *gy, double *gx, hipS
     d.A = GemmOperand{w.Zc, w.Zc, w.lda, w.lda, n, OP_N, nullptr};
     d.B = GemmOperand{B1, B1, n, n, n, OP_N, nullptr};
     d.y = gx; d.xbase = nullptr; d.svec_n = n; d.sign = 1.0;
+    d.dstatus = w.ksel + 2;
     return gemm_launch(d, true, EPI_SVEC, st);
 }
 

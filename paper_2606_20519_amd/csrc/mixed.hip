@@ -9,7 +9,8 @@
 //
 // Stages (FP64 only where it buys accuracy):
 //  * scale: alpha from a short FP64 Lanczos run (24 Hermitian mat-vecs, then
-//    the eigenvalues of the small tridiagonal by QL), alpha = 1.1 max|theta|;
+//    the extreme eigenvalues of the small tridiagonal by Sturm-count
+//    multisection), alpha = 1.1 max|theta|;
 //  * X_0 = X/alpha rounded (RNE) to BF16 or FP32 planar complex;
 //  * K scaled iterations X_{k+1} = (a_k/2) X_k (3I - a_k^2 X_k^2) (Chen and
 //    Chow's scaled Newton-Schulz, scalings capped at 1.5: a_k from the known
@@ -20,14 +21,16 @@
 //    kept in FP64;
 //  * c FP64 correction steps S <- S (3I - S^2)/2 (FP64 MFMA GEMMs over the
 //    lower tiles, each written with its conjugate mirror: both products are
-//    Hermitian), which square the error of every eigencomponent whose sign
+//    Hermitian), which square the error of every eigenvalue of S whose sign
 //    the low-precision iterations already resolved;
-//  * Pi = X/2 + X S/2 by one FP64 GEMM over the lower tiles writing the svec;
-//    est_rel_err = ||I - S^2||_F / sqrt(n) of the S entering the last
-//    correction, n_pos from tr S.
-// Components with |lambda| below the low precision's resolution (about
-// u ||X||: u = 2^-8 for BF16, 2^-24 for FP32) cannot be classified; their
-// contribution to the error is at most |lambda| each.
+//  * F = X S by one full FP64 GEMM, then Pi = X/2 + (F + F^H)/4, the
+//    Hermitian part (X and the exact sign commute), written as the svec;
+//    the anti-Hermitian part F - F^H = [X, S] gives the error estimate
+//    ||[X, S]||_F / (4 ||Pi||_F), and n_pos comes from tr S.
+// The low-precision iterations return the sign of a matrix within about
+// K u ||X|| of X (u = 2^-8 for BF16, 2^-24 for FP32); since Pi is
+// 1-Lipschitz the result is within that distance of Pi(X), and components
+// with |lambda| below it may be classified either way.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -757,51 +760,112 @@ __global__ void __launch_bounds__(256) ns128_tail_kernel(const float *__restrict
     ns128_store_block(re, im, i0 + wm * 64 + a * 16, j0 + wn * 64 + b * 16, lane, npad, epi, c, Cre, Cim, C64, ld64, n);
 }
 
-// ||T - 2I||_F^2 (T = 3I - S^2, so T - 2I = I - S^2) and tr S: partials per
-// column block (one workgroup per 16 columns), then one workgroup writes the
-// info record.
-constexpr int RES_COLS = 16;
-__global__ void __launch_bounds__(256) ns_residual_part_kernel(const double2 *__restrict__ T,
-                                                               const double2 *__restrict__ S, int64_t lda, int n,
-                                                               double *red_out, int64_t zs) {
+// Assembly of Pi = X/2 + (X S + S X)/4 from F = X S (full FP64 product):
+// (S X)_ij = conj(F_ji), since X and S are Hermitian, so each lower entry
+// needs F_ij and F_ji.  The Hermitian part is what the exact sign would give
+// (X and sign X commute); the anti-Hermitian part C = F - F^H = [X, S] is the
+// commutator, zero for the exact sign: its norm measures how far S's
+// eigenvectors are from X's.  One workgroup per 32x32 lower tile (I >= J)
+// loads tile (I, J) and, through LDS, tile (J, I); it writes the svec and
+// four partial sums: ||C||_F^2, ||Pi||_F^2, tr S, ||X||_F^2.
+constexpr int AT = 32;
+constexpr int ASM_SUMS = 4;
+__global__ void __launch_bounds__(256) mx_assemble_kernel(const double2 *__restrict__ M,
+                                                          const double2 *__restrict__ F,
+                                                          const double2 *__restrict__ S, int64_t lda, int n,
+                                                          double *y, const int64_t *__restrict__ ioff,
+                                                          const int *status, double *red_out, int64_t zs) {
+    __shared__ double2 U[AT][AT + 1];
     __shared__ double red[8];
-    T = member_ptr(T, zs, blockIdx.z);
-    S = member_ptr(S, zs, blockIdx.z);
-    red_out = member_ptr(red_out, zs, blockIdx.z);
-    const int j0 = blockIdx.x * RES_COLS;
-    double r2 = 0.0, tr = 0.0;
-    for (int j = j0; j < min(n, j0 + RES_COLS); ++j)
-        for (int i = threadIdx.x; i < n; i += blockDim.x) {
-            double2 v = T[i + (int64_t)j * lda];
-            if (i == j) { v.x -= 2.0; tr += S[i + (int64_t)i * lda].x; }
-            r2 += cabs2(v);
+    const int mb = blockIdx.z;
+    M = member_ptr(M, zs, mb);
+    F = member_ptr(F, zs, mb);
+    S = member_ptr(S, zs, mb);
+    status = member_ptr(status, zs, mb);
+    red_out = member_ptr(red_out, zs, mb);
+    if (ioff) y += ioff[mb];
+    const int tile = blockIdx.x;
+    int I = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= tile) ++I;
+    while (I * (I + 1) / 2 > tile) --I;
+    const int J = tile - I * (I + 1) / 2;
+    const int i0 = I * AT, j0 = J * AT, t = threadIdx.x;
+    // tile (J, I) of F: U[ii][jj] = F(j0 + jj, i0 + ii)
+#pragma unroll
+    for (int q = 0; q < AT * AT / 256; ++q) {
+        const int jj = t % AT, ii = t / AT + q * (256 / AT);
+        const int r = j0 + jj, c = i0 + ii;
+        U[ii][jj] = (r < n && c < n) ? F[r + (int64_t)c * lda] : cmk(0.0, 0.0);
+    }
+    __syncthreads();
+    const bool poison = status[2] == ST_ENONFINITE;
+    const double rt2 = 1.41421356237309504880, nan = __builtin_nan("");
+    double c2 = 0.0, p2 = 0.0, trs = 0.0, x2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < AT * AT / 256; ++q) {
+        const int ii = t % AT, jj = t / AT + q * (256 / AT);
+        const int i = i0 + ii, j = j0 + jj;
+        if (i >= n || j >= n || i < j) continue;
+        const double2 fij = F[i + (int64_t)j * lda], fji = U[ii][jj], m = M[i + (int64_t)j * lda];
+        const double2 h = cmk(0.25 * (fij.x + fji.x), 0.25 * (fij.y - fji.y));
+        const double2 out = cmk(0.5 * m.x + h.x, 0.5 * m.y + h.y);
+        const double2 cm = cmk(fij.x - fji.x, fij.y + fji.y);
+        if (i == j) {
+            const double o = 0.5 * m.x + 0.5 * fij.x;
+            y[svec_col_start(n, j)] = poison ? nan : o;
+            c2 += cabs2(cm);
+            p2 += o * o;
+            x2 += m.x * m.x;
+            trs += S[i + (int64_t)i * lda].x;
+        } else {
+            const int64_t o = svec_off(n, i, j);
+            y[o] = poison ? nan : rt2 * out.x;
+            y[o + 1] = poison ? nan : rt2 * out.y;
+            c2 += 2.0 * cabs2(cm);
+            p2 += 2.0 * cabs2(out);
+            x2 += 2.0 * cabs2(m);
         }
-    r2 = block_sum(r2, red);
-    tr = block_sum(tr, red + 4);
-    if (threadIdx.x == 0) { red_out[2 * blockIdx.x] = r2; red_out[2 * blockIdx.x + 1] = tr; }
+    }
+    c2 = block_sum(c2, red);
+    p2 = block_sum(p2, red);
+    trs = block_sum(trs, red);
+    x2 = block_sum(x2, red);
+    if (t == 0) {
+        double *o = red_out + (int64_t)tile * ASM_SUMS;
+        o[0] = c2; o[1] = p2; o[2] = trs; o[3] = x2;
+    }
 }
 
-__global__ void __launch_bounds__(256) ns_residual_final_kernel(const double *__restrict__ red_in, int nb, int n,
-                                                                int iters, const double *alpha, const int *status,
-                                                                psd_dev_info *info, int64_t zs, const int *infoidx) {
+// Info record of a mixed projection: the tile partials summed in tile order
+// (deterministic), n_pos = (n + tr S) / 2, and the first-order error estimate
+// ||[X, S]||_F / (4 ||Pi||_F) (relative to ||X||_F when Pi = 0).  In the
+// eigenbasis of X the error of the assembled Pi on an entry coupling
+// eigenvalues of opposite signs is (l_i + l_j) / (l_i - l_j) C_ij / 4, of
+// modulus at most |C_ij| / 4.
+__global__ void __launch_bounds__(256) mx_info_kernel(const double *__restrict__ red_in, int ntile, int n, int iters,
+                                                      const double *alpha, const int *status, psd_dev_info *info,
+                                                      int64_t zs, const int *infoidx) {
     __shared__ double red[8];
     red_in = member_ptr(red_in, zs, blockIdx.z);
     alpha = member_ptr(alpha, zs, blockIdx.z);
     status = member_ptr(status, zs, blockIdx.z);
     if (info) info += infoidx ? infoidx[blockIdx.z] : blockIdx.z;
-    double r2 = 0.0, tr = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) { r2 += red_in[2 * b]; tr += red_in[2 * b + 1]; }
-    r2 = block_sum(r2, red);
-    tr = block_sum(tr, red + 4);
+    double acc[ASM_SUMS] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < ntile; b += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < ASM_SUMS; ++k) acc[k] += red_in[(int64_t)b * ASM_SUMS + k];
+#pragma unroll
+    for (int k = 0; k < ASM_SUMS; ++k) acc[k] = block_sum(acc[k], red);
     if (threadIdx.x == 0 && info) {
-        const int npos = (int)llround(0.5 * (n + tr));
+        const double cn = sqrt(acc[0]), pn = sqrt(acc[1]), xn = sqrt(acc[3]);
+        const int npos = (int)llround(0.5 * (n + acc[2]));
         info->status = status[2];
         info->n_pos = min(max(npos, 0), n);
         info->n_neg = n - info->n_pos;
         info->iters = iters;
         info->fallback = 0;
         info->reserved = 0;
-        info->est_rel_err = sqrt(r2 / n);
+        info->est_rel_err = pn > 0.0 ? 0.25 * cn / pn : (xn > 0.0 ? 0.25 * cn / xn : 0.0);
         info->scale = *alpha;
     }
 }
@@ -900,30 +964,21 @@ hipError_t ns_run(const MixedWs &w, const double *x, double *y, psd_dev_info *in
         if (e != hipSuccess) return e;
         std::swap(S, S2);
     }
-    if (corr == 0) {
-        GemmDesc a{};
-        a.M = a.N = a.K = n;
-        a.A = GemmOperand{S, S, w.lda, w.lda, n, OP_N, nullptr};
-        a.B = GemmOperand{S, S, w.lda, w.lda, n, OP_N, nullptr};
-        a.C = w.T64; a.ldc = w.lda; a.alpha = -1.0; a.beta = 0.0; a.diag_add = 3.0;
-        a.lower_only = 1; a.mirror = 1;  // S^2 is Hermitian
-        a.nmem = B; a.zs = zs;
-        hipError_t e = gemm_launch(a, true, EPI_STORE, st);
-        if (e != hipSuccess) return e;
-    }
-    const int nrb = (n + RES_COLS - 1) / RES_COLS;
-    hipLaunchKernelGGL(ns_residual_part_kernel, dim3(nrb, 1, B), dim3(256), 0, st, w.T64, S, w.lda, n, w.red, zs);
-    hipLaunchKernelGGL(ns_residual_final_kernel, dim3(1, 1, B), dim3(256), 0, st, w.red, nrb, n, iters, w.alpha,
-                       w.status, info, zs, w.infoidx);
-    // Pi = X/2 + X S / 2, lower tiles, straight into the svec
+    // F = X S (full), then the symmetrised assembly and the info record
     GemmDesc f{};
     f.M = f.N = f.K = n;
-    f.lower_only = 1;
     f.A = GemmOperand{w.M, w.M, w.lda, w.lda, n, OP_N, nullptr};
     f.B = GemmOperand{S, S, w.lda, w.lda, n, OP_N, nullptr};
-    f.y = y; f.xbase = x; f.svec_n = n; f.sign = 0.5; f.xscale = 0.5;
-    f.nmem = B; f.zs = zs; f.ioff = w.ioff;
-    return gemm_launch(f, true, EPI_SVEC, st);
+    f.C = w.T64; f.ldc = w.lda; f.alpha = 1.0; f.beta = 0.0;
+    f.nmem = B; f.zs = zs;
+    hipError_t e = gemm_launch(f, true, EPI_STORE, st);
+    if (e != hipSuccess) return e;
+    const int at = (n + AT - 1) / AT, natile = at * (at + 1) / 2;
+    hipLaunchKernelGGL(mx_assemble_kernel, dim3(natile, 1, B), dim3(256), 0, st, w.M, w.T64, S, w.lda, n, y, w.ioff,
+                       w.status, w.red, zs);
+    hipLaunchKernelGGL(mx_info_kernel, dim3(1, 1, B), dim3(256), 0, st, w.red, natile, n, iters, w.alpha, w.status,
+                       info, zs, w.infoidx);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -957,7 +1012,10 @@ size_t mixed_layout(int n, int mode, void *base, MixedWs *w) {
     W.ab = (double *)take(sizeof(double) * (2 * LZ_STEPS + 8));
     W.alpha = (double *)take(sizeof(double));
     W.status = (int *)take(sizeof(int) * 4);
-    W.red = (double *)take(sizeof(double) * 2 * ((size_t)(n + 15) / 16 + 1));
+    {
+        const size_t at = ((size_t)n + AT - 1) / AT;
+        W.red = (double *)take(sizeof(double) * ASM_SUMS * (at * (at + 1) / 2));
+    }
     W.part = nullptr;
     W.ns_big = NS_BIG;
     if (mode == 1 && W.npad >= NS_BIG) {

@@ -40,6 +40,7 @@ using namespace psd;
 namespace {
 
 constexpr int kMaxConcurrency = 32;
+constexpr int kMaxGraphs = 8;  // captured (x, y, ws, infos) sets kept per plan
 
 struct GraphEntry {
     const double *x;
@@ -263,6 +264,13 @@ psd_status psd_plan_execute(psd_plan p, const double *x, double *y, void *ws, si
     if (ws && (reinterpret_cast<uintptr_t>(ws) % 256)) return PSD_EINVAL;
     hipGraphExec_t ex = find_graph(p, x, y, ws, infos, p->K);
     if (!ex) {
+        // at most kMaxGraphs captured buffer sets; the oldest is dropped once
+        // the work already queued on the stream (which may replay it) is done
+        if ((int)p->graphs.size() >= kMaxGraphs) {
+            if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return PSD_EDEVICE;
+            (void)hipGraphExecDestroy(p->graphs.front().exec);
+            p->graphs.erase(p->graphs.begin());
+        }
         if (capture(p, x, y, ws, infos, p->K, &ex) != hipSuccess) return PSD_EDEVICE;
         p->graphs.push_back(GraphEntry{x, y, ws, infos, p->K, p->group, p->ns_big, ex});
     }

@@ -12,9 +12,11 @@ namespace psd {
 // On exit d holds the eigenvalues (unsorted) and Z <- Z * (rotations), so
 // that T = Z diag(d) Z^T when Z started as I.
 //
-// Each sweep is the classical one of Bowdler, Martin, Reinsch and Wilkinson
-// (tql2): a Wilkinson-type shift from the leading 2x2 of the unreduced block,
-// then plane rotations chased from its bottom to its top.  Thread 0 computes
+// Each sweep is the implicit QL step of Dubrulle, Martin and Wilkinson
+// ("The implicit QL algorithm", Numer. Math. 12, 1968; EISPACK's imtql2): a
+// Wilkinson-type shift from the leading 2x2 of the unreduced block, then
+// plane rotations chased from its bottom to its top, the shift entering
+// only through the first rotation.  Thread 0 computes
 // a sweep's rotations sequentially (recording them in rc/rs/ri, >= n
 // entries each); then every thread applies them, in order, to its own rows
 // of Z.  nrot/done are LDS scalars.  All threads must call this.

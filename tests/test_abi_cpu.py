@@ -100,3 +100,14 @@ def test_project_rejects_bad_arguments_on_host(L):
     # vjp: needs x or saved
     assert lib.psd_project_vjp(16, None, None, fake, fake2, 0, ws, 1 << 20, None) == 1
     assert lib.psd_project_vjp(0, fake, None, fake, fake2, 0, ws, 1 << 20, None) == 1
+
+
+def test_setters_validate_on_host(L):
+    lib = L.lib()
+    assert lib.psd_set_mixed_fallback(-1.0) == 1
+    assert lib.psd_set_mixed_fallback(float("nan")) == 1
+    assert lib.psd_set_mixed_fallback(1e-3) == 0
+    assert lib.psd_set_mixed_fallback(0.0) == 0
+    assert lib.psd_set_ns_iterations(-1, 1) == 1
+    assert lib.psd_set_ns_iterations(0, 9) == 1
+    assert lib.psd_set_ns_iterations(0, 1) == 0

@@ -12,6 +12,8 @@ import pytest
 import oracle
 from paper_2606_20519_amd import workloads as W
 
+import bars
+
 pytestmark = pytest.mark.gpu
 
 
@@ -154,7 +156,7 @@ def test_plan_mixed_matches_eager(P):
         torch.cuda.synchronize()
         assert np.array_equal(y.cpu().numpy(), eager)
     for off, m, s in blocks(x_np, sizes):
-        tol = 1e-10 if m <= 64 else 3e-6
+        tol = 1e-10 if m <= 64 else bars.FP32_REL_BAR
         assert rel(eager[off:off + m * m], oracle.project(s, m)) <= tol
     plan.close()
 
@@ -175,7 +177,8 @@ def test_plan_bf16_tile_form(P, tmp_path):
         x_np = np.concatenate([c[0] for c in cons] + [W.gue(25, 8500 + i) for i in range(4)])
         sizes = [n] * count + [25] * 4
         x = dev(x_np)
-        eager = P.project_batched(x, sizes, "mixed_bf16").cpu().numpy()
+        eager_t, eager_inf = P.project_batched(x, sizes, "mixed_bf16", info=True)
+        eager = eager_t.cpu().numpy()
         plan = P.Plan(sizes, "mixed_bf16")
         assert plan.ns_tile_threshold == 2048
         assert np.array_equal(plan.execute(x).cpu().numpy(), eager)
@@ -191,10 +194,13 @@ def test_plan_bf16_tile_form(P, tmp_path):
             torch.cuda.synchronize()
             assert np.array_equal(plan.execute(x).cpu().numpy(), first)
         for i, (s, u, lam) in enumerate(cons):
+            # the 128x128 form sums in another order: allow twice the
+            # first-order term of the eager (64x64) run's estimate
             exact = oracle.constructed_projection(u, lam)
-            band = np.sqrt(np.sum(lam[np.abs(lam) < 0.03] ** 2))
+            nrm = np.linalg.norm(exact)
             err = np.linalg.norm(first[i * n * n:(i + 1) * n * n] - exact)
-            assert err <= 2.0 * band + 1e-9 * np.linalg.norm(exact), (i, err, band)
+            bar = bars.mixed_bar_abs(lam, "mixed_bf16", nrm, 2.0 * eager_inf[i]["est_rel_err"])
+            assert err <= bar, (i, err, bar)
         off = count * n * n
         assert np.array_equal(first[off:], eager[off:])  # the small blocks do not depend on it
         y = torch.empty_like(x)

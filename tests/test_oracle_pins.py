@@ -332,6 +332,37 @@ def test_vjp_constructed_spectrum(orc):
     assert rel(orc.vjp(sx, orc.pack(e), n), orc.pack(ref)) <= 1e-12
 
 
+def test_constructed_vjp_closed_form(orc):
+    # the closed form used at full size (n = 4096), pinned here against the
+    # hand-built divided-difference matrix, the Jacobi-based derivative and
+    # central differences of the Jacobi projection, and the Euler identity
+    n = 24
+    sx, u, lam = W.constructed(n, 1234, gap=1e-2)
+    e = herm(n, np.random.default_rng(8))
+    gam = np.empty((n, n))
+    for i in range(n):
+        for j in range(n):
+            a, b = lam[i], lam[j]
+            if a > 0 and b > 0:
+                gam[i, j] = 1.0
+            elif a <= 0 and b <= 0:
+                gam[i, j] = 0.0
+            else:
+                gam[i, j] = max(a, b) / (max(a, b) - min(a, b))
+    ref = orc.pack(u @ (gam * (u.conj().T @ e @ u)) @ u.conj().T)
+    got = orc.constructed_vjp(u, lam, orc.pack(e))
+    assert rel(got, ref) <= 1e-13
+    assert rel(got, orc.vjp(sx, orc.pack(e), n)) <= 1e-12
+    h = 1e-6
+    fd = (orc.project(sx + h * orc.pack(e), n) - orc.project(sx - h * orc.pack(e), n)) / (2 * h)
+    assert rel(got, fd) <= 1e-7
+    assert rel(orc.constructed_vjp(u, lam, sx), orc.constructed_projection(u, lam)) <= 1e-13
+    # opposite-sign pairs only: Gamma in (0, 1), and a pure sign flip of the
+    # spectrum maps DPi to I - DPi (Moreau: Pi(X) - Pi(-X) = X)
+    flip = orc.constructed_vjp(u, -lam, orc.pack(e))
+    assert rel(got + flip, orc.pack(e)) <= 1e-13
+
+
 # --------------------------------------------------------------------------
 # Newton-Schulz reference (mixed form attribution)
 # --------------------------------------------------------------------------
