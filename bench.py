@@ -1,34 +1,40 @@
 #!/usr/bin/env python3
 """Throughput of the PSD-cone projection on one MI355X.
 
-Default workload (c2): the n = 625 (d = 5) warm-start sequence -- 50 SCS-like
-iterates X_{k+1} = X_k + 1e-3 (H_k + H_k^H)/2 of a Hermitian (G + G^H)/2 --
-each projected by the FP64 eigen path (unpack, blocked Householder
-tridiagonalisation, divide and conquer, back-transform, fused clamp +
-reconstruction + svec pack).  One step = the 50 projections.  Inputs are
-resident in HBM before the timed region.
+Default workload (c5): one d = 8 process-matrix block, n = d^4 = 4096, X =
+(G + G^H)/2 with G iid circular CN(0,1) (seed 1005), projected by the FP64
+eigen path (unpack, blocked Householder tridiagonalisation, divide and
+conquer, back-transform, fused clamp + reconstruction + svec pack) -- the
+paper's c128 arithmetic at its largest size (Table III, d = 8).  One step =
+one projection; inputs are resident in HBM before the timed region.  Context
+fields of the same line: the derivative (VJP) rate from the saved eigen-pair;
+the FP32- and BF16-mixed rates at the same order; the error of every form
+against the closed form on a constructed spectrum of the same order (Haar U,
+|lambda| log-uniform in [1e-6, 1], half negative); the FP64 GEMMs' MFMA rate;
+the composite bound T* = F_MFMA / P_FP64 + B_HEMV / BW; and a NumPy eigh-based
+projection on the host (the paper's CPU column, Table III "NumPy c128").
 
 Other workloads (one JSON line each, selected with --workload):
   c1  50 blocks of order 16 (d = 2), one batched launch per step
+  c2  the n = 625 (d = 5) warm-start sequence: 50 SCS-like iterates
+      X_{k+1} = X_k + 1e-3 (H_k + H_k^H)/2 projected one after another
   c3  orders 1296 and 2401 (d = 6, 7), spectra in [-1,-1e-6] u [1e-6,1],
       --mode mixed_bf16 | mixed_fp32 | fp64 (--n picks the order)
   c4  one cone of 32 instances x [W (d^4) + 8 Choi (d^2)] by one graph
       launch per step (--d picks d, --mode the precision)
-  c5  order 4096 (d = 8): forward projection, and the derivative (VJP) timed
-      after it (--mode fp64 | mixed_*)
+  c5  (default) order 4096, --mode fp64 | mixed_*
 
 The JSON line carries the roofline of the dominant kernel, timed live with
 HIP events recorded by the library on the kernel's own launch stream (FP64:
 the tridiagonalisation's HEMV; mixed: the Newton-Schulz products or the FP64
-correction products, whichever takes more of a projection in an untimed
-probe, with the other as context), and the
-CPU oracle timed on a bounded sample of the same workload.  Its "traffic" is
-the HBM bytes per launch that rocprofv3 counters measured for that kernel
-(profiles/traffic_*.txt, scaled by the counters of a plain copy of known
-size, --copy-calibration); it is null when the kernel's source file no longer
-has the hash recorded with the counters.
+products, whichever takes more of a projection in an untimed probe, with the
+other as context), and the CPU oracle timed on a bounded sample of the same
+workload.  Its "traffic" is the HBM bytes per launch that rocprofv3 counters
+measured for that kernel (profiles/traffic_*.txt, scaled by the counters of a
+plain copy of known size, --copy-calibration); it is null when the kernel's
+source files no longer have the hash recorded with the counters.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c2]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload c5]
 """
 import hashlib
 import argparse
@@ -56,8 +62,42 @@ def flops_eig(n: int, k: int) -> float:
 def flops_ns(n: int, iters: int, corr: int) -> float:
     """Algorithmic real flops of one mixed projection: per Newton-Schulz step
     two Hermitian products (lower half: 4 n^3 each), per FP64 correction two
-    full complex products (8 n^3 each), and the final product (lower half)."""
-    return iters * 2 * 4.0 * n ** 3 + corr * 2 * 8.0 * n ** 3 + 4.0 * n ** 3
+    Hermitian products (lower half: 4 n^3 each), and the final full product
+    X S (8 n^3; its Hermitian and anti-Hermitian parts are both used)."""
+    return iters * 2 * 4.0 * n ** 3 + corr * 2 * 4.0 * n ** 3 + 8.0 * n ** 3
+
+
+def flops_mfma_eig(n: int, k: int) -> float:
+    """GEMM-shaped part of the FP64 path: the rank-2k trailing updates of the
+    tridiagonalisation (half of its 16/3 n^3), back-transform and
+    reconstruction."""
+    return 8.0 / 3.0 * n ** 3 + 12.0 * n * n * k
+
+
+def bytes_hemv(n: int) -> float:
+    """Bytes the tridiagonalisation's HEMVs must stream: the lower triangle of
+    each trailing matrix once per column, 16 bytes per complex entry."""
+    return 8.0 / 3.0 * n ** 3
+
+
+def log(msg):
+    """Progress of the benchmark's phases (stderr; stdout carries the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def host_cpu():
+    """CPU model and socket count of the host (from /proc/cpuinfo)."""
+    model, sockets = None, set()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name") and model is None:
+                    model = line.split(":", 1)[1].strip()
+                elif line.startswith("physical id"):
+                    sockets.add(line.split(":", 1)[1].strip())
+    except OSError:
+        pass
+    return model, (len(sockets) or None)
 
 
 def measured_traffic(kernel, n, sources):
@@ -108,12 +148,62 @@ def mfma_roofline(fp64_gemm, mode, n, timed):
             "algorithmic_flops_per_launch": round(timed[2] / timed[1], 1)}
 
 
+def c5_closed_form_errors(P, oracle, W, n, g_np, dev, extra):
+    """Errors of the FP64, FP32- and BF16-mixed projections and of the
+    derivative against the closed forms on a constructed spectrum of order n
+    (seed 1009, |lambda| log-uniform in [1e-6, 1], half negative).  Returns
+    the FP64 error; the others go to `extra`."""
+    import numpy as np
+    import torch
+    log("closed-form errors on a constructed spectrum")
+    s, u, lam = W.constructed(n, 1009, gap=1e-6)
+    exact = oracle.constructed_projection(u, lam)
+    xc = torch.from_numpy(s).to(dev)
+    nrm = np.linalg.norm(exact)
+    out = None
+    for mm in ("fp64", "mixed_fp32", "mixed_bf16"):
+        y, inf = P.project(xc, n, mm, info=True)
+        e = float(np.linalg.norm(y.cpu().numpy() - exact) / nrm)
+        if mm == "fp64":
+            out = e
+        else:
+            extra[f"{mm}_rel_err_vs_closed_form"] = e
+            extra[f"{mm}_est_rel_err"] = inf["est_rel_err"]
+    gx = P.vjp(torch.from_numpy(g_np).to(dev), n, x=xc).cpu().numpy()
+    ref = oracle.constructed_vjp(u, lam, g_np)
+    extra["vjp_rel_err_vs_closed_form"] = float(np.linalg.norm(gx - ref) / np.linalg.norm(ref))
+    extra["closed_form_input"] = "Haar U, |lambda| log-uniform in [1e-6, 1], half negative (seed 1009)"
+    return out
+
+
+def numpy_eigh_baseline(np, oracle, x_svec, n):
+    """The paper's CPU column (Table III, NumPy c128): numpy.linalg.eigh of
+    the block, negative eigenvalues set to zero, reconstruction by a BLAS
+    product; timed on the host cores."""
+    try:
+        from threadpoolctl import threadpool_info
+        pools = [{"api": p.get("internal_api"), "threads": p.get("num_threads"), "version": p.get("version")}
+                 for p in threadpool_info()]
+    except Exception:
+        pools = None
+    log("NumPy eigh projection on the host")
+    a = oracle.unpack(x_svec, n)
+    t = time.perf_counter()
+    w, v = np.linalg.eigh(a)
+    p = (v * np.maximum(w, 0.0)) @ v.conj().T
+    dt = time.perf_counter() - t
+    del p
+    model, sockets = host_cpu()
+    return {"seconds": round(dt, 3), "proj_per_s": round(1.0 / dt, 5), "blas": pools, "cpu_model": model,
+            "sockets": sockets}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c5", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--mode", default=None, help="fp64 | mixed_bf16 | mixed_fp32")
     ap.add_argument("--n", type=int, default=1296, help="order for c3")
     ap.add_argument("--d", type=int, default=5, help="local dimension for c4")
@@ -164,6 +254,7 @@ def main():
         extra["fp64_corrections"] = corr
 
     # ---- inputs (host, seeded) -> HBM
+    log(f"workload {wl} mode {mode}: building inputs")
     plan = None
     if wl == "c2":
         n, count = 625, args.blocks
@@ -192,7 +283,8 @@ def main():
         n, count = 4096, 1
         xs_np = [W.gue(n, 1005)]
         g_np = W.gue(n, 1006)
-        desc = "d=8 process matrix 4096x4096: forward projection and DK derivative"
+        desc = ("d=8 process matrix: one 4096x4096 complex Hermitian block (G+G^H)/2, projected one "
+                "after another")
         sizes = [n]
     if wl in ("c2", "c3", "c5"):
         X = torch.from_numpy(np.stack(xs_np)).to(dev)
@@ -238,6 +330,7 @@ def main():
             os.environ["PSD_TUNE_CACHE"] = os.path.join(tempfile.gettempdir(), "psdproj_bench_tune.jsonl")
         plan.tune(X, Y, reps=3 if args.d <= 6 else 2, max_concurrency=8)
         plan.execute(X, out=Y)   # capture outside timing
+    log("warm-up")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -275,6 +368,7 @@ def main():
         o = _lib.KF_GEMM if fam == _lib.KF_NS else _lib.KF_NS
         if probe[o][1] > 0:
             other = (o, probe[o])
+    log(f"timing {args.steps} steps")
     if fam:
         _lib.timing_start(fam, sample)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -358,7 +452,10 @@ def main():
     if wl == "c4":
         extra["block_projections_per_s"] = round(value * len(sizes), 1)
 
-    if wl == "c5":
+    if wl == "c5" and mode == "fp64" and not args.no_context:
+        log("context: derivative, FP64 GEMMs, mixed forms")
+        per_proj_ms = ms_per_step
+        k = ks[0]
         # derivative after the forward (eigen-pair saved by the forward)
         sv = torch.empty(P.saved_numel(n), dtype=torch.float64, device=dev)
         G = torch.from_numpy(g_np).to(dev)
@@ -371,10 +468,43 @@ def main():
         torch.cuda.synchronize()
         extra["vjp_per_s"] = round(args.steps / (time.perf_counter() - t), 4)
         extra["vjp_algorithmic_tflops"] = round(32.0 * n ** 3 * extra["vjp_per_s"] / 1e12, 3)
+        # the FP64 GEMMs of one projection (HER2K updates, back-transform,
+        # reconstruction): algorithmic MFMA flops over their summed launch time
+        _lib.timing_start(_lib.KF_GEMM, 4096)
+        P.project(X[0], n, mode, out=Y[0])
+        torch.cuda.synchronize()
+        gms, glaunch, _ = _lib.timing_stop()
+        fm = flops_mfma_eig(n, k)
+        gt = fm / (gms * 1e-3) / 1e12
+        extra["fp64_gemm_mfma"] = {"kernel": "gemm_kernel<cd,...> (FP64 complex GEMMs: rank-2k updates, "
+                                             "back-transform, reconstruction)",
+                                   "achieved": round(gt, 2), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": round(gt / PEAK_FP64_TFLOPS, 4), "launches": glaunch,
+                                   "ms_per_projection": round(gms, 3),
+                                   "algorithmic_flops": fm}
+        # composite bound: MFMA work at the FP64 peak plus the HEMV stream at HBM peak
+        tstar = (fm / (PEAK_FP64_TFLOPS * 1e12) + bytes_hemv(n) / (PEAK_HBM_GBS * 1e9)) * 1e3
+        extra["composite_bound_ms"] = round(tstar, 3)
+        extra["frac_of_composite_bound"] = round(tstar / per_proj_ms, 4)
+        # the mixed forms at the same order (their error against the closed
+        # form is measured in the baseline leg below)
+        for mm, reps in (("mixed_fp32", 3), ("mixed_bf16", 5)):
+            _, inf = P.project(X[0], n, mm, out=Y[0], info=True)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                P.project(X[0], n, mm, out=Y[0])
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t) / reps
+            extra[f"{mm}_proj_per_s"] = round(1.0 / dt, 3)
+            extra[f"{mm}_est_rel_err_gue"] = inf["est_rel_err"]
+        P.project(X[0], n, mode, out=Y[0])   # Y holds the FP64 result again
+        torch.cuda.synchronize()
 
     # parity on a sample of the timed outputs; CPU oracle baseline
     cpu, err = None, None
     if not args.no_cpu_baseline:
+        log("CPU baselines and errors against the oracle / closed forms")
         import oracle
         y_np = Y.cpu().numpy()
         if wl in ("c1", "c4"):
@@ -395,6 +525,24 @@ def main():
             sample = f"blocks {pick} of the cone (orders {[sizes[i] for i in pick]})"
             value_cpu = len(pick) / dt
             unit = "block projections/s"
+        elif wl == "c5":
+            # bounded sample: the oracle's Jacobi at n = 4096 takes several
+            # minutes per sweep; one full oracle projection of a 1024 x 1024
+            # block of the same construction is timed and scaled by
+            # (1024/4096)^3 (its sweep count grows slowly with n: 11 at 512,
+            # 12 at 1024)
+            ns = 1024
+            xs_s = W.gue(ns, 1005)
+            t = time.perf_counter()
+            oracle.project(xs_s, ns)
+            dt = time.perf_counter() - t
+            value_cpu = (ns / n) ** 3 / dt
+            unit = "projections/s"
+            sample = (f"one oracle projection (cyclic Jacobi, round-robin, FP64) of a {ns}x{ns} block of the same "
+                      f"construction, {dt:.1f} s, scaled to n={n} by ({ns}/{n})^3")
+            if not args.no_context:
+                err = c5_closed_form_errors(P, oracle, W, n, g_np, dev, extra)
+                extra["numpy_eigh_projection"] = numpy_eigh_baseline(np, oracle, xs_np[0], n)
         else:
             m = max(1, min(args.cpu_sample, count))
             if n > 1300:
@@ -420,8 +568,9 @@ def main():
                 exact = oracle.constructed_projection(cons[0][1], cons[0][2])
                 trunc = oracle.ns_constructed_projection(cons[0][1], cons[0][2], inf0["scale"], inf0["iters"], sched)
                 extra["ns_truncation_rel_err"] = float(np.linalg.norm(trunc - exact) / np.linalg.norm(exact))
-        cpu = {"value": round(value_cpu, 5) if value_cpu else None, "unit": unit, "cores": oracle.num_threads(),
-               "kind": "oracle", "sample": sample}
+        model, sockets = host_cpu()
+        cpu = {"value": round(value_cpu, 6) if value_cpu else None, "unit": unit, "cores": oracle.num_threads(),
+               "kind": "oracle", "sample": sample, "cpu_model": model, "sockets": sockets}
 
     metric = {"c4": "PSD cone projections/sec (one graph launch per cone)"}.get(wl, "PSD projections/sec")
     out = {

@@ -79,10 +79,12 @@ typedef struct {
     int32_t iters;        /* NS iterations (mixed) or 0 */
     int32_t fallback;     /* 1 if a mixed request fell back to the FP64 path */
     int32_t reserved;
-    double est_rel_err;   /* mixed: first-order estimate of ||y - Pi(X)||_F / ||Pi(X)||_F,
-                             ||[X, S]||_F / (4 ||y||_F) for the sign estimate S (the
-                             commutator vanishes for the exact sign; relative to ||X||_F
-                             when y = 0); FP64: 0 */
+    double est_rel_err;   /* mixed: first-order estimate of ||y - Pi(X)||_F / ||Pi(X)||_F for
+                             the sign estimate S: sqrt(||[X, S]||_F^2 + ||X||_F^2 -
+                             ||X S||_F^2) / (4 ||y||_F) -- the eigenvector part (the
+                             commutator vanishes for the exact sign) and the eigenvalue
+                             part (S^2 = I for it); relative to ||X||_F when y = 0;
+                             FP64: 0 */
     double scale;         /* mixed: spectral scale alpha (~1.1 ||X||_2); FP64: 0 */
 } psd_info;
 

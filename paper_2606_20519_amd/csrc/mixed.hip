@@ -25,8 +25,8 @@
 //    the low-precision iterations already resolved;
 //  * F = X S by one full FP64 GEMM, then Pi = X/2 + (F + F^H)/4, the
 //    Hermitian part (X and the exact sign commute), written as the svec;
-//    the anti-Hermitian part F - F^H = [X, S] gives the error estimate
-//    ||[X, S]||_F / (4 ||Pi||_F), and n_pos comes from tr S.
+//    the anti-Hermitian part F - F^H = [X, S] and ||X||_F^2 - ||F||_F^2
+//    give the error estimate, and n_pos comes from tr S.
 // The low-precision iterations return the sign of a matrix within about
 // K u ||X|| of X (u = 2^-8 for BF16, 2^-24 for FP32); since Pi is
 // 1-Lipschitz the result is within that distance of Pi(X), and components
@@ -767,9 +767,9 @@ __global__ void __launch_bounds__(256) ns128_tail_kernel(const float *__restrict
 // commutator, zero for the exact sign: its norm measures how far S's
 // eigenvectors are from X's.  One workgroup per 32x32 lower tile (I >= J)
 // loads tile (I, J) and, through LDS, tile (J, I); it writes the svec and
-// four partial sums: ||C||_F^2, ||Pi||_F^2, tr S, ||X||_F^2.
+// five partial sums: ||C||_F^2, ||Pi||_F^2, tr S, ||X||_F^2, ||F||_F^2.
 constexpr int AT = 32;
-constexpr int ASM_SUMS = 4;
+constexpr int ASM_SUMS = 5;
 __global__ void __launch_bounds__(256) mx_assemble_kernel(const double2 *__restrict__ M,
                                                           const double2 *__restrict__ F,
                                                           const double2 *__restrict__ S, int64_t lda, int n,
@@ -800,7 +800,7 @@ __global__ void __launch_bounds__(256) mx_assemble_kernel(const double2 *__restr
     __syncthreads();
     const bool poison = status[2] == ST_ENONFINITE;
     const double rt2 = 1.41421356237309504880, nan = __builtin_nan("");
-    double c2 = 0.0, p2 = 0.0, trs = 0.0, x2 = 0.0;
+    double c2 = 0.0, p2 = 0.0, trs = 0.0, x2 = 0.0, f2 = 0.0;
 #pragma unroll
     for (int q = 0; q < AT * AT / 256; ++q) {
         const int ii = t % AT, jj = t / AT + q * (256 / AT);
@@ -816,6 +816,7 @@ __global__ void __launch_bounds__(256) mx_assemble_kernel(const double2 *__restr
             c2 += cabs2(cm);
             p2 += o * o;
             x2 += m.x * m.x;
+            f2 += cabs2(fij);
             trs += S[i + (int64_t)i * lda].x;
         } else {
             const int64_t o = svec_off(n, i, j);
@@ -824,24 +825,32 @@ __global__ void __launch_bounds__(256) mx_assemble_kernel(const double2 *__restr
             c2 += 2.0 * cabs2(cm);
             p2 += 2.0 * cabs2(out);
             x2 += 2.0 * cabs2(m);
+            f2 += cabs2(fij) + cabs2(fji);
         }
     }
     c2 = block_sum(c2, red);
     p2 = block_sum(p2, red);
     trs = block_sum(trs, red);
     x2 = block_sum(x2, red);
+    f2 = block_sum(f2, red);
     if (t == 0) {
         double *o = red_out + (int64_t)tile * ASM_SUMS;
-        o[0] = c2; o[1] = p2; o[2] = trs; o[3] = x2;
+        o[0] = c2; o[1] = p2; o[2] = trs; o[3] = x2; o[4] = f2;
     }
 }
 
 // Info record of a mixed projection: the tile partials summed in tile order
-// (deterministic), n_pos = (n + tr S) / 2, and the first-order error estimate
-// ||[X, S]||_F / (4 ||Pi||_F) (relative to ||X||_F when Pi = 0).  In the
-// eigenbasis of X the error of the assembled Pi on an entry coupling
-// eigenvalues of opposite signs is (l_i + l_j) / (l_i - l_j) C_ij / 4, of
-// modulus at most |C_ij| / 4.
+// (deterministic), n_pos = (n + tr S) / 2, and a first-order estimate of the
+// relative error from its two parts (relative to ||X||_F when Pi = 0):
+//  * eigenvectors: in the eigenbasis of X the error of the assembled Pi on an
+//    entry coupling eigenvalues of opposite signs is
+//    (l_i + l_j) / (l_i - l_j) C_ij / 4, of modulus at most |C_ij| / 4:
+//    ||C||_F / 4;
+//  * eigenvalues: S's eigenvalue s_i in place of sgn l_i costs
+//    |l_i| (1 - |s_i|) / 2 <= |l_i| (1 - s_i^2) / 4 (the iterations keep
+//    |s_i| <= 1), and sum l_i^2 (1 - s_i^2) = ||X||_F^2 - ||X S||_F^2, so
+//    their share is at most sqrt(||X||_F^2 - ||F||_F^2) / 4.
+// The two parts add in quadrature (different entries of the eigenbasis).
 __global__ void __launch_bounds__(256) mx_info_kernel(const double *__restrict__ red_in, int ntile, int n, int iters,
                                                       const double *alpha, const int *status, psd_dev_info *info,
                                                       int64_t zs, const int *infoidx) {
@@ -850,14 +859,14 @@ __global__ void __launch_bounds__(256) mx_info_kernel(const double *__restrict__
     alpha = member_ptr(alpha, zs, blockIdx.z);
     status = member_ptr(status, zs, blockIdx.z);
     if (info) info += infoidx ? infoidx[blockIdx.z] : blockIdx.z;
-    double acc[ASM_SUMS] = {0.0, 0.0, 0.0, 0.0};
+    double acc[ASM_SUMS] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < ntile; b += blockDim.x)
 #pragma unroll
         for (int k = 0; k < ASM_SUMS; ++k) acc[k] += red_in[(int64_t)b * ASM_SUMS + k];
 #pragma unroll
     for (int k = 0; k < ASM_SUMS; ++k) acc[k] = block_sum(acc[k], red);
     if (threadIdx.x == 0 && info) {
-        const double cn = sqrt(acc[0]), pn = sqrt(acc[1]), xn = sqrt(acc[3]);
+        const double en = sqrt(acc[0] + fmax(acc[3] - acc[4], 0.0)), pn = sqrt(acc[1]), xn = sqrt(acc[3]);
         const int npos = (int)llround(0.5 * (n + acc[2]));
         info->status = status[2];
         info->n_pos = min(max(npos, 0), n);
@@ -865,7 +874,7 @@ __global__ void __launch_bounds__(256) mx_info_kernel(const double *__restrict__
         info->iters = iters;
         info->fallback = 0;
         info->reserved = 0;
-        info->est_rel_err = pn > 0.0 ? 0.25 * cn / pn : (xn > 0.0 ? 0.25 * cn / xn : 0.0);
+        info->est_rel_err = pn > 0.0 ? 0.25 * en / pn : (xn > 0.0 ? 0.25 * en / xn : 0.0);
         info->scale = *alpha;
     }
 }

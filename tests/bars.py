@@ -10,9 +10,10 @@ error of the assembled projection:
   at most band(tau) = sqrt(sum of lambda^2 over |lambda| < tau);
 * the remaining components carry the first-order eigenvector error, which in
   the eigenbasis of X is (l_i + l_j)/(l_i - l_j) [X, S]_ij / 4 on entries
-  coupling opposite signs, of modulus at most |[X, S]_ij| / 4: the library's
-  est_rel_err = ||[X, S]||_F / (4 ||Pi||_F) (first order, so a factor 2 of
-  slack).
+  coupling opposite signs, of modulus at most |[X, S]_ij| / 4, and the
+  eigenvalue error of S, at most sqrt(||X||_F^2 - ||X S||_F^2) / 4: the
+  library's est_rel_err combines the two relative to ||Pi||_F (first order,
+  so a factor 2 of slack).
 
 The stated bar of a mixed result is band(2 u ||X||_2) + 2 est ||Pi||_F.  For
 FP32 there is also the fixed bar FP32_REL_BAR = 1e-5, from

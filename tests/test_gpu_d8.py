@@ -161,5 +161,5 @@ def test_d8_window_directions_fd(P):
         # the difference of two independent rounding errors of size
         # ~1e-13 ||Pi||_F, seen through G (a random direction in n^2
         # coordinates: a factor ||G|| / n), divided by 2h; plus O(h^2)
-        assert d <= 100.0 * noise + 1e-7 * abs(an)
+        assert d <= noise + 1e-7 * abs(an)
     print(f"n=4096 window FD: worst relative difference {worst:.3e}", flush=True)
