@@ -111,6 +111,23 @@ psd_status psd_project(int32_t n, const double *x, double *y, psd_mode mode,
                        void *ws, size_t ws_bytes, void *stream, psd_info *info,
                        double *saved);
 
+/* psd_project without a workspace argument, for callers that cannot
+ * allocate (code under graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The workspace is a fixed device array of
+ * PSD_NOALLOC_SCRATCH_BYTES inside the library, one copy on each device it
+ * runs on, held until the process ends; the call itself allocates nothing.
+ * Its address is looked up on the first call made with a device current.
+ * Orders whose psd_workspace_size(1, &n, mode, 0) exceeds the array are
+ * rejected with PSD_EWORKSPACE before anything is enqueued (n <= 831 in
+ * FP64, n <= 768 in BF16-mixed, n <= 704 in FP32-mixed; n <= 64 needs none).  Calls on one
+ * device share the array: calls that overlap in time on one device (other
+ * streams, other host threads) race and must be serialised by the caller.
+ * Same arguments and results as psd_project, without `saved` and without
+ * the mixed modes' FP64 fallback. */
+#define PSD_NOALLOC_SCRATCH_BYTES ((size_t)48 << 20)
+psd_status psd_project_noalloc(int32_t n, const double *x, double *y, psd_mode mode,
+                               void *stream, psd_info *info);
+
 /* Projects nblocks independent blocks (orders n[0..nblocks), host array)
  * stored back to back in x into y (same layout).  infos: nullable array of
  * nblocks records. */

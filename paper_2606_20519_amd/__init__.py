@@ -21,7 +21,7 @@ from . import _lib
 from ._lib import MODES, PSD_FLAG_SAVE, PsdError, PsdInfo, check  # noqa: F401
 
 __all__ = ["project", "project_batched", "vjp", "PSDProject", "Plan", "workspace", "set_ns_iterations",
-           "set_mixed_fallback",
+           "set_mixed_fallback", "project_noalloc",
            "PsdError", "MODES"]
 
 _ws_cache: dict = {}
@@ -87,6 +87,22 @@ def project(x: torch.Tensor, n: int, mode="fp64", out: torch.Tensor = None, info
     st = _lib.lib().psd_project(n, _ptr(x), _ptr(y), m, _ptr(ws), ws.numel(), ctypes.c_void_p(_stream_ptr(x.device)),
                                 _ptr(inf_t), _ptr(saved))
     check(st, "psd_project")
+    if info:
+        return y, _info_dict(inf_t)
+    return y
+
+
+def project_noalloc(x: torch.Tensor, n: int, mode="fp64", out: torch.Tensor = None, info: bool = False):
+    """svec(Pi(mat(x))) through psd_project_noalloc: the library's fixed
+    device scratch instead of a workspace (orders up to 831 in FP64, 768 in
+    BF16-mixed, 704 in FP32-mixed)."""
+    _check_vec(x, n * n, "x")
+    y = torch.empty_like(x) if out is None else out
+    _check_vec(y, n * n, "out")
+    inf_t = torch.zeros(INFO_WORDS, dtype=torch.int32, device=x.device) if info else None
+    st = _lib.lib().psd_project_noalloc(n, _ptr(x), _ptr(y), _mode(mode), ctypes.c_void_p(_stream_ptr(x.device)),
+                                        _ptr(inf_t))
+    check(st, "psd_project_noalloc")
     if info:
         return y, _info_dict(inf_t)
     return y

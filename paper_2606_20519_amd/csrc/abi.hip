@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "../../include/psdproj.h"
@@ -17,6 +18,12 @@
 using namespace psd;
 
 static_assert(sizeof(psd_info) == sizeof(psd_dev_info), "psd_info layout");
+
+// Workspace of psd_project_noalloc: a fixed device array, one copy on every
+// device the library runs on, held until the process ends.  Host code never
+// passes `scratch` itself (its host-side name is not a device address): the
+// address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[PSD_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -195,6 +202,29 @@ hipError_t project_group(int n, int nmem, psd_mode mode, const double *x, double
 
 psd_status status_of(hipError_t e) { return e == hipSuccess ? PSD_OK : PSD_EDEVICE; }
 
+// Device address of `scratch` on the current device (looked up on the first
+// call made with that device current, then cached).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_address(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
 
 // Mixed projection of one block with the FP64 fallback: the record of the
 // mixed run goes to the workspace, the stream is synchronised, and when the
@@ -338,6 +368,27 @@ psd_status psd_project(int32_t n, const double *x, double *y, psd_mode mode, voi
         return status_of(launch_small_one(job, x, y, dinfo, saved, s));
     }
     return status_of(project_block(n, x, y, mode, ws, s, dinfo, saved, true));
+}
+
+psd_status psd_project_noalloc(int32_t n, const double *x, double *y, psd_mode mode, void *stream,
+                               psd_info *info) {
+    if (n < 1 || !x || !y || !valid_mode(mode)) return PSD_EINVAL;
+    if (!aligned8(x) || !aligned8(y)) return PSD_EINVAL;
+    const size_t nb = sizeof(double) * (size_t)n * (size_t)n;
+    if (partial_overlap(x, nb, y, nb)) return PSD_EINVAL;
+    size_t need = 0;
+    psd_status st = psd_workspace_size(1, &n, mode, 0, &need);
+    if (st != PSD_OK) return st;
+    if (need > PSD_NOALLOC_SCRATCH_BYTES) return PSD_EWORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    psd_dev_info *dinfo = reinterpret_cast<psd_dev_info *>(info);
+    if (n <= 64) {
+        SmallJob job{0, 0, n, 0};
+        return status_of(launch_small_one(job, x, y, dinfo, nullptr, s));
+    }
+    void *ws = nullptr;
+    if (scratch_address(&ws) != hipSuccess) return PSD_EDEVICE;
+    return status_of(project_block(n, x, y, mode, ws, s, dinfo, nullptr, false));
 }
 
 psd_status psd_project_batched(int32_t nblocks, const int32_t *n, const double *x, double *y,
