@@ -212,6 +212,9 @@ def main():
     ap.add_argument("--no-context", action="store_true",
                     help="skip the context measurements after the timed region (counter runs)")
     ap.add_argument("--blocks", type=int, default=50, help="blocks per step for c1 / c2 (counter runs use fewer)")
+    ap.add_argument("--counter-run", action="store_true",
+                    help="only project the workload's inputs once (one step, no probes, no JSON line): the "
+                         "program profiled by the rocprofv3 counter runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device 3 times (counter calibration) and exit")
     args = ap.parse_args()
@@ -305,6 +308,13 @@ def main():
         def step():
             for i in range(count):
                 P.project(X[i], n, mode, out=Y[i])
+
+    if args.counter_run:
+        log("counter run: one step")
+        step()
+        torch.cuda.synchronize()
+        log("counter run done")
+        return
 
     # side counts for the algorithmic flops (outside timing)
     ks = []
