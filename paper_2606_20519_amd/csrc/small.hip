@@ -23,7 +23,7 @@
 namespace psd {
 
 constexpr int SB_MAX = 64;     // largest order served
-constexpr int SB_LD = 64;      // LDS leading dimension
+constexpr int SB_LD = 65;      // LDS leading dimension (odd: row and column walks spread over the banks)
 constexpr int SB_NT = 256;     // threads per workgroup
 constexpr int SB_SWEEPS = 40;  // sweeps before reporting non-convergence
 
