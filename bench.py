@@ -510,6 +510,22 @@ def main():
             extra[f"{mm}_est_rel_err_gue"] = inf["est_rel_err"]
         P.project(X[0], n, mode, out=Y[0])   # Y holds the FP64 result again
         torch.cuda.synchronize()
+        # the affine step on either side of the projection (App. D.2), same order
+        dloc = round(n ** 0.25)
+        if dloc ** 4 == n:
+            nx, _ = P.affine_dims(dloc)
+            ax = torch.randn(nx, dtype=torch.float64, device=dev)
+            zx, zy = P.affine_step(ax, X[0], dloc)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(args.steps):
+                P.affine_step(ax, X[0], dloc, zx=zx, zy=zy)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t) / args.steps
+            minbytes = 16.0 * (nx + n * n)   # read a_x, a_y; write z_x, z_y
+            extra["affine_step"] = {"ms": round(1e3 * dt, 3), "share_of_projection": round(1e3 * dt / per_proj_ms, 4),
+                                    "nx": nx, "min_hbm_gbs": round(minbytes / dt / 1e9, 1),
+                                    "passes": "unpack, 4 local transforms, gather, scatter, 4 transforms, pack"}
 
     # parity on a sample of the timed outputs; CPU oracle baseline
     cpu, err = None, None

@@ -233,6 +233,38 @@ psd_status psd_timing_stop(double *ms, int32_t *launches, double *work);
  * Returns PSD_EINVAL outside 0..200 / 0..8. */
 psd_status psd_set_ns_iterations(int32_t iters, int32_t corrections);
 
+/* Affine step of the SCS iteration for the bipartite process-matrix SDP
+ * (App. D.1-D.2), the step on either side of the cone projection.  With the
+ * constraint map over the allowed traceless multi-indices
+ * mu = (alpha_1, beta_1, alpha_2, beta_2) (App. "Sparse basis for the
+ * process-matrix subspace": every party with beta >= 1 needs a party with
+ * alpha >= 1, beta = 0; the all-identity index excluded),
+ *     A x = -sum_mu x_mu F_mu,   (A^T Z)_mu = -tr[F_mu Z]   (eq. constraint_map_def),
+ *     F_mu = s_a1 (x) s_b1 (x) s_a2 (x) s_b2 on A_i (x) A_o (x) B_i (x) B_o,
+ * s_alpha the normalised generalised Gell-Mann matrices of local dimension d
+ * in the paper's order (eq. gellmann_basis: identity/sqrt d, the d-1
+ * diagonal ones, the symmetric then the antisymmetric off-diagonal ones,
+ * pairs j < k lexicographic), and A^T A = I, the affine projection is
+ *     z_x = (a_x - A^T a_y) / 2,   z_y = a_y + A z_x   (App. D.2).
+ * x, a_x, z_x: real vectors of nx = |I| = d^8 - (1 + d^2(d^2 - 1))^2
+ * entries, in lexicographic order of mu; y, a_y, z_y: svec of d^4 x d^4
+ * Hermitian matrices (ny = d^8 doubles).  2 <= d <= 8.  The device workspace
+ * (psd_affine_workspace_size: two d^8-entry complex tensors, 256-byte aligned)
+ * is caller-owned; nothing is allocated.  zx may alias ax and zy may alias
+ * ay; other overlaps return PSD_EINVAL.  Errors are host-side only (the maps
+ * are linear: no device status). */
+psd_status psd_affine_dims(int32_t d, int64_t *nx, int64_t *ny);
+psd_status psd_affine_workspace_size(int32_t d, size_t *bytes);
+/* y <- svec(A x). */
+psd_status psd_constraint_apply(int32_t d, const double *x, double *y, void *ws, size_t ws_bytes,
+                                void *stream);
+/* x <- A^T mat(y). */
+psd_status psd_constraint_adjoint(int32_t d, const double *y, double *x, void *ws, size_t ws_bytes,
+                                  void *stream);
+/* (zx, zy) <- ((ax - A^T mat(ay)) / 2, ay + svec(A zx)). */
+psd_status psd_affine_step(int32_t d, const double *ax, const double *ay, double *zx, double *zy,
+                           void *ws, size_t ws_bytes, void *stream);
+
 /* FP64 fallback of the mixed modes (process-wide; not thread-safe):
  * with max_rel_err > 0, psd_project in a mixed mode writes the mixed run's
  * record to its workspace, synchronises the stream and, if that record

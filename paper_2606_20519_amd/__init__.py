@@ -21,7 +21,8 @@ from . import _lib
 from ._lib import MODES, PSD_FLAG_SAVE, PsdError, PsdInfo, check  # noqa: F401
 
 __all__ = ["project", "project_batched", "vjp", "PSDProject", "Plan", "workspace", "set_ns_iterations",
-           "set_mixed_fallback", "project_noalloc",
+           "set_mixed_fallback", "project_noalloc", "affine_dims", "constraint_apply", "constraint_adjoint",
+           "affine_step",
            "PsdError", "MODES"]
 
 _ws_cache: dict = {}
@@ -159,6 +160,64 @@ def vjp(gy: torch.Tensor, n: int, x: torch.Tensor = None, saved: torch.Tensor = 
                                     ctypes.c_void_p(_stream_ptr(gy.device)))
     check(st, "psd_project_vjp")
     return gx
+
+
+_aff_ws: dict = {}
+
+
+def _affine_ws(d: int, device) -> torch.Tensor:
+    nbytes = _lib.affine_workspace_size(d)
+    key = (str(device), d)
+    ws = _aff_ws.get(key)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        _aff_ws[key] = ws
+    return ws
+
+
+def affine_dims(d: int):
+    """(nx, ny) of the bipartite process-matrix SDP at local dimension d."""
+    return _lib.affine_dims(d)
+
+
+def constraint_apply(x: torch.Tensor, d: int, out: torch.Tensor = None) -> torch.Tensor:
+    """svec(A x), A x = -sum_mu x_mu F_mu (App. D.1)."""
+    nx, ny = _lib.affine_dims(d)
+    _check_vec(x, nx, "x")
+    y = torch.empty(ny, dtype=torch.float64, device=x.device) if out is None else out
+    _check_vec(y, ny, "out")
+    ws = _affine_ws(d, x.device)
+    check(_lib.lib().psd_constraint_apply(d, _ptr(x), _ptr(y), _ptr(ws), ws.numel(),
+                                          ctypes.c_void_p(_stream_ptr(x.device))), "psd_constraint_apply")
+    return y
+
+
+def constraint_adjoint(y: torch.Tensor, d: int, out: torch.Tensor = None) -> torch.Tensor:
+    """A^T mat(y), (A^T Z)_mu = -tr[F_mu Z] (App. D.1)."""
+    nx, ny = _lib.affine_dims(d)
+    _check_vec(y, ny, "y")
+    x = torch.empty(nx, dtype=torch.float64, device=y.device) if out is None else out
+    _check_vec(x, nx, "out")
+    ws = _affine_ws(d, y.device)
+    check(_lib.lib().psd_constraint_adjoint(d, _ptr(y), _ptr(x), _ptr(ws), ws.numel(),
+                                            ctypes.c_void_p(_stream_ptr(y.device))), "psd_constraint_adjoint")
+    return x
+
+
+def affine_step(ax: torch.Tensor, ay: torch.Tensor, d: int, zx: torch.Tensor = None, zy: torch.Tensor = None):
+    """(z_x, z_y) = ((a_x - A^T a_y)/2, a_y + A z_x): the affine projection of
+    the SCS iteration (App. D.2)."""
+    nx, ny = _lib.affine_dims(d)
+    _check_vec(ax, nx, "ax")
+    _check_vec(ay, ny, "ay")
+    zx = torch.empty_like(ax) if zx is None else zx
+    zy = torch.empty_like(ay) if zy is None else zy
+    _check_vec(zx, nx, "zx")
+    _check_vec(zy, ny, "zy")
+    ws = _affine_ws(d, ay.device)
+    check(_lib.lib().psd_affine_step(d, _ptr(ax), _ptr(ay), _ptr(zx), _ptr(zy), _ptr(ws), ws.numel(),
+                                     ctypes.c_void_p(_stream_ptr(ay.device))), "psd_affine_step")
+    return zx, zy
 
 
 class PSDProject(torch.autograd.Function):

@@ -23,7 +23,9 @@ EXPORTS = ("psd_workspace_size", "psd_saved_size", "psd_project", "psd_project_n
            "psd_project_vjp", "psd_plan_create", "psd_plan_workspace_size", "psd_plan_concurrency",
            "psd_plan_group_size", "psd_plan_ns_tile_threshold",
            "psd_plan_execute", "psd_plan_tune", "psd_plan_destroy", "psd_timing_start", "psd_timing_stop",
-           "psd_set_ns_iterations", "psd_set_mixed_fallback", "psd_status_string", "psd_version")
+           "psd_set_ns_iterations", "psd_set_mixed_fallback", "psd_status_string", "psd_version",
+           "psd_affine_dims", "psd_affine_workspace_size", "psd_constraint_apply", "psd_constraint_adjoint",
+           "psd_affine_step")
 KF_HEMV, KF_GEMM, KF_NS, KF_WSTEP = 1, 2, 3, 4
 
 
@@ -87,6 +89,17 @@ def lib():
     L.psd_set_ns_iterations.restype = i32
     L.psd_set_mixed_fallback.argtypes = [ctypes.c_double]
     L.psd_set_mixed_fallback.restype = i32
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    L.psd_affine_dims.argtypes = [i32, i64p, i64p]
+    L.psd_affine_dims.restype = i32
+    L.psd_affine_workspace_size.argtypes = [i32, ctypes.POINTER(sz)]
+    L.psd_affine_workspace_size.restype = i32
+    L.psd_constraint_apply.argtypes = [i32, vp, vp, vp, sz, vp]
+    L.psd_constraint_apply.restype = i32
+    L.psd_constraint_adjoint.argtypes = [i32, vp, vp, vp, sz, vp]
+    L.psd_constraint_adjoint.restype = i32
+    L.psd_affine_step.argtypes = [i32, vp, vp, vp, vp, vp, sz, vp]
+    L.psd_affine_step.restype = i32
     L.psd_timing_start.argtypes = [i32, i32]
     L.psd_timing_start.restype = i32
     L.psd_timing_stop.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
@@ -140,3 +153,16 @@ def set_ns_iterations(iters: int, corrections: int):
 
 def set_mixed_fallback(max_rel_err: float):
     check(lib().psd_set_mixed_fallback(float(max_rel_err)), "psd_set_mixed_fallback")
+
+
+def affine_dims(d: int):
+    """(nx, ny): lengths of x (allowed multi-indices) and of the svec of y."""
+    nx, ny = ctypes.c_int64(0), ctypes.c_int64(0)
+    check(lib().psd_affine_dims(d, ctypes.byref(nx), ctypes.byref(ny)), "psd_affine_dims")
+    return int(nx.value), int(ny.value)
+
+
+def affine_workspace_size(d: int) -> int:
+    out = ctypes.c_size_t(0)
+    check(lib().psd_affine_workspace_size(d, ctypes.byref(out)), "psd_affine_workspace_size")
+    return int(out.value)

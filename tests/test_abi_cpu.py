@@ -111,3 +111,25 @@ def test_setters_validate_on_host(L):
     assert lib.psd_set_ns_iterations(-1, 1) == 1
     assert lib.psd_set_ns_iterations(0, 9) == 1
     assert lib.psd_set_ns_iterations(0, 1) == 0
+
+
+def test_affine_host_validation(L):
+    lib = L.lib()
+    nx, ny = ctypes.c_int64(0), ctypes.c_int64(0)
+    for d in range(2, 9):
+        assert lib.psd_affine_dims(d, ctypes.byref(nx), ctypes.byref(ny)) == 0
+        D = d * d
+        assert nx.value == d ** 8 - (1 + D * (D - 1)) ** 2 and ny.value == d ** 8
+    assert lib.psd_affine_dims(1, ctypes.byref(nx), ctypes.byref(ny)) == 1
+    assert lib.psd_affine_dims(9, ctypes.byref(nx), ctypes.byref(ny)) == 1
+    out = ctypes.c_size_t(0)
+    assert lib.psd_affine_workspace_size(8, ctypes.byref(out)) == 0 and out.value == 2 * 16 * 8 ** 8
+    fake = ctypes.c_void_p(0x10000)
+    ws = ctypes.c_void_p(0x100000)
+    big = 1 << 40
+    # workspace too small, bad d, misaligned workspace, overlapping outputs
+    assert lib.psd_constraint_apply(2, fake, fake, ws, 0, None) == 2
+    assert lib.psd_constraint_apply(9, fake, fake, ws, big, None) == 1
+    assert lib.psd_constraint_adjoint(2, fake, fake, ctypes.c_void_p(0x100008), big, None) == 1
+    ax, ay = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000)
+    assert lib.psd_affine_step(2, ax, ay, ctypes.c_void_p(0x20008), ctypes.c_void_p(0x40000), ws, big, None) == 1
