@@ -21,6 +21,12 @@ iterates are available, so these seeded constructions stand in for them:
   magnitudes 10^(-log10(1/gap) t), t ~ U[0,1], each sign group's extreme
   magnitudes pinned to exactly gap and 1.
 * ``cone(d, instance, seed)``: one SCS cone = W (d^4) + 8 Choi blocks (d^2).
+* ``random_instrument`` / ``gyni_objective(d, seed)``: the objective
+  G = 1/4 sum_{x,y} C^A_{a=y|x} (x) C^B_{b=x|y} of the GYNI game (two
+  inputs and outputs per party, win iff a = y and b = x) for a pair of random
+  feasible two-outcome instruments (random Kraus operators normalised to a
+  trace-preserving sum) -- the paper's "randomly generated feasible pair of
+  instruments" of its wall-clock table.
 """
 from __future__ import annotations
 
@@ -132,3 +138,40 @@ def cone(d: int, instances: int = 32, seed_base: int = 4000):
         for _ in range(8):
             parts.append(upper_pack(gue_matrix(d ** 2, rng)))
     return np.concatenate(parts), cone_sizes(d, instances)
+
+
+def random_instrument(d: int, rng: np.random.Generator, outcomes: int = 2, kraus: int = 2):
+    """Choi operators C_a (a < outcomes) on A_i (x) A_o (input factor first) of
+    a random quantum instrument d -> d: random complex Gaussian Kraus
+    operators K_{a,k}, normalised so that sum_{a,k} K^H K = 1 (trace
+    preserving), C_a = sum_k |K_{a,k}>><<K_{a,k}| with |K>> = sum_i |i> (x) K|i>."""
+    ks = [[cn01(rng, (d, d)) for _ in range(kraus)] for _ in range(outcomes)]
+    s = sum(k.conj().T @ k for row in ks for k in row)
+    w, v = np.linalg.eigh(s)
+    inv_sqrt = (v * (1.0 / np.sqrt(w))) @ v.conj().T
+    out = []
+    for row in ks:
+        c = np.zeros((d * d, d * d), dtype=np.complex128)
+        for k in row:
+            kk = k @ inv_sqrt
+            vec = np.zeros(d * d, dtype=np.complex128)
+            for i in range(d):
+                vec[i * d:(i + 1) * d] = kk[:, i]     # |i> (x) K|i>
+            c += np.outer(vec, vec.conj())
+        out.append(c)
+    return out
+
+
+def gyni_objective(d: int, seed: int) -> np.ndarray:
+    """G = 1/4 sum_{x,y} C^A_{a=y|x} (x) C^B_{b=x|y} of the GYNI game for a
+    seeded random instrument pair (two inputs, two outcomes per party), on
+    A_i (x) A_o (x) B_i (x) B_o; max tr[G W] over process matrices W is the
+    winning probability with these instruments."""
+    rng = np.random.default_rng(seed)
+    ca = [random_instrument(d, rng) for _ in range(2)]   # ca[x][a]
+    cb = [random_instrument(d, rng) for _ in range(2)]   # cb[y][b]
+    g = np.zeros((d ** 4, d ** 4), dtype=np.complex128)
+    for x in range(2):
+        for y in range(2):
+            g += np.kron(ca[x][y], cb[y][x])
+    return g / 4.0
