@@ -265,6 +265,78 @@ psd_status psd_constraint_adjoint(int32_t d, const double *y, double *x, void *w
 psd_status psd_affine_step(int32_t d, const double *ax, const double *ay, double *zx, double *zy,
                            void *ws, size_t ws_bytes, void *stream);
 
+/* ---- SCS solver for the bipartite process-matrix SDP (App. D) ----------
+ *
+ * Maximises tr[W G] over process matrices W = gamma 1 + sum_mu x_mu F_mu >= 0
+ * (eq. sparse_process_sdp; gamma = 1/d^2) in the SCS form
+ *     min c^T x  s.t.  A x + s = b,  s in H_+^{d^4}
+ * (eq. constraint_map_def: A as in psd_constraint_apply, b = gamma 1,
+ * c = A^T G), through the homogeneous self-dual embedding and the iteration
+ * of eq. final_iterates: u~ = (1 + Q)^-1 (u + v), u = Pi_C(u~_r - v),
+ * v = v - u~_r + u, with u~_r = alpha u~ + (1 - alpha) u (over-relaxation;
+ * alpha = 1 is the printed iteration), (1 + Q)^-1 by Sherman-Morrison over
+ * the closed-form M^-1 of psd_affine_step, and Pi_C by psd_project on the
+ * Hermitian block.  Start: u = v = (0, 0, 1), or with warm_start
+ * u = (x, sigma y, 1), v = (0, s, 0) from the caller's x, y, s.  Partial
+ * normalisation (App. D.2): c is scaled inside the iteration by
+ * sigma = ||b||_2 / ||c||_2.  Termination (App. D.1, "Convergence
+ * criteria"): with x = u_x/tau, s = v_s/tau, y = u_y/(sigma tau),
+ * p = A x + s - b, r = A^T y + c, g = c^T x + b^T y and
+ * ||p||_inf <= eps (1 + max(||A x||_inf, ||s||_inf, ||b||_inf)),
+ * ||r||_inf <= eps (1 + max(||A^T y||_inf, ||c||_inf)),
+ * |g| <= eps (1 + max(|c^T x|, |b^T y|)), tested every check_every
+ * iterations and after the last one; eps = 0 runs exactly max_iters.
+ * The first mixed_iters cone projections use mixed_mode, the rest FP64 (the
+ * paper's low-to-high precision switch after a fixed iteration count). */
+typedef struct {
+    int32_t d;             /* local dimension, 2..8 (W has order d^4) */
+    int32_t max_iters;     /* >= 1 */
+    int32_t check_every;   /* >= 1 */
+    int32_t mixed_iters;   /* >= 0 */
+    int32_t mixed_mode;    /* PSD_MIXED_BF16 or PSD_MIXED_FP32 when mixed_iters > 0 */
+    int32_t normalize;     /* 0 or 1 */
+    int32_t warm_start;    /* 0 or 1 */
+    int32_t anderson;      /* reserved, must be 0 */
+    double eps;            /* eps_abs = eps_rel >= 0 */
+    double alpha;          /* over-relaxation, 0 < alpha < 2 */
+} psd_scs_settings;
+
+/* Result record (host memory, complete when psd_scs_solve returns). */
+typedef struct {
+    int32_t status;        /* PSD_OK converged; PSD_ENOCONV max_iters reached
+                              (outputs: the last iterate); PSD_ENONFINITE a
+                              residual or the data was not finite */
+    int32_t iters;         /* iterations run */
+    int32_t proj_status;   /* first non-OK status of a cone projection, else 0 */
+    int32_t reserved;
+    double pobj;           /* tr[W G] at x: gamma tr G - c^T x (last check) */
+    double dobj;           /* dual bound gamma tr G + b^T y (last check) */
+    double res_pri, res_dual, gap;   /* ||p||_inf, ||r||_inf, |g| (last check) */
+    double tau, kappa;     /* embedding scalars of the last iterate */
+    double sigma;          /* normalisation scale */
+    double post_lambda;    /* post-processing mixing weight (0: W was PSD) */
+    double post_lambda_min;/* lambda_min of W = b - A x before mixing */
+} psd_scs_info;
+
+/* Device workspace bytes of psd_scs_solve for these settings (EINVAL for
+ * settings out of range). */
+psd_status psd_scs_workspace_size(const psd_scs_settings *s, size_t *bytes);
+
+/* Solve for the objective g (svec of G, d^8 doubles).  x (nx doubles), y and
+ * s (d^8 doubles each): the unscaled solution x = u_x/tau, y = u_y/(sigma
+ * tau), s = v_s/tau (with tau = 0: u_x, u_y, v_s); with warm_start they
+ * also carry the start.  w (nullable, d^8 doubles): the process matrix
+ * W = b - A x post-processed as in App. "Sparse SDP formulation for process
+ * matrices and post-processing": W' = (1 - lam) W + lam gamma 1 with the
+ * smallest lam in [0, 1] that makes W' PSD (lambda_min from an FP64
+ * eigendecomposition).  g, x, y, s, w must not overlap.  info: host.
+ * Synchronises `stream` at setup and at every residual check (the host
+ * decides termination); allocates nothing.  Host-side errors return
+ * EINVAL / EWORKSPACE / EDEVICE with info unspecified; otherwise PSD_OK
+ * with the outcome in info->status. */
+psd_status psd_scs_solve(const psd_scs_settings *s, const double *g, double *x, double *y, double *s_out,
+                         double *w, void *ws, size_t ws_bytes, void *stream, psd_scs_info *info);
+
 /* FP64 fallback of the mixed modes (process-wide; not thread-safe):
  * with max_rel_err > 0, psd_project in a mixed mode writes the mixed run's
  * record to its workspace, synchronises the stream and, if that record

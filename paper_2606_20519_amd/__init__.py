@@ -10,6 +10,7 @@ sqrt(2) Re X_ij, sqrt(2) Im X_ij for j > i; a block of order n has n*n reals.
     project_batched(x, sizes, mode)       -> blocks projected independently
     vjp(gy, n, x=None, saved=None)        -> svec(DPi(X)[mat(gy)])
     PSDProject.apply(x, n, mode)          -> differentiable projection
+    scs_solve(g, d, eps=1e-5, ...)        -> SCS solve of the process-matrix SDP
 """
 from __future__ import annotations
 
@@ -22,7 +23,7 @@ from ._lib import MODES, PSD_FLAG_SAVE, PsdError, PsdInfo, check  # noqa: F401
 
 __all__ = ["project", "project_batched", "vjp", "PSDProject", "Plan", "workspace", "set_ns_iterations",
            "set_mixed_fallback", "project_noalloc", "affine_dims", "constraint_apply", "constraint_adjoint",
-           "affine_step",
+           "affine_step", "scs_solve",
            "PsdError", "MODES"]
 
 _ws_cache: dict = {}
@@ -218,6 +219,41 @@ def affine_step(ax: torch.Tensor, ay: torch.Tensor, d: int, zx: torch.Tensor = N
     check(_lib.lib().psd_affine_step(d, _ptr(ax), _ptr(ay), _ptr(zx), _ptr(zy), _ptr(ws), ws.numel(),
                                      ctypes.c_void_p(_stream_ptr(ay.device))), "psd_affine_step")
     return zx, zy
+
+
+def scs_solve(g: torch.Tensor, d: int, eps: float = 1e-5, alpha: float = 1.5, max_iters: int = 5000,
+              check_every: int = 1, normalize: bool = True, mixed_iters: int = 0, mixed_mode="mixed_fp32",
+              warm=None, post: bool = True, ws: torch.Tensor = None) -> dict:
+    """Solve max tr[W G] over process matrices by the SCS iteration on the
+    GPU (App. D; psd_scs_solve).  g: svec of G (d^8 float64 on the device).
+    warm: optional (x, y, s) start.  Returns the unscaled x, y, s, the
+    post-processed process matrix w (if `post`), and the info record as a
+    dict (status, iters, pobj, dobj, residuals, tau, kappa, sigma, ...)."""
+    nx, ny = _lib.affine_dims(d)
+    _check_vec(g, ny, "g")
+    st = _lib.ScsSettings(d=d, max_iters=max_iters, check_every=check_every, mixed_iters=mixed_iters,
+                          mixed_mode=_mode(mixed_mode), normalize=int(bool(normalize)),
+                          warm_start=int(warm is not None), anderson=0, eps=eps, alpha=alpha)
+    nbytes = _lib.scs_workspace_size(st)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=g.device)
+    if warm is not None:
+        x, y, s = (t.clone() for t in warm)
+        _check_vec(x, nx, "warm x")
+        _check_vec(y, ny, "warm y")
+        _check_vec(s, ny, "warm s")
+    else:
+        x = torch.empty(nx, dtype=torch.float64, device=g.device)
+        y = torch.empty(ny, dtype=torch.float64, device=g.device)
+        s = torch.empty(ny, dtype=torch.float64, device=g.device)
+    w = torch.empty(ny, dtype=torch.float64, device=g.device) if post else None
+    info = _lib.ScsInfo()
+    check(_lib.lib().psd_scs_solve(ctypes.byref(st), _ptr(g), _ptr(x), _ptr(y), _ptr(s), _ptr(w), _ptr(ws),
+                                   ws.numel(), ctypes.c_void_p(_stream_ptr(g.device)), ctypes.byref(info)),
+          "psd_scs_solve")
+    out = {f: getattr(info, f) for f, _ in _lib.ScsInfo._fields_}
+    out.update(x=x, y=y, s=s, w=w)
+    return out
 
 
 class PSDProject(torch.autograd.Function):

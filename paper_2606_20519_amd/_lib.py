@@ -25,7 +25,7 @@ EXPORTS = ("psd_workspace_size", "psd_saved_size", "psd_project", "psd_project_n
            "psd_plan_execute", "psd_plan_tune", "psd_plan_destroy", "psd_timing_start", "psd_timing_stop",
            "psd_set_ns_iterations", "psd_set_mixed_fallback", "psd_status_string", "psd_version",
            "psd_affine_dims", "psd_affine_workspace_size", "psd_constraint_apply", "psd_constraint_adjoint",
-           "psd_affine_step")
+           "psd_affine_step", "psd_scs_workspace_size", "psd_scs_solve")
 KF_HEMV, KF_GEMM, KF_NS, KF_WSTEP = 1, 2, 3, 4
 
 
@@ -39,6 +39,21 @@ class PsdInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("n_pos", ctypes.c_int32), ("n_neg", ctypes.c_int32),
                 ("iters", ctypes.c_int32), ("fallback", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("est_rel_err", ctypes.c_double), ("scale", ctypes.c_double)]
+
+
+class ScsSettings(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("mixed_iters", ctypes.c_int32), ("mixed_mode", ctypes.c_int32), ("normalize", ctypes.c_int32),
+                ("warm_start", ctypes.c_int32), ("anderson", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("alpha", ctypes.c_double)]
+
+
+class ScsInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("proj_status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("pobj", ctypes.c_double), ("dobj", ctypes.c_double),
+                ("res_pri", ctypes.c_double), ("res_dual", ctypes.c_double), ("gap", ctypes.c_double),
+                ("tau", ctypes.c_double), ("kappa", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("post_lambda", ctypes.c_double), ("post_lambda_min", ctypes.c_double)]
 
 
 _lib = None
@@ -100,6 +115,10 @@ def lib():
     L.psd_constraint_adjoint.restype = i32
     L.psd_affine_step.argtypes = [i32, vp, vp, vp, vp, vp, sz, vp]
     L.psd_affine_step.restype = i32
+    L.psd_scs_workspace_size.argtypes = [ctypes.POINTER(ScsSettings), ctypes.POINTER(sz)]
+    L.psd_scs_workspace_size.restype = i32
+    L.psd_scs_solve.argtypes = [ctypes.POINTER(ScsSettings), vp, vp, vp, vp, vp, vp, sz, vp, ctypes.POINTER(ScsInfo)]
+    L.psd_scs_solve.restype = i32
     L.psd_timing_start.argtypes = [i32, i32]
     L.psd_timing_start.restype = i32
     L.psd_timing_stop.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
@@ -160,6 +179,12 @@ def affine_dims(d: int):
     nx, ny = ctypes.c_int64(0), ctypes.c_int64(0)
     check(lib().psd_affine_dims(d, ctypes.byref(nx), ctypes.byref(ny)), "psd_affine_dims")
     return int(nx.value), int(ny.value)
+
+
+def scs_workspace_size(settings: "ScsSettings") -> int:
+    out = ctypes.c_size_t(0)
+    check(lib().psd_scs_workspace_size(ctypes.byref(settings), ctypes.byref(out)), "psd_scs_workspace_size")
+    return int(out.value)
 
 
 def affine_workspace_size(d: int) -> int:

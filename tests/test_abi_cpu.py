@@ -133,3 +133,29 @@ def test_affine_host_validation(L):
     assert lib.psd_constraint_adjoint(2, fake, fake, ctypes.c_void_p(0x100008), big, None) == 1
     ax, ay = ctypes.c_void_p(0x10000), ctypes.c_void_p(0x20000)
     assert lib.psd_affine_step(2, ax, ay, ctypes.c_void_p(0x20008), ctypes.c_void_p(0x40000), ws, big, None) == 1
+
+
+def test_scs_settings_validation():
+    import ctypes
+    from paper_2606_20519_amd import _lib
+    L = _lib.lib()
+
+    def st(**kw):
+        base = dict(d=4, max_iters=10, check_every=1, mixed_iters=0, mixed_mode=2, normalize=1, warm_start=0,
+                    anderson=0, eps=1e-5, alpha=1.5)
+        base.update(kw)
+        return _lib.ScsSettings(**base)
+
+    out = ctypes.c_size_t(0)
+    assert L.psd_scs_workspace_size(ctypes.byref(st()), ctypes.byref(out)) == 0 and out.value > 0
+    for bad in (dict(d=1), dict(d=9), dict(max_iters=0), dict(check_every=0), dict(alpha=2.0), dict(alpha=0.0),
+                dict(eps=-1.0), dict(eps=float("nan")), dict(mixed_iters=5, mixed_mode=0), dict(anderson=3),
+                dict(normalize=2), dict(mixed_iters=-1)):
+        assert L.psd_scs_workspace_size(ctypes.byref(st(**bad)), ctypes.byref(out)) == 1, bad
+    info = _lib.ScsInfo()
+    # host-side rejections enqueue nothing
+    assert L.psd_scs_solve(ctypes.byref(st(d=9)), None, None, None, None, None, None, 0, None,
+                           ctypes.byref(info)) == 1
+    assert L.psd_scs_solve(ctypes.byref(st()), ctypes.c_void_p(256), ctypes.c_void_p(1 << 40),
+                           ctypes.c_void_p(2 << 40), ctypes.c_void_p(3 << 40), None, ctypes.c_void_p(4 << 40),
+                           16, None, ctypes.byref(info)) == 2          # workspace too small
