@@ -198,6 +198,39 @@ def numpy_eigh_baseline(np, oracle, x_svec, n):
             "sockets": sockets}
 
 
+def scs_context(P, W, torch, dev) -> dict:
+    """The whole SCS iteration (App. D) on GPU-resident data: a GYNI process
+    SDP from a seeded pair of random feasible instruments solved to
+    eps = 1e-5 at d = 5, and the per-iteration time at d = 8 over a fixed
+    iteration count (FP64 cone steps, then mixed-precision ones).  The
+    paper's wall-clock table for comparison (T4 GPU / one CPU, other
+    hardware): d = 5, 275 iterations, 21 s; d = 8, 300 iterations, 44 min
+    (SCS on the CPU: 4.4 h)."""
+    out = {}
+    for d, eps, iters in ((5, 1e-5, 5000), (8, 0.0, 8)):
+        g = torch.from_numpy(W.upper_pack(W.gyni_objective(d, 7))).to(dev)
+        P.scs_solve(g, d, eps=0.0, max_iters=2, post=False)     # warm-up (code objects, workspace)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = P.scs_solve(g, d, eps=eps, max_iters=iters, post=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        rec = {"eps": eps, "status": r["status"], "iterations": r["iters"], "seconds": round(dt, 3),
+               "ms_per_iteration": round(1e3 * dt / r["iters"], 3), "value": r["pobj"], "dual_bound": r["dobj"],
+               "residuals": [r["res_pri"], r["res_dual"], r["gap"]]}
+        if d == 8:
+            rec["projected_300_iterations_s"] = round(0.3 * dt / r["iters"] * 1e3, 1)
+            for mm in ("mixed_fp32", "mixed_bf16"):
+                t = time.perf_counter()
+                rm = P.scs_solve(g, d, eps=0.0, max_iters=iters, mixed_iters=iters, mixed_mode=mm, post=False)
+                torch.cuda.synchronize()
+                rec[f"ms_per_iteration_{mm}"] = round(1e3 * (time.perf_counter() - t) / rm["iters"], 3)
+        out[f"d{d}"] = rec
+        log(f"SCS d={d}: {rec}")
+    out["paper_t4_gpu"] = {"d5": {"iterations": 275, "seconds": 21}, "d8": {"iterations": 300, "seconds": 2640}}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -526,6 +559,9 @@ def main():
             extra["affine_step"] = {"ms": round(1e3 * dt, 3), "share_of_projection": round(1e3 * dt / per_proj_ms, 4),
                                     "nx": nx, "min_hbm_gbs": round(minbytes / dt / 1e9, 1),
                                     "passes": "unpack, 4 local transforms, gather, scatter, 4 transforms, pack"}
+        if wl == "c5" and not args.no_context:
+            log("SCS solves (GYNI, d = 5 to 1e-5; d = 8 per-iteration time)")
+            extra["scs"] = scs_context(P, W, torch, dev)
 
     # parity on a sample of the timed outputs; CPU oracle baseline
     cpu, err = None, None

@@ -287,7 +287,16 @@ psd_status psd_affine_step(int32_t d, const double *ax, const double *ay, double
  * |g| <= eps (1 + max(|c^T x|, |b^T y|)), tested every check_every
  * iterations and after the last one; eps = 0 runs exactly max_iters.
  * The first mixed_iters cone projections use mixed_mode, the rest FP64 (the
- * paper's low-to-high precision switch after a fixed iteration count). */
+ * paper's low-to-high precision switch after a fixed iteration count).
+ * anderson = m > 0: type-I Anderson acceleration (App. D.2 keeps SCS's) of
+ * the map q -> G(q) on the cone step's input q = u~_r - v (which fixes
+ * u = Pi_C(q) and v = u - q): with the last m differences S of the inputs
+ * and Y of the residuals f = q - G(q), gamma solves
+ * (S^T Y + 1e-8 ||S||_F ||Y||_F 1) gamma = S^T f and the next input is
+ * G(q) - (S - Y) gamma; an input whose residual exceeds twice the previous
+ * one is replaced by the plain G(q) it displaced and the memory cleared; a
+ * singular system or |gamma| > 1e10 skips the step.  With m > 0 the stream
+ * is also synchronised once per iteration. */
 typedef struct {
     int32_t d;             /* local dimension, 2..8 (W has order d^4) */
     int32_t max_iters;     /* >= 1 */
@@ -296,7 +305,7 @@ typedef struct {
     int32_t mixed_mode;    /* PSD_MIXED_BF16 or PSD_MIXED_FP32 when mixed_iters > 0 */
     int32_t normalize;     /* 0 or 1 */
     int32_t warm_start;    /* 0 or 1 */
-    int32_t anderson;      /* reserved, must be 0 */
+    int32_t anderson;      /* Anderson memory m, 0 (off) .. 16 */
     double eps;            /* eps_abs = eps_rel >= 0 */
     double alpha;          /* over-relaxation, 0 < alpha < 2 */
 } psd_scs_settings;
@@ -308,6 +317,8 @@ typedef struct {
                               residual or the data was not finite */
     int32_t iters;         /* iterations run */
     int32_t proj_status;   /* first non-OK status of a cone projection, else 0 */
+    int32_t aa_accepted;   /* Anderson steps taken */
+    int32_t aa_rejected;   /* Anderson steps undone by the safeguard */
     int32_t reserved;
     double pobj;           /* tr[W G] at x: gamma tr G - c^T x (last check) */
     double dobj;           /* dual bound gamma tr G + b^T y (last check) */

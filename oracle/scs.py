@@ -26,7 +26,7 @@ Everything below is the plain definition with explicit matrices:
   ("Solving the affine projection"): u~_xy = (1 - (M^-1 h) h^T /
   (1 + h^T M^-1 h)) (M^-1 a_xy - a_tau M^-1 h), u~_tau = a_tau + c^T u~_x +
   b^T u~_y, with h = (c, b).
-* ``Solver.step`` -- the iteration of eq. final_iterates: u~ = (1 + Q)^-1 (u + v),
+* ``Solver.cone_input`` / ``cone_step`` -- the iteration of eq. final_iterates: u~ = (1 + Q)^-1 (u + v),
   u = Pi_C(u~ - v), v = v - u~ + u, with C = R^n x H_+ x R_+; over-relaxation
   replaces u~ in the last two updates by alpha u~ + (1 - alpha) u (alpha = 1
   is the printed iteration).
@@ -37,6 +37,19 @@ Everything below is the plain definition with explicit matrices:
   sigma = ||b|| / ||c|| inside the iteration, so that the two norms agree,
   and the residuals are reported for the unscaled problem (y = u_y /
   (sigma tau)); projections in FP64 by the Jacobi oracle.
+* ``Anderson`` -- type-I Anderson acceleration (the paper keeps SCS's;
+  App. D.2).  The iterate is fixed by the cone step's input q = u~_r - v
+  alone (u = Pi_C(q), v = u - q by Moreau), so the iteration is the
+  fixed-point map q -> G(q) (project q, then the affine step), of dimension
+  n_x + n_y + 1, and the acceleration acts on q: with the last m differences
+  s_i = q_{i+1} - q_i and y_i = f_{i+1} - f_i of the inputs and of the
+  residuals f = q - G(q), gamma solves (S^T Y + lam 1) gamma = S^T f_k,
+  lam = 1e-8 ||S||_F ||Y||_F, and the next input is G(q_k) - (S - Y) gamma.
+  Safeguard: when the residual at an accelerated input exceeds twice the
+  previous one, the plain G(q_{k-1}) it replaced is projected instead and
+  the memory is cleared; a step with max |gamma| > 1e10 or a singular
+  system is not taken.  (Type-I Anderson with these safeguards after Zhang, O'Donoghue
+  and Boyd, SIAM J. Optim. 2020; the constants are this solver's reading.)
 * ``postprocess`` -- W' = (1 - lam) W + lam gamma 1 with the smallest
   lam in [0, 1] that makes W' PSD (App. "Sparse SDP formulation for process
   matrices and post-processing").
@@ -123,14 +136,24 @@ class Solver:
             self.v[self.nx:] = s
             self.ut, self.vk = 1.0, 0.0
 
-    def step(self):
+    def cone_input(self):
+        """q = u~_r - v with u~ = (1 + Q)^-1 (u + v): the point the next cone
+        step projects (x, y and tau parts)."""
         ut_xy, ut_tau = self.affine(self.u + self.v, self.ut + self.vk)
         r_xy = self.alpha * ut_xy + (1.0 - self.alpha) * self.u
         r_tau = self.alpha * ut_tau + (1.0 - self.alpha) * self.ut
-        u_new, t_new = self.cone(r_xy - self.v, r_tau - self.vk)
-        self.v = self.v - r_xy + u_new
-        self.vk = self.vk - r_tau + t_new
+        return r_xy - self.v, r_tau - self.vk
+
+    def cone_step(self, q_xy: np.ndarray, q_tau: float):
+        """u = Pi_C(q), v = v - u~_r + u = u - q (Moreau: v in C*)."""
+        u_new, t_new = self.cone(q_xy, q_tau)
+        self.v = u_new - q_xy
+        self.v[: self.nx] = 0.0          # x is free: v_x = 0 exactly
+        self.vk = t_new - q_tau
         self.u, self.ut = u_new, t_new
+
+    def step(self):
+        self.cone_step(*self.cone_input())
 
     def iterate_state(self):
         """(x, y, s, tau, kappa) of the current iterate, unscaled."""
@@ -167,28 +190,92 @@ class Solver:
         return out
 
 
+AA_REG = 1e-8
+AA_MAX_WEIGHT = 1e10
+AA_SAFEGUARD = 2.0
+
+
+class Anderson:
+    """Type-I Anderson acceleration of q -> G(q) with memory m (module
+    docstring)."""
+
+    def __init__(self, m: int):
+        self.m = m
+        self.accepted = self.rejected = 0
+        self.reset()
+
+    def reset(self):
+        self.S, self.Y = [], []
+        self.prev = None          # (q_k, f_k) of the last input
+        self.g_save = None        # the plain G(q_{k-1}) behind an accelerated input
+        self.nf_save = None       # ||f_{k-1}|| at that step
+
+    def next_input(self, qk: np.ndarray, g: np.ndarray) -> np.ndarray:
+        """Given the input q_k just projected and G(q_k), the next input."""
+        f = qk - g
+        nf = float(np.linalg.norm(f))
+        if self.g_save is not None:           # q_k was accelerated: safeguard
+            back, limit = self.g_save, self.nf_save
+            self.g_save = None
+            if not nf <= AA_SAFEGUARD * limit:
+                self.reset()
+                self.rejected += 1
+                return back
+        if self.prev is not None:
+            self.S.append(qk - self.prev[0])
+            self.Y.append(f - self.prev[1])
+            if len(self.S) > self.m:
+                self.S.pop(0)
+                self.Y.pop(0)
+        self.prev = (qk, f)
+        if not self.S:
+            return g
+        S, Y = np.column_stack(self.S), np.column_stack(self.Y)
+        lam = AA_REG * np.linalg.norm(S) * np.linalg.norm(Y)
+        try:
+            gam = np.linalg.solve(S.T @ Y + lam * np.eye(S.shape[1]), S.T @ f)
+        except np.linalg.LinAlgError:
+            return g
+        if not np.all(np.isfinite(gam)) or np.max(np.abs(gam)) > AA_MAX_WEIGHT:
+            return g
+        self.g_save, self.nf_save = g, nf
+        self.accepted += 1
+        return g - (S - Y) @ gam
+
+
 def solve(g_svec, d: int, eps: float = 1e-5, alpha: float = 1.5, max_iters: int = 5000,
-          normalize: bool = True, warm=None, prob=None) -> dict:
+          normalize: bool = True, warm=None, prob=None, anderson: int = 0) -> dict:
     """Run the iteration until the termination test holds (checked after
     every iteration) or `max_iters` iterations; eps = 0 runs exactly
-    max_iters.  Returns the unscaled (x, y, s), tau, kappa, the iteration
-    count, the last residuals and the history of (res_pri, res_dual, gap)."""
+    max_iters.  anderson = m > 0 accelerates the cone-step inputs.  Returns
+    the unscaled (x, y, s), tau, kappa, the iteration count, the last
+    residuals and the history of (res_pri, res_dual, gap)."""
     prob = prob if prob is not None else problem(g_svec, d)
     sv = Solver(prob, alpha=alpha, normalize=normalize)
     sv.start(warm)
+    aa = Anderson(anderson) if anderson > 0 else None
     hist = []
-    res = None
+    res = {"converged": False}
     it = 0
+    q_xy, q_tau = sv.cone_input()
     for it in range(1, max_iters + 1):
-        sv.step()
+        sv.cone_step(q_xy, q_tau)
         res = sv.residuals(eps)
         hist.append((res["res_pri"], res["res_dual"], res["gap"]))
         if eps > 0 and res["converged"]:
             break
+        if it == max_iters:
+            break
+        g_xy, g_tau = sv.cone_input()
+        if aa:
+            nxt = aa.next_input(np.append(q_xy, q_tau), np.append(g_xy, g_tau))
+            g_xy, g_tau = nxt[:-1], float(nxt[-1])
+        q_xy, q_tau = g_xy, g_tau
     x, y, s, tau, kappa = sv.iterate_state()
     return {"x": x, "y": y, "s": s, "tau": tau, "kappa": kappa, "iters": it,
             "converged": bool(res["converged"]), "res": res, "history": hist,
-            "sigma": sv.sigma, "prob": prob}
+            "sigma": sv.sigma, "prob": prob,
+            "aa": (aa.accepted, aa.rejected) if aa else None}
 
 
 def process_matrix(prob: dict, x) -> np.ndarray:

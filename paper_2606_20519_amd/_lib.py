@@ -50,6 +50,7 @@ class ScsSettings(ctypes.Structure):
 
 class ScsInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("proj_status", ctypes.c_int32),
+                ("aa_accepted", ctypes.c_int32), ("aa_rejected", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("pobj", ctypes.c_double), ("dobj", ctypes.c_double),
                 ("res_pri", ctypes.c_double), ("res_dual", ctypes.c_double), ("gap", ctypes.c_double),
                 ("tau", ctypes.c_double), ("kappa", ctypes.c_double), ("sigma", ctypes.c_double),

@@ -148,8 +148,13 @@ def test_scs_settings_validation():
 
     out = ctypes.c_size_t(0)
     assert L.psd_scs_workspace_size(ctypes.byref(st()), ctypes.byref(out)) == 0 and out.value > 0
+    plain = out.value
+    assert L.psd_scs_workspace_size(ctypes.byref(st(anderson=10)), ctypes.byref(out)) == 0
+    nx, ny = _lib.affine_dims(4)
+    assert out.value >= plain + 24 * 8 * (nx + ny + 1)       # 2m + 4 vectors of the cone input
     for bad in (dict(d=1), dict(d=9), dict(max_iters=0), dict(check_every=0), dict(alpha=2.0), dict(alpha=0.0),
-                dict(eps=-1.0), dict(eps=float("nan")), dict(mixed_iters=5, mixed_mode=0), dict(anderson=3),
+                dict(eps=-1.0), dict(eps=float("nan")), dict(mixed_iters=5, mixed_mode=0), dict(anderson=17),
+                dict(anderson=-1),
                 dict(normalize=2), dict(mixed_iters=-1)):
         assert L.psd_scs_workspace_size(ctypes.byref(st(**bad)), ctypes.byref(out)) == 1, bad
     info = _lib.ScsInfo()

@@ -10,6 +10,9 @@ and against optimality certificates that share nothing with either:
   and LAPACK eigenvalues (s, y PSD, s in the process subspace with
   tr s = d^2, y + G orthogonal to the traceless process subspace, value and
   dual bound equal); the post-processed W is PSD and in the subspace;
+* with type-I Anderson acceleration (memory 10): the iterates equal the
+  oracle's for the first iterations at d = 2, the full solve reaches the
+  oracle's value, and a d = 4 solve needs fewer iterations than without;
 * closed-form optima (G = an allowed Pauli string: 1; a forbidden element:
   0; G = 1: d^2 with c = 0), warm start at the solution, the low-precision
   start (mixed_iters), a non-finite objective;
@@ -84,6 +87,38 @@ def test_iterates_match_oracle(P, d, k):
     assert abs(r["sigma"] - sv.sigma) <= 1e-14 * sv.sigma
 
 
+@pytest.mark.parametrize("k", [2, 5, 12])
+def test_anderson_iterates_match_oracle(P, k):
+    d = 2
+    g, prob = gyni(d)
+    ref = scs.solve(g, d, eps=0.0, max_iters=k, prob=prob, anderson=10)
+    r = P.scs_solve(dev(g), d, eps=0.0, max_iters=k, post=False, anderson=10)
+    print(f"AA iterates k={k}: oracle tau {ref['tau']:.12e} accepted/rejected {ref['aa']}; GPU tau {r['tau']:.12e} "
+          f"{r['aa_accepted']}/{r['aa_rejected']}", flush=True)
+    assert (r["aa_accepted"], r["aa_rejected"]) == ref["aa"]
+    assert abs(r["tau"] - ref["tau"]) <= 1e-10 * max(1.0, abs(ref["tau"]))
+    for key in ("x", "y", "s"):
+        e = rel(host(r[key]), ref[key])
+        print(f"  {key}: {e:.2e}", flush=True)
+        assert e <= 1e-9
+
+
+def test_anderson_full_solve(P):
+    g, prob = gyni(2)
+    ref = scs.solve(g, 2, eps=1e-5, prob=prob, anderson=10)
+    r = P.scs_solve(dev(g), 2, eps=1e-5, anderson=10)
+    plain = P.scs_solve(dev(g), 2, eps=1e-5, post=False)
+    print(f"d=2 AA: oracle {ref['iters']} iterations {ref['res']['pobj']:.10f}; GPU {r['iters']} "
+          f"{r['pobj']:.10f} ({r['aa_accepted']} accepted, {r['aa_rejected']} rejected); plain {plain['iters']}",
+          flush=True)
+    assert r["status"] == 0
+    # the accelerated trajectory is sensitive to rounding: the same solution, a similar count
+    assert abs(r["pobj"] - ref["res"]["pobj"]) < 1e-4
+    assert r["iters"] <= 1.5 * ref["iters"] + 10 and r["iters"] < plain["iters"]
+    gmat = oracle.unpack(g, 16)
+    _certificate(2, r, gmat, 1e-4)
+
+
 def test_full_solve_matches_oracle_d2(P):
     g, prob = gyni(2)
     ref = scs.solve(g, 2, eps=1e-5, prob=prob)
@@ -117,13 +152,14 @@ def _certificate(d, r, gmat, tol):
     return value, bound
 
 
-@pytest.mark.parametrize("d", [3, 4, 5])
-def test_certificate(P, d):
+@pytest.mark.parametrize("d, aa", [(3, 0), (4, 0), (5, 0), (4, 10), (5, 10)])
+def test_certificate(P, d, aa):
     g, _ = gyni(d)
     gmat = oracle.unpack(g, d ** 4)
     eps = 1e-6 if d < 5 else 1e-5
-    r = P.scs_solve(dev(g), d, eps=eps, max_iters=10000)
-    print(f"d={d}: {r['iters']} iterations, value {r['pobj']:.9f} bound {r['dobj']:.9f} "
+    r = P.scs_solve(dev(g), d, eps=eps, max_iters=10000, anderson=aa)
+    print(f"d={d} anderson={aa}: {r['iters']} iterations ({r['aa_accepted']}/{r['aa_rejected']}), "
+          f"value {r['pobj']:.9f} bound {r['dobj']:.9f} "
           f"res {r['res_pri']:.1e} {r['res_dual']:.1e} {r['gap']:.1e} post lam {r['post_lambda']:.1e}", flush=True)
     assert r["status"] == 0 and r["proj_status"] == 0
     _certificate(d, r, gmat, 10 * eps)
