@@ -66,8 +66,12 @@ typedef enum {
 typedef enum {
     PSD_FP64_EIG = 0,     /* FP64 eigendecomposition path (exact up to rounding) */
     PSD_MIXED_BF16 = 1,   /* Newton-Schulz sign iteration, BF16 MFMA + FP64 correction */
-    PSD_MIXED_FP32 = 2    /* Newton-Schulz sign iteration, FP32 MFMA + FP64 correction;
-                             blocks of order <= 64 always take the exact LDS kernel */
+    PSD_MIXED_FP32 = 2,   /* Newton-Schulz sign iteration, FP32 MFMA + FP64 correction */
+    PSD_MIXED_BF16X3 = 3  /* Newton-Schulz sign iteration on split BF16 operands: each
+                             FP32 value as hi + lo (two BF16 terms), each real product as
+                             hi*hi + hi*lo + lo*hi (three BF16 MFMAs, about 16 bits) +
+                             FP64 correction.  In every mixed mode, blocks of order
+                             <= 64 take the exact LDS kernel */
 } psd_mode;
 
 /* Per-block result record, written by the device (device or pinned host
@@ -119,7 +123,7 @@ psd_status psd_project(int32_t n, const double *x, double *y, psd_mode mode,
  * Its address is looked up on the first call made with a device current.
  * Orders whose psd_workspace_size(1, &n, mode, 0) exceeds the array are
  * rejected with PSD_EWORKSPACE before anything is enqueued (n <= 831 in
- * FP64, n <= 768 in BF16-mixed, n <= 704 in FP32-mixed; n <= 64 needs none).  Calls on one
+ * FP64, n <= 768 in BF16-mixed, n <= 704 in FP32- and BF16x3-mixed; n <= 64 needs none).  Calls on one
  * device share the array: calls that overlap in time on one device (other
  * streams, other host threads) race and must be serialised by the caller.
  * Same arguments and results as psd_project, without `saved` and without
@@ -302,7 +306,7 @@ typedef struct {
     int32_t max_iters;     /* >= 1 */
     int32_t check_every;   /* >= 1 */
     int32_t mixed_iters;   /* >= 0 */
-    int32_t mixed_mode;    /* PSD_MIXED_BF16 or PSD_MIXED_FP32 when mixed_iters > 0 */
+    int32_t mixed_mode;    /* a mixed psd_mode when mixed_iters > 0 */
     int32_t normalize;     /* 0 or 1 */
     int32_t warm_start;    /* 0 or 1 */
     int32_t anderson;      /* Anderson memory m, 0 (off) .. 16 */

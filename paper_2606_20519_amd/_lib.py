@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libpsdproj.so")
 PSD_OK = 0
 STATUS_NAMES = {0: "PSD_OK", 1: "PSD_EINVAL", 2: "PSD_EWORKSPACE", 3: "PSD_ENOMEM",
                 4: "PSD_ENONFINITE", 5: "PSD_ENOCONV", 6: "PSD_EDEVICE", 7: "PSD_EUNSUPPORTED"}
-MODES = {"fp64": 0, "mixed_bf16": 1, "mixed_fp32": 2}
+MODES = {"fp64": 0, "mixed_bf16": 1, "mixed_fp32": 2, "mixed_bf16x3": 3}
 PSD_FLAG_SAVE = 1
 NOALLOC_SCRATCH_BYTES = 48 << 20   # PSD_NOALLOC_SCRATCH_BYTES
 

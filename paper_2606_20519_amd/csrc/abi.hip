@@ -30,7 +30,9 @@ namespace {
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
 
-bool valid_mode(int m) { return m == PSD_FP64_EIG || m == PSD_MIXED_BF16 || m == PSD_MIXED_FP32; }
+bool valid_mode(int m) {
+    return m == PSD_FP64_EIG || m == PSD_MIXED_BF16 || m == PSD_MIXED_FP32 || m == PSD_MIXED_BF16X3;
+}
 
 bool aligned8(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 7u) == 0; }
 
@@ -59,14 +61,14 @@ struct Carve {
 // input and one info record for the FP64 fallback (psd_set_mixed_fallback).
 size_t large_ws_bytes(int n, int mode, int flags) {
     size_t b = large_layout(n, flags, nullptr, nullptr);
-    if ((mode == PSD_MIXED_BF16 || mode == PSD_MIXED_FP32) && !(flags & PSD_FLAG_SAVE)) {
+    if ((mode == PSD_MIXED_BF16 || mode == PSD_MIXED_FP32 || mode == PSD_MIXED_BF16X3) && !(flags & PSD_FLAG_SAVE)) {
         b = align_up(std::max(b, mixed_layout(n, mode, nullptr, nullptr)));
         b += align_up(sizeof(double) * (size_t)n * (size_t)n) + align_up(sizeof(psd_info));
     }
     return b;
 }
 
-bool is_mixed(int mode) { return mode == PSD_MIXED_BF16 || mode == PSD_MIXED_FP32; }
+bool is_mixed(int mode) { return mode == PSD_MIXED_BF16 || mode == PSD_MIXED_FP32 || mode == PSD_MIXED_BF16X3; }
 
 int g_ns_iters = 0;  // automatic
 int g_ns_corr = 1;

@@ -34,7 +34,8 @@ struct MixedWs {
 constexpr int NS_BIG_DEFAULT = 2048;
 constexpr int NS_BIG_MIN = 1024;
 
-// mode: 1 = BF16, 2 = FP32 low-precision iterations.
+// mode: 1 = BF16, 2 = FP32, 3 = split BF16 (hi + lo, three products per real
+// product) low-precision iterations.
 size_t mixed_layout(int n, int mode, void *base, MixedWs *w);
 hipError_t mixed_project(const MixedWs &w, int mode, const double *x, double *y, psd_dev_info *info, int iters,
                          int corr, hipStream_t st);

@@ -259,6 +259,37 @@ __global__ void __launch_bounds__(256) ns_scale_kernel(const double2 *__restrict
     Xim[i + (int64_t)j * npad] = to_low<L>((float)(v.y * inv));
 }
 
+// The two-term BF16 split of an FP32 value: hi = bf16(v), lo = bf16(v - hi)
+// (v - hi is exact in FP32), so hi + lo carries about 16 significant bits.
+__device__ __forceinline__ void bf16_split(float v, __bf16 &hi, __bf16 &lo) {
+    hi = (__bf16)v;
+    lo = (__bf16)(v - (float)hi);
+}
+
+// X0 = M / alpha as split BF16 planes: Re hi, Im hi at X, X + plane; the lo
+// terms lo_off elements further.
+__global__ void __launch_bounds__(256) ns_scale_split_kernel(const double2 *__restrict__ M, int64_t lda, int n,
+                                                             int npad, const double *alpha, __bf16 *X, int64_t plane,
+                                                             int64_t lo_off, int64_t zs) {
+    M = member_ptr(M, zs, blockIdx.z);
+    alpha = member_ptr(alpha, zs, blockIdx.z);
+    X = member_ptr(X, zs, blockIdx.z);
+    const int j = blockIdx.y;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= npad) return;
+    const double inv = 1.0 / *alpha;
+    double2 v = cmk(0.0, 0.0);
+    if (i < n && j < n) v = M[i + (int64_t)j * lda];
+    const int64_t o = i + (int64_t)j * npad;
+    __bf16 h, l;
+    bf16_split((float)(v.x * inv), h, l);
+    X[o] = h;
+    X[o + lo_off] = l;
+    bf16_split((float)(v.y * inv), h, l);
+    X[o + plane] = h;
+    X[o + plane + lo_off] = l;
+}
+
 enum { NS_EPI_T = 0, NS_EPI_HALF = 1, NS_EPI_F64 = 2 };
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
@@ -292,33 +323,49 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 // Epilogue of one 32x32 block at (ib, jb), BF16 planes (as ns_gemm_kernel's
 // 16x16 one: the lower part with its conjugate mirror).  32x32x16 output
 // layout: D[i][j] in lane j + 32 ((i / 4) % 2), element 4 (i / 8) + i % 4.
+template <int SPLIT = 1>
 __device__ __forceinline__ void ns_store_block32(const v16f &accr, const v16f &acci, int ib, int jb, int lane, int npad,
                                                  int epi, float c, __bf16 *Cre, __bf16 *Cim, double2 *C64,
-                                                 int64_t ld64, int n) {
+                                                 int64_t ld64, int n, int64_t lo_off = 0) {
     if (ib < jb || ib >= npad) return;
     const int j = jb + (lane & 31), ih = 4 * (lane >> 5);
     if (epi != NS_EPI_F64 && ib > jb) {
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
             const int ir = ib + 8 * g + ih;
-            union { __bf16 h[4]; uint2 u; } pr, pi, pn;
+            union { __bf16 h[4]; uint2 u; } pr, pi, pn, qr, qi, qn;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 float re = accr[4 * g + v], im = acci[4 * g + v];
                 if (epi == NS_EPI_T) { re = -c * re; im = -c * im; }
                 else { re *= c; im *= c; }
-                pr.h[v] = (__bf16)re;
-                pi.h[v] = (__bf16)im;
-                pn.h[v] = (__bf16)(-im);
+                if constexpr (SPLIT == 2) {
+                    bf16_split(re, pr.h[v], qr.h[v]);
+                    bf16_split(im, pi.h[v], qi.h[v]);
+                    pn.h[v] = -pi.h[v];
+                    qn.h[v] = -qi.h[v];
+                } else {
+                    pr.h[v] = (__bf16)re;
+                    pi.h[v] = (__bf16)im;
+                    pn.h[v] = (__bf16)(-im);
+                }
             }
             const int64_t o = (int64_t)ir + (int64_t)j * npad;
             *reinterpret_cast<uint2 *>(Cre + o) = pr.u;
             *reinterpret_cast<uint2 *>(Cim + o) = pi.u;
+            if constexpr (SPLIT == 2) {
+                *reinterpret_cast<uint2 *>(Cre + lo_off + o) = qr.u;
+                *reinterpret_cast<uint2 *>(Cim + lo_off + o) = qi.u;
+            }
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int64_t om = (int64_t)j + (int64_t)(ir + v) * npad;
                 Cre[om] = pr.h[v];
                 Cim[om] = pn.h[v];
+                if constexpr (SPLIT == 2) {
+                    Cre[lo_off + om] = qr.h[v];
+                    Cim[lo_off + om] = qn.h[v];
+                }
             }
         }
         return;
@@ -332,10 +379,20 @@ __device__ __forceinline__ void ns_store_block32(const v16f &accr, const v16f &a
         else { re *= c; im *= c; }
         if (i == j) im = 0.0f;
         if (epi != NS_EPI_F64) {
-            const __bf16 lr = (__bf16)re, li = (__bf16)im, lni = (__bf16)(-im);
             const int64_t o = (int64_t)i + (int64_t)j * npad, om = (int64_t)j + (int64_t)i * npad;
-            Cre[o] = lr; Cim[o] = li;
-            Cre[om] = lr; Cim[om] = lni;
+            if constexpr (SPLIT == 2) {
+                __bf16 hr, lr, hi, li;
+                bf16_split(re, hr, lr);
+                bf16_split(im, hi, li);
+                Cre[o] = hr; Cim[o] = hi;
+                Cre[om] = hr; Cim[om] = -hi;
+                Cre[lo_off + o] = lr; Cim[lo_off + o] = li;
+                Cre[lo_off + om] = lr; Cim[lo_off + om] = -li;
+            } else {
+                const __bf16 lr = (__bf16)re, li = (__bf16)im, lni = (__bf16)(-im);
+                Cre[o] = lr; Cim[o] = li;
+                Cre[om] = lr; Cim[om] = lni;
+            }
         } else if (i < n && j < n) {
             C64[i + (int64_t)j * ld64] = cmk((double)re, (double)im);
             C64[j + (int64_t)i * ld64] = cmk((double)re, -(double)im);
@@ -354,12 +411,19 @@ __device__ __forceinline__ void ns_store_block32(const v16f &accr, const v16f &a
 // Planar low precision, column-major, ld npad (npad % 64 == 0), FP32
 // accumulation on the MFMA cores.  Tile 64x64x32, 4 waves in 2x2, each
 // 32x32 = 2x2 MFMA blocks of 16x16.
-template <typename L>
+// SPLIT = 2 (BF16 only): every operand is the two-term split hi + lo of its
+// FP32 value (the lo planes lo_off elements after the hi ones), and each
+// real product is formed as hi*hi + hi*lo + lo*hi (the lo*lo term, below
+// 2^-16 relative, is dropped): three BF16 MFMAs for about 16 significant
+// bits, the split ("BF16x3") products of the paper's outlook (Sec. V).
+template <typename L, int SPLIT = 1>
 __global__ void __launch_bounds__(256) ns_gemm_kernel(const L *__restrict__ Are, const L *__restrict__ Aim,
                                                       const L *__restrict__ Bre, const L *__restrict__ Bim, int npad,
                                                       int epi, float c, L *Cre, L *Cim, double2 *C64, int64_t ld64,
-                                                      int n, int64_t zs) {
+                                                      int n, int64_t zs, int64_t lo_off = 0) {
     constexpr bool BF = sizeof(L) == 2;
+    constexpr bool X3 = SPLIT == 2;
+    static_assert(!X3 || BF, "split products are BF16");
     {
         const int mb = blockIdx.z;
         Are = member_ptr(Are, zs, mb);
@@ -374,7 +438,9 @@ __global__ void __launch_bounds__(256) ns_gemm_kernel(const L *__restrict__ Are,
     // position q ^ f(r), f(r) = ((r >> 2) ^ (r >> 1)) & 3 (conflict-free
     // stores and fragment reads); FP32 padded by 4
     constexpr int KP = 32 + (BF ? 0 : 4);
+    constexpr int LR = X3 ? 64 : 1;   // the lo planes' tiles (split products only)
     __shared__ __align__(16) L sAr[64][KP], sAi[64][KP], sBr[64][KP], sBi[64][KP];
+    __shared__ __align__(16) L sArl[LR][KP], sAil[LR][KP], sBrl[LR][KP], sBil[LR][KP];
     const int tb = xcd_tile(blockIdx.x, gridDim.x);
     int ti = (int)((sqrt(8.0 * tb + 1.0) - 1.0) * 0.5);
     while ((ti + 1) * (ti + 2) / 2 <= tb) ++ti;
@@ -401,9 +467,14 @@ __global__ void __launch_bounds__(256) ns_gemm_kernel(const L *__restrict__ Are,
     const int lr = t >> 2, lk = (t & 3) * 8;
     const int lks = BF ? (((t & 3) ^ (((lr >> 2) ^ (lr >> 1)) & 3)) * 8) : lk;  // swizzled store position
     uint4 xr[1], xi[1], yr[1], yi[1];
+    uint4 xrl[1], xil[1], yrl[1], yil[1];
     if constexpr (BF)
         ns_load_chunks<L, 1>(Are, Aim, Bre, Bim, (int64_t)lk + (int64_t)(i0 + lr) * npad,
                              (int64_t)lk + (int64_t)(j0 + lr) * npad, xr, xi, yr, yi);
+    if constexpr (X3)
+        ns_load_chunks<L, 1>(Are + lo_off, Aim + lo_off, Bre + lo_off, Bim + lo_off,
+                             (int64_t)lk + (int64_t)(i0 + lr) * npad, (int64_t)lk + (int64_t)(j0 + lr) * npad, xrl,
+                             xil, yrl, yil);
     for (int k0 = 0; k0 < npad; k0 += 32) {
         if constexpr (BF) {
             uint4 ai = xi[0];
@@ -412,6 +483,14 @@ __global__ void __launch_bounds__(256) ns_gemm_kernel(const L *__restrict__ Are,
             *reinterpret_cast<uint4 *>(&sAi[lr][lks]) = ai;
             *reinterpret_cast<uint4 *>(&sBr[lr][lks]) = yr[0];
             *reinterpret_cast<uint4 *>(&sBi[lr][lks]) = yi[0];
+            if constexpr (X3) {
+                uint4 al = xil[0];
+                al.x ^= 0x80008000u; al.y ^= 0x80008000u; al.z ^= 0x80008000u; al.w ^= 0x80008000u;
+                *reinterpret_cast<uint4 *>(&sArl[lr][lks]) = xrl[0];
+                *reinterpret_cast<uint4 *>(&sAil[lr][lks]) = al;
+                *reinterpret_cast<uint4 *>(&sBrl[lr][lks]) = yrl[0];
+                *reinterpret_cast<uint4 *>(&sBil[lr][lks]) = yil[0];
+            }
         } else {
             const int64_t ao = (int64_t)(k0 + lk) + (int64_t)(i0 + lr) * npad;
             const int64_t bo = (int64_t)(k0 + lk) + (int64_t)(j0 + lr) * npad;
@@ -430,6 +509,10 @@ __global__ void __launch_bounds__(256) ns_gemm_kernel(const L *__restrict__ Are,
             const int kn = k0 + 32 < npad ? k0 + 32 : k0;  // the last slice again at the end: no branch
             ns_load_chunks<L, 1>(Are, Aim, Bre, Bim, (int64_t)(kn + lk) + (int64_t)(i0 + lr) * npad,
                                  (int64_t)(kn + lk) + (int64_t)(j0 + lr) * npad, xr, xi, yr, yi);
+            if constexpr (X3)
+                ns_load_chunks<L, 1>(Are + lo_off, Aim + lo_off, Bre + lo_off, Bim + lo_off,
+                                     (int64_t)(kn + lk) + (int64_t)(i0 + lr) * npad,
+                                     (int64_t)(kn + lk) + (int64_t)(j0 + lr) * npad, xrl, xil, yrl, yil);
         }
         const int ii = lane & 15, kg = lane >> 4;
         if constexpr (BF) {
@@ -448,6 +531,24 @@ __global__ void __launch_bounds__(256) ns_gemm_kernel(const L *__restrict__ Are,
                     const v8bf ain = *reinterpret_cast<const v8bf *>(&u);
                     const v8bf br = *reinterpret_cast<const v8bf *>(&sBr[wn * 32 + rl][pos]);
                     const v8bf bi = *reinterpret_cast<const v8bf *>(&sBi[wn * 32 + rl][pos]);
+                    if constexpr (X3) {
+                        // the cross terms first (the small ones), then hi * hi
+                        const v8bf arl = *reinterpret_cast<const v8bf *>(&sArl[wm * 32 + rl][pos]);
+                        uint4 ul = *reinterpret_cast<const uint4 *>(&sAil[wm * 32 + rl][pos]);
+                        const v8bf ail = *reinterpret_cast<const v8bf *>(&ul);
+                        ul.x ^= 0x80008000u; ul.y ^= 0x80008000u; ul.z ^= 0x80008000u; ul.w ^= 0x80008000u;
+                        const v8bf ainl = *reinterpret_cast<const v8bf *>(&ul);
+                        const v8bf brl = *reinterpret_cast<const v8bf *>(&sBrl[wn * 32 + rl][pos]);
+                        const v8bf bil = *reinterpret_cast<const v8bf *>(&sBil[wn * 32 + rl][pos]);
+                        accr32 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar, brl, accr32, 0, 0, 0);
+                        accr32 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl, br, accr32, 0, 0, 0);
+                        acci32 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar, bil, acci32, 0, 0, 0);
+                        acci32 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(arl, bi, acci32, 0, 0, 0);
+                        accr32 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ain, bil, accr32, 0, 0, 0);
+                        accr32 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ainl, bi, accr32, 0, 0, 0);
+                        acci32 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ai, brl, acci32, 0, 0, 0);
+                        acci32 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ail, br, acci32, 0, 0, 0);
+                    }
                     accr32 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar, br, accr32, 0, 0, 0);
                     acci32 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ar, bi, acci32, 0, 0, 0);
                     accr32 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ain, bi, accr32, 0, 0, 0);
@@ -483,7 +584,8 @@ __global__ void __launch_bounds__(256) ns_gemm_kernel(const L *__restrict__ Are,
     }
     if constexpr (BF) {
         if (!idle)
-            ns_store_block32(accr32, acci32, i0 + wm * 32, j0 + wn * 32, lane, npad, epi, c, Cre, Cim, C64, ld64, n);
+            ns_store_block32<SPLIT>(accr32, acci32, i0 + wm * 32, j0 + wn * 32, lane, npad, epi, c, Cre, Cim, C64,
+                                    ld64, n, lo_off);
         return;
     }
     // epilogue; f32-accumulating 16x16 MFMA layout: D[i][j] in lane
@@ -903,7 +1005,7 @@ std::vector<double> ns_scalings(int iters) {
     return a;
 }
 
-template <typename L>
+template <typename L, int SPLIT = 1>
 hipError_t ns_run(const MixedWs &w, const double *x, double *y, psd_dev_info *info, int iters_req, int corr,
                   hipStream_t st) {
     const std::vector<double> sc = ns_scalings(iters_req);
@@ -914,12 +1016,19 @@ hipError_t ns_run(const MixedWs &w, const double *x, double *y, psd_dev_info *in
     const int B = w.nmem;
     const int64_t zs = w.zs;
     dim3 sg((npad + 255) / 256, npad, B);
-    hipLaunchKernelGGL((ns_scale_kernel<L>), sg, dim3(256), 0, st, w.M, w.lda, n, npad, w.alpha, X, X + plane, zs);
+    // split products: the lo planes follow the two hi planes of each matrix
+    const int64_t lo_off = SPLIT == 2 ? 2 * plane : 0;
+    if constexpr (SPLIT == 2)
+        hipLaunchKernelGGL(ns_scale_split_kernel, sg, dim3(256), 0, st, w.M, w.lda, n, npad, w.alpha,
+                           reinterpret_cast<__bf16 *>(X), plane, lo_off, zs);
+    else
+        hipLaunchKernelGGL((ns_scale_kernel<L>), sg, dim3(256), 0, st, w.M, w.lda, n, npad, w.alpha, X, X + plane,
+                           zs);
     // BF16 at npad >= w.ns_big: 128x128 tiles with a split tail; otherwise
     // the 64x64 tile (the choice depends on npad and the threshold only, so
     // that group members match single-block calls bit for bit under the
     // same threshold)
-    const bool big = sizeof(L) == 2 && npad >= w.ns_big;
+    const bool big = SPLIT == 1 && sizeof(L) == 2 && npad >= w.ns_big;
     int ntile, tfull, rem, split;
     if (big) ns_tail_plan(npad, &ntile, &tfull, &rem, &split);
     else { const int mt = npad / 64; ntile = mt * (mt + 1) / 2; tfull = ntile; rem = 0; split = 1; }
@@ -928,7 +1037,7 @@ hipError_t ns_run(const MixedWs &w, const double *x, double *y, psd_dev_info *in
     const double ns_flops = 8.0 * (double)n * (double)n * (double)(n + 1) / 2.0 * B;
     auto product = [&](const L *A, const L *Bm, int epi, float cf, L *C, double2 *C64) {
         const int slot = timing_begin(KF_NS, st);
-        if constexpr (sizeof(L) == 2) {
+        if constexpr (sizeof(L) == 2 && SPLIT == 1) {
             if (big) {
                 hipLaunchKernelGGL(ns_gemm128_kernel, dim3(tfull + rem * split, 1, B), dim3(256), 0, st, A, A + plane,
                                    Bm, Bm + plane, npad, epi, cf, C, C + plane, C64, w.lda, n, tfull, split, w.part,
@@ -940,8 +1049,8 @@ hipError_t ns_run(const MixedWs &w, const double *x, double *y, psd_dev_info *in
                 return;
             }
         }
-        hipLaunchKernelGGL((ns_gemm_kernel<L>), dim3(ntile, 1, B), dim3(256), 0, st, A, A + plane, Bm, Bm + plane, npad,
-                           epi, cf, C, C + plane, C64, w.lda, n, zs);
+        hipLaunchKernelGGL((ns_gemm_kernel<L, SPLIT>), dim3(ntile, 1, B), dim3(256), 0, st, A, A + plane, Bm,
+                           Bm + plane, npad, epi, cf, C, C + plane, C64, w.lda, n, zs, lo_off);
         timing_end(slot, st, ns_flops);
     };
     for (int k = 0; k < iters; ++k) {
@@ -1059,6 +1168,7 @@ hipError_t mixed_project(const MixedWs &w, int mode, const double *x, double *y,
     }
     hipLaunchKernelGGL(lz_final_kernel, dim3(1, 1, B), dim3(64), 0, st, w.ab, w.alpha, zs);
     if (mode == 1) return ns_run<__bf16>(w, x, y, info, iters, corr, st);
+    if (mode == 3) return ns_run<__bf16, 2>(w, x, y, info, iters, corr, st);
     return ns_run<float>(w, x, y, info, iters, corr, st);
 }
 

@@ -199,7 +199,8 @@ extern "C" {
 psd_status psd_plan_create(int32_t nblocks, const int32_t *n, psd_mode mode, int32_t concurrency,
                            psd_plan *plan) {
     if (nblocks < 1 || !n || !plan || concurrency < 0 || concurrency > kMaxConcurrency) return PSD_EINVAL;
-    if (mode != PSD_FP64_EIG && mode != PSD_MIXED_BF16 && mode != PSD_MIXED_FP32) return PSD_EINVAL;
+    if (mode != PSD_FP64_EIG && mode != PSD_MIXED_BF16 && mode != PSD_MIXED_FP32 && mode != PSD_MIXED_BF16X3)
+        return PSD_EINVAL;
     psd_plan_s *p = new (std::nothrow) psd_plan_s();
     if (!p) return PSD_ENOMEM;
     p->mode = mode;

@@ -526,7 +526,8 @@ bool scs_layout(const psd_scs_settings &s, ScsLayout &L) {
 
 bool settings_ok(const psd_scs_settings *s) {
     return s && s->d >= 2 && s->d <= 8 && s->max_iters >= 1 && s->check_every >= 1 && s->mixed_iters >= 0 &&
-           (s->mixed_iters == 0 || s->mixed_mode == PSD_MIXED_BF16 || s->mixed_mode == PSD_MIXED_FP32) &&
+           (s->mixed_iters == 0 || s->mixed_mode == PSD_MIXED_BF16 || s->mixed_mode == PSD_MIXED_FP32 ||
+            s->mixed_mode == PSD_MIXED_BF16X3) &&
            (s->normalize == 0 || s->normalize == 1) && (s->warm_start == 0 || s->warm_start == 1) &&
            s->anderson >= 0 && s->anderson <= AA_MAX && s->eps >= 0.0 && std::isfinite(s->eps) && s->alpha > 0.0 &&
            s->alpha < 2.0;

@@ -18,18 +18,24 @@ error of the assembled projection:
 The stated bar of a mixed result is band(2 u ||X||_2) + 2 est ||Pi||_F.  For
 FP32 there is also the fixed bar FP32_REL_BAR = 1e-5, from
 K u sqrt(2) c = 21 * 2^-24 * 1.41 * 4 = 7.1e-6 (||X||_F / ||Pi||_F is about
-sqrt(2) for spectra symmetric about 0), rounded up.
+sqrt(2) for spectra symmetric about 0), rounded up.  The split-BF16 form
+("BF16x3", u = 2^-16) is held to the band at 2 u ||X||_2 plus twice its
+estimate, like BF16.
 """
 import numpy as np
 
 U_BF16 = 2.0 ** -8
 U_FP32 = 2.0 ** -24
+# split BF16 products: an FP32 value as hi + lo (two BF16 terms) is within
+# 2^-17 of itself relative, and dropping lo*lo costs at most 2^-16 of a
+# product, so a split product carries the unit roundoff of a 16-bit format
+U_BF16X3 = 2.0 ** -16
 FP32_REL_BAR = 1e-5
 BAND_C = 2.0
 
 
 def unit_roundoff(mode: str) -> float:
-    return U_BF16 if mode == "mixed_bf16" else U_FP32
+    return {"mixed_bf16": U_BF16, "mixed_bf16x3": U_BF16X3}.get(mode, U_FP32)
 
 
 def band_norm(lam, mode: str, c: float = BAND_C) -> float:

@@ -64,7 +64,7 @@ def test_d8_forward_fp64_constructed(P, c3_4096):
     assert err <= TOL
 
 
-@pytest.mark.parametrize("mode", ["mixed_fp32", "mixed_bf16"])
+@pytest.mark.parametrize("mode", ["mixed_fp32", "mixed_bf16", "mixed_bf16x3"])
 def test_d8_forward_mixed_constructed(P, c3_4096, mode):
     s, u, lam, exact = c3_4096
     nrm = np.linalg.norm(exact)
@@ -76,6 +76,8 @@ def test_d8_forward_mixed_constructed(P, c3_4096, mode):
     assert info["status"] == 0
     if mode == "mixed_fp32":
         assert err <= bars.FP32_REL_BAR
+        assert err * nrm <= bars.mixed_bar_abs(lam, mode, nrm, info["est_rel_err"])
+    elif mode == "mixed_bf16x3":
         assert err * nrm <= bars.mixed_bar_abs(lam, mode, nrm, info["est_rel_err"])
     else:
         assert err * nrm <= band + 1e-9 * nrm

@@ -42,7 +42,7 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
 
 
-@pytest.mark.parametrize("mode,amp", [("mixed_fp32", 4.0), ("mixed_bf16", 2.0)])
+@pytest.mark.parametrize("mode,amp", [("mixed_fp32", 4.0), ("mixed_bf16", 2.0), ("mixed_bf16x3", 4.0)])
 @pytest.mark.parametrize("iters", [1, 2, 5])
 def test_ns_iterations_match_reference(P, mode, amp, iters):
     # No FP64 correction: the output is the Hermitian part of (X + X X_K)/2
@@ -103,6 +103,51 @@ def test_mixed_bf16_gue_within_band(P, n):
     assert err_abs <= bars.mixed_bar_abs(lam, "mixed_bf16", nrm, info["est_rel_err"])
 
 
+@pytest.mark.parametrize("n", [100, 200, 333])
+def test_mixed_bf16x3_gue(P, n):
+    # split-BF16 products: the band at 2 u ||X||_2 with u = 2^-16, plus twice
+    # the first-order estimate; and well inside the plain BF16 form's error
+    s = W.gue(n, 3150 + n)
+    print(f"mixed bf16x3 n={n}", flush=True)
+    y, info = P.project(dev(s), n, mode="mixed_bf16x3", info=True)
+    yb = P.project(dev(s), n, mode="mixed_bf16")
+    ref = oracle.project(s, n)
+    lam = np.linalg.eigvalsh(oracle.unpack(s, n))
+    nrm = np.linalg.norm(ref)
+    err_abs = np.linalg.norm(y.cpu().numpy() - ref)
+    eb = rel(yb.cpu().numpy(), ref)
+    print(f"  rel err {err_abs / nrm:.3e} (bf16 {eb:.3e}) est {info['est_rel_err']:.3e}", flush=True)
+    assert info["status"] == 0 and info["n_pos"] == int((lam > 0).sum())
+    assert err_abs <= bars.mixed_bar_abs(lam, "mixed_bf16x3", nrm, info["est_rel_err"])
+    assert err_abs / nrm <= 0.05 * eb
+    est = info["est_rel_err"]
+    assert est <= 100.0 * err_abs / nrm
+
+
+def test_mixed_bf16x3_batched_and_plan(P):
+    sizes = [100, 25, 70, 100]
+    parts = [W.gue(m, 3350 + i) for i, m in enumerate(sizes)]
+    x = dev(np.concatenate(parts))
+    y = P.project_batched(x, sizes, mode="mixed_bf16x3").cpu().numpy()
+    plan = P.Plan(sizes, "mixed_bf16x3")
+    yp = plan.execute(x).cpu().numpy()
+    plan.close()
+    off = 0
+    for m, s in zip(sizes, parts):
+        ref = oracle.project(s, m)
+        got = y[off:off + m * m]
+        if m <= 64:
+            assert rel(got, ref) <= 1e-10      # the exact LDS kernel
+        else:
+            lam = np.linalg.eigvalsh(oracle.unpack(s, m))
+            nrm = np.linalg.norm(ref)
+            assert np.linalg.norm(got - ref) <= bars.mixed_bar_abs(lam, "mixed_bf16x3", nrm, 1e-5)
+        single = P.project(dev(s), m, mode="mixed_bf16x3").cpu().numpy()
+        assert np.array_equal(got, single)                     # grouping does not change a member
+        assert np.array_equal(yp[off:off + m * m], single)     # nor does the graph
+        off += m * m
+
+
 def test_mixed_constructed_gap(P):
     n = 130
     sx, u, lam = W.constructed(n, 3200, gap=1e-3)
@@ -110,6 +155,10 @@ def test_mixed_constructed_gap(P):
     nrm = np.linalg.norm(exact)
     y32, i32 = P.project(dev(sx), n, mode="mixed_fp32", info=True)
     e32 = rel(y32.cpu().numpy(), exact)
+    yx, ix = P.project(dev(sx), n, mode="mixed_bf16x3", info=True)
+    ex = rel(yx.cpu().numpy(), exact)
+    print(f"constructed gap 1e-3: bf16x3 {ex:.3e} (est {ix['est_rel_err']:.2e})", flush=True)
+    assert ex * nrm <= bars.mixed_bar_abs(lam, "mixed_bf16x3", nrm, ix["est_rel_err"])
     yb, ib = P.project(dev(sx), n, mode="mixed_bf16", info=True)
     eb = rel(yb.cpu().numpy(), exact)
     band = bars.band_norm(lam, "mixed_bf16") / nrm
