@@ -261,6 +261,11 @@ def main():
     ap.add_argument("--counter-run", action="store_true",
                     help="only project the workload's inputs once (one step, no probes, no JSON line): the "
                          "program profiled by the rocprofv3 counter runs")
+    ap.add_argument("--scs-run", type=int, default=0, metavar="D",
+                    help="only run the SCS solver on the GYNI objective at local dimension D for --scs-iters "
+                         "iterations (no JSON line): the program profiled for the solver's kernel trace")
+    ap.add_argument("--scs-iters", type=int, default=5)
+    ap.add_argument("--scs-anderson", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device 3 times (counter calibration) and exit")
     args = ap.parse_args()
@@ -287,6 +292,16 @@ def main():
     import paper_2606_20519_amd as P
     from paper_2606_20519_amd import _lib
     from paper_2606_20519_amd import workloads as W
+
+    if args.scs_run:
+        d = args.scs_run
+        log(f"SCS run: d={d}, {args.scs_iters} iterations, Anderson memory {args.scs_anderson}")
+        g = torch.from_numpy(W.upper_pack(W.gyni_objective(d, 7))).to("cuda:0")
+        t = time.perf_counter()
+        r = P.scs_solve(g, d, eps=0.0, max_iters=args.scs_iters, anderson=args.scs_anderson, post=False)
+        torch.cuda.synchronize()
+        log(f"SCS run done: {r['iters']} iterations in {time.perf_counter() - t:.3f} s, tau {r['tau']:.6e}")
+        return
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
