@@ -308,14 +308,14 @@ def main():
     wl = args.workload
     mode = args.mode or ("mixed_bf16" if wl == "c3" else "fp64")
     extra = {}
-    corr = 1
-    P.set_ns_iterations(0, corr)  # automatic step count (scaled schedule)
+    corr = -1
+    P.set_ns_iterations(0, corr)  # automatic step count (scaled schedule) and corrections
     iters = 0
     if mode != "fp64":
         _, inf = P.project(torch.from_numpy(W.gue(100, 1)).to(dev), 100, mode, info=True)
         iters = inf["iters"]
         extra["ns_steps"] = iters
-        extra["fp64_corrections"] = corr
+        extra["fp64_corrections"] = 1 if mode == "mixed_bf16" else 0
 
     # ---- inputs (host, seeded) -> HBM
     log(f"workload {wl} mode {mode}: building inputs")
@@ -391,7 +391,7 @@ def main():
         else:
             flops_step = sum(flops_eig(n, k) for k in ks)
     else:
-        flops_step = sum(flops_ns(m, iters, corr) for m in sizes if m > 64)
+        flops_step = sum(flops_ns(m, iters, extra["fp64_corrections"]) for m in sizes if m > 64)
 
     if wl == "c4":
         # the autotuner picks the group size and the concurrency (outside

@@ -231,10 +231,13 @@ psd_status psd_timing_stop(double *ms, int32_t *launches, double *work);
  * sqrt(3/(1+l+l^2))) for the current lower bound l of the scaled spectrum,
  * starting from 1e-6); 0 (the default) = automatic, as many steps as bring
  * l within 1e-7 of 1 (21): eigenvalues down to about 1e-6 ||X||_2 resolved.
- * `corrections`: FP64 correction steps (>= 0, default 1: one squares the
- * eigenvalue error of the resolved components to below the subspace error
- * of the low-precision iterations, which no further step reduces).
- * Returns PSD_EINVAL outside 0..200 / 0..8. */
+ * `corrections`: FP64 correction steps S <- S (3I - S^2)/2 (0..8), or -1
+ * (the default) for automatic: 1 in BF16-mixed, 0 in FP32- and
+ * BF16x3-mixed.  A step squares S's eigenvalue error; the error of the
+ * result is set by the subspace error of the low-precision iterations,
+ * which no step reduces, so it only tightens the estimate's eigenvalue part
+ * where that error is large (BF16).
+ * Returns PSD_EINVAL outside 0..200 / -1..8. */
 psd_status psd_set_ns_iterations(int32_t iters, int32_t corrections);
 
 /* Affine step of the SCS iteration for the bipartite process-matrix SDP

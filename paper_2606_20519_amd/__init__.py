@@ -30,9 +30,10 @@ _ws_cache: dict = {}
 INFO_WORDS = ctypes.sizeof(PsdInfo) // 4
 
 
-def set_ns_iterations(iters: int = 0, corrections: int = 1):
+def set_ns_iterations(iters: int = 0, corrections: int = -1):
     """Newton-Schulz steps (0: automatic, the scaled schedule's 21) and FP64
-    correction steps of the mixed modes."""
+    correction steps of the mixed modes (-1: automatic, 1 for BF16 and 0 for
+    FP32 and split BF16)."""
     _lib.set_ns_iterations(iters, corrections)
 
 

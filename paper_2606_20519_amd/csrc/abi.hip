@@ -71,7 +71,7 @@ size_t large_ws_bytes(int n, int mode, int flags) {
 bool is_mixed(int mode) { return mode == PSD_MIXED_BF16 || mode == PSD_MIXED_FP32 || mode == PSD_MIXED_BF16X3; }
 
 int g_ns_iters = 0;  // automatic
-int g_ns_corr = 1;
+int g_ns_corr = -1;  // automatic: 1 for BF16, 0 for FP32 and split BF16
 double g_fallback_bound = 0.0;  // 0: no FP64 fallback of the mixed modes
 
 // Marks a record written by the FP64 path as the fallback of a mixed call.
@@ -301,7 +301,7 @@ extern "C" {
 const char *psd_version(void) { return "psdproj 0.1 (gfx950)"; }
 
 psd_status psd_set_ns_iterations(int32_t iters, int32_t corrections) {
-    if (iters < 0 || iters > 200 || corrections < 0 || corrections > 8) return PSD_EINVAL;
+    if (iters < 0 || iters > 200 || corrections < -1 || corrections > 8) return PSD_EINVAL;
     g_ns_iters = iters;
     g_ns_corr = corrections;
     return PSD_OK;

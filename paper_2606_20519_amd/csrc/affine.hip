@@ -116,21 +116,19 @@ __device__ __forceinline__ int gm_col(int d, int p, int *as_, cd *cs) {
 __device__ __forceinline__ int sector_of(int alpha, int beta) { return beta >= 1 ? 2 : (alpha >= 1 ? 1 : 0); }
 
 // Effect-like values q' = alpha' D (alpha' >= 1) below q (party index q = alpha D + beta).
-__device__ __forceinline__ int64_t effect_below(int D, int64_t q) {
-    return q > 0 ? std::min<int64_t>(D - 1, (q - 1) / D) : 0;
-}
+__device__ __forceinline__ int effect_below(int D, int q) { return q > 0 ? min(D - 1, (q - 1) / D) : 0; }
 
 // Rank of an allowed mu = (q1, q2), q = alpha D + beta, in the lexicographic
 // order of the allowed traceless multi-indices, or -1 if mu is not allowed.
 // Allowed sector pairs: (B,E), (E,B), (E,E), (E,T), (T,E); a first party in
 // B or T admits D - 1 second parties (the effect-like ones), one in E all D^2.
-__device__ __forceinline__ int64_t mu_rank(int D, int64_t q1, int64_t q2) {
-    const int s1 = sector_of((int)(q1 / D), (int)(q1 % D)), s2 = sector_of((int)(q2 / D), (int)(q2 % D));
+__device__ __forceinline__ int64_t mu_rank(int D, int q1, int q2) {
+    const int s1 = sector_of(q1 / D, q1 % D), s2 = sector_of(q2 / D, q2 % D);
     const bool ok = (s1 == 1) || (s2 == 1);  // some effect-like party (excludes (B,B), (B,T), (T,B), (T,T))
     if (!ok) return -1;
-    const int64_t nb = q1 > 0 ? 1 : 0, ne = effect_below(D, q1), nt = q1 - nb - ne;
-    const int64_t prefix = nb * (D - 1) + ne * (int64_t)D * D + nt * (D - 1);
-    const int64_t within = (s1 == 1) ? q2 : effect_below(D, q2);
+    const int nb = q1 > 0 ? 1 : 0, ne = effect_below(D, q1), nt = q1 - nb - ne;
+    const int prefix = nb * (D - 1) + ne * D * D + nt * (D - 1);   // < d^8 <= 2^24
+    const int within = (s1 == 1) ? q2 : effect_below(D, q2);
     return prefix + within;
 }
 
@@ -140,11 +138,11 @@ __global__ void __launch_bounds__(256) aff_unpack_kernel(const double *__restric
     if (t >= total) return;
     const int D = d * d, n = D * D;
     int a = 0, b = 0;
-    int64_t rem = t;
+    unsigned rem = (unsigned)t;   // d^8 <= 2^24
     int mul = 1;
     for (int m = 3; m >= 0; --m) {
-        const int p = (int)(rem % D);
-        rem /= D;
+        const int p = (int)(rem % (unsigned)D);
+        rem /= (unsigned)D;
         a += (p / d) * mul;
         b += (p % d) * mul;
         mul *= d;
@@ -163,22 +161,36 @@ __global__ void __launch_bounds__(256) aff_unpack_kernel(const double *__restric
     T[t] = v;
 }
 
-// One local transform along mode m (0 = most significant) of the D^4 tensor.
+// One local transform along mode m (0 = most significant) of the D^4 tensor
+// (d^8 <= 2^24 entries: 32-bit indices).  Each workgroup first tabulates the
+// nonzeros of the D rows of the local transform in LDS.
 __global__ void __launch_bounds__(256) aff_mode_kernel(const cd *__restrict__ in, cd *out, int d, int m, int adjoint,
-                                                       int64_t total) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= total) return;
+                                                       int total) {
+    __shared__ int tab_j[64][8];
+    __shared__ cd tab_c[64][8];
+    __shared__ int tab_n[64];
     const int D = d * d;
-    int64_t inner = 1;
-    for (int k = m + 1; k < 4; ++k) inner *= D;
-    const int64_t lo = t % inner, hi = t / inner;
-    const int idx = (int)(hi % D);
-    const int64_t base = (hi / D) * D * inner + lo;
-    int js[8];
-    cd cs[8];
-    const int cnt = adjoint ? gm_col(d, idx, js, cs) : gm_row(d, idx, js, cs);
+    for (int r = threadIdx.x; r < D; r += 256) {
+        int js[8];
+        cd cs[8];
+        const int c = adjoint ? gm_col(d, r, js, cs) : gm_row(d, r, js, cs);
+        tab_n[r] = c;
+        for (int q = 0; q < c; ++q) {
+            tab_j[r][q] = js[q];
+            tab_c[r][q] = cs[q];
+        }
+    }
+    __syncthreads();
+    const unsigned t = blockIdx.x * 256u + threadIdx.x;
+    if (t >= (unsigned)total) return;
+    unsigned inner = 1;
+    for (int k = m + 1; k < 4; ++k) inner *= (unsigned)D;
+    const unsigned hi = t / inner, lo = t - hi * inner;
+    const unsigned idx = hi % (unsigned)D;
+    const unsigned base = (hi - idx) * inner + lo;
+    const int cnt = tab_n[idx];
     cd acc = cmk(0.0, 0.0);
-    for (int q = 0; q < cnt; ++q) acc = cfma(cs[q], in[base + (int64_t)js[q] * inner], acc);
+    for (int q = 0; q < cnt; ++q) acc = cfma(tab_c[idx][q], in[base + (unsigned)tab_j[idx][q] * inner], acc);
     out[t] = acc;
 }
 
@@ -189,8 +201,8 @@ __global__ void __launch_bounds__(256) aff_gather_kernel(const cd *__restrict__ 
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= total) return;
     const int D = d * d;
-    const int64_t DD = (int64_t)D * D;
-    const int64_t r = mu_rank(D, t / DD, t % DD);
+    const unsigned DD = (unsigned)(D * D), tt = (unsigned)t;
+    const int64_t r = mu_rank(D, (int)(tt / DD), (int)(tt % DD));
     if (r < 0) return;
     const double v = c[t].x;
     x[r] = ax ? 0.5 * (ax[r] + v) : -v;
@@ -202,8 +214,8 @@ __global__ void __launch_bounds__(256) aff_scatter_kernel(const double *__restri
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (t >= total) return;
     const int D = d * d;
-    const int64_t DD = (int64_t)D * D;
-    const int64_t r = mu_rank(D, t / DD, t % DD);
+    const unsigned DD = (unsigned)(D * D), tt = (unsigned)t;
+    const int64_t r = mu_rank(D, (int)(tt / DD), (int)(tt % DD));
     c[t] = r < 0 ? cmk(0.0, 0.0) : cmk(coef * x[r], 0.0);
 }
 
@@ -215,11 +227,11 @@ __global__ void __launch_bounds__(256) aff_pack_kernel(const cd *__restrict__ T,
     if (t >= total) return;
     const int D = d * d, n = D * D;
     int a = 0, b = 0;
-    int64_t rem = t;
+    unsigned rem = (unsigned)t;   // d^8 <= 2^24
     int mul = 1;
     for (int m = 3; m >= 0; --m) {
-        const int p = (int)(rem % D);
-        rem /= D;
+        const int p = (int)(rem % (unsigned)D);
+        rem /= (unsigned)D;
         a += (p / d) * mul;
         b += (p % d) * mul;
         mul *= d;
@@ -240,7 +252,7 @@ __global__ void __launch_bounds__(256) aff_pack_kernel(const cd *__restrict__ T,
 hipError_t aff_modes(const AffGeo &g, cd *&cur, cd *&other, int adjoint, hipStream_t st) {
     const int grid = (int)((g.total + 255) / 256);
     for (int m = 0; m < 4; ++m) {
-        hipLaunchKernelGGL(aff_mode_kernel, dim3(grid), dim3(256), 0, st, cur, other, g.d, m, adjoint, g.total);
+        hipLaunchKernelGGL(aff_mode_kernel, dim3(grid), dim3(256), 0, st, cur, other, g.d, m, adjoint, (int)g.total);
         std::swap(cur, other);
     }
     return hipGetLastError();

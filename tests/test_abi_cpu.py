@@ -111,6 +111,8 @@ def test_setters_validate_on_host(L):
     assert lib.psd_set_ns_iterations(-1, 1) == 1
     assert lib.psd_set_ns_iterations(0, 9) == 1
     assert lib.psd_set_ns_iterations(0, 1) == 0
+    assert lib.psd_set_ns_iterations(0, -2) == 1
+    assert lib.psd_set_ns_iterations(0, -1) == 0      # automatic corrections
 
 
 def test_affine_host_validation(L):
