@@ -12,10 +12,11 @@
 // with y reindexed as a 4-mode tensor T[p_1, p_2, p_3, p_4], p_n = (a_n, b_n)
 // the row and column digits of subsystem n, tr[F_mu y] is the product of
 // four local transforms, one per mode, each a D x D matrix with at most d
-// nonzeros per row (s_alpha has 1, 2 or up to d entries).  Each transform is
-// one memory-bound pass over the d^8 complex entries; the allowed
-// coefficients are gathered to x (or scattered from it) by a closed-form
-// rank, and the svec is unpacked / packed in the first and last passes.
+// nonzeros per row (s_alpha has 1, 2 or up to d entries).  Each direction is
+// three memory-bound passes over the d^8 complex entries, each reading its
+// input once into LDS: modes 2 and 3 of one D x D block of y together (with
+// the svec unpack or pack), mode 1, and mode 0 (with the gather of the
+// allowed coefficients to x by a closed-form rank, or the scatter from x).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -132,151 +133,198 @@ __device__ __forceinline__ int64_t mu_rank(int D, int q1, int q2) {
     return prefix + within;
 }
 
-// y (svec, order n = d^4) -> T[p1, p2, p3, p4], p_m = a_m d + b_m.
-__global__ void __launch_bounds__(256) aff_unpack_kernel(const double *__restrict__ y, cd *T, int d, int64_t total) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= total) return;
-    const int D = d * d, n = D * D;
-    int a = 0, b = 0;
-    unsigned rem = (unsigned)t;   // d^8 <= 2^24
-    int mul = 1;
-    for (int m = 3; m >= 0; --m) {
-        const int p = (int)(rem % (unsigned)D);
-        rem /= (unsigned)D;
-        a += (p / d) * mul;
-        b += (p % d) * mul;
-        mul *= d;
-    }
-    const double rs2 = 0.70710678118654752440;
-    cd v;
-    if (a == b) {
-        v = cmk(y[svec_col_start(n, a)], 0.0);
-    } else if (a < b) {
-        const int64_t o = svec_off(n, b, a);  // y_ab, a < b: row a of the upper triangle
-        v = cmk(y[o] * rs2, y[o + 1] * rs2);
-    } else {
-        const int64_t o = svec_off(n, a, b);
-        v = cmk(y[o] * rs2, -y[o + 1] * rs2);
-    }
-    T[t] = v;
-}
+// Nonzeros of the D rows of one local transform (dir 0: the forward rows
+// gm_row, dir 1: the adjoint rows gm_col), tabulated in LDS by each
+// workgroup.
+struct AffTab {
+    int j[64][8];
+    cd c[64][8];
+    int n[64];
+};
 
-// One local transform along mode m (0 = most significant) of the D^4 tensor
-// (d^8 <= 2^24 entries: 32-bit indices).  Each workgroup first tabulates the
-// nonzeros of the D rows of the local transform in LDS.
-__global__ void __launch_bounds__(256) aff_mode_kernel(const cd *__restrict__ in, cd *out, int d, int m, int adjoint,
-                                                       int total) {
-    __shared__ int tab_j[64][8];
-    __shared__ cd tab_c[64][8];
-    __shared__ int tab_n[64];
+__device__ __forceinline__ void aff_build_tab(AffTab &T, int d, int dir) {
     const int D = d * d;
-    for (int r = threadIdx.x; r < D; r += 256) {
+    for (int r = threadIdx.x; r < D; r += blockDim.x) {
         int js[8];
         cd cs[8];
-        const int c = adjoint ? gm_col(d, r, js, cs) : gm_row(d, r, js, cs);
-        tab_n[r] = c;
+        const int c = dir ? gm_col(d, r, js, cs) : gm_row(d, r, js, cs);
+        T.n[r] = c;
         for (int q = 0; q < c; ++q) {
-            tab_j[r][q] = js[q];
-            tab_c[r][q] = cs[q];
+            T.j[r][q] = js[q];
+            T.c[r][q] = cs[q];
+        }
+    }
+}
+
+constexpr int AFF_T = 512;                 // threads per workgroup
+constexpr int AFF_PER = 4096 / AFF_T;      // tile entries per thread (D^2 <= 4096, D x 64 <= 4096)
+
+// Modes 2 and 3 of one slab T[p1, p2, :, :] (D^2 entries, contiguous in the
+// tensor), which is the D x D block of y with rows a = (a1 d + a2) D + a_lo
+// and columns b = (b1 d + b2) D + b_lo (p_m = a_m d + b_m; a_lo = a3 d + a4,
+// b_lo = b3 d + b4).  dir 0: the block is read from the svec (upper rows,
+// conjugated below the diagonal), transformed by the forward rows and
+// written to the tensor.  dir 1: the tensor slab is transformed by the
+// adjoint rows and its upper part written to the svec, y = base + result
+// (base nullable); a block strictly below the diagonal is left to its
+// mirror.  One workgroup per slab; the block stays in LDS (64 KiB at d = 8,
+// two workgroups per CU), each mode's results staged in registers.
+__global__ void __launch_bounds__(AFF_T) aff_slab_kernel(const double *__restrict__ ysv, const cd *__restrict__ tin,
+                                                         cd *tout, const double *base, double *yout, int d, int dir) {
+    __shared__ cd S[4096];
+    __shared__ AffTab tab;
+    const int D = d * d, n = D * D, DD = D * D;
+    const int slab = blockIdx.x;
+    const int p1 = slab / D, p2 = slab - p1 * D;
+    const int a1 = p1 / d, b1 = p1 - a1 * d, a2 = p2 / d, b2 = p2 - a2 * d;
+    const int A0 = (a1 * d + a2) * D, B0 = (b1 * d + b2) * D;
+    const double rs2 = 0.70710678118654752440, rt2 = 1.41421356237309504880;
+    aff_build_tab(tab, d, dir);
+    const int tid = threadIdx.x;
+    if (dir == 0) {
+        for (int e = tid; e < DD; e += AFF_T) {
+            // consecutive threads walk a stored svec row
+            int al, bl;
+            if (A0 > B0) { bl = e / D; al = e - bl * D; }
+            else { al = e / D; bl = e - al * D; }
+            const int a = A0 + al, b = B0 + bl;
+            cd v;
+            if (a == b) {
+                v = cmk(ysv[svec_col_start(n, a)], 0.0);
+            } else if (a < b) {
+                const int64_t o = svec_off(n, b, a);
+                v = cmk(ysv[o] * rs2, ysv[o + 1] * rs2);
+            } else {
+                const int64_t o = svec_off(n, a, b);
+                v = cmk(ysv[o] * rs2, -ysv[o + 1] * rs2);
+            }
+            const int a3 = al / d, a4 = al - a3 * d, b3 = bl / d, b4 = bl - b3 * d;
+            S[(a3 * d + b3) * D + (a4 * d + b4)] = v;
+        }
+    } else {
+        for (int e = tid; e < DD; e += AFF_T) S[e] = tin[(int64_t)slab * DD + e];
+    }
+    __syncthreads();
+    cd acc[AFF_PER];
+#pragma unroll
+    for (int k = 0; k < AFF_PER; ++k) {  // mode 3
+        const int e = tid + k * AFF_T;
+        acc[k] = cmk(0.0, 0.0);
+        if (e < DD) {
+            const int r = e / D, o = e - r * D;
+            for (int q = 0; q < tab.n[o]; ++q) acc[k] = cfma(tab.c[o][q], S[r * D + tab.j[o][q]], acc[k]);
         }
     }
     __syncthreads();
-    const unsigned t = blockIdx.x * 256u + threadIdx.x;
-    if (t >= (unsigned)total) return;
-    unsigned inner = 1;
-    for (int k = m + 1; k < 4; ++k) inner *= (unsigned)D;
-    const unsigned hi = t / inner, lo = t - hi * inner;
-    const unsigned idx = hi % (unsigned)D;
-    const unsigned base = (hi - idx) * inner + lo;
-    const int cnt = tab_n[idx];
-    cd acc = cmk(0.0, 0.0);
-    for (int q = 0; q < cnt; ++q) acc = cfma(tab_c[idx][q], in[base + (unsigned)tab_j[idx][q] * inner], acc);
-    out[t] = acc;
-}
-
-// Allowed coefficients of c = tr[F_mu y] to x: x = -Re c (A^T y), or
-// x = (a_x + Re c)/2 (the affine step's z_x, with A^T a_y = -c).
-__global__ void __launch_bounds__(256) aff_gather_kernel(const cd *__restrict__ c, const double *__restrict__ ax,
-                                                         double *x, int d, int64_t total) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= total) return;
-    const int D = d * d;
-    const unsigned DD = (unsigned)(D * D), tt = (unsigned)t;
-    const int64_t r = mu_rank(D, (int)(tt / DD), (int)(tt % DD));
-    if (r < 0) return;
-    const double v = c[t].x;
-    x[r] = ax ? 0.5 * (ax[r] + v) : -v;
-}
-
-// c[mu] = coef x[rank(mu)] for allowed mu, 0 elsewhere.
-__global__ void __launch_bounds__(256) aff_scatter_kernel(const double *__restrict__ x, cd *c, int d, double coef,
-                                                          int64_t total) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= total) return;
-    const int D = d * d;
-    const unsigned DD = (unsigned)(D * D), tt = (unsigned)t;
-    const int64_t r = mu_rank(D, (int)(tt / DD), (int)(tt % DD));
-    c[t] = r < 0 ? cmk(0.0, 0.0) : cmk(coef * x[r], 0.0);
-}
-
-// T -> y (svec), y = base + T (base nullable): each svec entry once, from
-// the tensor entry of (a, b), a <= b.
-__global__ void __launch_bounds__(256) aff_pack_kernel(const cd *__restrict__ T, const double *base, double *y, int d,
-                                                       int64_t total) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (t >= total) return;
-    const int D = d * d, n = D * D;
-    int a = 0, b = 0;
-    unsigned rem = (unsigned)t;   // d^8 <= 2^24
-    int mul = 1;
-    for (int m = 3; m >= 0; --m) {
-        const int p = (int)(rem % (unsigned)D);
-        rem /= (unsigned)D;
-        a += (p / d) * mul;
-        b += (p % d) * mul;
-        mul *= d;
+#pragma unroll
+    for (int k = 0; k < AFF_PER; ++k)
+        if (tid + k * AFF_T < DD) S[tid + k * AFF_T] = acc[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < AFF_PER; ++k) {  // mode 2
+        const int e = tid + k * AFF_T;
+        acc[k] = cmk(0.0, 0.0);
+        if (e < DD) {
+            const int o = e / D, c = e - o * D;
+            for (int q = 0; q < tab.n[o]; ++q) acc[k] = cfma(tab.c[o][q], S[tab.j[o][q] * D + c], acc[k]);
+            if (dir == 0) tout[(int64_t)slab * DD + e] = acc[k];
+        }
     }
-    if (a > b) return;
-    const double rt2 = 1.41421356237309504880;
-    const cd v = T[t];
-    if (a == b) {
-        const int64_t o = svec_col_start(n, a);
-        y[o] = (base ? base[o] : 0.0) + v.x;
-    } else {
-        const int64_t o = svec_off(n, b, a);
-        y[o] = (base ? base[o] : 0.0) + rt2 * v.x;
-        y[o + 1] = (base ? base[o + 1] : 0.0) + rt2 * v.y;
+    if (dir == 0 || A0 > B0) return;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < AFF_PER; ++k)
+        if (tid + k * AFF_T < DD) S[tid + k * AFF_T] = acc[k];
+    __syncthreads();
+    for (int e = tid; e < DD; e += AFF_T) {
+        const int al = e / D, bl = e - al * D;
+        const int a = A0 + al, b = B0 + bl;
+        if (a > b) continue;
+        const int a3 = al / d, a4 = al - a3 * d, b3 = bl / d, b4 = bl - b3 * d;
+        const cd v = S[(a3 * d + b3) * D + (a4 * d + b4)];
+        if (a == b) {
+            const int64_t o = svec_col_start(n, a);
+            yout[o] = (base ? base[o] : 0.0) + v.x;
+        } else {
+            const int64_t o = svec_off(n, b, a);
+            yout[o] = (base ? base[o] : 0.0) + rt2 * v.x;
+            yout[o + 1] = (base ? base[o + 1] : 0.0) + rt2 * v.y;
+        }
     }
 }
 
-hipError_t aff_modes(const AffGeo &g, cd *&cur, cd *&other, int adjoint, hipStream_t st) {
-    const int grid = (int)((g.total + 255) / 256);
-    for (int m = 0; m < 4; ++m) {
-        hipLaunchKernelGGL(aff_mode_kernel, dim3(grid), dim3(256), 0, st, cur, other, g.d, m, adjoint, (int)g.total);
-        std::swap(cur, other);
+// Mode m in {0, 1} of the tensor viewed as [H][D][R] (R = D^(3-m)): one
+// workgroup per (h, 64 consecutive r), the D x 64 tile read once into LDS.
+// Mode 0, dir 0 also gathers the allowed coefficients to x:
+// x = -Re c (A^T y), or (a_x + Re c)/2 with a_x given; mode 0, dir 1 reads
+// its input from x (coefficient -1 at the allowed indices, 0 elsewhere)
+// instead of a tensor.
+__global__ void __launch_bounds__(AFF_T) aff_outer_kernel(const cd *__restrict__ tin, cd *tout,
+                                                          const double *__restrict__ xin, const double *ax,
+                                                          double *xout, int d, int m, int dir) {
+    __shared__ cd tile[64][64];
+    __shared__ AffTab tab;
+    const int D = d * d, DD = D * D;
+    const int R = m == 0 ? DD * D : DD;
+    const int ntr = (R + 63) / 64;
+    const int h = blockIdx.x / ntr, r0 = (blockIdx.x - h * ntr) * 64;
+    aff_build_tab(tab, d, dir);
+    const int tid = threadIdx.x;
+    for (int e = tid; e < D * 64; e += AFF_T) {
+        const int j = e >> 6, r = e & 63;
+        if (r0 + r >= R) continue;
+        const unsigned t = (unsigned)(h * D + j) * (unsigned)R + (unsigned)(r0 + r);
+        cd v;
+        if (m == 0 && dir == 1) {
+            const int64_t rk = mu_rank(D, (int)(t / DD), (int)(t % DD));
+            v = rk < 0 ? cmk(0.0, 0.0) : cmk(-xin[rk], 0.0);
+        } else {
+            v = tin[t];
+        }
+        tile[j][r] = v;
     }
-    return hipGetLastError();
+    __syncthreads();
+    for (int e = tid; e < D * 64; e += AFF_T) {
+        const int o = e >> 6, r = e & 63;
+        if (r0 + r >= R) continue;
+        cd acc = cmk(0.0, 0.0);
+        for (int q = 0; q < tab.n[o]; ++q) acc = cfma(tab.c[o][q], tile[tab.j[o][q]][r], acc);
+        const unsigned t = (unsigned)(h * D + o) * (unsigned)R + (unsigned)(r0 + r);
+        if (m == 0 && dir == 0) {
+            const int64_t rk = mu_rank(D, (int)(t / DD), (int)(t % DD));
+            if (rk >= 0) xout[rk] = ax ? 0.5 * (ax[rk] + acc.x) : -acc.x;
+        } else {
+            tout[t] = acc;
+        }
+    }
 }
 
-// x = A^T y, or z_x = (a_x - A^T y)/2 when ax is given.  Leaves the buffers swapped.
+int aff_outer_grid(const AffGeo &g, int m) {
+    const int R = m == 0 ? g.D * g.D * g.D : g.D * g.D;
+    return (m == 0 ? 1 : g.D) * ((R + 63) / 64);
+}
+
+// x = A^T y, or z_x = (a_x - A^T y)/2 when ax is given: modes 3 and 2 with
+// the svec unpack, mode 1, mode 0 with the gather.
 hipError_t aff_adjoint(const AffGeo &g, const double *y, const double *ax, double *x, cd *b0, cd *b1, hipStream_t st) {
-    const int grid = (int)((g.total + 255) / 256);
-    hipLaunchKernelGGL(aff_unpack_kernel, dim3(grid), dim3(256), 0, st, y, b0, g.d, g.total);
-    cd *cur = b0, *other = b1;
-    hipError_t e = aff_modes(g, cur, other, 0, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(aff_gather_kernel, dim3(grid), dim3(256), 0, st, cur, ax, x, g.d, g.total);
+    hipLaunchKernelGGL(aff_slab_kernel, dim3(g.D * g.D), dim3(AFF_T), 0, st, y, (const cd *)nullptr, b0,
+                       (const double *)nullptr, (double *)nullptr, g.d, 0);
+    hipLaunchKernelGGL(aff_outer_kernel, dim3(aff_outer_grid(g, 1)), dim3(AFF_T), 0, st, b0, b1, (const double *)nullptr,
+                       (const double *)nullptr, (double *)nullptr, g.d, 1, 0);
+    hipLaunchKernelGGL(aff_outer_kernel, dim3(aff_outer_grid(g, 0)), dim3(AFF_T), 0, st, b1, (cd *)nullptr,
+                       (const double *)nullptr, ax, x, g.d, 0, 0);
     return hipGetLastError();
 }
 
-// y = base + A x (base nullable).
+// y = base + A x (base nullable): mode 0 with the scatter, mode 1, modes 2
+// and 3 with the svec pack.
 hipError_t aff_apply(const AffGeo &g, const double *x, const double *base, double *y, cd *b0, cd *b1, hipStream_t st) {
-    const int grid = (int)((g.total + 255) / 256);
-    hipLaunchKernelGGL(aff_scatter_kernel, dim3(grid), dim3(256), 0, st, x, b0, g.d, -1.0, g.total);
-    cd *cur = b0, *other = b1;
-    hipError_t e = aff_modes(g, cur, other, 1, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(aff_pack_kernel, dim3(grid), dim3(256), 0, st, cur, base, y, g.d, g.total);
+    hipLaunchKernelGGL(aff_outer_kernel, dim3(aff_outer_grid(g, 0)), dim3(AFF_T), 0, st, (const cd *)nullptr, b0, x,
+                       (const double *)nullptr, (double *)nullptr, g.d, 0, 1);
+    hipLaunchKernelGGL(aff_outer_kernel, dim3(aff_outer_grid(g, 1)), dim3(AFF_T), 0, st, b0, b1, (const double *)nullptr,
+                       (const double *)nullptr, (double *)nullptr, g.d, 1, 1);
+    hipLaunchKernelGGL(aff_slab_kernel, dim3(g.D * g.D), dim3(AFF_T), 0, st, (const double *)nullptr, b1, (cd *)nullptr,
+                       base, y, g.d, 1);
     return hipGetLastError();
 }
 
