@@ -641,13 +641,15 @@ constexpr int NS_PART_FLOATS = 32768;  // raw accumulators of one tile part
 
 // Tail split of the 128x128 path for an npad x npad product (per block:
 // independent of the group size, so group members match single calls).
-void ns_tail_plan(int npad, int *ntile, int *tfull, int *rem, int *split) {
+// slots: resident workgroups of the kernel (NS_SLOTS for BF16; half for the
+// split-BF16 form, whose doubled LDS ring leaves one workgroup per CU).
+void ns_tail_plan(int npad, int *ntile, int *tfull, int *rem, int *split, int slots = NS_SLOTS) {
     const int m = (npad + 127) / 128, T = m * (m + 1) / 2;
-    int r = T > NS_SLOTS ? T % NS_SLOTS : 0;
-    if (r > NS_SLOTS / 4) r = 0;
+    int r = T > slots ? T % slots : 0;
+    if (r > slots / 4) r = 0;
     *ntile = T;
     *rem = r;
-    *split = r ? std::min(16, NS_SLOTS / r) : 1;
+    *split = r ? std::min(16, slots / r) : 1;
     *tfull = T - r;
 }
 
@@ -670,30 +672,46 @@ __device__ __forceinline__ void ns_tile_ij(int tb, int &ti, int &tj) {
 // Epilogue of one 16x16 block at (ib, jb) as in ns_gemm_kernel: the lower
 // part with its conjugate mirror; blocks strictly below the diagonal write
 // four consecutive rows per lane as one 8-byte store.
+template <int SPLIT = 1>
 __device__ __forceinline__ void ns128_store_block(const v4f &accr, const v4f &acci, int ib, int jb, int lane, int npad,
                                                   int epi, float c, __bf16 *Cre, __bf16 *Cim, double2 *C64,
-                                                  int64_t ld64, int n) {
+                                                  int64_t ld64, int n, int64_t lo_off = 0) {
     if (ib < jb || ib >= npad) return;
     const int ir = ib + 4 * (lane >> 4), j = jb + (lane & 15);
     if (epi != NS_EPI_F64 && ib > jb) {
-        union { __bf16 h[4]; uint2 u; } pr, pi, pn;
+        union { __bf16 h[4]; uint2 u; } pr, pi, pn, qr, qi, qn;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             float re = accr[v], im = acci[v];
             if (epi == NS_EPI_T) { re = -c * re; im = -c * im; }
             else { re *= c; im *= c; }
-            pr.h[v] = (__bf16)re;
-            pi.h[v] = (__bf16)im;
-            pn.h[v] = (__bf16)(-im);
+            if constexpr (SPLIT == 2) {
+                bf16_split(re, pr.h[v], qr.h[v]);
+                bf16_split(im, pi.h[v], qi.h[v]);
+                pn.h[v] = -pi.h[v];
+                qn.h[v] = -qi.h[v];
+            } else {
+                pr.h[v] = (__bf16)re;
+                pi.h[v] = (__bf16)im;
+                pn.h[v] = (__bf16)(-im);
+            }
         }
         const int64_t o = (int64_t)ir + (int64_t)j * npad;
         *reinterpret_cast<uint2 *>(Cre + o) = pr.u;
         *reinterpret_cast<uint2 *>(Cim + o) = pi.u;
+        if constexpr (SPLIT == 2) {
+            *reinterpret_cast<uint2 *>(Cre + lo_off + o) = qr.u;
+            *reinterpret_cast<uint2 *>(Cim + lo_off + o) = qi.u;
+        }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int64_t om = (int64_t)j + (int64_t)(ir + v) * npad;
             Cre[om] = pr.h[v];
             Cim[om] = pn.h[v];
+            if constexpr (SPLIT == 2) {
+                Cre[lo_off + om] = qr.h[v];
+                Cim[lo_off + om] = qn.h[v];
+            }
         }
         return;
     }
@@ -706,10 +724,20 @@ __device__ __forceinline__ void ns128_store_block(const v4f &accr, const v4f &ac
         else { re *= c; im *= c; }
         if (i == j) im = 0.0f;
         if (epi != NS_EPI_F64) {
-            const __bf16 lr = (__bf16)re, li = (__bf16)im, lni = (__bf16)(-im);
             const int64_t o = (int64_t)i + (int64_t)j * npad, om = (int64_t)j + (int64_t)i * npad;
-            Cre[o] = lr; Cim[o] = li;
-            Cre[om] = lr; Cim[om] = lni;
+            if constexpr (SPLIT == 2) {
+                __bf16 hr, lr, hi, li;
+                bf16_split(re, hr, lr);
+                bf16_split(im, hi, li);
+                Cre[o] = hr; Cim[o] = hi;
+                Cre[om] = hr; Cim[om] = -hi;
+                Cre[lo_off + o] = lr; Cim[lo_off + o] = li;
+                Cre[lo_off + om] = lr; Cim[lo_off + om] = -li;
+            } else {
+                const __bf16 lr = (__bf16)re, li = (__bf16)im, lni = (__bf16)(-im);
+                Cre[o] = lr; Cim[o] = li;
+                Cre[om] = lr; Cim[om] = lni;
+            }
         } else if (i < n && j < n) {
             C64[i + (int64_t)j * ld64] = cmk((double)re, (double)im);
             C64[j + (int64_t)i * ld64] = cmk((double)re, -(double)im);
@@ -719,10 +747,18 @@ __device__ __forceinline__ void ns128_store_block(const v4f &accr, const v4f &ac
 
 // Workgroups g < tfull: whole tiles (XCD-aware order); the rest: part
 // (g - tfull) % split of tail tile tfull + (g - tfull) / split.
-__global__ void __launch_bounds__(256, 2) ns_gemm128_kernel(const __bf16 *Are, const __bf16 *Aim, const __bf16 *Bre,
-                                                            const __bf16 *Bim, int npad, int epi, float c, __bf16 *Cre,
-                                                            __bf16 *Cim, double2 *C64, int64_t ld64, int n, int tfull,
-                                                            int split, float *part, int64_t zs) {
+// SPLIT = 2: the split-BF16 products (see ns_gemm_kernel): every wave also
+// streams the lo plane of its operand plane (lo_off elements on) into a
+// second half of the ring, and each real product takes three MFMAs; the
+// ring doubles to 128 KiB, one workgroup per CU.
+template <int SPLIT>
+__global__ void __launch_bounds__(256, 3 - SPLIT) ns_gemm128_kernel(const __bf16 *Are, const __bf16 *Aim,
+                                                                   const __bf16 *Bre, const __bf16 *Bim, int npad,
+                                                                   int epi, float c, __bf16 *Cre, __bf16 *Cim,
+                                                                   double2 *C64, int64_t ld64, int n, int tfull,
+                                                                   int split, float *part, int64_t zs,
+                                                                   int64_t lo_off) {
+    constexpr bool X3 = SPLIT == 2;
     {
         const int mb = blockIdx.z;
         Are = member_ptr(Are, zs, mb);
@@ -734,8 +770,8 @@ __global__ void __launch_bounds__(256, 2) ns_gemm128_kernel(const __bf16 *Are, c
         C64 = member_ptr(C64, zs, mb);
         part = member_ptr(part, zs, mb);
     }
-    // [slot][plane: Re A, Im A, Re B, Im B][128 rows x 64 bytes, swizzled]
-    __shared__ __align__(16) char lds[2][4][8192];
+    // [slot][plane: Re A, Im A, Re B, Im B (then their lo terms)][128 rows x 64 bytes, swizzled]
+    __shared__ __align__(16) char lds[2][4 * SPLIT][8192];
     const int g = blockIdx.x;
     const int q = g < tfull ? -1 : g - tfull;
     const int tb = q < 0 ? xcd_tile(g, tfull) : tfull + q / split;
@@ -770,9 +806,13 @@ __global__ void __launch_bounds__(256, 2) ns_gemm128_kernel(const __bf16 *Are, c
     const unsigned lds0 = (unsigned)(size_t)(__attribute__((address_space(3))) char *)&lds[0][w][0];
 #define NS128_ISSUE(ST)                                                          \
     {                                                                            \
-        const unsigned dst = lds0 + (unsigned)((ST) & 1) * (4 * 8192);           \
+        const unsigned dst = lds0 + (unsigned)((ST) & 1) * (4 * SPLIT * 8192);   \
         const __bf16 *s0 = src + (ST) * 32;                                      \
         _Pragma("unroll") for (int p = 0; p < 8; ++p) dma16(s0 + goff[p], dst + p * 1024); \
+        if constexpr (X3) {                                                      \
+            _Pragma("unroll") for (int p = 0; p < 8; ++p)                        \
+                dma16(s0 + lo_off + goff[p], dst + 4 * 8192 + p * 1024);         \
+        }                                                                        \
     }
     if (kbeg < kend) NS128_ISSUE(kbeg)
     const int ii = lane & 15, kg = lane >> 4;
@@ -783,12 +823,16 @@ __global__ void __launch_bounds__(256, 2) ns_gemm128_kernel(const __bf16 *Are, c
         if (s + 1 < kend) NS128_ISSUE(s + 1)
         if (!idle) {
             const char *bA = &lds[s & 1][0][0];
-            v8bf br[4], bi[4];
+            v8bf br[4], bi[4], brl[4], bil[4];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const int off = (wn * 64 + b * 16 + ii) * 64 + rsw;
                 br[b] = *reinterpret_cast<const v8bf *>(bA + 2 * 8192 + off);
                 bi[b] = *reinterpret_cast<const v8bf *>(bA + 3 * 8192 + off);
+                if constexpr (X3) {
+                    brl[b] = *reinterpret_cast<const v8bf *>(bA + 6 * 8192 + off);
+                    bil[b] = *reinterpret_cast<const v8bf *>(bA + 7 * 8192 + off);
+                }
             }
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
@@ -800,6 +844,25 @@ __global__ void __launch_bounds__(256, 2) ns_gemm128_kernel(const __bf16 *Are, c
                 const v8bf ai = *reinterpret_cast<const v8bf *>(&u);
                 u.x ^= 0x80008000u; u.y ^= 0x80008000u; u.z ^= 0x80008000u; u.w ^= 0x80008000u;
                 const v8bf ain = *reinterpret_cast<const v8bf *>(&u);
+                if constexpr (X3) {
+                    // lo terms of the A fragment, then the cross terms (the small ones first)
+                    const v8bf arl = *reinterpret_cast<const v8bf *>(bA + 4 * 8192 + off);
+                    uint4 ul = *reinterpret_cast<const uint4 *>(bA + 5 * 8192 + off);
+                    const v8bf ail = *reinterpret_cast<const v8bf *>(&ul);
+                    ul.x ^= 0x80008000u; ul.y ^= 0x80008000u; ul.z ^= 0x80008000u; ul.w ^= 0x80008000u;
+                    const v8bf ainl = *reinterpret_cast<const v8bf *>(&ul);
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        accr[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, brl[b], accr[a][b], 0, 0, 0);
+                        accr[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, br[b], accr[a][b], 0, 0, 0);
+                        accr[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ai, bil[b], accr[a][b], 0, 0, 0);
+                        accr[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ail, bi[b], accr[a][b], 0, 0, 0);
+                        acci[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, bil[b], acci[a][b], 0, 0, 0);
+                        acci[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(arl, bi[b], acci[a][b], 0, 0, 0);
+                        acci[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ain, brl[b], acci[a][b], 0, 0, 0);
+                        acci[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ainl, br[b], acci[a][b], 0, 0, 0);
+                    }
+                }
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     accr[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ar, br[b], accr[a][b], 0, 0, 0);
@@ -830,16 +893,17 @@ __global__ void __launch_bounds__(256, 2) ns_gemm128_kernel(const __bf16 *Are, c
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b)
-            ns128_store_block(accr[a][b], acci[a][b], i0 + wm * 64 + a * 16, j0 + wn * 64 + b * 16, lane, npad, epi, c,
-                              Cre, Cim, C64, ld64, n);
+            ns128_store_block<SPLIT>(accr[a][b], acci[a][b], i0 + wm * 64 + a * 16, j0 + wn * 64 + b * 16, lane,
+                                     npad, epi, c, Cre, Cim, C64, ld64, n, lo_off);
 }
 
 // Tail tile tfull + blockIdx.x: its split partials summed in part order,
 // then the epilogue; workgroup y covers the 16x16 block (a, b) = (y / 4,
 // y % 4) of every wave.
+template <int SPLIT>
 __global__ void __launch_bounds__(256) ns128_tail_kernel(const float *__restrict__ part, int tfull, int split, int npad,
                                                          int epi, float c, __bf16 *Cre, __bf16 *Cim, double2 *C64,
-                                                         int64_t ld64, int n, int64_t zs) {
+                                                         int64_t ld64, int n, int64_t zs, int64_t lo_off) {
     {
         const int mb = blockIdx.z;
         part = member_ptr(part, zs, mb);
@@ -859,7 +923,8 @@ __global__ void __launch_bounds__(256) ns128_tail_kernel(const float *__restrict
         re += *reinterpret_cast<const v4f *>(pp + (int64_t)p * NS_PART_FLOATS);
         im += *reinterpret_cast<const v4f *>(pp + (int64_t)p * NS_PART_FLOATS + NS_PART_FLOATS / 2);
     }
-    ns128_store_block(re, im, i0 + wm * 64 + a * 16, j0 + wn * 64 + b * 16, lane, npad, epi, c, Cre, Cim, C64, ld64, n);
+    ns128_store_block<SPLIT>(re, im, i0 + wm * 64 + a * 16, j0 + wn * 64 + b * 16, lane, npad, epi, c, Cre, Cim, C64,
+                             ld64, n, lo_off);
 }
 
 // Assembly of Pi = X/2 + (X S + S X)/4 from F = X S (full FP64 product):
@@ -1028,23 +1093,23 @@ hipError_t ns_run(const MixedWs &w, const double *x, double *y, psd_dev_info *in
     // the 64x64 tile (the choice depends on npad and the threshold only, so
     // that group members match single-block calls bit for bit under the
     // same threshold)
-    const bool big = SPLIT == 1 && sizeof(L) == 2 && npad >= w.ns_big;
+    const bool big = sizeof(L) == 2 && npad >= w.ns_big;
     int ntile, tfull, rem, split;
-    if (big) ns_tail_plan(npad, &ntile, &tfull, &rem, &split);
+    if (big) ns_tail_plan(npad, &ntile, &tfull, &rem, &split, NS_SLOTS / SPLIT);
     else { const int mt = npad / 64; ntile = mt * (mt + 1) / 2; tfull = ntile; rem = 0; split = 1; }
     // algorithmic count: the n (n + 1) / 2 lower entries of an order-n
     // Hermitian product, n complex multiply-adds (8 flops) each
     const double ns_flops = 8.0 * (double)n * (double)n * (double)(n + 1) / 2.0 * B;
     auto product = [&](const L *A, const L *Bm, int epi, float cf, L *C, double2 *C64) {
         const int slot = timing_begin(KF_NS, st);
-        if constexpr (sizeof(L) == 2 && SPLIT == 1) {
+        if constexpr (sizeof(L) == 2) {
             if (big) {
-                hipLaunchKernelGGL(ns_gemm128_kernel, dim3(tfull + rem * split, 1, B), dim3(256), 0, st, A, A + plane,
-                                   Bm, Bm + plane, npad, epi, cf, C, C + plane, C64, w.lda, n, tfull, split, w.part,
-                                   zs);
+                hipLaunchKernelGGL(ns_gemm128_kernel<SPLIT>, dim3(tfull + rem * split, 1, B), dim3(256), 0, st, A,
+                                   A + plane, Bm, Bm + plane, npad, epi, cf, C, C + plane, C64, w.lda, n, tfull, split,
+                                   w.part, zs, lo_off);
                 if (rem)
-                    hipLaunchKernelGGL(ns128_tail_kernel, dim3(rem, 16, B), dim3(256), 0, st, w.part, tfull, split, npad,
-                                       epi, cf, C, C + plane, C64, w.lda, n, zs);
+                    hipLaunchKernelGGL(ns128_tail_kernel<SPLIT>, dim3(rem, 16, B), dim3(256), 0, st, w.part, tfull,
+                                       split, npad, epi, cf, C, C + plane, C64, w.lda, n, zs, lo_off);
                 timing_end(slot, st, ns_flops);
                 return;
             }
@@ -1136,9 +1201,9 @@ size_t mixed_layout(int n, int mode, void *base, MixedWs *w) {
     }
     W.part = nullptr;
     W.ns_big = NS_BIG;
-    if (mode == 1 && W.npad >= NS_BIG) {
+    if ((mode == 1 || mode == 3) && W.npad >= NS_BIG) {
         int ntile, tfull, rem, split;
-        ns_tail_plan(W.npad, &ntile, &tfull, &rem, &split);
+        ns_tail_plan(W.npad, &ntile, &tfull, &rem, &split, mode == 3 ? NS_SLOTS / 2 : NS_SLOTS);
         if (rem) W.part = (float *)take(sizeof(float) * NS_PART_FLOATS * (size_t)rem * split);
     }
     W.nmem = 1;

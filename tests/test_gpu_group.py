@@ -120,18 +120,33 @@ def test_mixed_bf16_group_many_members(P):
             assert np.array_equal(got, P.project(dev(s), n, "mixed_bf16").cpu().numpy()), i
 
 
-def test_mixed_bf16_group_large_orders(P):
+@pytest.mark.parametrize("mode", ["mixed_bf16", "mixed_bf16x3"])
+def test_mixed_bf16_group_large_orders(P, mode):
     # orders on the 128x128-tile product: two members of order 4000 (split
     # tail, ragged last tile row) and one of 2100, each bitwise equal to its
     # single-block call (the tile form depends on the order only)
     sizes = [4000, 2100, 4000]
     parts = [W.gue(m, 7400 + i) for i, m in enumerate(sizes)]
-    y, infos = P.project_batched(dev(np.concatenate(parts)), sizes, "mixed_bf16", info=True)
+    y, infos = P.project_batched(dev(np.concatenate(parts)), sizes, mode, info=True)
     y = y.cpu().numpy()
     off = 0
     for i, (m, s, inf) in enumerate(zip(sizes, parts, infos)):
-        single, sinf = P.project(dev(s), m, "mixed_bf16", info=True)
+        single, sinf = P.project(dev(s), m, mode, info=True)
         assert np.array_equal(y[off:off + m * m], single.cpu().numpy()), (i, m)
         assert inf == sinf, i
         assert inf["status"] == 0
         off += m * m
+
+
+def test_mixed_bf16x3_large_order_closed_form(P):
+    # the split 128x128-tile product at order 2100 (ragged last tile row)
+    # against the closed form, within the split form's band bar
+    n = 2100
+    s, u, lam = W.constructed(n, 7450, gap=1e-6)
+    exact = oracle.constructed_projection(u, lam)
+    y, inf = P.project(dev(s), n, "mixed_bf16x3", info=True)
+    err = np.linalg.norm(y.cpu().numpy() - exact)
+    nrm = np.linalg.norm(exact)
+    print(f"bf16x3 n=2100: rel err {err / nrm:.3e} est {inf['est_rel_err']:.3e}", flush=True)
+    assert inf["status"] == 0
+    assert err <= bars.mixed_bar_abs(lam, "mixed_bf16x3", nrm, inf["est_rel_err"])
