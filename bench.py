@@ -141,6 +141,8 @@ def mfma_roofline(fp64_gemm, mode, n, timed):
     npad = (n + 63) // 64 * 64
     kname = ("ns_gemm128_kernel (128x128 tiles, direct global-to-LDS loads; split tail summed by "
              "ns128_tail_kernel)" if mode == "mixed_bf16" and npad >= 2048 else
+             "ns_gemm128_kernel<split> (128x128 tiles, eight planes direct to LDS, hi*hi + hi*lo + lo*hi)"
+             if mode == "mixed_bf16x3" and npad >= 2048 else
              "ns_gemm_kernel<bf16, split> (64x64 tiles, hi*hi + hi*lo + lo*hi)" if mode == "mixed_bf16x3" else
              f"ns_gemm_kernel<{'bf16' if mode == 'mixed_bf16' else 'f32'}> (64x64 tiles)")
     out = {"kernel": kname + ", Hermitian-half complex GEMM of the Newton-Schulz steps",
