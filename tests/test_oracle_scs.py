@@ -20,7 +20,10 @@ mathematics fix, not against its own formulas:
 * the optimum does not depend on the partial normalisation or on the
   over-relaxation; a warm start at the solution stops at once;
 * post-processing leaves a PSD process matrix with lambda_min = 0 exactly
-  when the input had a negative eigenvalue.
+  when the input had a negative eigenvalue;
+* Anderson acceleration: the accelerated solve reaches the same certified
+  optimum, and with memory 1 the step is the secant step written out by
+  hand (gamma = s^T f / s^T y).
 """
 import numpy as np
 import pytest
@@ -146,3 +149,28 @@ def test_postprocess_restores_psd(gyni2):
     m2 = oracle.unpack(w2, 16)
     np.testing.assert_allclose(AF.p_proc(m2, 2), m2, atol=1e-13)
     assert abs(np.trace(m2).real - 4.0) < 1e-13
+
+
+def test_anderson_same_optimum(gyni2):
+    g, prob = gyni2
+    ref = scs.solve(g, 2, eps=1e-9, prob=prob, max_iters=20000)
+    acc = scs.solve(g, 2, eps=1e-9, prob=prob, max_iters=20000, anderson=5)
+    assert acc["converged"]
+    assert abs(acc["res"]["pobj"] - ref["res"]["pobj"]) < 1e-7
+    assert abs(acc["res"]["dobj"] - ref["res"]["dobj"]) < 1e-7
+    assert acc["aa"][0] > 0
+
+
+def test_anderson_memory_one_is_the_secant_step():
+    # with one stored pair (s, y) the type-I system is the scalar
+    # (s^T y + lam) gamma = s^T f; the next input g - (s - y) gamma
+    rng = np.random.default_rng(9)
+    aa = scs.Anderson(1)
+    q0, g0 = rng.standard_normal(7), rng.standard_normal(7)
+    assert np.array_equal(aa.next_input(q0, g0), g0)          # no pair yet: the plain step
+    q1, g1 = g0, rng.standard_normal(7)
+    out = aa.next_input(q1, g1)
+    s, y, f = q1 - q0, (q1 - g1) - (q0 - g0), q1 - g1
+    lam = scs.AA_REG * np.linalg.norm(s) * np.linalg.norm(y)
+    gam = (s @ f) / (s @ y + lam)
+    np.testing.assert_allclose(out, g1 - (s - y) * gam, rtol=1e-13, atol=1e-13)
