@@ -294,7 +294,10 @@ psd_status psd_affine_step(int32_t d, const double *ax, const double *ay, double
  * |g| <= eps (1 + max(|c^T x|, |b^T y|)), tested every check_every
  * iterations and after the last one; eps = 0 runs exactly max_iters.
  * The first mixed_iters cone projections use mixed_mode, the rest FP64 (the
- * paper's low-to-high precision switch after a fixed iteration count).
+ * paper's low-to-high precision switch after a fixed iteration count); with
+ * mixed_switch > 0 the switch also comes as soon as a residual check finds
+ * the iterate within mixed_switch times the tolerance (so mixed_iters =
+ * max_iters with mixed_switch = 10 switches on the residuals alone).
  * anderson = m > 0: type-I Anderson acceleration (App. D.2 keeps SCS's) of
  * the map q -> G(q) on the cone step's input q = u~_r - v (which fixes
  * u = Pi_C(q) and v = u - q): with the last m differences S of the inputs
@@ -315,6 +318,9 @@ typedef struct {
     int32_t anderson;      /* Anderson memory m, 0 (off) .. 16 */
     double eps;            /* eps_abs = eps_rel >= 0 */
     double alpha;          /* over-relaxation, 0 < alpha < 2 */
+    double mixed_switch;   /* >= 0; > 0: leave mixed_mode for FP64 for good once a
+                              residual check finds every termination ratio
+                              (||p||/bound_p, ||r||/bound_r, |g|/bound_g) below it */
 } psd_scs_settings;
 
 /* Result record (host memory, complete when psd_scs_solve returns). */
@@ -326,7 +332,7 @@ typedef struct {
     int32_t proj_status;   /* first non-OK status of a cone projection, else 0 */
     int32_t aa_accepted;   /* Anderson steps taken */
     int32_t aa_rejected;   /* Anderson steps undone by the safeguard */
-    int32_t reserved;
+    int32_t switch_iter;   /* iteration after which mixed_switch moved to FP64, else 0 */
     double pobj;           /* tr[W G] at x: gamma tr G - c^T x (last check) */
     double dobj;           /* dual bound gamma tr G + b^T y (last check) */
     double res_pri, res_dual, gap;   /* ||p||_inf, ||r||_inf, |g| (last check) */

@@ -224,18 +224,22 @@ def affine_step(ax: torch.Tensor, ay: torch.Tensor, d: int, zx: torch.Tensor = N
 
 def scs_solve(g: torch.Tensor, d: int, eps: float = 1e-5, alpha: float = 1.5, max_iters: int = 5000,
               check_every: int = 1, normalize: bool = True, mixed_iters: int = 0, mixed_mode="mixed_fp32",
-              warm=None, post: bool = True, anderson: int = 0, ws: torch.Tensor = None) -> dict:
+              warm=None, post: bool = True, anderson: int = 0, mixed_switch: float = 0.0,
+              ws: torch.Tensor = None) -> dict:
     """Solve max tr[W G] over process matrices by the SCS iteration on the
     GPU (App. D; psd_scs_solve).  g: svec of G (d^8 float64 on the device).
     warm: optional (x, y, s) start.  anderson: memory of the type-I
-    Anderson acceleration (0: off).  Returns the unscaled x, y, s, the
+    Anderson acceleration (0: off).  mixed_iters / mixed_mode: cone steps in
+    a mixed mode first; mixed_switch > 0 moves to FP64 as soon as the
+    residuals are within that factor of the tolerance.  Returns the unscaled x, y, s, the
     post-processed process matrix w (if `post`), and the info record as a
     dict (status, iters, pobj, dobj, residuals, tau, kappa, sigma, ...)."""
     nx, ny = _lib.affine_dims(d)
     _check_vec(g, ny, "g")
     st = _lib.ScsSettings(d=d, max_iters=max_iters, check_every=check_every, mixed_iters=mixed_iters,
                           mixed_mode=_mode(mixed_mode), normalize=int(bool(normalize)),
-                          warm_start=int(warm is not None), anderson=anderson, eps=eps, alpha=alpha)
+                          warm_start=int(warm is not None), anderson=anderson, eps=eps, alpha=alpha,
+                          mixed_switch=mixed_switch)
     nbytes = _lib.scs_workspace_size(st)
     if ws is None or ws.numel() < nbytes:
         ws = torch.empty(nbytes, dtype=torch.uint8, device=g.device)

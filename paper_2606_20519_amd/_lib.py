@@ -45,13 +45,13 @@ class ScsSettings(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("mixed_iters", ctypes.c_int32), ("mixed_mode", ctypes.c_int32), ("normalize", ctypes.c_int32),
                 ("warm_start", ctypes.c_int32), ("anderson", ctypes.c_int32), ("eps", ctypes.c_double),
-                ("alpha", ctypes.c_double)]
+                ("alpha", ctypes.c_double), ("mixed_switch", ctypes.c_double)]
 
 
 class ScsInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("proj_status", ctypes.c_int32),
                 ("aa_accepted", ctypes.c_int32), ("aa_rejected", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("pobj", ctypes.c_double), ("dobj", ctypes.c_double),
+                ("switch_iter", ctypes.c_int32), ("pobj", ctypes.c_double), ("dobj", ctypes.c_double),
                 ("res_pri", ctypes.c_double), ("res_dual", ctypes.c_double), ("gap", ctypes.c_double),
                 ("tau", ctypes.c_double), ("kappa", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("post_lambda", ctypes.c_double), ("post_lambda_min", ctypes.c_double)]

@@ -55,7 +55,7 @@ namespace psd {
 
 namespace {
 
-static_assert(sizeof(psd_scs_settings) == 48, "psd_scs_settings layout");
+static_assert(sizeof(psd_scs_settings) == 56, "psd_scs_settings layout");
 static_assert(sizeof(psd_scs_info) == 104, "psd_scs_info layout");
 
 constexpr int SCS_BLOCK = 256;
@@ -530,7 +530,7 @@ bool settings_ok(const psd_scs_settings *s) {
             s->mixed_mode == PSD_MIXED_BF16X3) &&
            (s->normalize == 0 || s->normalize == 1) && (s->warm_start == 0 || s->warm_start == 1) &&
            s->anderson >= 0 && s->anderson <= AA_MAX && s->eps >= 0.0 && std::isfinite(s->eps) && s->alpha > 0.0 &&
-           s->alpha < 2.0;
+           s->alpha < 2.0 && s->mixed_switch >= 0.0 && std::isfinite(s->mixed_switch);
 }
 
 int grid_of(int64_t n) { return (int)((n + SCS_BLOCK - 1) / SCS_BLOCK); }
@@ -796,6 +796,7 @@ psd_status psd_scs_solve(const psd_scs_settings *s, const double *g, double *x, 
     const double bound_b = gamma;   // ||b||_inf
     int status = PSD_ENOCONV;
     int k = 0;
+    bool switched = false;   // left the mixed cone steps on the residuals
     double r[R_SLOTS + 2] = {};
     SCS_TRY(cone_input());
     if (L.m) {
@@ -804,7 +805,7 @@ psd_status psd_scs_solve(const psd_scs_settings *s, const double *g, double *x, 
     }
     for (k = 1; k <= s->max_iters; ++k) {
         // cone step: u_y = Pi(q_y), v_s = u_y - q_y, tau, kappa
-        const psd_mode mode = k <= s->mixed_iters ? (psd_mode)s->mixed_mode : PSD_FP64_EIG;
+        const psd_mode mode = (k <= s->mixed_iters && !switched) ? (psd_mode)s->mixed_mode : PSD_FP64_EIG;
         SCS_TRY(psd_project(n, zy, uy, mode, proj, L.proj_bytes, st, pinfo, nullptr));
         hipLaunchKernelGGL(scs_fold_kernel, dim3(1), dim3(64), 0, st, pinfo, sticky);
         hipLaunchKernelGGL(scs_dual_kernel, dim3(grid_of(ny)), dim3(SCS_BLOCK), 0, st, vy, zy, uy, sc, ny);
@@ -838,11 +839,18 @@ psd_status psd_scs_solve(const psd_scs_settings *s, const double *g, double *x, 
                 info->pobj = b0 - cx;
                 info->dobj = b0 + by;
                 const double e = s->eps;
-                if (e > 0.0 && res_pri <= e + e * std::max(ax_inf, std::max(s_inf, bound_b)) &&
-                    res_dual <= e + e * std::max(aty_inf, c_inf) &&
-                    gap <= e + e * std::max(std::fabs(cx), std::fabs(by))) {
+                const double bp = e + e * std::max(ax_inf, std::max(s_inf, bound_b));
+                const double bd = e + e * std::max(aty_inf, c_inf);
+                const double bg = e + e * std::max(std::fabs(cx), std::fabs(by));
+                if (e > 0.0 && res_pri <= bp && res_dual <= bd && gap <= bg) {
                     status = PSD_OK;
                     break;
+                }
+                const double ms = s->mixed_switch;
+                if (ms > 0.0 && e > 0.0 && k <= s->mixed_iters && !switched && res_pri <= ms * bp &&
+                    res_dual <= ms * bd && gap <= ms * bg) {
+                    switched = true;
+                    info->switch_iter = k;
                 }
             } else {
                 info->res_pri = info->res_dual = info->gap = INFINITY;

@@ -144,7 +144,7 @@ def test_scs_settings_validation():
 
     def st(**kw):
         base = dict(d=4, max_iters=10, check_every=1, mixed_iters=0, mixed_mode=2, normalize=1, warm_start=0,
-                    anderson=0, eps=1e-5, alpha=1.5)
+                    anderson=0, eps=1e-5, alpha=1.5, mixed_switch=0.0)
         base.update(kw)
         return _lib.ScsSettings(**base)
 
@@ -156,7 +156,7 @@ def test_scs_settings_validation():
     assert out.value >= plain + 24 * 8 * (nx + ny + 1)       # 2m + 4 vectors of the cone input
     for bad in (dict(d=1), dict(d=9), dict(max_iters=0), dict(check_every=0), dict(alpha=2.0), dict(alpha=0.0),
                 dict(eps=-1.0), dict(eps=float("nan")), dict(mixed_iters=5, mixed_mode=0), dict(anderson=17),
-                dict(anderson=-1),
+                dict(anderson=-1), dict(mixed_switch=-1.0), dict(mixed_switch=float("inf")),
                 dict(normalize=2), dict(mixed_iters=-1)):
         assert L.psd_scs_workspace_size(ctypes.byref(st(**bad)), ctypes.byref(out)) == 1, bad
     info = _lib.ScsInfo()

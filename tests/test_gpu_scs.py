@@ -191,12 +191,20 @@ def test_warm_start_and_mixed_start(P):
     warm = P.scs_solve(gd, d, eps=1e-6, warm=(ref["x"], ref["y"], ref["s"]))
     print(f"d=4 cold {ref['iters']} iterations; warm {warm['iters']}", flush=True)
     assert warm["status"] == 0 and warm["iters"] <= 2
-    for mode in ("mixed_fp32", "mixed_bf16"):
+    for mode in ("mixed_fp32", "mixed_bf16", "mixed_bf16x3"):
         mx = P.scs_solve(gd, d, eps=1e-6, max_iters=20000, mixed_iters=60, mixed_mode=mode)
         print(f"d=4 {mode} for 60 iterations: {mx['iters']} iterations, value {mx['pobj']:.9f} "
               f"(FP64 {ref['pobj']:.9f})", flush=True)
-        assert mx["status"] == 0
+        assert mx["status"] == 0 and mx["switch_iter"] == 0
         assert abs(mx["pobj"] - ref["pobj"]) < 1e-5
+    # the residual-based switch: mixed cone steps until the iterate is within
+    # 10x the tolerance, then FP64 to the end
+    sw = P.scs_solve(gd, d, eps=1e-6, max_iters=20000, mixed_iters=20000, mixed_mode="mixed_bf16x3",
+                     mixed_switch=10.0)
+    print(f"d=4 BF16x3 until 10x the tolerance: switched after {sw['switch_iter']}, {sw['iters']} iterations, "
+          f"value {sw['pobj']:.9f}", flush=True)
+    assert sw["status"] == 0 and 0 < sw["switch_iter"] < sw["iters"]
+    assert abs(sw["pobj"] - ref["pobj"]) < 1e-5
 
 
 def test_nonfinite_objective(P):
