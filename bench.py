@@ -588,7 +588,8 @@ def main():
             minbytes = 16.0 * (nx + n * n)   # read a_x, a_y; write z_x, z_y
             extra["affine_step"] = {"ms": round(1e3 * dt, 3), "share_of_projection": round(1e3 * dt / per_proj_ms, 4),
                                     "nx": nx, "min_hbm_gbs": round(minbytes / dt / 1e9, 1),
-                                    "passes": "unpack, 4 local transforms, gather, scatter, 4 transforms, pack"}
+                                    "passes": "per direction: modes 2+3 with the svec unpack/pack, mode 1, mode 0 with the "
+                                              "gather/scatter (each input read once through LDS)"}
         if wl == "c5" and not args.no_context:
             log("SCS solves (GYNI, d = 5 to 1e-5; d = 8 per-iteration time)")
             extra["scs"] = scs_context(P, W, torch, dev)
