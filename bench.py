@@ -207,6 +207,7 @@ def numpy_eigh_baseline(np, oracle, x_svec, n):
 
 
 def scs_context(P, W, torch, dev) -> dict:
+    import numpy as np
     """The whole SCS iteration (App. D) on GPU-resident data: a GYNI process
     SDP from a seeded pair of random feasible instruments solved to
     eps = 1e-5 at d = 5 (plain, then with Anderson memory 5), and the
@@ -242,6 +243,21 @@ def scs_context(P, W, torch, dev) -> dict:
                 rec[f"ms_per_iteration_{mm}"] = round(1e3 * (time.perf_counter() - t) / rm["iters"], 3)
         out[f"d{d}"] = rec
         log(f"SCS d={d}: {rec}")
+    # many independent d = 5 solves in lockstep (the paper's exploration
+    # stage runs the see-saw from many random starts): per-iteration rate of
+    # a batch of 32 against one instance
+    d, B, its = 5, 32, 10
+    G = torch.from_numpy(np.stack([W.upper_pack(W.gyni_objective(d, 100 + b)) for b in range(B)])).to(dev)
+    P.scs_solve_batched(G[:2], d, eps=0.0, max_iters=2, post=False)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    P.scs_solve_batched(G, d, eps=0.0, max_iters=its, post=False)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t) / its
+    out["batched_d5"] = {"instances": B, "ms_per_iteration": round(1e3 * tb, 3),
+                         "ms_per_instance_iteration": round(1e3 * tb / B, 4),
+                         "throughput_vs_single": round(out["d5"]["ms_per_iteration"] * 1e-3 * B / tb, 2)}
+    log(f"SCS batched d=5: {out['batched_d5']}")
     out["paper_t4_gpu"] = {"d5": {"iterations": 275, "seconds": 21}, "d8": {"iterations": 300, "seconds": 2640}}
     return out
 

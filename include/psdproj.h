@@ -361,6 +361,23 @@ psd_status psd_scs_workspace_size(const psd_scs_settings *s, size_t *bytes);
 psd_status psd_scs_solve(const psd_scs_settings *s, const double *g, double *x, double *y, double *s_out,
                          double *w, void *ws, size_t ws_bytes, void *stream, psd_scs_info *info);
 
+/* A batch of nbatch >= 1 independent solves with the same settings (many
+ * objectives, e.g. the restarts of the paper's exploration stage, §IV):
+ * g, y, s_out, w hold nbatch d^8-vectors back to back, x nbatch n_x-vectors,
+ * infos nbatch records.  The instances advance in lockstep and their cone
+ * steps are one psd_project_batched call (same-order blocks in lockstep
+ * groups, each block's result bitwise that of a single call), so each
+ * instance's iterates and results are bitwise those of psd_scs_solve on its
+ * own.  An instance that stops (converged, non-finite) has its outputs
+ * written and is not advanced further; its block is still projected with
+ * the others.  With mixed_switch > 0 the batch leaves the mixed mode
+ * when every running instance is within the factor.  Workspace from
+ * psd_scs_workspace_size_batched (it grows with nbatch). */
+psd_status psd_scs_workspace_size_batched(const psd_scs_settings *s, int32_t nbatch, size_t *bytes);
+psd_status psd_scs_solve_batched(const psd_scs_settings *s, int32_t nbatch, const double *g, double *x, double *y,
+                                 double *s_out, double *w, void *ws, size_t ws_bytes, void *stream,
+                                 psd_scs_info *infos);
+
 /* FP64 fallback of the mixed modes (process-wide; not thread-safe):
  * with max_rel_err > 0, psd_project in a mixed mode writes the mixed run's
  * record to its workspace, synchronises the stream and, if that record

@@ -23,7 +23,7 @@ from ._lib import MODES, PSD_FLAG_SAVE, PsdError, PsdInfo, check  # noqa: F401
 
 __all__ = ["project", "project_batched", "vjp", "PSDProject", "Plan", "workspace", "set_ns_iterations",
            "set_mixed_fallback", "project_noalloc", "affine_dims", "constraint_apply", "constraint_adjoint",
-           "affine_step", "scs_solve",
+           "affine_step", "scs_solve", "scs_solve_batched",
            "PsdError", "MODES"]
 
 _ws_cache: dict = {}
@@ -231,34 +231,61 @@ def scs_solve(g: torch.Tensor, d: int, eps: float = 1e-5, alpha: float = 1.5, ma
     warm: optional (x, y, s) start.  anderson: memory of the type-I
     Anderson acceleration (0: off).  mixed_iters / mixed_mode: cone steps in
     a mixed mode first; mixed_switch > 0 moves to FP64 as soon as the
-    residuals are within that factor of the tolerance.  Returns the unscaled x, y, s, the
-    post-processed process matrix w (if `post`), and the info record as a
-    dict (status, iters, pobj, dobj, residuals, tau, kappa, sigma, ...)."""
+    residuals are within that factor of the tolerance.  Returns the unscaled
+    x, y, s, the post-processed process matrix w (if `post`), and the info
+    record as a dict (status, iters, pobj, dobj, residuals, tau, kappa,
+    sigma, ...)."""
+    out = scs_solve_batched(g.reshape(1, -1), d, eps=eps, alpha=alpha, max_iters=max_iters,
+                            check_every=check_every, normalize=normalize, mixed_iters=mixed_iters,
+                            mixed_mode=mixed_mode, warm=None if warm is None else tuple(t.reshape(1, -1) for t in warm),
+                            post=post, anderson=anderson, mixed_switch=mixed_switch, ws=ws, _single=True)
+    return out[0]
+
+
+def scs_solve_batched(g: torch.Tensor, d: int, eps: float = 1e-5, alpha: float = 1.5, max_iters: int = 5000,
+                      check_every: int = 1, normalize: bool = True, mixed_iters: int = 0, mixed_mode="mixed_fp32",
+                      warm=None, post: bool = True, anderson: int = 0, mixed_switch: float = 0.0,
+                      ws: torch.Tensor = None, _single: bool = False) -> list:
+    """A batch of independent solves in lockstep (psd_scs_solve_batched):
+    g is (B, d^8); warm an optional (x, y, s) of shapes (B, n_x), (B, d^8),
+    (B, d^8).  Returns one dict per instance, as scs_solve."""
     nx, ny = _lib.affine_dims(d)
-    _check_vec(g, ny, "g")
+    if g.dim() != 2 or g.shape[1] != ny:
+        raise ValueError(f"g must be (B, {ny})")
+    B = g.shape[0]
+    _check_vec(g.reshape(-1), B * ny, "g")
     st = _lib.ScsSettings(d=d, max_iters=max_iters, check_every=check_every, mixed_iters=mixed_iters,
                           mixed_mode=_mode(mixed_mode), normalize=int(bool(normalize)),
                           warm_start=int(warm is not None), anderson=anderson, eps=eps, alpha=alpha,
                           mixed_switch=mixed_switch)
-    nbytes = _lib.scs_workspace_size(st)
+    nbytes = _lib.scs_workspace_size(st, B)
     if ws is None or ws.numel() < nbytes:
         ws = torch.empty(nbytes, dtype=torch.uint8, device=g.device)
     if warm is not None:
-        x, y, s = (t.clone() for t in warm)
-        _check_vec(x, nx, "warm x")
-        _check_vec(y, ny, "warm y")
-        _check_vec(s, ny, "warm s")
+        x, y, s = (t.contiguous().clone() for t in warm)
+        _check_vec(x.reshape(-1), B * nx, "warm x")
+        _check_vec(y.reshape(-1), B * ny, "warm y")
+        _check_vec(s.reshape(-1), B * ny, "warm s")
     else:
-        x = torch.empty(nx, dtype=torch.float64, device=g.device)
-        y = torch.empty(ny, dtype=torch.float64, device=g.device)
-        s = torch.empty(ny, dtype=torch.float64, device=g.device)
-    w = torch.empty(ny, dtype=torch.float64, device=g.device) if post else None
-    info = _lib.ScsInfo()
-    check(_lib.lib().psd_scs_solve(ctypes.byref(st), _ptr(g), _ptr(x), _ptr(y), _ptr(s), _ptr(w), _ptr(ws),
-                                   ws.numel(), ctypes.c_void_p(_stream_ptr(g.device)), ctypes.byref(info)),
-          "psd_scs_solve")
-    out = {f: getattr(info, f) for f, _ in _lib.ScsInfo._fields_}
-    out.update(x=x, y=y, s=s, w=w)
+        x = torch.empty(B, nx, dtype=torch.float64, device=g.device)
+        y = torch.empty(B, ny, dtype=torch.float64, device=g.device)
+        s = torch.empty(B, ny, dtype=torch.float64, device=g.device)
+    w = torch.empty(B, ny, dtype=torch.float64, device=g.device) if post else None
+    infos = (_lib.ScsInfo * B)()
+    fn = _lib.lib().psd_scs_solve if _single else None
+    if _single:
+        st_ = fn(ctypes.byref(st), _ptr(g), _ptr(x), _ptr(y), _ptr(s), _ptr(w), _ptr(ws), ws.numel(),
+                 ctypes.c_void_p(_stream_ptr(g.device)), infos)
+        check(st_, "psd_scs_solve")
+    else:
+        check(_lib.lib().psd_scs_solve_batched(ctypes.byref(st), B, _ptr(g), _ptr(x), _ptr(y), _ptr(s), _ptr(w),
+                                               _ptr(ws), ws.numel(), ctypes.c_void_p(_stream_ptr(g.device)), infos),
+              "psd_scs_solve_batched")
+    out = []
+    for b in range(B):
+        rec = {f: getattr(infos[b], f) for f, _ in _lib.ScsInfo._fields_}
+        rec.update(x=x[b], y=y[b], s=s[b], w=None if w is None else w[b])
+        out.append(rec)
     return out
 
 

@@ -25,7 +25,8 @@ EXPORTS = ("psd_workspace_size", "psd_saved_size", "psd_project", "psd_project_n
            "psd_plan_execute", "psd_plan_tune", "psd_plan_destroy", "psd_timing_start", "psd_timing_stop",
            "psd_set_ns_iterations", "psd_set_mixed_fallback", "psd_status_string", "psd_version",
            "psd_affine_dims", "psd_affine_workspace_size", "psd_constraint_apply", "psd_constraint_adjoint",
-           "psd_affine_step", "psd_scs_workspace_size", "psd_scs_solve")
+           "psd_affine_step", "psd_scs_workspace_size", "psd_scs_solve", "psd_scs_workspace_size_batched",
+           "psd_scs_solve_batched")
 KF_HEMV, KF_GEMM, KF_NS, KF_WSTEP = 1, 2, 3, 4
 
 
@@ -120,6 +121,11 @@ def lib():
     L.psd_scs_workspace_size.restype = i32
     L.psd_scs_solve.argtypes = [ctypes.POINTER(ScsSettings), vp, vp, vp, vp, vp, vp, sz, vp, ctypes.POINTER(ScsInfo)]
     L.psd_scs_solve.restype = i32
+    L.psd_scs_workspace_size_batched.argtypes = [ctypes.POINTER(ScsSettings), i32, ctypes.POINTER(sz)]
+    L.psd_scs_workspace_size_batched.restype = i32
+    L.psd_scs_solve_batched.argtypes = [ctypes.POINTER(ScsSettings), i32, vp, vp, vp, vp, vp, vp, sz, vp,
+                                        ctypes.POINTER(ScsInfo)]
+    L.psd_scs_solve_batched.restype = i32
     L.psd_timing_start.argtypes = [i32, i32]
     L.psd_timing_start.restype = i32
     L.psd_timing_stop.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]
@@ -182,9 +188,10 @@ def affine_dims(d: int):
     return int(nx.value), int(ny.value)
 
 
-def scs_workspace_size(settings: "ScsSettings") -> int:
+def scs_workspace_size(settings: "ScsSettings", nbatch: int = 1) -> int:
     out = ctypes.c_size_t(0)
-    check(lib().psd_scs_workspace_size(ctypes.byref(settings), ctypes.byref(out)), "psd_scs_workspace_size")
+    check(lib().psd_scs_workspace_size_batched(ctypes.byref(settings), nbatch, ctypes.byref(out)),
+          "psd_scs_workspace_size_batched")
     return int(out.value)
 
 

@@ -47,6 +47,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "../../include/psdproj.h"
 #include "common.h"
@@ -465,25 +466,34 @@ __global__ void scs_fold_kernel(const psd_info *info, int *sticky) {
     if (threadIdx.x == 0 && *sticky == 0 && info->status != 0) *sticky = info->status;
 }
 
+// Workspace of a batch of B instances: the affine workspace, the projection
+// workspace and the reduction partials are shared (every step runs in stream
+// order); the cone-step blocks of the instances are back to back (u_y and
+// z_y, so that one batched projection covers them) as are their info
+// records, residual and Anderson read-backs; the rest of an instance's
+// vectors sit in a slot of its own, `inst` bytes apart.
 struct ScsLayout {
-    int d, n;
+    int d, n, B;
     int64_t nx, ny, nq;
-    size_t ux, cv, mhx, zx, tx;           // nx each
-    size_t uy, vy, zy, mhy, ty;           // ny each
     size_t aff, aff_bytes;
     size_t proj, proj_bytes;
-    size_t part, sc, red, pinfo, sticky;
-    int m;                                // Anderson memory (0: off)
-    int64_t ld;                           // stride of the Anderson vectors (doubles)
-    size_t qk, qprev, fprev, gsave, S, Y, aapart, aaout;
+    size_t part, aapart;
+    size_t UY, ZY, PINFO, RED, AAOUT, STICKY;   // batched, instance b at b * (its size)
+    size_t slot0, inst;                           // instance slots
+    // offsets inside a slot
+    size_t ux, cv, mhx, zx, tx, vy, mhy, ty, sc;
+    int m;                                        // Anderson memory (0: off)
+    int64_t ld;                                   // stride of the Anderson vectors (doubles)
+    size_t qk, qprev, fprev, gsave, S, Y;
     size_t total;
 };
 
-bool scs_layout(const psd_scs_settings &s, ScsLayout &L) {
+bool scs_layout(const psd_scs_settings &s, int B, ScsLayout &L) {
     int64_t nx = 0, ny = 0;
-    if (psd_affine_dims(s.d, &nx, &ny) != PSD_OK) return false;
+    if (B < 1 || psd_affine_dims(s.d, &nx, &ny) != PSD_OK) return false;
     L.d = s.d;
     L.n = s.d * s.d * s.d * s.d;
+    L.B = B;
     L.nx = nx;
     L.ny = ny;
     L.nq = nx + ny + 1;
@@ -493,33 +503,48 @@ bool scs_layout(const psd_scs_settings &s, ScsLayout &L) {
         off += align256(bytes);
         return o;
     };
-    const size_t bx = sizeof(double) * (size_t)nx, by = sizeof(double) * (size_t)ny;
-    L.ux = take(bx); L.cv = take(bx); L.mhx = take(bx); L.zx = take(bx); L.tx = take(bx);
-    L.uy = take(by); L.vy = take(by); L.zy = take(by); L.mhy = take(by); L.ty = take(by);
     if (psd_affine_workspace_size(s.d, &L.aff_bytes) != PSD_OK) return false;
     L.aff = take(L.aff_bytes);
-    size_t pb = 0, pm = 0;
+    size_t pb = 0, pg = 0, pm = 0;
     const int32_t n = L.n;
+    std::vector<int32_t> sizes(B, n);
     if (psd_workspace_size(1, &n, PSD_FP64_EIG, PSD_FLAG_SAVE, &pb) != PSD_OK) return false;
-    if (s.mixed_iters > 0 && psd_workspace_size(1, &n, (psd_mode)s.mixed_mode, 0, &pm) != PSD_OK) return false;
-    L.proj_bytes = std::max(pb, pm);
+    if (psd_workspace_size(B, sizes.data(), PSD_FP64_EIG, 0, &pg) != PSD_OK) return false;
+    if (s.mixed_iters > 0 && psd_workspace_size(B, sizes.data(), (psd_mode)s.mixed_mode, 0, &pm) != PSD_OK)
+        return false;
+    L.proj_bytes = std::max(pb, std::max(pg, pm));
     L.proj = take(L.proj_bytes);
     L.part = take(sizeof(double) * SCS_PARTS * R_SLOTS);
-    L.sc = take(sizeof(double) * SC_COUNT);
-    L.red = take(sizeof(double) * 16);
-    L.pinfo = take(sizeof(psd_info));
-    L.sticky = take(sizeof(int));
+    L.aapart = take(sizeof(double) * SCS_PARTS * AA_VALS);
+    const size_t by = sizeof(double) * (size_t)ny, bx = sizeof(double) * (size_t)nx;
+    L.UY = take(by * B);
+    L.ZY = take(by * B);
+    L.PINFO = take(sizeof(psd_info) * B);
+    L.RED = take(sizeof(double) * 16 * B);
+    L.AAOUT = take(sizeof(double) * AA_VALS * B);
+    L.STICKY = take(sizeof(int) * B);
+    // one instance slot
+    size_t o = 0;
+    auto slot = [&](size_t bytes) {
+        const size_t r = o;
+        o += align256(bytes);
+        return r;
+    };
+    L.ux = slot(bx); L.cv = slot(bx); L.mhx = slot(bx); L.zx = slot(bx); L.tx = slot(bx);
+    L.vy = slot(by); L.mhy = slot(by); L.ty = slot(by);
+    L.sc = slot(sizeof(double) * SC_COUNT);
     L.m = s.anderson;
     L.ld = (int64_t)(align256(sizeof(double) * (size_t)L.nq) / sizeof(double));
-    L.qk = L.qprev = L.fprev = L.gsave = L.S = L.Y = L.aapart = L.aaout = 0;
+    L.qk = L.qprev = L.fprev = L.gsave = L.S = L.Y = 0;
     if (L.m > 0) {
         const size_t bq = sizeof(double) * (size_t)L.ld;
-        L.qk = take(bq); L.qprev = take(bq); L.fprev = take(bq); L.gsave = take(bq);
-        L.S = take(bq * L.m);
-        L.Y = take(bq * L.m);
-        L.aapart = take(sizeof(double) * SCS_PARTS * AA_VALS);
-        L.aaout = take(sizeof(double) * AA_VALS);
+        L.qk = slot(bq); L.qprev = slot(bq); L.fprev = slot(bq); L.gsave = slot(bq);
+        L.S = slot(bq * L.m);
+        L.Y = slot(bq * L.m);
     }
+    L.inst = o;
+    L.slot0 = off;
+    off += L.inst * (size_t)B;
     L.total = off;
     return true;
 }
@@ -581,54 +606,77 @@ struct AaHost {
     }
 };
 
-}  // namespace
+// Host view of one instance of a batch.
+struct ScsInst {
+    double *ux, *cv, *mhx, *zx, *tx, *uy, *vy, *zy, *mhy, *ty, *sc, *red, *aaout;
+    psd_info *pinfo;
+    int *sticky;
+    double *qk, *qprev, *fprev, *gsave, *S, *Y;
+    const double *g;
+    double *x, *y, *s, *w;
+    double sigma = 1.0, eta = 0.0, b0 = 0.0, c_inf = 0.0;
+    psd_scs_info *info;
+    AaHost aa;
+    int status = PSD_ENOCONV;
+    bool done = false;     // converged, failed or stopped: its state is frozen
+    bool within = false;   // last check within mixed_switch times the tolerance
+};
 
-}  // namespace psd
-
-using namespace psd;
-
-extern "C" {
-
-psd_status psd_scs_workspace_size(const psd_scs_settings *s, size_t *bytes) {
-    if (!settings_ok(s) || !bytes) return PSD_EINVAL;
+psd_status scs_solve_batch(const psd_scs_settings *s, int B, const double *g, double *x, double *y, double *sl,
+                           double *w, void *ws, size_t ws_bytes, void *stream, psd_scs_info *infos) {
+    if (!settings_ok(s) || B < 1 || !g || !x || !y || !sl || !infos) return PSD_EINVAL;
     ScsLayout L;
-    if (!scs_layout(*s, L)) return PSD_EINVAL;
-    *bytes = L.total;
-    return PSD_OK;
-}
-
-psd_status psd_scs_solve(const psd_scs_settings *s, const double *g, double *x, double *y, double *sl, double *w,
-                         void *ws, size_t ws_bytes, void *stream, psd_scs_info *info) {
-    if (!settings_ok(s) || !g || !x || !y || !sl || !info) return PSD_EINVAL;
-    ScsLayout L;
-    if (!scs_layout(*s, L)) return PSD_EINVAL;
+    if (!scs_layout(*s, B, L)) return PSD_EINVAL;
     if (!ws || ws_bytes < L.total) return PSD_EWORKSPACE;
     if (reinterpret_cast<uintptr_t>(ws) % 256) return PSD_EINVAL;
     for (const void *p : {(const void *)g, (const void *)x, (const void *)y, (const void *)sl, (const void *)w})
         if (p && (reinterpret_cast<uintptr_t>(p) & 7u)) return PSD_EINVAL;
-    {   // x, y, s, w, g pairwise disjoint
-        const size_t bx = sizeof(double) * (size_t)L.nx, by = sizeof(double) * (size_t)L.ny;
+    {   // g, x, y, s, w (each B vectors back to back) pairwise disjoint
+        const size_t bx = sizeof(double) * (size_t)L.nx * B, by = sizeof(double) * (size_t)L.ny * B;
         const char *pp[5] = {(const char *)g, (const char *)x, (const char *)y, (const char *)sl, (const char *)w};
         const size_t nb[5] = {by, bx, by, by, by};
         for (int i = 0; i < 5; ++i)
             for (int j = i + 1; j < 5; ++j)
                 if (pp[i] && pp[j] && pp[i] < pp[j] + nb[j] && pp[j] < pp[i] + nb[i]) return PSD_EINVAL;
     }
-    *info = psd_scs_info{};
     hipStream_t st = static_cast<hipStream_t>(stream);
     char *base = static_cast<char *>(ws);
     auto D = [&](size_t off) { return reinterpret_cast<double *>(base + off); };
-    double *ux = D(L.ux), *cv = D(L.cv), *mhx = D(L.mhx), *zx = D(L.zx), *tx = D(L.tx);
-    double *uy = D(L.uy), *vy = D(L.vy), *zy = D(L.zy), *mhy = D(L.mhy), *ty = D(L.ty);
     void *aff = base + L.aff;
     void *proj = base + L.proj;
-    double *part = D(L.part), *sc = D(L.sc), *red = D(L.red);
-    psd_info *pinfo = reinterpret_cast<psd_info *>(base + L.pinfo);
-    int *sticky = reinterpret_cast<int *>(base + L.sticky);
+    double *part = D(L.part), *aapart = D(L.aapart);
+    double *UY = D(L.UY), *ZY = D(L.ZY), *RED = D(L.RED), *AAOUT = D(L.AAOUT);
+    psd_info *PINFO = reinterpret_cast<psd_info *>(base + L.PINFO);
+    int *STICKY = reinterpret_cast<int *>(base + L.STICKY);
     const int d = L.d, n = L.n;
     const int64_t nx = L.nx, ny = L.ny, nq = L.nq;
     const double gamma = 1.0 / (double)(d * d);
     const double alpha = s->alpha;
+    std::vector<ScsInst> inst(B);
+    for (int b = 0; b < B; ++b) {
+        ScsInst &I = inst[b];
+        char *sb = base + L.slot0 + L.inst * (size_t)b;
+        auto S_ = [&](size_t off) { return reinterpret_cast<double *>(sb + off); };
+        I.ux = S_(L.ux); I.cv = S_(L.cv); I.mhx = S_(L.mhx); I.zx = S_(L.zx); I.tx = S_(L.tx);
+        I.vy = S_(L.vy); I.mhy = S_(L.mhy); I.ty = S_(L.ty); I.sc = S_(L.sc);
+        I.uy = UY + ny * b;
+        I.zy = ZY + ny * b;
+        I.red = RED + 16 * b;
+        I.aaout = AAOUT + AA_VALS * b;
+        I.pinfo = PINFO + b;
+        I.sticky = STICKY + b;
+        I.qk = L.m ? S_(L.qk) : nullptr; I.qprev = L.m ? S_(L.qprev) : nullptr;
+        I.fprev = L.m ? S_(L.fprev) : nullptr; I.gsave = L.m ? S_(L.gsave) : nullptr;
+        I.S = L.m ? S_(L.S) : nullptr; I.Y = L.m ? S_(L.Y) : nullptr;
+        I.g = g + ny * b;
+        I.x = x + nx * b;
+        I.y = y + ny * b;
+        I.s = sl + ny * b;
+        I.w = w ? w + ny * b : nullptr;
+        I.info = infos + b;
+        *I.info = psd_scs_info{};
+        I.aa.m = L.m;
+    }
 
 #define SCS_TRY(call)                                    \
     do {                                                 \
@@ -646,262 +694,372 @@ psd_status psd_scs_solve(const psd_scs_settings *s, const double *g, double *x, 
             return PSD_EDEVICE;                                                            \
     } while (0)
 
-    // ---- setup: c = A^T G, norms, sigma, M^-1 h, eta --------------------
-    SCS_TRY(psd_constraint_adjoint(d, g, cv, aff, L.aff_bytes, st));
+    // ---- setup: c = A^T G, norms, sigma, M^-1 h, eta (per instance) ---------
     const int parts_x = std::min<int64_t>(SCS_PARTS, std::max<int64_t>(1, grid_of(nx + n)));
-    hipLaunchKernelGGL(scs_setup_kernel, dim3(parts_x), dim3(SCS_BLOCK), 0, st, cv, g, nx, n, part);
-    hipLaunchKernelGGL(scs_final3_kernel, dim3(1), dim3(64 * 3), 0, st, part, parts_x, red);
-    SCS_LAUNCHED();
-    double h3[3];
-    SCS_READ(h3, red, sizeof h3);
-    const double c_norm = std::sqrt(h3[0]), c_inf = h3[1], b0 = gamma * h3[2];
-    const double b_norm = gamma * std::sqrt((double)n);
-    const double sigma = (s->normalize && c_norm > 0.0) ? b_norm / c_norm : 1.0;
-    hipLaunchKernelGGL(scs_h_kernel, dim3(grid_of(nx + ny)), dim3(SCS_BLOCK), 0, st, cv, mhx, mhy, nx, n, sigma,
-                       gamma);
-    hipLaunchKernelGGL(scs_diag_add_kernel, dim3(grid_of(n)), dim3(SCS_BLOCK), 0, st, mhy, n, gamma);
-    SCS_LAUNCHED();
-    SCS_TRY(psd_affine_step(d, mhx, mhy, mhx, mhy, aff, L.aff_bytes, st));
-    hipLaunchKernelGGL(scs_dot_kernel, dim3(parts_x), dim3(SCS_BLOCK), 0, st, cv, mhx, mhy, nx, n, sigma, gamma, part);
-    hipLaunchKernelGGL(scs_final3_kernel, dim3(1), dim3(64 * 3), 0, st, part, parts_x, red);
-    SCS_LAUNCHED();
-    double eta = 0.0;
-    SCS_READ(&eta, red, sizeof eta);
-    info->sigma = sigma;
-    if (!std::isfinite(eta) || !std::isfinite(c_norm) || !std::isfinite(b0)) {
-        info->status = PSD_ENONFINITE;
-        return PSD_OK;
+    for (int b = 0; b < B; ++b) {
+        ScsInst &I = inst[b];
+        SCS_TRY(psd_constraint_adjoint(d, I.g, I.cv, aff, L.aff_bytes, st));
+        hipLaunchKernelGGL(scs_setup_kernel, dim3(parts_x), dim3(SCS_BLOCK), 0, st, I.cv, I.g, nx, n, part);
+        hipLaunchKernelGGL(scs_final3_kernel, dim3(1), dim3(64 * 3), 0, st, part, parts_x, I.red);
     }
-    hipLaunchKernelGGL(scs_start_kernel, dim3(grid_of(nx + ny)), dim3(SCS_BLOCK), 0, st, x, y, sl, ux, uy, vy, sc,
-                       nx, ny, sigma, s->warm_start);
-    if (hipMemsetAsync(sticky, 0, sizeof(int), st) != hipSuccess) return PSD_EDEVICE;
+    SCS_LAUNCHED();
+    std::vector<double> host(16 * (size_t)B);
+    SCS_READ(host.data(), RED, sizeof(double) * 16 * B);
+    for (int b = 0; b < B; ++b) {
+        ScsInst &I = inst[b];
+        const double *h3 = &host[16 * b];
+        const double c_norm = std::sqrt(h3[0]);
+        I.c_inf = h3[1];
+        I.b0 = gamma * h3[2];
+        const double b_norm = gamma * std::sqrt((double)n);
+        I.sigma = (s->normalize && c_norm > 0.0) ? b_norm / c_norm : 1.0;
+        I.info->sigma = I.sigma;
+        if (!std::isfinite(c_norm) || !std::isfinite(I.b0)) {
+            I.status = PSD_ENONFINITE;
+            I.done = true;
+            continue;
+        }
+        hipLaunchKernelGGL(scs_h_kernel, dim3(grid_of(nx + ny)), dim3(SCS_BLOCK), 0, st, I.cv, I.mhx, I.mhy, nx, n,
+                           I.sigma, gamma);
+        hipLaunchKernelGGL(scs_diag_add_kernel, dim3(grid_of(n)), dim3(SCS_BLOCK), 0, st, I.mhy, n, gamma);
+        SCS_LAUNCHED();
+        SCS_TRY(psd_affine_step(d, I.mhx, I.mhy, I.mhx, I.mhy, aff, L.aff_bytes, st));
+        hipLaunchKernelGGL(scs_dot_kernel, dim3(parts_x), dim3(SCS_BLOCK), 0, st, I.cv, I.mhx, I.mhy, nx, n, I.sigma,
+                           gamma, part);
+        hipLaunchKernelGGL(scs_final3_kernel, dim3(1), dim3(64 * 3), 0, st, part, parts_x, I.red);
+    }
+    SCS_LAUNCHED();
+    SCS_READ(host.data(), RED, sizeof(double) * 16 * B);
+    for (int b = 0; b < B; ++b) {
+        ScsInst &I = inst[b];
+        if (I.done) continue;
+        I.eta = host[16 * b];
+        if (!std::isfinite(I.eta)) {
+            I.status = PSD_ENONFINITE;
+            I.done = true;
+            continue;
+        }
+        hipLaunchKernelGGL(scs_start_kernel, dim3(grid_of(nx + ny)), dim3(SCS_BLOCK), 0, st, I.x, I.y, I.s, I.ux,
+                           I.uy, I.vy, I.sc, nx, ny, I.sigma, s->warm_start);
+    }
+    if (hipMemsetAsync(STICKY, 0, sizeof(int) * B, st) != hipSuccess) return PSD_EDEVICE;
+    for (int b = 0; b < B; ++b)   // an instance stopped at setup still has a block in the batched projection
+        if (inst[b].done && hipMemsetAsync(inst[b].zy, 0, sizeof(double) * (size_t)ny, st) != hipSuccess)
+            return PSD_EDEVICE;
     SCS_LAUNCHED();
 
     // the cone input q = u~_r - v of the current (u, v): (u_x, z_y, q_tau)
-    auto cone_input = [&]() -> psd_status {
-        hipLaunchKernelGGL(scs_sum_kernel, dim3(grid_of(nx + ny)), dim3(SCS_BLOCK), 0, st, ux, uy, vy, zx, zy, nx, ny);
+    auto cone_input = [&](ScsInst &I) -> psd_status {
+        hipLaunchKernelGGL(scs_sum_kernel, dim3(grid_of(nx + ny)), dim3(SCS_BLOCK), 0, st, I.ux, I.uy, I.vy, I.zx,
+                           I.zy, nx, ny);
         if (hipGetLastError() != hipSuccess) return PSD_EDEVICE;
-        const psd_status e = psd_affine_step(d, zx, zy, zx, zy, aff, L.aff_bytes, st);
+        const psd_status e = psd_affine_step(d, I.zx, I.zy, I.zx, I.zy, aff, L.aff_bytes, st);
         if (e != PSD_OK) return e;
-        hipLaunchKernelGGL(scs_dot_kernel, dim3(parts_x), dim3(SCS_BLOCK), 0, st, cv, zx, zy, nx, n, sigma, gamma,
-                           part);
-        hipLaunchKernelGGL(scs_tau_kernel, dim3(1), dim3(64), 0, st, part, parts_x, sc, eta, alpha);
-        hipLaunchKernelGGL(scs_update_kernel, dim3(grid_of(nx + ny)), dim3(SCS_BLOCK), 0, st, zx, zy, mhx, mhy, ux,
-                           uy, vy, sc, nx, ny, alpha);
+        hipLaunchKernelGGL(scs_dot_kernel, dim3(parts_x), dim3(SCS_BLOCK), 0, st, I.cv, I.zx, I.zy, nx, n, I.sigma,
+                           gamma, part);
+        hipLaunchKernelGGL(scs_tau_kernel, dim3(1), dim3(64), 0, st, part, parts_x, I.sc, I.eta, alpha);
+        hipLaunchKernelGGL(scs_update_kernel, dim3(grid_of(nx + ny)), dim3(SCS_BLOCK), 0, st, I.zx, I.zy, I.mhx,
+                           I.mhy, I.ux, I.uy, I.vy, I.sc, nx, ny, alpha);
         return hipGetLastError() == hipSuccess ? PSD_OK : PSD_EDEVICE;
     };
 
-    // Anderson state
-    const QView qv{ux, zy, sc, nx, ny};
-    double *qk = L.m ? D(L.qk) : nullptr, *qprev = L.m ? D(L.qprev) : nullptr;
-    double *fprev = L.m ? D(L.fprev) : nullptr, *gsave = L.m ? D(L.gsave) : nullptr;
-    double *Sb = L.m ? D(L.S) : nullptr, *Yb = L.m ? D(L.Y) : nullptr;
-    double *aapart = L.m ? D(L.aapart) : nullptr, *aaout = L.m ? D(L.aaout) : nullptr;
+    // Anderson, first half: the new pair and the inner products (device)
     const int aa_parts = std::min<int64_t>(SCS_PARTS, std::max<int64_t>(1, grid_of(nq)));
-    AaHost aa;
-    aa.m = L.m;
-
-    // after G(q_k) is in q: the next input (accelerated, plain or restored)
-    auto anderson = [&]() -> psd_status {
-        int jnew = -1;
-        int evict = -1;
-        if (aa.have_prev) {
-            if (aa.count < aa.m) {
+    std::vector<AaCols> cols(B);
+    std::vector<int> jnew(B, -1), evict(B, -1);
+    auto anderson_launch = [&](int b) -> psd_status {
+        ScsInst &I = inst[b];
+        const QView qv{I.ux, I.zy, I.sc, nx, ny};
+        jnew[b] = evict[b] = -1;
+        if (I.aa.have_prev) {
+            if (I.aa.count < I.aa.m) {
                 bool used[AA_MAX] = {};
-                for (int c = 0; c < aa.count; ++c) used[aa.order[c]] = true;
-                for (int i = 0; i < aa.m; ++i)
-                    if (!used[i]) { jnew = i; break; }
+                for (int c = 0; c < I.aa.count; ++c) used[I.aa.order[c]] = true;
+                for (int i = 0; i < I.aa.m; ++i)
+                    if (!used[i]) { jnew[b] = i; break; }
             } else {
-                jnew = evict = aa.order[0];
+                jnew[b] = evict[b] = I.aa.order[0];
             }
         }
-        hipLaunchKernelGGL(aa_pair_kernel, dim3(grid_of(nq)), dim3(SCS_BLOCK), 0, st, qv, qk, qprev, fprev, Sb, Yb,
-                           L.ld, jnew, nq);
-        AaCols cols{};
+        hipLaunchKernelGGL(aa_pair_kernel, dim3(grid_of(nq)), dim3(SCS_BLOCK), 0, st, qv, I.qk, I.qprev, I.fprev,
+                           I.S, I.Y, L.ld, jnew[b], nq);
+        AaCols &cl = cols[b];
+        cl = AaCols{};
         int ncols = 0;
-        for (int c = 0; c < aa.count; ++c)
-            if (aa.order[c] != evict) cols.slot[ncols++] = aa.order[c];
-        if (jnew >= 0) cols.slot[ncols++] = jnew;
-        cols.count = ncols;
-        cols.jnew = jnew;
-        hipLaunchKernelGGL(aa_dot_kernel, dim3(aa_parts), dim3(SCS_BLOCK), 0, st, Sb, Yb, L.ld, fprev, cols, nq, aapart,
-                           SCS_PARTS);
-        const int nvals = 3 + 3 * ncols;
-        hipLaunchKernelGGL(aa_dot_final_kernel, dim3(nvals), dim3(64), 0, st, aapart, aa_parts, SCS_PARTS, aaout);
-        if (hipGetLastError() != hipSuccess) return PSD_EDEVICE;
-        double v[AA_VALS];
-        if (hipMemcpyAsync(v, aaout, sizeof(double) * nvals, hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess)
-            return PSD_EDEVICE;
+        for (int c = 0; c < I.aa.count; ++c)
+            if (I.aa.order[c] != evict[b]) cl.slot[ncols++] = I.aa.order[c];
+        if (jnew[b] >= 0) cl.slot[ncols++] = jnew[b];
+        cl.count = ncols;
+        cl.jnew = jnew[b];
+        hipLaunchKernelGGL(aa_dot_kernel, dim3(aa_parts), dim3(SCS_BLOCK), 0, st, I.S, I.Y, L.ld, I.fprev, cl, nq,
+                           aapart, SCS_PARTS);
+        hipLaunchKernelGGL(aa_dot_final_kernel, dim3(3 + 3 * ncols), dim3(64), 0, st, aapart, aa_parts, SCS_PARTS,
+                           I.aaout);
+        return hipGetLastError() == hipSuccess ? PSD_OK : PSD_EDEVICE;
+    };
+    // Anderson, second half: the host decision and the next input
+    auto anderson_finish = [&](int b, const double *v) -> psd_status {
+        ScsInst &I = inst[b];
+        const QView qv{I.ux, I.zy, I.sc, nx, ny};
+        const AaCols &cl = cols[b];
+        const int ncols = cl.count;
         const double nf = std::sqrt(v[0]);
-        if (aa.pending) {
-            aa.pending = false;
-            if (!(nf <= 2.0 * aa.nf_save)) {      // safeguard: back to the plain input
-                hipLaunchKernelGGL(aa_copy_kernel, dim3(grid_of(nq)), dim3(SCS_BLOCK), 0, st, qv, qk, gsave, nq);
-                aa.reset();
-                ++aa.rejected;
+        if (I.aa.pending) {
+            I.aa.pending = false;
+            if (!(nf <= 2.0 * I.aa.nf_save)) {      // safeguard: back to the plain input
+                hipLaunchKernelGGL(aa_copy_kernel, dim3(grid_of(nq)), dim3(SCS_BLOCK), 0, st, qv, I.qk, I.gsave, nq);
+                I.aa.reset();
+                ++I.aa.rejected;
                 return hipGetLastError() == hipSuccess ? PSD_OK : PSD_EDEVICE;
             }
         }
-        if (jnew >= 0) {
+        if (jnew[b] >= 0) {
             for (int c = 0; c < ncols; ++c) {
-                const int i = cols.slot[c];
-                aa.M[i][jnew] = v[3 + 3 * c];   // s_i^T y_j
-                aa.M[jnew][i] = v[4 + 3 * c];   // s_j^T y_i
+                const int i = cl.slot[c];
+                I.aa.M[i][jnew[b]] = v[3 + 3 * c];   // s_i^T y_j
+                I.aa.M[jnew[b]][i] = v[4 + 3 * c];   // s_j^T y_i
             }
-            aa.ss[jnew] = v[1];
-            aa.yy[jnew] = v[2];
-            for (int c = 0; c < ncols; ++c) aa.order[c] = cols.slot[c];
-            aa.count = ncols;
+            I.aa.ss[jnew[b]] = v[1];
+            I.aa.yy[jnew[b]] = v[2];
+            for (int c = 0; c < ncols; ++c) I.aa.order[c] = cl.slot[c];
+            I.aa.count = ncols;
         }
-        aa.have_prev = true;
-        bool step = aa.count > 0;
+        I.aa.have_prev = true;
+        bool step = I.aa.count > 0;
         AaGamma gm{};
         if (step) {
-            const int c = aa.count;
-            double A[AA_MAX * AA_MAX], b[AA_MAX], s2 = 0.0, y2 = 0.0;
-            for (int p = 0; p < c; ++p) {
-                s2 += aa.ss[aa.order[p]];
-                y2 += aa.yy[aa.order[p]];
+            const int c = I.aa.count;
+            double A[AA_MAX * AA_MAX], bb[AA_MAX], s2 = 0.0, y2 = 0.0;
+            for (int q = 0; q < c; ++q) {
+                s2 += I.aa.ss[I.aa.order[q]];
+                y2 += I.aa.yy[I.aa.order[q]];
             }
             const double lam = 1e-8 * std::sqrt(s2) * std::sqrt(y2);
-            for (int p = 0; p < c; ++p) {
-                for (int q2 = 0; q2 < c; ++q2) A[p * c + q2] = aa.M[aa.order[p]][aa.order[q2]] + (p == q2 ? lam : 0.0);
-                b[p] = v[5 + 3 * p];              // s_i^T f, columns in the order above
+            for (int q = 0; q < c; ++q) {
+                for (int r2 = 0; r2 < c; ++r2)
+                    A[q * c + r2] = I.aa.M[I.aa.order[q]][I.aa.order[r2]] + (q == r2 ? lam : 0.0);
+                bb[q] = v[5 + 3 * q];              // s_i^T f, columns in the order above
             }
-            step = small_solve(c, A, b);
-            for (int p = 0; step && p < c; ++p) step = std::fabs(b[p]) <= 1e10;
+            step = small_solve(c, A, bb);
+            for (int q = 0; step && q < c; ++q) step = std::fabs(bb[q]) <= 1e10;
             if (step) {
-                for (int p = 0; p < c; ++p) {
-                    gm.g[p] = b[p];
-                    gm.slot[p] = aa.order[p];
+                for (int q = 0; q < c; ++q) {
+                    gm.g[q] = bb[q];
+                    gm.slot[q] = I.aa.order[q];
                 }
                 gm.count = c;
             }
         }
         if (step) {
-            hipLaunchKernelGGL(aa_extrapolate_kernel, dim3(grid_of(nq)), dim3(SCS_BLOCK), 0, st, qv, Sb, Yb, L.ld, gm,
-                               qk, gsave, nq);
-            aa.pending = true;
-            aa.nf_save = nf;
-            ++aa.accepted;
+            hipLaunchKernelGGL(aa_extrapolate_kernel, dim3(grid_of(nq)), dim3(SCS_BLOCK), 0, st, qv, I.S, I.Y, L.ld,
+                               gm, I.qk, I.gsave, nq);
+            I.aa.pending = true;
+            I.aa.nf_save = nf;
+            ++I.aa.accepted;
         } else {
-            hipLaunchKernelGGL(aa_copy_kernel, dim3(grid_of(nq)), dim3(SCS_BLOCK), 0, st, qv, qk, nullptr, nq);
+            hipLaunchKernelGGL(aa_copy_kernel, dim3(grid_of(nq)), dim3(SCS_BLOCK), 0, st, qv, I.qk, nullptr, nq);
         }
         return hipGetLastError() == hipSuccess ? PSD_OK : PSD_EDEVICE;
+    };
+
+    // the unscaled outputs of an instance, written when it stops (later
+    // batched projections may recompute its u_y in another mode)
+    auto write_outputs = [&](ScsInst &I) {
+        hipLaunchKernelGGL(scs_out_kernel, dim3(grid_of(nx + ny)), dim3(SCS_BLOCK), 0, st, I.ux, I.uy, I.vy, I.x, I.y,
+                           I.s, I.sc, nx, ny, I.sigma);
     };
 
     // ---- iterations -------------------------------------------------------
     const int parts_r = std::min(SCS_PARTS, std::max(n, 1));
     const double bound_b = gamma;   // ||b||_inf
-    int status = PSD_ENOCONV;
+    std::vector<int32_t> sizes(B, n);
+    std::vector<double> aa_host((size_t)AA_VALS * B);
+    bool switched = false;          // the batch left the mixed cone steps
     int k = 0;
-    bool switched = false;   // left the mixed cone steps on the residuals
-    double r[R_SLOTS + 2] = {};
-    SCS_TRY(cone_input());
-    if (L.m) {
-        hipLaunchKernelGGL(aa_copy_kernel, dim3(grid_of(nq)), dim3(SCS_BLOCK), 0, st, qv, qk, nullptr, nq);
-        SCS_LAUNCHED();
+    for (int b = 0; b < B; ++b) {
+        if (inst[b].done) continue;
+        SCS_TRY(cone_input(inst[b]));
+        if (L.m) hipLaunchKernelGGL(aa_copy_kernel, dim3(grid_of(nq)), dim3(SCS_BLOCK), 0, st,
+                                    QView{inst[b].ux, inst[b].zy, inst[b].sc, nx, ny}, inst[b].qk, nullptr, nq);
     }
+    SCS_LAUNCHED();
+    int last = 0;
     for (k = 1; k <= s->max_iters; ++k) {
-        // cone step: u_y = Pi(q_y), v_s = u_y - q_y, tau, kappa
+        // cone step of every instance: u_y = Pi(q_y) in one batched call
+        // (cheaper than calls over the runs of running instances, whose
+        // smaller groups are latency-bound: a stopped instance's block is
+        // projected again, its outputs already written), then v_s = u_y - q_y,
+        // tau, kappa for the running ones
         const psd_mode mode = (k <= s->mixed_iters && !switched) ? (psd_mode)s->mixed_mode : PSD_FP64_EIG;
-        SCS_TRY(psd_project(n, zy, uy, mode, proj, L.proj_bytes, st, pinfo, nullptr));
-        hipLaunchKernelGGL(scs_fold_kernel, dim3(1), dim3(64), 0, st, pinfo, sticky);
-        hipLaunchKernelGGL(scs_dual_kernel, dim3(grid_of(ny)), dim3(SCS_BLOCK), 0, st, vy, zy, uy, sc, ny);
+        SCS_TRY(psd_project_batched(B, sizes.data(), ZY, UY, mode, proj, L.proj_bytes, st, PINFO));
+        for (int b = 0; b < B; ++b) {
+            ScsInst &I = inst[b];
+            if (I.done) continue;
+            hipLaunchKernelGGL(scs_fold_kernel, dim3(1), dim3(64), 0, st, I.pinfo, I.sticky);
+            hipLaunchKernelGGL(scs_dual_kernel, dim3(grid_of(ny)), dim3(SCS_BLOCK), 0, st, I.vy, I.zy, I.uy, I.sc, ny);
+        }
         SCS_LAUNCHED();
+        last = k;
         if (k % s->check_every == 0 || k == s->max_iters) {
-            SCS_TRY(psd_constraint_apply(d, ux, ty, aff, L.aff_bytes, st));
-            SCS_TRY(psd_constraint_adjoint(d, uy, tx, aff, L.aff_bytes, st));
-            hipLaunchKernelGGL(scs_resid_kernel, dim3(parts_r), dim3(SCS_BLOCK), 0, st, ty, vy, uy, tx, ux, cv, sc, n,
-                               nx, sigma, gamma, part);
-            hipLaunchKernelGGL(scs_resid_final_kernel, dim3(1), dim3(64 * R_SLOTS), 0, st, part, parts_r, sc, red);
-            SCS_LAUNCHED();
-            SCS_READ(r, red, sizeof r);
-            const double tau = r[R_SLOTS], kappa = r[R_SLOTS + 1];
-            info->tau = tau;
-            info->kappa = kappa;
-            bool finite = std::isfinite(tau) && std::isfinite(kappa);
-            for (int q2 = 0; q2 < R_SLOTS; ++q2) finite = finite && std::isfinite(r[q2]);
-            if (!finite) {
-                status = PSD_ENONFINITE;
-                break;
+            for (int b = 0; b < B; ++b) {
+                ScsInst &I = inst[b];
+                if (I.done) continue;
+                SCS_TRY(psd_constraint_apply(d, I.ux, I.ty, aff, L.aff_bytes, st));
+                SCS_TRY(psd_constraint_adjoint(d, I.uy, I.tx, aff, L.aff_bytes, st));
+                hipLaunchKernelGGL(scs_resid_kernel, dim3(parts_r), dim3(SCS_BLOCK), 0, st, I.ty, I.vy, I.uy, I.tx,
+                                   I.ux, I.cv, I.sc, n, nx, I.sigma, gamma, part);
+                hipLaunchKernelGGL(scs_resid_final_kernel, dim3(1), dim3(64 * R_SLOTS), 0, st, part, parts_r, I.sc,
+                                   I.red);
             }
-            if (tau > 0.0) {
-                const double it = 1.0 / tau, ist = 1.0 / (sigma * tau);
-                const double res_pri = r[R_PRI] * it, ax_inf = r[R_AX] * it, s_inf = r[R_S] * it;
-                const double res_dual = r[R_DUAL] * ist, aty_inf = r[R_ATY] * ist;
-                const double cx = r[R_CX] * it, by = gamma * r[R_TRY] * ist;
-                const double gap = std::fabs(cx + by);
-                info->res_pri = res_pri;
-                info->res_dual = res_dual;
-                info->gap = gap;
-                info->pobj = b0 - cx;
-                info->dobj = b0 + by;
-                const double e = s->eps;
-                const double bp = e + e * std::max(ax_inf, std::max(s_inf, bound_b));
-                const double bd = e + e * std::max(aty_inf, c_inf);
-                const double bg = e + e * std::max(std::fabs(cx), std::fabs(by));
-                if (e > 0.0 && res_pri <= bp && res_dual <= bd && gap <= bg) {
-                    status = PSD_OK;
-                    break;
+            SCS_LAUNCHED();
+            SCS_READ(host.data(), RED, sizeof(double) * 16 * B);
+            bool all_within = true;
+            for (int b = 0; b < B; ++b) {
+                ScsInst &I = inst[b];
+                if (I.done) continue;
+                const double *r = &host[16 * b];
+                const double tau = r[R_SLOTS], kappa = r[R_SLOTS + 1];
+                I.info->tau = tau;
+                I.info->kappa = kappa;
+                I.info->iters = k;
+                bool finite = std::isfinite(tau) && std::isfinite(kappa);
+                for (int q2 = 0; q2 < R_SLOTS; ++q2) finite = finite && std::isfinite(r[q2]);
+                if (!finite) {
+                    I.status = PSD_ENONFINITE;
+                    I.done = true;
+                    write_outputs(I);
+                    continue;
                 }
-                const double ms = s->mixed_switch;
-                if (ms > 0.0 && e > 0.0 && k <= s->mixed_iters && !switched && res_pri <= ms * bp &&
-                    res_dual <= ms * bd && gap <= ms * bg) {
+                I.within = false;
+                if (tau > 0.0) {
+                    const double it = 1.0 / tau, ist = 1.0 / (I.sigma * tau);
+                    const double res_pri = r[R_PRI] * it, ax_inf = r[R_AX] * it, s_inf = r[R_S] * it;
+                    const double res_dual = r[R_DUAL] * ist, aty_inf = r[R_ATY] * ist;
+                    const double cx = r[R_CX] * it, by = gamma * r[R_TRY] * ist;
+                    const double gap = std::fabs(cx + by);
+                    I.info->res_pri = res_pri;
+                    I.info->res_dual = res_dual;
+                    I.info->gap = gap;
+                    I.info->pobj = I.b0 - cx;
+                    I.info->dobj = I.b0 + by;
+                    const double e = s->eps;
+                    const double bp = e + e * std::max(ax_inf, std::max(s_inf, bound_b));
+                    const double bd = e + e * std::max(aty_inf, I.c_inf);
+                    const double bg = e + e * std::max(std::fabs(cx), std::fabs(by));
+                    if (e > 0.0 && res_pri <= bp && res_dual <= bd && gap <= bg) {
+                        I.status = PSD_OK;
+                        I.done = true;
+                        write_outputs(I);
+                        continue;
+                    }
+                    const double ms = s->mixed_switch;
+                    I.within = ms > 0.0 && e > 0.0 && res_pri <= ms * bp && res_dual <= ms * bd && gap <= ms * bg;
+                } else {
+                    I.info->res_pri = I.info->res_dual = I.info->gap = INFINITY;
+                }
+                all_within = all_within && I.within;
+            }
+            if (!switched && k <= s->mixed_iters && s->mixed_switch > 0.0 && all_within) {
+                bool any = false;
+                for (int b = 0; b < B; ++b) any = any || !inst[b].done;
+                if (any) {
                     switched = true;
-                    info->switch_iter = k;
+                    for (int b = 0; b < B; ++b)
+                        if (!inst[b].done) inst[b].info->switch_iter = k;
                 }
-            } else {
-                info->res_pri = info->res_dual = info->gap = INFINITY;
             }
         }
-        if (k == s->max_iters) break;
-        SCS_TRY(cone_input());
-        if (L.m) SCS_TRY(anderson());
+        bool any = false;
+        for (int b = 0; b < B; ++b) any = any || !inst[b].done;
+        if (!any || k == s->max_iters) break;
+        for (int b = 0; b < B; ++b)
+            if (!inst[b].done) SCS_TRY(cone_input(inst[b]));
+        if (L.m) {
+            for (int b = 0; b < B; ++b)
+                if (!inst[b].done) SCS_TRY(anderson_launch(b));
+            SCS_READ(aa_host.data(), AAOUT, sizeof(double) * AA_VALS * B);
+        }
+        if (L.m)
+            for (int b = 0; b < B; ++b)
+                if (!inst[b].done) SCS_TRY(anderson_finish(b, &aa_host[(size_t)AA_VALS * b]));
     }
-    info->iters = std::min(k, s->max_iters);
-    info->aa_accepted = aa.accepted;
-    info->aa_rejected = aa.rejected;
-    int proj_status = 0;
-    SCS_READ(&proj_status, sticky, sizeof proj_status);
-    info->proj_status = proj_status;
-    if (status == PSD_OK && proj_status == PSD_ENONFINITE) status = PSD_ENONFINITE;
-
-    hipLaunchKernelGGL(scs_out_kernel, dim3(grid_of(nx + ny)), dim3(SCS_BLOCK), 0, st, ux, uy, vy, x, y, sl, sc, nx,
-                       ny, sigma);
+    std::vector<int> stick(B, 0);
+    SCS_READ(stick.data(), STICKY, sizeof(int) * B);
+    for (int b = 0; b < B; ++b) {
+        ScsInst &I = inst[b];
+        if (I.info->iters == 0) I.info->iters = last;
+        I.info->aa_accepted = I.aa.accepted;
+        I.info->aa_rejected = I.aa.rejected;
+        I.info->proj_status = stick[b];
+        if (I.status == PSD_OK && stick[b] == PSD_ENONFINITE) I.status = PSD_ENONFINITE;
+        if (!I.done) write_outputs(I);
+    }
     SCS_LAUNCHED();
 
     // ---- post-processing of W = b - A x (App. "Sparse SDP formulation") --
-    if (w && info->tau > 0.0 && status != PSD_ENONFINITE) {
-        SCS_TRY(psd_constraint_apply(d, ux, ty, aff, L.aff_bytes, st));
-        hipLaunchKernelGGL(scs_scale_kernel, dim3(grid_of(ny)), dim3(SCS_BLOCK), 0, st, ty, w, sc, ny, -1.0, 1);
-        hipLaunchKernelGGL(scs_diag_add_kernel, dim3(grid_of(n)), dim3(SCS_BLOCK), 0, st, w, n, gamma);
+    for (int b = 0; b < B && w; ++b) {
+        ScsInst &I = inst[b];
+        if (!(I.info->tau > 0.0) || I.status == PSD_ENONFINITE) continue;
+        SCS_TRY(psd_constraint_apply(d, I.ux, I.ty, aff, L.aff_bytes, st));
+        hipLaunchKernelGGL(scs_scale_kernel, dim3(grid_of(ny)), dim3(SCS_BLOCK), 0, st, I.ty, I.w, I.sc, ny, -1.0, 1);
+        hipLaunchKernelGGL(scs_diag_add_kernel, dim3(grid_of(n)), dim3(SCS_BLOCK), 0, st, I.w, n, gamma);
         SCS_LAUNCHED();
         // lambda_min(W) from the saved eigenvalues (ascending) of an FP64 projection
         double *saved = static_cast<double *>(aff);
-        SCS_TRY(psd_project(n, w, zy, PSD_FP64_EIG, proj, L.proj_bytes, st, pinfo, saved));
+        SCS_TRY(psd_project(n, I.w, I.zy, PSD_FP64_EIG, proj, L.proj_bytes, st, I.pinfo, saved));
         double lmin = 0.0;
         psd_info pi{};
         if (hipMemcpyAsync(&lmin, saved, sizeof lmin, hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipMemcpyAsync(&pi, pinfo, sizeof pi, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipMemcpyAsync(&pi, I.pinfo, sizeof pi, hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess)
             return PSD_EDEVICE;
         double lam = 0.0;
         if (pi.status == PSD_OK && lmin < 0.0) {
             lam = -lmin / (gamma - lmin);
-            hipLaunchKernelGGL(scs_scale_kernel, dim3(grid_of(ny)), dim3(SCS_BLOCK), 0, st, w, w, sc, ny, 1.0 - lam, 0);
-            hipLaunchKernelGGL(scs_diag_add_kernel, dim3(grid_of(n)), dim3(SCS_BLOCK), 0, st, w, n, lam * gamma);
+            hipLaunchKernelGGL(scs_scale_kernel, dim3(grid_of(ny)), dim3(SCS_BLOCK), 0, st, I.w, I.w, I.sc, ny,
+                               1.0 - lam, 0);
+            hipLaunchKernelGGL(scs_diag_add_kernel, dim3(grid_of(n)), dim3(SCS_BLOCK), 0, st, I.w, n, lam * gamma);
             SCS_LAUNCHED();
         }
-        info->post_lambda = lam;
-        info->post_lambda_min = lmin;
+        I.info->post_lambda = lam;
+        I.info->post_lambda_min = lmin;
     }
-    info->status = status;
+    for (int b = 0; b < B; ++b) inst[b].info->status = inst[b].status;
 #undef SCS_TRY
 #undef SCS_LAUNCHED
 #undef SCS_READ
     return PSD_OK;
+}
+
+}  // namespace
+
+}  // namespace psd
+
+using namespace psd;
+
+extern "C" {
+
+psd_status psd_scs_workspace_size(const psd_scs_settings *s, size_t *bytes) {
+    return psd_scs_workspace_size_batched(s, 1, bytes);
+}
+
+psd_status psd_scs_workspace_size_batched(const psd_scs_settings *s, int32_t nbatch, size_t *bytes) {
+    if (!settings_ok(s) || !bytes || nbatch < 1) return PSD_EINVAL;
+    ScsLayout L;
+    if (!scs_layout(*s, nbatch, L)) return PSD_EINVAL;
+    *bytes = L.total;
+    return PSD_OK;
+}
+
+psd_status psd_scs_solve(const psd_scs_settings *s, const double *g, double *x, double *y, double *s_out, double *w,
+                         void *ws, size_t ws_bytes, void *stream, psd_scs_info *info) {
+    return scs_solve_batch(s, 1, g, x, y, s_out, w, ws, ws_bytes, stream, info);
+}
+
+psd_status psd_scs_solve_batched(const psd_scs_settings *s, int32_t nbatch, const double *g, double *x, double *y,
+                                 double *s_out, double *w, void *ws, size_t ws_bytes, void *stream,
+                                 psd_scs_info *infos) {
+    return scs_solve_batch(s, nbatch, g, x, y, s_out, w, ws, ws_bytes, stream, infos);
 }
 
 }  // extern "C"

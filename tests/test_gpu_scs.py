@@ -244,3 +244,28 @@ def test_d8_iterations(P):
     w = r["w"]
     pw = P.project(w, n)
     assert float(torch.linalg.vector_norm(pw - w)) <= 1e-10 * float(torch.linalg.vector_norm(w))
+
+
+@pytest.mark.parametrize("d, anderson", [(3, 0), (4, 5)])
+def test_batched_equals_single_solves(P, d, anderson):
+    # instances of a batch advance in lockstep, their cone steps in one
+    # batched projection: each equals its own single solve bit for bit; an
+    # instance with a non-finite objective stops at setup without touching
+    # the others
+    import torch
+    gs = [W.upper_pack(W.gyni_objective(d, seed)) for seed in (7, 8, 9)]
+    bad = gs[1].copy()
+    bad[3] = np.nan
+    batch = np.stack([gs[0], bad, gs[2]])
+    outs = P.scs_solve_batched(dev(batch), d, eps=1e-6, max_iters=5000, anderson=anderson)
+    assert outs[1]["status"] == 4
+    for b in (0, 2):
+        one = P.scs_solve(dev(gs[b]), d, eps=1e-6, max_iters=5000, anderson=anderson)
+        print(f"d={d} batch member {b}: {outs[b]['iters']} iterations (single {one['iters']}), "
+              f"value {outs[b]['pobj']:.10f}", flush=True)
+        assert outs[b]["status"] == 0 and one["status"] == 0
+        for key in ("iters", "pobj", "dobj", "res_pri", "res_dual", "gap", "tau", "kappa", "aa_accepted",
+                    "aa_rejected", "post_lambda"):
+            assert outs[b][key] == one[key], key
+        for key in ("x", "y", "s", "w"):
+            assert torch.equal(outs[b][key], one[key]), key
