@@ -154,6 +154,11 @@ def test_scs_settings_validation():
     assert L.psd_scs_workspace_size(ctypes.byref(st(anderson=10)), ctypes.byref(out)) == 0
     nx, ny = _lib.affine_dims(4)
     assert out.value >= plain + 24 * 8 * (nx + ny + 1)       # 2m + 4 vectors of the cone input
+    one = ctypes.c_size_t(0)
+    assert L.psd_scs_workspace_size_batched(ctypes.byref(st()), 1, ctypes.byref(one)) == 0 and one.value == plain
+    assert L.psd_scs_workspace_size_batched(ctypes.byref(st()), 8, ctypes.byref(out)) == 0
+    assert out.value > plain + 7 * 8 * (2 * ny)               # every instance's cone-step blocks
+    assert L.psd_scs_workspace_size_batched(ctypes.byref(st()), 0, ctypes.byref(out)) == 1
     for bad in (dict(d=1), dict(d=9), dict(max_iters=0), dict(check_every=0), dict(alpha=2.0), dict(alpha=0.0),
                 dict(eps=-1.0), dict(eps=float("nan")), dict(mixed_iters=5, mixed_mode=0), dict(anderson=17),
                 dict(anderson=-1), dict(mixed_switch=-1.0), dict(mixed_switch=float("inf")),
