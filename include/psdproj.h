@@ -156,7 +156,7 @@ psd_status psd_project_vjp(int32_t n, const double *x, const double *saved,
  * hipGraph launch.  The graph holds the whole-block LDS kernel for all blocks
  * of order <= 64 and the large blocks as jobs spread over `concurrency`
  * streams (each with its own workspace slot), fork/join by events.  A job is
- * a lockstep group: up to 32 blocks of one order (fewer where their
+ * a lockstep group: up to 128 blocks of one order (fewer where their
  * workspace would pass 4 GiB, or the group size the autotuner chose) that
  * share every kernel launch.  The graph is captured on a
  * stream the plan owns the first time a given (x, y, ws, infos) is executed

@@ -100,9 +100,9 @@ hipError_t upload_table(void *dst, const void *src, size_t bytes, hipStream_t s)
 }
 
 // Lockstep groups: blocks of one order n > 64 go through the path (FP64 or
-// mixed) together, at most group_cap(n, mode) at a time (32, fewer where 32
+// mixed) together, at most group_cap(n, mode) at a time (128, fewer where 128
 // workspace slots would pass 4 GiB).
-constexpr int kMaxGroup = 32;
+constexpr int kMaxGroup = 128;
 constexpr size_t kGroupBytes = size_t(4) << 30;
 
 // Workspace slot of one group member.

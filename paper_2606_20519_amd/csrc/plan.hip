@@ -297,7 +297,7 @@ psd_status psd_plan_tune(psd_plan p, const double *x, double *y, void *ws, size_
                 break;
             }
         }
-    // group sizes: the memory-derived limit (up to 32), then 16 and 8 where
+    // group sizes: the memory-derived limit (up to 128), then 16 and 8 where
     // they split differently; for each, concurrency 1, 2, 4, ... and the
     // number of jobs.  Each candidate is captured and replayed once untimed,
     // then scored by its fastest of `reps` timed replays (the minimum is not

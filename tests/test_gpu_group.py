@@ -65,10 +65,10 @@ def test_group_members_select_different_sides(P):
 
 
 def test_group_cap_splits_into_chunks(P):
-    # 40 blocks of one order: a group of 32 and one of 8
-    sizes = [65] * 40
-    parts = [W.gue(65, 7100 + i) for i in range(40)]
-    check_against_single(P, parts, sizes, oracle_every=7)
+    # 130 blocks of one order: a group of 128 and one of 2
+    sizes = [65] * 130
+    parts = [W.gue(65, 7100 + i) for i in range(130)]
+    check_against_single(P, parts, sizes, oracle_every=13)
 
 
 def test_cone_blocks_grouped(P):
