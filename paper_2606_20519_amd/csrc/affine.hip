@@ -169,10 +169,29 @@ constexpr int AFF_PER = 4096 / AFF_T;      // tile entries per thread (D^2 <= 40
 // (base nullable); a block strictly below the diagonal is left to its
 // mirror.  One workgroup per slab; the block stays in LDS (64 KiB at d = 8,
 // two workgroups per CU), each mode's results staged in registers.
+// Instance z of a batch (blockIdx.z) uses every pointer moved by z times its
+// stride (elements); single calls pass zero strides.
+// Per-instance strides of a batch (instance = grid z); an instance whose
+// flag in `active` (nullable) is 0 is skipped.
+struct AffStrides {
+    int64_t y, t, base, yout;
+    const int *active;
+};
+
 __global__ void __launch_bounds__(AFF_T) aff_slab_kernel(const double *__restrict__ ysv, const cd *__restrict__ tin,
-                                                         cd *tout, const double *base, double *yout, int d, int dir) {
+                                                         cd *tout, const double *base, double *yout, int d, int dir,
+                                                         AffStrides zs) {
     __shared__ cd S[4096];
     __shared__ AffTab tab;
+    if (zs.active && !zs.active[blockIdx.z]) return;
+    {
+        const int64_t z = blockIdx.z;
+        if (ysv) ysv += z * zs.y;
+        if (tin) tin += z * zs.t;
+        if (tout) tout += z * zs.t;
+        if (base) base += z * zs.base;
+        if (yout) yout += z * zs.yout;
+    }
     const int D = d * d, n = D * D, DD = D * D;
     const int slab = blockIdx.x;
     const int p1 = slab / D, p2 = slab - p1 * D;
@@ -259,11 +278,26 @@ __global__ void __launch_bounds__(AFF_T) aff_slab_kernel(const double *__restric
 // x = -Re c (A^T y), or (a_x + Re c)/2 with a_x given; mode 0, dir 1 reads
 // its input from x (coefficient -1 at the allowed indices, 0 elsewhere)
 // instead of a tensor.
+// Strides as for aff_slab_kernel: t for the tensors, x for x_in / a_x / x_out.
+struct AffOuterStrides {
+    int64_t t, x;
+    const int *active;
+};
+
 __global__ void __launch_bounds__(AFF_T) aff_outer_kernel(const cd *__restrict__ tin, cd *tout,
                                                           const double *__restrict__ xin, const double *ax,
-                                                          double *xout, int d, int m, int dir) {
+                                                          double *xout, int d, int m, int dir, AffOuterStrides zs) {
     __shared__ cd tile[64][64];
     __shared__ AffTab tab;
+    if (zs.active && !zs.active[blockIdx.z]) return;
+    {
+        const int64_t z = blockIdx.z;
+        if (tin) tin += z * zs.t;
+        if (tout) tout += z * zs.t;
+        if (xin) xin += z * zs.x;
+        if (ax) ax += z * zs.x;
+        if (xout) xout += z * zs.x;
+    }
     const int D = d * d, DD = D * D;
     const int R = m == 0 ? DD * D : DD;
     const int ntr = (R + 63) / 64;
@@ -305,26 +339,32 @@ int aff_outer_grid(const AffGeo &g, int m) {
 }
 
 // x = A^T y, or z_x = (a_x - A^T y)/2 when ax is given: modes 3 and 2 with
-// the svec unpack, mode 1, mode 0 with the gather.
-hipError_t aff_adjoint(const AffGeo &g, const double *y, const double *ax, double *x, cd *b0, cd *b1, hipStream_t st) {
-    hipLaunchKernelGGL(aff_slab_kernel, dim3(g.D * g.D), dim3(AFF_T), 0, st, y, (const cd *)nullptr, b0,
-                       (const double *)nullptr, (double *)nullptr, g.d, 0);
-    hipLaunchKernelGGL(aff_outer_kernel, dim3(aff_outer_grid(g, 1)), dim3(AFF_T), 0, st, b0, b1, (const double *)nullptr,
-                       (const double *)nullptr, (double *)nullptr, g.d, 1, 0);
-    hipLaunchKernelGGL(aff_outer_kernel, dim3(aff_outer_grid(g, 0)), dim3(AFF_T), 0, st, b1, (cd *)nullptr,
-                       (const double *)nullptr, ax, x, g.d, 0, 0);
+// the svec unpack, mode 1, mode 0 with the gather.  nb instances (grid z):
+// y, a_x and x move by ys and xs elements per instance, the two tensors b0,
+// b1 by ts elements.
+hipError_t aff_adjoint(const AffGeo &g, const double *y, const double *ax, double *x, cd *b0, cd *b1, hipStream_t st,
+                       int nb = 1, int64_t ys = 0, int64_t xs = 0, int64_t ts = 0, const int *act = nullptr) {
+    hipLaunchKernelGGL(aff_slab_kernel, dim3(g.D * g.D, 1, nb), dim3(AFF_T), 0, st, y, (const cd *)nullptr, b0,
+                       (const double *)nullptr, (double *)nullptr, g.d, 0, AffStrides{ys, ts, 0, 0, act});
+    hipLaunchKernelGGL(aff_outer_kernel, dim3(aff_outer_grid(g, 1), 1, nb), dim3(AFF_T), 0, st, b0, b1,
+                       (const double *)nullptr, (const double *)nullptr, (double *)nullptr, g.d, 1, 0,
+                       AffOuterStrides{ts, 0, act});
+    hipLaunchKernelGGL(aff_outer_kernel, dim3(aff_outer_grid(g, 0), 1, nb), dim3(AFF_T), 0, st, b1, (cd *)nullptr,
+                       (const double *)nullptr, ax, x, g.d, 0, 0, AffOuterStrides{ts, xs, act});
     return hipGetLastError();
 }
 
 // y = base + A x (base nullable): mode 0 with the scatter, mode 1, modes 2
-// and 3 with the svec pack.
-hipError_t aff_apply(const AffGeo &g, const double *x, const double *base, double *y, cd *b0, cd *b1, hipStream_t st) {
-    hipLaunchKernelGGL(aff_outer_kernel, dim3(aff_outer_grid(g, 0)), dim3(AFF_T), 0, st, (const cd *)nullptr, b0, x,
-                       (const double *)nullptr, (double *)nullptr, g.d, 0, 1);
-    hipLaunchKernelGGL(aff_outer_kernel, dim3(aff_outer_grid(g, 1)), dim3(AFF_T), 0, st, b0, b1, (const double *)nullptr,
-                       (const double *)nullptr, (double *)nullptr, g.d, 1, 1);
-    hipLaunchKernelGGL(aff_slab_kernel, dim3(g.D * g.D), dim3(AFF_T), 0, st, (const double *)nullptr, b1, (cd *)nullptr,
-                       base, y, g.d, 1);
+// and 3 with the svec pack; batched as aff_adjoint.
+hipError_t aff_apply(const AffGeo &g, const double *x, const double *base, double *y, cd *b0, cd *b1, hipStream_t st,
+                     int nb = 1, int64_t xs = 0, int64_t ys = 0, int64_t ts = 0, const int *act = nullptr) {
+    hipLaunchKernelGGL(aff_outer_kernel, dim3(aff_outer_grid(g, 0), 1, nb), dim3(AFF_T), 0, st, (const cd *)nullptr,
+                       b0, x, (const double *)nullptr, (double *)nullptr, g.d, 0, 1, AffOuterStrides{ts, xs, act});
+    hipLaunchKernelGGL(aff_outer_kernel, dim3(aff_outer_grid(g, 1), 1, nb), dim3(AFF_T), 0, st, b0, b1,
+                       (const double *)nullptr, (const double *)nullptr, (double *)nullptr, g.d, 1, 1,
+                       AffOuterStrides{ts, 0, act});
+    hipLaunchKernelGGL(aff_slab_kernel, dim3(g.D * g.D, 1, nb), dim3(AFF_T), 0, st, (const double *)nullptr, b1,
+                       (cd *)nullptr, base, y, g.d, 1, AffStrides{0, ts, ys, ys, act});
     return hipGetLastError();
 }
 
@@ -342,6 +382,40 @@ psd_status aff_check(int d, size_t ws_bytes, const void *ws) {
 }
 
 }  // namespace
+
+// Batched forms for the SCS solver (one launch per pass for nb instances):
+// instance z reads and writes its vectors ys / xs elements after instance
+// 0's, and uses the two tensors of its workspace, wss bytes after instance
+// 0's workspace (psd_affine_workspace_size bytes each).
+hipError_t affine_step_batched(int d, const double *ax, const double *ay, double *zx, double *zy, int64_t xs,
+                               int64_t ys, void *ws, int64_t wss, int nb, const int *active, hipStream_t st) {
+    const AffGeo g = aff_geo(d);
+    const size_t one = ((size_t)g.total * sizeof(cd) + 255) / 256 * 256;
+    if (wss % (int64_t)sizeof(cd)) return hipErrorInvalidValue;
+    cd *b0 = static_cast<cd *>(ws), *b1 = reinterpret_cast<cd *>(static_cast<char *>(ws) + one);
+    const int64_t ts = wss / (int64_t)sizeof(cd);
+    hipError_t e = aff_adjoint(g, ay, ax, zx, b0, b1, st, nb, ys, xs, ts, active);
+    if (e != hipSuccess) return e;
+    return aff_apply(g, zx, ay, zy, b0, b1, st, nb, xs, ys, ts, active);
+}
+
+hipError_t constraint_apply_batched(int d, const double *x, double *y, int64_t xs, int64_t ys, void *ws, int64_t wss,
+                                    int nb, const int *active, hipStream_t st) {
+    const AffGeo g = aff_geo(d);
+    const size_t one = ((size_t)g.total * sizeof(cd) + 255) / 256 * 256;
+    if (wss % (int64_t)sizeof(cd)) return hipErrorInvalidValue;
+    cd *b0 = static_cast<cd *>(ws), *b1 = reinterpret_cast<cd *>(static_cast<char *>(ws) + one);
+    return aff_apply(g, x, nullptr, y, b0, b1, st, nb, xs, ys, wss / (int64_t)sizeof(cd), active);
+}
+
+hipError_t constraint_adjoint_batched(int d, const double *y, double *x, int64_t ys, int64_t xs, void *ws,
+                                      int64_t wss, int nb, const int *active, hipStream_t st) {
+    const AffGeo g = aff_geo(d);
+    const size_t one = ((size_t)g.total * sizeof(cd) + 255) / 256 * 256;
+    if (wss % (int64_t)sizeof(cd)) return hipErrorInvalidValue;
+    cd *b0 = static_cast<cd *>(ws), *b1 = reinterpret_cast<cd *>(static_cast<char *>(ws) + one);
+    return aff_adjoint(g, y, nullptr, x, b0, b1, st, nb, ys, xs, wss / (int64_t)sizeof(cd), active);
+}
 
 }  // namespace psd
 

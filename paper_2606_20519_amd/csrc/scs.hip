@@ -50,6 +50,7 @@
 #include <vector>
 
 #include "../../include/psdproj.h"
+#include "affine.h"
 #include "common.h"
 
 namespace psd {
@@ -63,7 +64,20 @@ constexpr int SCS_BLOCK = 256;
 constexpr int SCS_PARTS = 512;   // blocks of the first reduction level
 
 // Device scalars of the iteration.
-enum { SC_UT = 0, SC_VK = 1, SC_UTT = 2, SC_QT = 3, SC_COUNT = 8 };
+enum { SC_UT = 0, SC_VK = 1, SC_UTT = 2, SC_QT = 3, SC_SIGMA = 4, SC_ETA = 5, SC_COUNT = 8 };
+
+// Instance blockIdx.z of a batch: its slot vectors sit `slot` bytes apart,
+// its cone-step blocks (u_y, z_y) `blk` bytes apart; `active` (nullable)
+// marks the instances still running (the others are left untouched).
+struct ScsZ {
+    int64_t slot, blk;
+    const int *active;
+};
+template <class T>
+__device__ __forceinline__ T *zmove(T *p, int64_t bytes) {
+    return reinterpret_cast<T *>(reinterpret_cast<uintptr_t>(p) + (uintptr_t)(bytes * (int64_t)blockIdx.z));
+}
+__device__ __forceinline__ bool zrunning(const ScsZ &z) { return !z.active || z.active[blockIdx.z]; }
 // Reduction slots.
 enum {
     R_PRI = 0,     // max |A u_x + v_s - tau b|
@@ -110,17 +124,26 @@ __device__ void block_reduce(double (&v)[NV], const bool (&is_max)[NV], const in
 // a = u + v (v_x = 0): z_x = u_x, z_y = u_y + v_s.
 __global__ void __launch_bounds__(SCS_BLOCK) scs_sum_kernel(const double *__restrict__ ux, const double *__restrict__ uy,
                                                             const double *__restrict__ vy, double *zx, double *zy,
-                                                            int64_t nx, int64_t ny) {
+                                                            int64_t nx, int64_t ny, ScsZ z) {
+    if (!zrunning(z)) return;
+    ux = zmove(ux, z.slot); vy = zmove(vy, z.slot); zx = zmove(zx, z.slot);
+    uy = zmove(uy, z.blk); zy = zmove(zy, z.blk);
     const int64_t t = (int64_t)blockIdx.x * SCS_BLOCK + threadIdx.x;
     if (t < nx) zx[t] = ux[t];
     else if (t < nx + ny) zy[t - nx] = uy[t - nx] + vy[t - nx];
 }
 
-// Partial sums of h^T z = sigma c^T z_x + gamma tr(z_y) into part[0 ..).
+// Partial sums of h^T z = sigma c^T z_x + gamma tr(z_y) into part[0 ..)
+// (sigma = sc[SC_SIGMA]).
 __global__ void __launch_bounds__(SCS_BLOCK) scs_dot_kernel(const double *__restrict__ c,
                                                             const double *__restrict__ zx,
                                                             const double *__restrict__ zy, int64_t nx, int n,
-                                                            double sigma, double gamma, double *part) {
+                                                            const double *__restrict__ sc, double gamma, double *part,
+                                                            ScsZ z) {
+    if (!zrunning(z)) return;
+    c = zmove(c, z.slot); zx = zmove(zx, z.slot); sc = zmove(sc, z.slot); part = zmove(part, z.slot);
+    zy = zmove(zy, z.blk);
+    const double sigma = sc[SC_SIGMA];
     double acc = 0.0;
     for (int64_t t = (int64_t)blockIdx.x * SCS_BLOCK + threadIdx.x; t < nx + n; t += (int64_t)gridDim.x * SCS_BLOCK)
         acc += t < nx ? sigma * c[t] * zx[t] : gamma * zy[svec_col_start(n, (int)(t - nx))];
@@ -146,10 +169,13 @@ __device__ double sum_parts(const double *part, int slot, int parts, bool is_max
 
 // tau part of the affine step: u~_tau, then the cone input
 // q_tau = alpha u~_tau + (1 - alpha) tau - kappa.  One wave.
-__global__ void __launch_bounds__(64) scs_tau_kernel(const double *part, int parts, double *sc, double eta,
-                                                     double alpha) {
+__global__ void __launch_bounds__(64) scs_tau_kernel(const double *part, int parts, double *sc, double alpha,
+                                                     ScsZ z) {
+    if (!zrunning(z)) return;
+    part = zmove(part, z.slot); sc = zmove(sc, z.slot);
     const double hz = sum_parts(part, 0, parts, false);
     if (threadIdx.x != 0) return;
+    const double eta = sc[SC_ETA];
     const double ut = sc[SC_UT], vk = sc[SC_VK];
     const double at = ut + vk;
     const double utt = at + (hz - at * eta) / (1.0 + eta);
@@ -165,7 +191,11 @@ __global__ void __launch_bounds__(SCS_BLOCK) scs_update_kernel(const double *__r
                                                                const double *__restrict__ uy,
                                                                const double *__restrict__ vy,
                                                                const double *__restrict__ sc, int64_t nx, int64_t ny,
-                                                               double alpha) {
+                                                               double alpha, ScsZ z) {
+    if (!zrunning(z)) return;
+    zx = zmove(zx, z.slot); mhx = zmove(mhx, z.slot); mhy = zmove(mhy, z.slot); ux = zmove(ux, z.slot);
+    vy = zmove(vy, z.slot); sc = zmove(sc, z.slot);
+    zy = zmove(zy, z.blk); uy = zmove(uy, z.blk);
     const int64_t t = (int64_t)blockIdx.x * SCS_BLOCK + threadIdx.x;
     const double utt = sc[SC_UTT];
     if (t < nx) {
@@ -179,7 +209,11 @@ __global__ void __launch_bounds__(SCS_BLOCK) scs_update_kernel(const double *__r
 // Cone step after the projection u_y = Pi(q_y): v_s = u_y - q_y; tau and
 // kappa from q_tau.
 __global__ void __launch_bounds__(SCS_BLOCK) scs_dual_kernel(double *vy, const double *__restrict__ qy,
-                                                             const double *__restrict__ uy, double *sc, int64_t ny) {
+                                                             const double *__restrict__ uy, double *sc, int64_t ny,
+                                                             ScsZ z) {
+    if (!zrunning(z)) return;
+    vy = zmove(vy, z.slot); sc = zmove(sc, z.slot);
+    qy = zmove(qy, z.blk); uy = zmove(uy, z.blk);
     const int64_t t = (int64_t)blockIdx.x * SCS_BLOCK + threadIdx.x;
     if (t < ny) vy[t] = uy[t] - qy[t];
     if (t == 0) {
@@ -334,8 +368,12 @@ __global__ void __launch_bounds__(SCS_BLOCK) scs_resid_kernel(const double *__re
                                                               const double *__restrict__ ux,
                                                               const double *__restrict__ c,
                                                               const double *__restrict__ sc, int n, int64_t nx,
-                                                              double sigma, double gamma, double *part) {
-    const double tau = sc[SC_UT];
+                                                              double gamma, double *part, ScsZ z) {
+    if (!zrunning(z)) return;
+    ty = zmove(ty, z.slot); vy = zmove(vy, z.slot); tx = zmove(tx, z.slot); ux = zmove(ux, z.slot);
+    c = zmove(c, z.slot); sc = zmove(sc, z.slot); part = zmove(part, z.slot);
+    uy = zmove(uy, z.blk);
+    const double tau = sc[SC_UT], sigma = sc[SC_SIGMA];
     double m_pri = 0.0, m_ax = 0.0, m_s = 0.0, m_dual = 0.0, m_aty = 0.0, s_cx = 0.0, s_try = 0.0;
     for (int i = blockIdx.x; i < n; i += gridDim.x) {
         const int64_t o = svec_col_start(n, i);
@@ -363,7 +401,10 @@ __global__ void __launch_bounds__(SCS_BLOCK) scs_resid_kernel(const double *__re
 
 // Final level: out[k] = reduction of slot k, out[R_SLOTS..] = tau, kappa.
 __global__ void __launch_bounds__(64 * R_SLOTS) scs_resid_final_kernel(const double *part, int parts,
-                                                                       const double *sc, double *out) {
+                                                                       const double *sc, double *out, ScsZ z) {
+    if (!zrunning(z)) return;
+    part = zmove(part, z.slot); sc = zmove(sc, z.slot);
+    out += 16 * (int64_t)blockIdx.z;
     const int w = threadIdx.x >> 6;
     const double x = sum_parts(part, w, parts, w < R_CX);
     if ((threadIdx.x & 63) == 0) out[w] = x;
@@ -461,27 +502,44 @@ __global__ void __launch_bounds__(SCS_BLOCK) scs_diag_add_kernel(double *y, int 
     if (t < n) y[svec_col_start(n, t)] += v;
 }
 
-// Sticky status of the cone projections: first non-OK record.
-__global__ void scs_fold_kernel(const psd_info *info, int *sticky) {
+// Sticky status of the cone projections: first non-OK record (instance
+// blockIdx.z: record and flag z).
+__global__ void scs_fold_kernel(const psd_info *info, int *sticky, ScsZ z) {
+    if (!zrunning(z)) return;
+    info += blockIdx.z;
+    sticky += blockIdx.z;
     if (threadIdx.x == 0 && *sticky == 0 && info->status != 0) *sticky = info->status;
 }
 
-// Workspace of a batch of B instances: the affine workspace, the projection
-// workspace and the reduction partials are shared (every step runs in stream
-// order); the cone-step blocks of the instances are back to back (u_y and
-// z_y, so that one batched projection covers them) as are their info
-// records, residual and Anderson read-backs; the rest of an instance's
-// vectors sit in a slot of its own, `inst` bytes apart.
+// sc[idx] = v (one instance); a[i] = v (the running flags).
+__global__ void scs_set_kernel(double *sc, int idx, double v) {
+    if (threadIdx.x == 0) sc[idx] = v;
+}
+__global__ void scs_flag_kernel(int *a, int i, int v) {
+    if (threadIdx.x == 0) a[i] = v;
+}
+__global__ void scs_flags_kernel(int *a, int nb, int v) {
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) a[i] = v;
+}
+
+// Workspace of a batch of B instances: the projection workspace and the
+// Anderson partials are shared (every step runs in stream order); the
+// cone-step blocks of the instances are back to back (u_y and z_y, so that
+// one batched projection covers them) as are their info records, residual
+// and Anderson read-backs and running flags; the rest of an instance's
+// vectors, its reduction partials and its affine workspace sit in a slot of
+// its own, `inst` bytes apart, so that one launch of each step covers the
+// batch (instance = grid z).
 struct ScsLayout {
     int d, n, B;
     int64_t nx, ny, nq;
-    size_t aff, aff_bytes;
+    size_t aff_bytes;
     size_t proj, proj_bytes;
-    size_t part, aapart;
-    size_t UY, ZY, PINFO, RED, AAOUT, STICKY;   // batched, instance b at b * (its size)
-    size_t slot0, inst;                           // instance slots
-    // offsets inside a slot
-    size_t ux, cv, mhx, zx, tx, vy, mhy, ty, sc;
+    size_t aapart;
+    size_t UY, ZY, PINFO, RED, AAOUT, STICKY, ACTIVE;   // batched, instance b at b * (its size)
+    size_t slot0, inst;                                   // instance slots
+    // offsets inside a slot (the affine workspace and the reduction partials too)
+    size_t ux, cv, mhx, zx, tx, vy, mhy, ty, sc, part, aff;
     int m;                                        // Anderson memory (0: off)
     int64_t ld;                                   // stride of the Anderson vectors (doubles)
     size_t qk, qprev, fprev, gsave, S, Y;
@@ -504,7 +562,6 @@ bool scs_layout(const psd_scs_settings &s, int B, ScsLayout &L) {
         return o;
     };
     if (psd_affine_workspace_size(s.d, &L.aff_bytes) != PSD_OK) return false;
-    L.aff = take(L.aff_bytes);
     size_t pb = 0, pg = 0, pm = 0;
     const int32_t n = L.n;
     std::vector<int32_t> sizes(B, n);
@@ -514,7 +571,6 @@ bool scs_layout(const psd_scs_settings &s, int B, ScsLayout &L) {
         return false;
     L.proj_bytes = std::max(pb, std::max(pg, pm));
     L.proj = take(L.proj_bytes);
-    L.part = take(sizeof(double) * SCS_PARTS * R_SLOTS);
     L.aapart = take(sizeof(double) * SCS_PARTS * AA_VALS);
     const size_t by = sizeof(double) * (size_t)ny, bx = sizeof(double) * (size_t)nx;
     L.UY = take(by * B);
@@ -523,6 +579,7 @@ bool scs_layout(const psd_scs_settings &s, int B, ScsLayout &L) {
     L.RED = take(sizeof(double) * 16 * B);
     L.AAOUT = take(sizeof(double) * AA_VALS * B);
     L.STICKY = take(sizeof(int) * B);
+    L.ACTIVE = take(sizeof(int) * B);
     // one instance slot
     size_t o = 0;
     auto slot = [&](size_t bytes) {
@@ -533,6 +590,8 @@ bool scs_layout(const psd_scs_settings &s, int B, ScsLayout &L) {
     L.ux = slot(bx); L.cv = slot(bx); L.mhx = slot(bx); L.zx = slot(bx); L.tx = slot(bx);
     L.vy = slot(by); L.mhy = slot(by); L.ty = slot(by);
     L.sc = slot(sizeof(double) * SC_COUNT);
+    L.part = slot(sizeof(double) * SCS_PARTS * R_SLOTS);
+    L.aff = slot(L.aff_bytes);
     L.m = s.anderson;
     L.ld = (int64_t)(align256(sizeof(double) * (size_t)L.nq) / sizeof(double));
     L.qk = L.qprev = L.fprev = L.gsave = L.S = L.Y = 0;
@@ -608,7 +667,8 @@ struct AaHost {
 
 // Host view of one instance of a batch.
 struct ScsInst {
-    double *ux, *cv, *mhx, *zx, *tx, *uy, *vy, *zy, *mhy, *ty, *sc, *red, *aaout;
+    double *ux, *cv, *mhx, *zx, *tx, *uy, *vy, *zy, *mhy, *ty, *sc, *red, *aaout, *part;
+    void *aff;
     psd_info *pinfo;
     int *sticky;
     double *qk, *qprev, *fprev, *gsave, *S, *Y;
@@ -642,12 +702,12 @@ psd_status scs_solve_batch(const psd_scs_settings *s, int B, const double *g, do
     hipStream_t st = static_cast<hipStream_t>(stream);
     char *base = static_cast<char *>(ws);
     auto D = [&](size_t off) { return reinterpret_cast<double *>(base + off); };
-    void *aff = base + L.aff;
     void *proj = base + L.proj;
-    double *part = D(L.part), *aapart = D(L.aapart);
+    double *aapart = D(L.aapart);
     double *UY = D(L.UY), *ZY = D(L.ZY), *RED = D(L.RED), *AAOUT = D(L.AAOUT);
     psd_info *PINFO = reinterpret_cast<psd_info *>(base + L.PINFO);
     int *STICKY = reinterpret_cast<int *>(base + L.STICKY);
+    int *ACTIVE = reinterpret_cast<int *>(base + L.ACTIVE);
     const int d = L.d, n = L.n;
     const int64_t nx = L.nx, ny = L.ny, nq = L.nq;
     const double gamma = 1.0 / (double)(d * d);
@@ -659,6 +719,8 @@ psd_status scs_solve_batch(const psd_scs_settings *s, int B, const double *g, do
         auto S_ = [&](size_t off) { return reinterpret_cast<double *>(sb + off); };
         I.ux = S_(L.ux); I.cv = S_(L.cv); I.mhx = S_(L.mhx); I.zx = S_(L.zx); I.tx = S_(L.tx);
         I.vy = S_(L.vy); I.mhy = S_(L.mhy); I.ty = S_(L.ty); I.sc = S_(L.sc);
+        I.part = S_(L.part);
+        I.aff = sb + L.aff;
         I.uy = UY + ny * b;
         I.zy = ZY + ny * b;
         I.red = RED + 16 * b;
@@ -696,11 +758,12 @@ psd_status scs_solve_batch(const psd_scs_settings *s, int B, const double *g, do
 
     // ---- setup: c = A^T G, norms, sigma, M^-1 h, eta (per instance) ---------
     const int parts_x = std::min<int64_t>(SCS_PARTS, std::max<int64_t>(1, grid_of(nx + n)));
+    const ScsZ one{0, 0, nullptr};
     for (int b = 0; b < B; ++b) {
         ScsInst &I = inst[b];
-        SCS_TRY(psd_constraint_adjoint(d, I.g, I.cv, aff, L.aff_bytes, st));
-        hipLaunchKernelGGL(scs_setup_kernel, dim3(parts_x), dim3(SCS_BLOCK), 0, st, I.cv, I.g, nx, n, part);
-        hipLaunchKernelGGL(scs_final3_kernel, dim3(1), dim3(64 * 3), 0, st, part, parts_x, I.red);
+        SCS_TRY(psd_constraint_adjoint(d, I.g, I.cv, I.aff, L.aff_bytes, st));
+        hipLaunchKernelGGL(scs_setup_kernel, dim3(parts_x), dim3(SCS_BLOCK), 0, st, I.cv, I.g, nx, n, I.part);
+        hipLaunchKernelGGL(scs_final3_kernel, dim3(1), dim3(64 * 3), 0, st, I.part, parts_x, I.red);
     }
     SCS_LAUNCHED();
     std::vector<double> host(16 * (size_t)B);
@@ -722,11 +785,12 @@ psd_status scs_solve_batch(const psd_scs_settings *s, int B, const double *g, do
         hipLaunchKernelGGL(scs_h_kernel, dim3(grid_of(nx + ny)), dim3(SCS_BLOCK), 0, st, I.cv, I.mhx, I.mhy, nx, n,
                            I.sigma, gamma);
         hipLaunchKernelGGL(scs_diag_add_kernel, dim3(grid_of(n)), dim3(SCS_BLOCK), 0, st, I.mhy, n, gamma);
+        hipLaunchKernelGGL(scs_set_kernel, dim3(1), dim3(64), 0, st, I.sc, (int)SC_SIGMA, I.sigma);
         SCS_LAUNCHED();
-        SCS_TRY(psd_affine_step(d, I.mhx, I.mhy, I.mhx, I.mhy, aff, L.aff_bytes, st));
-        hipLaunchKernelGGL(scs_dot_kernel, dim3(parts_x), dim3(SCS_BLOCK), 0, st, I.cv, I.mhx, I.mhy, nx, n, I.sigma,
-                           gamma, part);
-        hipLaunchKernelGGL(scs_final3_kernel, dim3(1), dim3(64 * 3), 0, st, part, parts_x, I.red);
+        SCS_TRY(psd_affine_step(d, I.mhx, I.mhy, I.mhx, I.mhy, I.aff, L.aff_bytes, st));
+        hipLaunchKernelGGL(scs_dot_kernel, dim3(parts_x), dim3(SCS_BLOCK), 0, st, I.cv, I.mhx, I.mhy, nx, n,
+                           (const double *)I.sc, gamma, I.part, one);
+        hipLaunchKernelGGL(scs_final3_kernel, dim3(1), dim3(64 * 3), 0, st, I.part, parts_x, I.red);
     }
     SCS_LAUNCHED();
     SCS_READ(host.data(), RED, sizeof(double) * 16 * B);
@@ -741,25 +805,34 @@ psd_status scs_solve_batch(const psd_scs_settings *s, int B, const double *g, do
         }
         hipLaunchKernelGGL(scs_start_kernel, dim3(grid_of(nx + ny)), dim3(SCS_BLOCK), 0, st, I.x, I.y, I.s, I.ux,
                            I.uy, I.vy, I.sc, nx, ny, I.sigma, s->warm_start);
+        hipLaunchKernelGGL(scs_set_kernel, dim3(1), dim3(64), 0, st, I.sc, (int)SC_ETA, I.eta);
     }
+    hipLaunchKernelGGL(scs_flags_kernel, dim3(1), dim3(256), 0, st, ACTIVE, B, 1);
+    for (int b = 0; b < B; ++b)
+        if (inst[b].done) hipLaunchKernelGGL(scs_flag_kernel, dim3(1), dim3(64), 0, st, ACTIVE, b, 0);
     if (hipMemsetAsync(STICKY, 0, sizeof(int) * B, st) != hipSuccess) return PSD_EDEVICE;
     for (int b = 0; b < B; ++b)   // an instance stopped at setup still has a block in the batched projection
         if (inst[b].done && hipMemsetAsync(inst[b].zy, 0, sizeof(double) * (size_t)ny, st) != hipSuccess)
             return PSD_EDEVICE;
     SCS_LAUNCHED();
 
+    // One launch per step for the whole batch (instance = grid z); the
+    // instances that stopped are skipped by their flags.
+    ScsInst &I0 = inst[0];
+    const ScsZ zb{(int64_t)L.inst, (int64_t)(sizeof(double) * ny), ACTIVE};
+    const int64_t xs = (int64_t)(L.inst / sizeof(double));
     // the cone input q = u~_r - v of the current (u, v): (u_x, z_y, q_tau)
-    auto cone_input = [&](ScsInst &I) -> psd_status {
-        hipLaunchKernelGGL(scs_sum_kernel, dim3(grid_of(nx + ny)), dim3(SCS_BLOCK), 0, st, I.ux, I.uy, I.vy, I.zx,
-                           I.zy, nx, ny);
+    auto cone_input = [&]() -> psd_status {
+        hipLaunchKernelGGL(scs_sum_kernel, dim3(grid_of(nx + ny), 1, B), dim3(SCS_BLOCK), 0, st, I0.ux, UY, I0.vy,
+                           I0.zx, ZY, nx, ny, zb);
         if (hipGetLastError() != hipSuccess) return PSD_EDEVICE;
-        const psd_status e = psd_affine_step(d, I.zx, I.zy, I.zx, I.zy, aff, L.aff_bytes, st);
-        if (e != PSD_OK) return e;
-        hipLaunchKernelGGL(scs_dot_kernel, dim3(parts_x), dim3(SCS_BLOCK), 0, st, I.cv, I.zx, I.zy, nx, n, I.sigma,
-                           gamma, part);
-        hipLaunchKernelGGL(scs_tau_kernel, dim3(1), dim3(64), 0, st, part, parts_x, I.sc, I.eta, alpha);
-        hipLaunchKernelGGL(scs_update_kernel, dim3(grid_of(nx + ny)), dim3(SCS_BLOCK), 0, st, I.zx, I.zy, I.mhx,
-                           I.mhy, I.ux, I.uy, I.vy, I.sc, nx, ny, alpha);
+        if (affine_step_batched(d, I0.zx, ZY, I0.zx, ZY, xs, ny, I0.aff, (int64_t)L.inst, B, ACTIVE, st) != hipSuccess)
+            return PSD_EDEVICE;
+        hipLaunchKernelGGL(scs_dot_kernel, dim3(parts_x, 1, B), dim3(SCS_BLOCK), 0, st, I0.cv, I0.zx, ZY, nx, n,
+                           (const double *)I0.sc, gamma, I0.part, zb);
+        hipLaunchKernelGGL(scs_tau_kernel, dim3(1, 1, B), dim3(64), 0, st, I0.part, parts_x, I0.sc, alpha, zb);
+        hipLaunchKernelGGL(scs_update_kernel, dim3(grid_of(nx + ny), 1, B), dim3(SCS_BLOCK), 0, st, I0.zx, ZY, I0.mhx,
+                           I0.mhy, I0.ux, UY, I0.vy, I0.sc, nx, ny, alpha, zb);
         return hipGetLastError() == hipSuccess ? PSD_OK : PSD_EDEVICE;
     };
 
@@ -876,9 +949,9 @@ psd_status scs_solve_batch(const psd_scs_settings *s, int B, const double *g, do
     std::vector<double> aa_host((size_t)AA_VALS * B);
     bool switched = false;          // the batch left the mixed cone steps
     int k = 0;
+    SCS_TRY(cone_input());
     for (int b = 0; b < B; ++b) {
         if (inst[b].done) continue;
-        SCS_TRY(cone_input(inst[b]));
         if (L.m) hipLaunchKernelGGL(aa_copy_kernel, dim3(grid_of(nq)), dim3(SCS_BLOCK), 0, st,
                                     QView{inst[b].ux, inst[b].zy, inst[b].sc, nx, ny}, inst[b].qk, nullptr, nq);
     }
@@ -892,25 +965,19 @@ psd_status scs_solve_batch(const psd_scs_settings *s, int B, const double *g, do
         // tau, kappa for the running ones
         const psd_mode mode = (k <= s->mixed_iters && !switched) ? (psd_mode)s->mixed_mode : PSD_FP64_EIG;
         SCS_TRY(psd_project_batched(B, sizes.data(), ZY, UY, mode, proj, L.proj_bytes, st, PINFO));
-        for (int b = 0; b < B; ++b) {
-            ScsInst &I = inst[b];
-            if (I.done) continue;
-            hipLaunchKernelGGL(scs_fold_kernel, dim3(1), dim3(64), 0, st, I.pinfo, I.sticky);
-            hipLaunchKernelGGL(scs_dual_kernel, dim3(grid_of(ny)), dim3(SCS_BLOCK), 0, st, I.vy, I.zy, I.uy, I.sc, ny);
-        }
+        hipLaunchKernelGGL(scs_fold_kernel, dim3(1, 1, B), dim3(64), 0, st, PINFO, STICKY, zb);
+        hipLaunchKernelGGL(scs_dual_kernel, dim3(grid_of(ny), 1, B), dim3(SCS_BLOCK), 0, st, I0.vy, ZY, UY, I0.sc, ny,
+                           zb);
         SCS_LAUNCHED();
         last = k;
         if (k % s->check_every == 0 || k == s->max_iters) {
-            for (int b = 0; b < B; ++b) {
-                ScsInst &I = inst[b];
-                if (I.done) continue;
-                SCS_TRY(psd_constraint_apply(d, I.ux, I.ty, aff, L.aff_bytes, st));
-                SCS_TRY(psd_constraint_adjoint(d, I.uy, I.tx, aff, L.aff_bytes, st));
-                hipLaunchKernelGGL(scs_resid_kernel, dim3(parts_r), dim3(SCS_BLOCK), 0, st, I.ty, I.vy, I.uy, I.tx,
-                                   I.ux, I.cv, I.sc, n, nx, I.sigma, gamma, part);
-                hipLaunchKernelGGL(scs_resid_final_kernel, dim3(1), dim3(64 * R_SLOTS), 0, st, part, parts_r, I.sc,
-                                   I.red);
-            }
+            if (constraint_apply_batched(d, I0.ux, I0.ty, xs, xs, I0.aff, (int64_t)L.inst, B, ACTIVE, st) != hipSuccess ||
+                constraint_adjoint_batched(d, UY, I0.tx, ny, xs, I0.aff, (int64_t)L.inst, B, ACTIVE, st) != hipSuccess)
+                return PSD_EDEVICE;
+            hipLaunchKernelGGL(scs_resid_kernel, dim3(parts_r, 1, B), dim3(SCS_BLOCK), 0, st, I0.ty, I0.vy, UY, I0.tx,
+                               I0.ux, I0.cv, I0.sc, n, nx, gamma, I0.part, zb);
+            hipLaunchKernelGGL(scs_resid_final_kernel, dim3(1, 1, B), dim3(64 * R_SLOTS), 0, st, I0.part, parts_r,
+                               I0.sc, RED, zb);
             SCS_LAUNCHED();
             SCS_READ(host.data(), RED, sizeof(double) * 16 * B);
             bool all_within = true;
@@ -928,6 +995,7 @@ psd_status scs_solve_batch(const psd_scs_settings *s, int B, const double *g, do
                     I.status = PSD_ENONFINITE;
                     I.done = true;
                     write_outputs(I);
+                    hipLaunchKernelGGL(scs_flag_kernel, dim3(1), dim3(64), 0, st, ACTIVE, b, 0);
                     continue;
                 }
                 I.within = false;
@@ -950,6 +1018,7 @@ psd_status scs_solve_batch(const psd_scs_settings *s, int B, const double *g, do
                         I.status = PSD_OK;
                         I.done = true;
                         write_outputs(I);
+                        hipLaunchKernelGGL(scs_flag_kernel, dim3(1), dim3(64), 0, st, ACTIVE, b, 0);
                         continue;
                     }
                     const double ms = s->mixed_switch;
@@ -972,8 +1041,7 @@ psd_status scs_solve_batch(const psd_scs_settings *s, int B, const double *g, do
         bool any = false;
         for (int b = 0; b < B; ++b) any = any || !inst[b].done;
         if (!any || k == s->max_iters) break;
-        for (int b = 0; b < B; ++b)
-            if (!inst[b].done) SCS_TRY(cone_input(inst[b]));
+        SCS_TRY(cone_input());
         if (L.m) {
             for (int b = 0; b < B; ++b)
                 if (!inst[b].done) SCS_TRY(anderson_launch(b));
@@ -1000,12 +1068,12 @@ psd_status scs_solve_batch(const psd_scs_settings *s, int B, const double *g, do
     for (int b = 0; b < B && w; ++b) {
         ScsInst &I = inst[b];
         if (!(I.info->tau > 0.0) || I.status == PSD_ENONFINITE) continue;
-        SCS_TRY(psd_constraint_apply(d, I.ux, I.ty, aff, L.aff_bytes, st));
+        SCS_TRY(psd_constraint_apply(d, I.ux, I.ty, I.aff, L.aff_bytes, st));
         hipLaunchKernelGGL(scs_scale_kernel, dim3(grid_of(ny)), dim3(SCS_BLOCK), 0, st, I.ty, I.w, I.sc, ny, -1.0, 1);
         hipLaunchKernelGGL(scs_diag_add_kernel, dim3(grid_of(n)), dim3(SCS_BLOCK), 0, st, I.w, n, gamma);
         SCS_LAUNCHED();
         // lambda_min(W) from the saved eigenvalues (ascending) of an FP64 projection
-        double *saved = static_cast<double *>(aff);
+        double *saved = static_cast<double *>(I.aff);
         SCS_TRY(psd_project(n, I.w, I.zy, PSD_FP64_EIG, proj, L.proj_bytes, st, I.pinfo, saved));
         double lmin = 0.0;
         psd_info pi{};
