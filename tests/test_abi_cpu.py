@@ -58,18 +58,20 @@ def test_workspace_size_validation(L):
 
 
 def test_workspace_size_lockstep_groups(L):
-    """Batched calls run same-order blocks in lockstep groups of at most 32,
+    """Batched calls run same-order blocks in lockstep groups of at most 128,
     one workspace slot per member, in every mode."""
     lib = L.lib()
     out = ctypes.c_size_t(0)
-    for mode in (0, 1, 2):
-        assert lib.psd_workspace_size(1, L.int_array([625]), mode, 0, ctypes.byref(out)) == 0
+    for mode in (0, 1, 2, 3):
+        assert lib.psd_workspace_size(1, L.int_array([256]), mode, 0, ctypes.byref(out)) == 0
         one = out.value
-        assert lib.psd_workspace_size(32, L.int_array([625] * 32), mode, 0, ctypes.byref(out)) == 0
+        assert lib.psd_workspace_size(32, L.int_array([256] * 32), mode, 0, ctypes.byref(out)) == 0
         assert out.value > 16 * one
-        g32 = out.value
-        assert lib.psd_workspace_size(40, L.int_array([625] * 40), mode, 0, ctypes.byref(out)) == 0
-        assert out.value < g32 + 4096  # groups of at most 32 share the slots
+        assert lib.psd_workspace_size(128, L.int_array([256] * 128), mode, 0, ctypes.byref(out)) == 0
+        assert out.value > 64 * one
+        g128 = out.value
+        assert lib.psd_workspace_size(140, L.int_array([256] * 140), mode, 0, ctypes.byref(out)) == 0
+        assert out.value < g128 + 4096  # groups of at most 128 share the slots
 
 
 def test_saved_size(L):
