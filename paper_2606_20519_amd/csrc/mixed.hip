@@ -669,6 +669,33 @@ __device__ __forceinline__ void ns_tile_ij(int tb, int &ti, int &tj) {
     tj = tb - ti * (ti + 1) / 2;
 }
 
+// Tile number o of the m x m lower tile triangle in blocked order: squares
+// of NS_SUPER x NS_SUPER tiles (J <= I, row by row), each row by row inside
+// (the diagonal squares over their lower triangle).  Consecutive numbers
+// share few row and column panels, so the contiguous run of tiles that one
+// XCD takes (xcd_tile) reuses its operand panels from that XCD's L2.
+constexpr int NS_SUPER = 8;
+__device__ __forceinline__ void ns128_tile(int o, int m, int &ti, int &tj) {
+    const int M = (m + NS_SUPER - 1) / NS_SUPER;
+    for (int I = 0; I < M; ++I) {
+        const int r = min(NS_SUPER, m - I * NS_SUPER);
+        for (int J = 0; J <= I; ++J) {
+            const int c = min(NS_SUPER, m - J * NS_SUPER);
+            const int cnt = I == J ? r * (r + 1) / 2 : r * c;
+            if (o < cnt) {
+                int li, lj;
+                if (I == J) ns_tile_ij(o, li, lj);
+                else { li = o / c; lj = o - li * c; }
+                ti = I * NS_SUPER + li;
+                tj = J * NS_SUPER + lj;
+                return;
+            }
+            o -= cnt;
+        }
+    }
+    ti = tj = 0;  // not reached for o < m (m + 1) / 2
+}
+
 // Epilogue of one 16x16 block at (ib, jb) as in ns_gemm_kernel: the lower
 // part with its conjugate mirror; blocks strictly below the diagonal write
 // four consecutive rows per lane as one 8-byte store.
@@ -776,7 +803,7 @@ __global__ void __launch_bounds__(256, 3 - SPLIT) ns_gemm128_kernel(const __bf16
     const int q = g < tfull ? -1 : g - tfull;
     const int tb = q < 0 ? xcd_tile(g, tfull) : tfull + q / split;
     int ti, tj;
-    ns_tile_ij(tb, ti, tj);
+    ns128_tile(tb, (npad + 127) / 128, ti, tj);
     const int i0 = ti * 128, j0 = tj * 128;
     const int t = threadIdx.x, lane = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6), wm = w & 1, wn = w >> 1;
@@ -913,7 +940,7 @@ __global__ void __launch_bounds__(256) ns128_tail_kernel(const float *__restrict
     }
     const int a = blockIdx.y >> 2, b = blockIdx.y & 3;
     int ti, tj;
-    ns_tile_ij(tfull + (int)blockIdx.x, ti, tj);
+    ns128_tile(tfull + (int)blockIdx.x, (npad + 127) / 128, ti, tj);
     const int i0 = ti * 128, j0 = tj * 128;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6, wm = w & 1, wn = w >> 1;
     if (ti == tj && wm == 0 && wn == 1) return;
