@@ -411,16 +411,21 @@ psd_status psd_project_batched(int32_t nblocks, const int32_t *n, const double *
     if (reinterpret_cast<uintptr_t>(ws) % kAlign) return PSD_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
 
-    std::vector<SmallJob> small;
+    std::vector<SmallJob> small, small64;  // orders <= 32 first, then 33 .. 64
     std::vector<int> large;
     std::vector<int64_t> boff(nblocks);
     int64_t off = 0;
     for (int b = 0; b < nblocks; ++b) {
         boff[b] = off;
-        if (n[b] <= 64) small.push_back(SmallJob{off, 0, n[b], b});
+        if (n[b] <= 32) small.push_back(SmallJob{off, 0, n[b], b});
+        else if (n[b] <= 64) small64.push_back(SmallJob{off, 0, n[b], b});
         else large.push_back(b);
         off += (int64_t)n[b] * n[b];
     }
+    const int n32 = (int)small.size();
+    int nt32 = 0;
+    for (const SmallJob &j : small) nt32 = std::max(nt32, small32_threads(j.n));
+    small.insert(small.end(), small64.begin(), small64.end());
     psd_dev_info *dinfos = reinterpret_cast<psd_dev_info *>(infos);
     const bool grouped = nblocks > 1;
     Carve cv(ws);
@@ -467,7 +472,7 @@ psd_status psd_project_batched(int32_t nblocks, const int32_t *n, const double *
         }
     }
     if (!small.empty()) {
-        hipError_t e = launch_small(djobs, (int)small.size(), x, y, dinfos, nullptr, s);
+        hipError_t e = launch_small(djobs, (int)small.size(), n32, nt32, x, y, dinfos, nullptr, s);
         if (e != hipSuccess) return PSD_EDEVICE;
     }
     return PSD_OK;

@@ -26,7 +26,12 @@ size_t small_lds_bytes();
 // One-time kernel attribute setup (dynamic LDS limits); call outside graph capture.
 hipError_t small_prepare();
 hipError_t dc_prepare();
-hipError_t launch_small(const SmallJob *jobs, int njobs, const double *x, double *y,
+// Workgroup size the order-<= 32 kernel needs for a block of order n.
+int small32_threads(int n);
+// jobs[0 .. n32) have order <= 32 (the one-barrier-per-step kernel, run
+// with nt32 threads: the largest small32_threads of their orders), the rest
+// order 33 .. 64.
+hipError_t launch_small(const SmallJob *jobs, int njobs, int n32, int nt32, const double *x, double *y,
                         psd_dev_info *infos, double *saved, hipStream_t st);
 hipError_t launch_small_one(const SmallJob &job, const double *x, double *y, psd_dev_info *info,
                             double *saved, hipStream_t st);

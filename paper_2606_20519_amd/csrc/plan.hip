@@ -103,7 +103,8 @@ struct psd_plan_s {
     int K = 1;
     int nlarge = 0;
     size_t slot_bytes = 0;
-    std::vector<SmallJob> small;
+    std::vector<SmallJob> small;     // orders <= 32 first (n32 of them), then 33 .. 64
+    int n32 = 0, nt32 = 0;
     SmallJob *dsmall = nullptr;
     std::vector<GroupChunk> chunks;  // jobs: lockstep groups
     int group = 0;                   // members per group at most (0: the memory-derived limit)
@@ -130,7 +131,7 @@ hipError_t capture(psd_plan_s *p, const double *x, double *y, void *ws, psd_info
         for (int i = 0; i < K; ++i) chk(hipStreamWaitEvent(p->side[i], p->fork, 0));
     }
     psd_dev_info *di = reinterpret_cast<psd_dev_info *>(infos);
-    if (!p->small.empty()) chk(launch_small(p->dsmall, (int)p->small.size(), x, y, di, nullptr, p->cap));
+    if (!p->small.empty()) chk(launch_small(p->dsmall, (int)p->small.size(), p->n32, p->nt32, x, y, di, nullptr, p->cap));
     int pos = 0;
     for (size_t ci = 0; ci < p->chunks.size(); ++ci) {
         const int slot = (int)(ci % K), cnt = (int)p->chunks[ci].blocks.size();
@@ -205,13 +206,18 @@ psd_status psd_plan_create(int32_t nblocks, const int32_t *n, psd_mode mode, int
     if (!p) return PSD_ENOMEM;
     p->mode = mode;
     int64_t off = 0;
+    std::vector<SmallJob> small64;
     for (int b = 0; b < nblocks; ++b) {
         if (n[b] < 1) { delete p; return PSD_EINVAL; }
         p->n.push_back(n[b]);
         p->off.push_back(off);
-        if (n[b] <= 64) p->small.push_back(SmallJob{off, 0, n[b], b});
+        if (n[b] <= 32) p->small.push_back(SmallJob{off, 0, n[b], b});
+        else if (n[b] <= 64) small64.push_back(SmallJob{off, 0, n[b], b});
         off += (int64_t)n[b] * n[b];
     }
+    p->n32 = (int)p->small.size();
+    for (const SmallJob &j : p->small) p->nt32 = std::max(p->nt32, small32_threads(j.n));
+    p->small.insert(p->small.end(), small64.begin(), small64.end());
     // jobs are lockstep groups; concurrency and group size from the cache
     int K = concurrency, group = 0;
     {
