@@ -31,7 +31,7 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 16, 17, 25, 31, 36, 49, 63, 64])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 8, 16, 17, 25, 31, 32, 33, 36, 49, 63, 64])
 def test_small_gue_parity(P, n):
     s = W.gue(n, 1001 + n)
     print(f"small gue n={n}", flush=True)
@@ -62,9 +62,13 @@ def test_small_clustered_and_wide_spectra(P):
     # multiplicity 32, and a spectrum over sixteen decades: against the
     # closed form and the oracle
     rng = np.random.default_rng(17)
+    # (orders <= 32 run the one-barrier-per-step kernel, larger ones the other)
     cases = [(33, np.concatenate([np.repeat([-2.0, 0.0, 1.5], 10), [3.0, -4.0, 0.25]])),
              (64, np.repeat([-1.0, 1.0], 32)),
-             (48, np.concatenate([np.logspace(-8, 8, 24), -np.logspace(-8, 8, 24)]))]
+             (48, np.concatenate([np.logspace(-8, 8, 24), -np.logspace(-8, 8, 24)])),
+             (25, np.concatenate([np.repeat([-2.0, 0.0, 1.5], 7), [3.0, -4.0, 0.25, 0.0]])),
+             (16, np.repeat([-1.0, 1.0], 8)),
+             (32, np.concatenate([np.logspace(-8, 8, 16), -np.logspace(-8, 8, 16)]))]
     for n, lam in cases:
         u = W.haar_unitary(n, rng)
         x = (u * lam) @ u.conj().T
@@ -89,8 +93,8 @@ def test_small_special_inputs(P):
     assert np.array_equal(P.project(dev(z), n).cpu().numpy(), z)
 
 
-def test_small_in_place_and_invariants(P):
-    n = 36
+@pytest.mark.parametrize("n", [20, 36])
+def test_small_in_place_and_invariants(P, n):
     s = W.gue(n, 77)
     x = dev(s)
     y = P.project(x, n).cpu().numpy()
@@ -124,9 +128,9 @@ def test_small_nonfinite_flagged(P):
     assert info["status"] == 4
 
 
-def test_small_saved_eigenpairs(P):
+@pytest.mark.parametrize("n", [16, 25, 40])
+def test_small_saved_eigenpairs(P, n):
     import torch
-    n = 40
     s = W.gue(n, 91)
     saved = torch.empty(P.saved_numel(n), dtype=torch.float64, device="cuda:0")
     P.project(dev(s), n, saved=saved)
@@ -140,8 +144,8 @@ def test_small_saved_eigenpairs(P):
     assert np.linalg.norm(v.conj().T @ v - np.eye(n)) <= 1e-12
 
 
-def test_small_deterministic(P):
-    n = 64
+@pytest.mark.parametrize("n", [16, 25, 64])
+def test_small_deterministic(P, n):
     s = W.gue(n, 8)
     a = P.project(dev(s), n).cpu().numpy()
     b = P.project(dev(s), n).cpu().numpy()
