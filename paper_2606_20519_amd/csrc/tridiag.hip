@@ -151,14 +151,16 @@ __device__ void hemv_tile(const double2 *__restrict__ M, int64_t lda, int n, int
     double sp = lane < nparts ? npart[lane] : 0.0;  // sigma: every wave sums the same partials in the same order
     const double2 alpha = colj[s];
     const double djj = (b == 0 && t == 0) ? colj[j].x : 0.0;
+    // the column's entries for v before the tile: loads complete in order,
+    // so the reflector and v are formed while the tile is still in flight
+    const int vrow = (t < TT ? r0 : c0) + lane;  // threads < 2*TT: entries of v_I, v_J
+    const double2 cv = (t < 2 * TT && vrow < n && vrow != s) ? colj[vrow] : cmk(0.0, 0.0);
     double2 tv[TT / 4];  // tile column g + 4k, row lane (diagonal tile: lower part only)
 #pragma unroll
     for (int k = 0; k < TT / 4; ++k) {
         const int cc = g + 4 * k, col = c0 + cc;
         tv[k] = (rowok && col < n && (!diag || lane >= cc)) ? M[(r0 + lane) + (int64_t)col * lda] : cmk(0.0, 0.0);
     }
-    const int vrow = (t < TT ? r0 : c0) + lane;  // threads < 2*TT: entries of v_I, v_J
-    const double2 cv = (t < 2 * TT && vrow < n && vrow != s) ? colj[vrow] : cmk(0.0, 0.0);
     for (int k = lane + 64; k < nparts; k += 64) sp += npart[k];
     const double sigma = wave_sum_dpp(sp);
     const Refl h = make_refl(alpha, sigma);
