@@ -361,7 +361,8 @@ psd_status psd_scs_workspace_size(const psd_scs_settings *s, size_t *bytes);
 psd_status psd_scs_solve(const psd_scs_settings *s, const double *g, double *x, double *y, double *s_out,
                          double *w, void *ws, size_t ws_bytes, void *stream, psd_scs_info *info);
 
-/* A batch of nbatch >= 1 independent solves with the same settings (many
+/* A batch of 1 <= nbatch <= PSD_SCS_MAX_BATCH independent solves with the
+ * same settings (many
  * objectives, e.g. the restarts of the paper's exploration stage, §IV):
  * g, y, s_out, w hold nbatch d^8-vectors back to back, x nbatch n_x-vectors,
  * infos nbatch records.  The instances advance in lockstep and their cone
@@ -373,6 +374,7 @@ psd_status psd_scs_solve(const psd_scs_settings *s, const double *g, double *x, 
  * the others.  With mixed_switch > 0 the batch leaves the mixed mode
  * when every running instance is within the factor.  Workspace from
  * psd_scs_workspace_size_batched (it grows with nbatch). */
+#define PSD_SCS_MAX_BATCH 65535 /* one grid dimension of the per-step launches */
 psd_status psd_scs_workspace_size_batched(const psd_scs_settings *s, int32_t nbatch, size_t *bytes);
 psd_status psd_scs_solve_batched(const psd_scs_settings *s, int32_t nbatch, const double *g, double *x, double *y,
                                  double *s_out, double *w, void *ws, size_t ws_bytes, void *stream,

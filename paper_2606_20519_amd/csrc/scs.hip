@@ -684,7 +684,7 @@ struct ScsInst {
 
 psd_status scs_solve_batch(const psd_scs_settings *s, int B, const double *g, double *x, double *y, double *sl,
                            double *w, void *ws, size_t ws_bytes, void *stream, psd_scs_info *infos) {
-    if (!settings_ok(s) || B < 1 || !g || !x || !y || !sl || !infos) return PSD_EINVAL;
+    if (!settings_ok(s) || B < 1 || B > PSD_SCS_MAX_BATCH || !g || !x || !y || !sl || !infos) return PSD_EINVAL;
     ScsLayout L;
     if (!scs_layout(*s, B, L)) return PSD_EINVAL;
     if (!ws || ws_bytes < L.total) return PSD_EWORKSPACE;
@@ -1112,7 +1112,7 @@ psd_status psd_scs_workspace_size(const psd_scs_settings *s, size_t *bytes) {
 }
 
 psd_status psd_scs_workspace_size_batched(const psd_scs_settings *s, int32_t nbatch, size_t *bytes) {
-    if (!settings_ok(s) || !bytes || nbatch < 1) return PSD_EINVAL;
+    if (!settings_ok(s) || !bytes || nbatch < 1 || nbatch > PSD_SCS_MAX_BATCH) return PSD_EINVAL;
     ScsLayout L;
     if (!scs_layout(*s, nbatch, L)) return PSD_EINVAL;
     *bytes = L.total;

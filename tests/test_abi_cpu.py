@@ -161,6 +161,8 @@ def test_scs_settings_validation():
     assert L.psd_scs_workspace_size_batched(ctypes.byref(st()), 8, ctypes.byref(out)) == 0
     assert out.value > plain + 7 * 8 * (2 * ny)               # every instance's cone-step blocks
     assert L.psd_scs_workspace_size_batched(ctypes.byref(st()), 0, ctypes.byref(out)) == 1
+    assert L.psd_scs_workspace_size_batched(ctypes.byref(st()), 65535, ctypes.byref(out)) == 0  # the bound
+    assert L.psd_scs_workspace_size_batched(ctypes.byref(st()), 65536, ctypes.byref(out)) == 1  # beyond it
     for bad in (dict(d=1), dict(d=9), dict(max_iters=0), dict(check_every=0), dict(alpha=2.0), dict(alpha=0.0),
                 dict(eps=-1.0), dict(eps=float("nan")), dict(mixed_iters=5, mixed_mode=0), dict(anderson=17),
                 dict(anderson=-1), dict(mixed_switch=-1.0), dict(mixed_switch=float("inf")),
