@@ -284,6 +284,8 @@ def main():
                          "iterations (no JSON line): the program profiled for the solver's kernel trace")
     ap.add_argument("--scs-iters", type=int, default=5)
     ap.add_argument("--scs-anderson", type=int, default=0)
+    ap.add_argument("--scs-batch", type=int, default=1,
+                    help="with --scs-run: solve this many instances (seeds 7, 8, ...) in one batched call")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 256 MiB device to device 3 times (counter calibration) and exit")
     args = ap.parse_args()
@@ -313,12 +315,17 @@ def main():
 
     if args.scs_run:
         d = args.scs_run
-        log(f"SCS run: d={d}, {args.scs_iters} iterations, Anderson memory {args.scs_anderson}")
-        g = torch.from_numpy(W.upper_pack(W.gyni_objective(d, 7))).to("cuda:0")
+        nb = max(1, args.scs_batch)
+        log(f"SCS run: d={d}, {nb} instance(s), {args.scs_iters} iterations, Anderson memory {args.scs_anderson}")
+        g = torch.from_numpy(np.stack([W.upper_pack(W.gyni_objective(d, 7 + b)) for b in range(nb)])).to("cuda:0")
         t = time.perf_counter()
-        r = P.scs_solve(g, d, eps=0.0, max_iters=args.scs_iters, anderson=args.scs_anderson, post=False)
+        if nb == 1:
+            rs = [P.scs_solve(g[0], d, eps=0.0, max_iters=args.scs_iters, anderson=args.scs_anderson, post=False)]
+        else:
+            rs = P.scs_solve_batched(g, d, eps=0.0, max_iters=args.scs_iters, anderson=args.scs_anderson, post=False)
         torch.cuda.synchronize()
-        log(f"SCS run done: {r['iters']} iterations in {time.perf_counter() - t:.3f} s, tau {r['tau']:.6e}")
+        log(f"SCS run done: {rs[0]['iters']} iterations of {nb} instance(s) in {time.perf_counter() - t:.3f} s, "
+            f"tau {rs[0]['tau']:.6e}")
         return
 
     dev = torch.device("cuda:0")
