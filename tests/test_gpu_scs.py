@@ -246,8 +246,9 @@ def test_d8_iterations(P):
     assert float(torch.linalg.vector_norm(pw - w)) <= 1e-10 * float(torch.linalg.vector_norm(w))
 
 
-@pytest.mark.parametrize("d, anderson", [(3, 0), (4, 5)])
-def test_batched_equals_single_solves(P, d, anderson):
+@pytest.mark.parametrize("d, anderson, mixed", [(3, 0, None), (4, 5, None), (3, 0, "mixed_bf16x3"),
+                                               (3, 5, "mixed_fp32")])
+def test_batched_equals_single_solves(P, d, anderson, mixed):
     # instances of a batch advance in lockstep, their cone steps in one
     # batched projection: each equals its own single solve bit for bit; an
     # instance with a non-finite objective stops at setup without touching
@@ -257,10 +258,13 @@ def test_batched_equals_single_solves(P, d, anderson):
     bad = gs[1].copy()
     bad[3] = np.nan
     batch = np.stack([gs[0], bad, gs[2]])
-    outs = P.scs_solve_batched(dev(batch), d, eps=1e-6, max_iters=5000, anderson=anderson)
+    # (a low-precision start, a fixed number of cone steps, is per instance
+    # too: the batched projection's groups match single calls in every mode)
+    kw = dict(mixed_iters=40, mixed_mode=mixed) if mixed else {}
+    outs = P.scs_solve_batched(dev(batch), d, eps=1e-6, max_iters=5000, anderson=anderson, **kw)
     assert outs[1]["status"] == 4
     for b in (0, 2):
-        one = P.scs_solve(dev(gs[b]), d, eps=1e-6, max_iters=5000, anderson=anderson)
+        one = P.scs_solve(dev(gs[b]), d, eps=1e-6, max_iters=5000, anderson=anderson, **kw)
         print(f"d={d} batch member {b}: {outs[b]['iters']} iterations (single {one['iters']}), "
               f"value {outs[b]['pobj']:.10f}", flush=True)
         assert outs[b]["status"] == 0 and one["status"] == 0
