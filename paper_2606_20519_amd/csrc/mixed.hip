@@ -1081,10 +1081,22 @@ __global__ void __launch_bounds__(256) mx_info_kernel(const double *__restrict__
 // give f equal values at both ends, but it pushes the converged top of the
 // spectrum far down (f(sqrt 3) = 0), and its regrowth in low precision
 // amplifies rounding; the cap keeps the unscaled map's accuracy.  iters = 0:
-// as many steps as take l from 1e-6 to within 1e-7 of 1 (21, against 40
-// unscaled), i.e. eigenvalues down to 1e-6 alpha resolved.
-std::vector<double> ns_scalings(int iters) {
-    constexpr double l0 = 1e-6, tol = 1e-7, amax = 1.5;
+// as many steps as take l from l0 to within 1e-7 of 1 (21 from 1e-6, against
+// 40 unscaled), i.e. eigenvalues down to l0 alpha resolved.
+//
+// l0 = max(1e-6, u/4) for the unit roundoff u of the iterates' format: the
+// rounding of X to that format moves its eigenvalues by about u alpha, so
+// the sign of an eigenvalue below that is not determined by the iteration
+// anyway, and an unconverged one of magnitude below l0 alpha adds at most
+// that much to the error (inside the band the error bounds already allow):
+// BF16 (u = 2^-8) takes 12 steps, split BF16 (2^-16) 19, FP32 21.
+double ns_l0(int mode) {
+    const double u = mode == 1 ? 0x1p-8 : mode == 3 ? 0x1p-16 : 0x1p-24;
+    return std::max(1e-6, 0.25 * u);
+}
+
+std::vector<double> ns_scalings(int iters, double l0) {
+    constexpr double tol = 1e-7, amax = 1.5;
     auto cubic = [](double t) { return 0.5 * (3.0 * t - t * t * t); };
     std::vector<double> a(1, 1.0);
     double l = cubic(l0);
@@ -1100,7 +1112,7 @@ std::vector<double> ns_scalings(int iters) {
 template <typename L, int SPLIT = 1>
 hipError_t ns_run(const MixedWs &w, const double *x, double *y, psd_dev_info *info, int iters_req, int corr,
                   hipStream_t st) {
-    const std::vector<double> sc = ns_scalings(iters_req);
+    const std::vector<double> sc = ns_scalings(iters_req, ns_l0(sizeof(L) == 4 ? 2 : SPLIT == 2 ? 3 : 1));
     const int iters = (int)sc.size();
     const int n = w.n, npad = w.npad;
     const int64_t plane = (int64_t)npad * npad;

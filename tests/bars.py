@@ -38,6 +38,14 @@ def unit_roundoff(mode: str) -> float:
     return {"mixed_bf16": U_BF16, "mixed_bf16x3": U_BF16X3}.get(mode, U_FP32)
 
 
+def ns_l0(mode: str) -> float:
+    """Lower end of the Newton-Schulz schedule the library uses in `mode`:
+    max(1e-6, u/4) for the unit roundoff u of the iterates' format (BF16
+    2^-8, split BF16 2^-16, FP32 2^-24)."""
+    u = {"mixed_bf16": 2.0 ** -8, "mixed_bf16x3": 2.0 ** -16}.get(mode, 2.0 ** -24)
+    return max(1e-6, 0.25 * u)
+
+
 def band_norm(lam, mode: str, c: float = BAND_C) -> float:
     """sqrt(sum lambda^2 over |lambda| < c u ||X||_2)."""
     lam = np.asarray(lam, dtype=np.float64)

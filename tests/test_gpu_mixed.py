@@ -60,7 +60,8 @@ def test_ns_iterations_match_reference(P, mode, amp, iters):
     finally:
         P.set_ns_iterations(0, 1)
     assert info["iters"] == iters
-    ref = oracle.ns_matrix_projection(s, n, info["scale"], iters, oracle.ns_schedule(iters=iters))
+    ref = oracle.ns_matrix_projection(s, n, info["scale"], iters,
+                                      oracle.ns_schedule(l0=bars.ns_l0(mode), iters=iters))
     err = rel(y.cpu().numpy(), ref)
     print(f"{mode} iters={iters}: rel err vs FP64 NS reference {err:.3e}", flush=True)
     assert err <= tol
