@@ -18,6 +18,8 @@ Other workloads (one JSON line each, selected with --workload):
   c1  50 blocks of order 16 (d = 2), one batched launch per step
   c2  the n = 625 (d = 5) warm-start sequence: 50 SCS-like iterates
       X_{k+1} = X_k + 1e-3 (H_k + H_k^H)/2 projected one after another
+      (--warm: iterates 1.. by psd_project_warm, each from the eigen-pair
+      the previous one left; the roofline is then the FP64 GEMMs')
   c3  orders 1296 and 2401 (d = 6, 7), spectra in [-1,-1e-6] u [1e-6,1],
       --mode mixed_bf16 | mixed_bf16x3 | mixed_fp32 | fp64 (--n picks the order)
   c4  one cone of 32 instances x [W (d^4) + 8 Choi (d^2)] by one graph
@@ -127,13 +129,15 @@ def measured_traffic(kernel, n, sources):
         return None
 
 
-def mfma_roofline(fp64_gemm, mode, n, timed):
+def mfma_roofline(fp64_gemm, mode, n, timed, warm=False):
     """Roofline entry of an MFMA kernel family from (ms, launches, flops):
     the FP64 GEMM or the Newton-Schulz products."""
     achieved = timed[2] / (timed[0] * 1e-3) / 1e12
     if fp64_gemm:
-        return {"kernel": "gemm_kernel<cd,...> (FP64 complex GEMM, 64x64 tiles: the FP64 corrections and "
-                          "the final product X S of the mixed form)",
+        use = ("the split-K products of the warm refinement (A X, X^H A X, X^H X, X E) and the "
+               "reconstruction, with the cold first iterate's trailing updates and back-transform" if warm else
+               "the FP64 corrections and the final product X S of the mixed form")
+        return {"kernel": f"gemm_kernel<cd,...> (FP64 complex GEMM, 64x64 tiles: {use})",
                 "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
                 "algorithmic_flops_per_launch": round(timed[2] / timed[1], 1)}
@@ -275,6 +279,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=10, help="blocks projected by the CPU oracle (bounded sample)")
     ap.add_argument("--no-context", action="store_true",
                     help="skip the context measurements after the timed region (counter runs)")
+    ap.add_argument("--warm", action="store_true",
+                    help="c2: iterates 1.. by psd_project_warm from the pair the previous one left")
     ap.add_argument("--blocks", type=int, default=50, help="blocks per step for c1 / c2 (counter runs use fewer)")
     ap.add_argument("--counter-run", action="store_true",
                     help="only project the workload's inputs once (one step, no probes, no JSON line): the "
@@ -350,6 +356,10 @@ def main():
         xs_np = W.warm_sequence(n, 1002, count)
         desc = (f"d=5 warm-start sequence: {count} iterates of a 625x625 Hermitian block, "
                 "projected one after another")
+        if args.warm:
+            assert mode == "fp64", "--warm is an FP64 path"
+            desc += (" (iterate 0 by the cold path, saving its eigen-pair; iterates 1.. by psd_project_warm from "
+                     "the pair the previous one left)")
         sizes = [n] * count
     elif wl == "c1":
         n, count = 16, args.blocks
@@ -390,6 +400,13 @@ def main():
     elif wl == "c1":
         def step():
             P.project_batched(X, sizes, mode, out=Y)
+    elif wl == "c2" and args.warm:
+        SAVED = torch.empty(P.saved_numel(n), dtype=torch.float64, device=dev)
+
+        def step():
+            P.project(X[0], n, mode, out=Y[0], saved=SAVED)
+            for i in range(1, count):
+                P.project_warm(X[i], n, SAVED, out=Y[i])
     else:
         def step():
             for i in range(count):
@@ -436,7 +453,24 @@ def main():
     # events on their launch stream -- the first projection's launches
     fam = None
     other = None
-    if mode == "fp64" and n > 64 and wl != "c4":
+    if wl == "c2" and args.warm:
+        # the FP64 GEMMs of the first timed step (mostly the refinements'
+        # products); per-iterate refinement steps and fallbacks from an
+        # untimed pass of the sequence
+        _lib.timing_start(_lib.KF_GEMM, 4096)
+        step()
+        torch.cuda.synchronize()
+        fam, sample = _lib.KF_GEMM, _lib.timing_stop()[1]   # the GEMM launches of one step
+        steps, falls = [], 0
+        P.project(X[0], n, mode, out=Y[0], saved=SAVED)
+        for i in range(1, count):
+            _, inf = P.project_warm(X[i], n, SAVED, out=Y[i], info=True)
+            steps.append(inf["iters"])
+            falls += inf["fallback"]
+        extra["warm"] = {"refinement_steps": {str(k): steps.count(k) for k in sorted(set(steps))},
+                         "fallbacks": falls, "iterates": count - 1}
+        flops_step = flops_eig(n, ks[0]) + sum(8.0 * n ** 3 * (3.0 * k + 0.5) for k in steps)
+    elif mode == "fp64" and n > 64 and wl != "c4":
         # one projection's HEMV launches (the columns before the LDS tail),
         # counted by an untimed probe
         _lib.timing_start(_lib.KF_HEMV, n)
@@ -501,7 +535,7 @@ def main():
                     "avg_launch_us": round(1e3 * pr[0] / pr[1], 3), "launches": pr[1],
                     "share_of_projection_ms": round(pr[0], 3), "sample": "untimed probe projection (HIP events)"}
         else:
-            roofline = mfma_roofline(fam == _lib.KF_GEMM, mode, n, timed)
+            roofline = mfma_roofline(fam == _lib.KF_GEMM, mode, n, timed, warm=args.warm)
             if other:
                 o, pr = other
                 ctx = mfma_roofline(o == _lib.KF_GEMM, mode, n, pr)
@@ -509,11 +543,16 @@ def main():
                             "share_of_projection_ms": round(pr[0], 3),
                             "sample": "untimed probe projection (HIP events)"})
                 roofline["other_mfma_kernel"] = ctx
-        # the timed launches belong to the first projection of the step
+        # the timed launches belong to the first projection of the step (with
+        # --warm: to the whole first step)
         per_proj_ms = ms_per_step / (1 if wl == "c4" else blocks_per_step)
         roofline.update({"launches_timed": timed[1], "avg_launch_us": round(1e3 * avg_ms, 3),
-                         "sample": "launches of the first projection in the timed region",
-                         "share_of_projection": round(timed[0] / per_proj_ms, 4)})
+                         "sample": ("GEMM launches of the first step in the timed region" if args.warm else
+                                    "launches of the first projection in the timed region")})
+        if args.warm:
+            roofline["share_of_step"] = round(timed[0] / ms_per_step, 4)
+        else:
+            roofline["share_of_projection"] = round(timed[0] / per_proj_ms, 4)
 
     if wl == "c2" and mode == "fp64" and not args.no_context:
         # context only: the same iterates as independent blocks of one batched

@@ -80,15 +80,17 @@ typedef struct {
     int32_t status;       /* psd_status of this block */
     int32_t n_pos;        /* number of eigenvalues > 0 */
     int32_t n_neg;        /* number of eigenvalues <= 0 */
-    int32_t iters;        /* NS iterations (mixed) or 0 */
-    int32_t fallback;     /* 1 if a mixed request fell back to the FP64 path */
+    int32_t iters;        /* NS iterations (mixed), refinement steps (psd_project_warm) or 0 */
+    int32_t fallback;     /* 1 if a mixed request fell back to the FP64 path, or a warm
+                             request to the cold FP64 path */
     int32_t reserved;
     double est_rel_err;   /* mixed: first-order estimate of ||y - Pi(X)||_F / ||Pi(X)||_F for
                              the sign estimate S: sqrt(||[X, S]||_F^2 + ||X||_F^2 -
                              ||X S||_F^2) / (4 ||y||_F) -- the eigenvector part (the
                              commutator vanishes for the exact sign) and the eigenvalue
                              part (S^2 = I for it); relative to ||X||_F when y = 0;
-                             FP64: 0 */
+                             psd_project_warm: the square of the last refinement
+                             step's largest rotation |E_ij|; FP64: 0 */
     double scale;         /* mixed: spectral scale alpha (~1.1 ||X||_2); FP64: 0 */
 } psd_info;
 
@@ -97,13 +99,17 @@ typedef struct {
  * psd_project_vjp.  flags: bit 0 = also return the eigen-pair for a later VJP
  * (PSD_FLAG_SAVE).  Returns PSD_EINVAL for n < 1, nblocks < 1 or a bad mode. */
 #define PSD_FLAG_SAVE 1
+/* bit 1: workspace of psd_project_warm (one block, PSD_FP64_EIG only) */
+#define PSD_FLAG_WARM 2
 psd_status psd_workspace_size(int32_t nblocks, const int32_t *n, psd_mode mode,
                               int32_t flags, size_t *bytes);
 
 /* Bytes of the `saved` record of one block of order n: lambda (n doubles,
- * ascending) followed by V (n x n complex, column-major, interleaved re/im)
- * with V[:,k] the unit eigenvector of lambda[k] -- of the conjugate matrix
- * mat(x)^T, in the svec convention above (Pi commutes with conjugation). */
+ * ascending when psd_project wrote it; psd_project_warm keeps the column
+ * order of its input record) followed by V (n x n complex, column-major,
+ * interleaved re/im) with V[:,k] the unit eigenvector of lambda[k] -- of the
+ * conjugate matrix mat(x)^T, in the svec convention above (Pi commutes with
+ * conjugation). */
 size_t psd_saved_size(int32_t n);
 
 /* y <- svec(Pi(mat(x))) for one block of order n >= 1.
@@ -114,6 +120,28 @@ size_t psd_saved_size(int32_t n);
 psd_status psd_project(int32_t n, const double *x, double *y, psd_mode mode,
                        void *ws, size_t ws_bytes, void *stream, psd_info *info,
                        double *saved);
+
+/* y <- svec(Pi(mat(x))) in FP64 for one block of order n >= 1, starting from
+ * the eigen-pair of a nearby matrix: saved_prev (psd_saved_size(n) bytes,
+ * from psd_project with `saved` or from an earlier call of this function).
+ * The successive inputs of the splitting method are such a sequence (warm
+ * starting, App. D.2 of the paper; the warm-started refinement, Sec. IV).
+ * The eigenvectors are refined by matrix products (the iteration of Ogita
+ * and Aishima, 2018: X <- X + X E from G = X^H X and S = X^H A X, at most 5
+ * steps, stopping once the largest rotation |E_ij| of a step is <= 1e-7),
+ * and Pi = X diag(max(lambda, 0)) X^H.  The refined pair goes to saved_out
+ * (may equal saved_prev), ready for the next call or psd_project_vjp.
+ * When the last step's largest rotation is above 1e-6 (the pair was not
+ * close, the spectrum moved too far) or x is not finite, the block is
+ * projected by the cold FP64 path instead (info->fallback = 1), which also
+ * writes saved_out.  Either way y is within the FP64 tolerance of Pi(X).
+ * The call synchronises `stream` once (the host reads the outcome) and so
+ * cannot be captured into a graph (PSD_EUNSUPPORTED).  y == x is allowed;
+ * x and y must not overlap saved_prev or saved_out.  Workspace:
+ * psd_workspace_size(1, &n, PSD_FP64_EIG, PSD_FLAG_WARM, &bytes). */
+psd_status psd_project_warm(int32_t n, const double *x, double *y, const double *saved_prev,
+                            double *saved_out, void *ws, size_t ws_bytes, void *stream,
+                            psd_info *info);
 
 /* psd_project without a workspace argument, for callers that cannot
  * allocate (code under graph capture, tight serving loops, harnesses that

@@ -19,7 +19,7 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import MODES, PSD_FLAG_SAVE, PsdError, PsdInfo, check  # noqa: F401
+from ._lib import MODES, PSD_FLAG_SAVE, PSD_FLAG_WARM, PsdError, PsdInfo, check  # noqa: F401
 
 __all__ = ["project", "project_batched", "vjp", "PSDProject", "Plan", "workspace", "set_ns_iterations",
            "set_mixed_fallback", "project_noalloc", "affine_dims", "constraint_apply", "constraint_adjoint",
@@ -90,6 +90,30 @@ def project(x: torch.Tensor, n: int, mode="fp64", out: torch.Tensor = None, info
     st = _lib.lib().psd_project(n, _ptr(x), _ptr(y), m, _ptr(ws), ws.numel(), ctypes.c_void_p(_stream_ptr(x.device)),
                                 _ptr(inf_t), _ptr(saved))
     check(st, "psd_project")
+    if info:
+        return y, _info_dict(inf_t)
+    return y
+
+
+def project_warm(x: torch.Tensor, n: int, saved_prev: torch.Tensor, saved_out: torch.Tensor = None,
+                 out: torch.Tensor = None, info: bool = False):
+    """svec(Pi(mat(x))) in FP64 through psd_project_warm: the eigen-pair in
+    `saved_prev` (from project(..., saved=) or an earlier call) is refined
+    for x, and the refined pair goes to `saved_out` (default: saved_prev,
+    updated in place).  Falls back to the cold path when the pair is not
+    close (info["fallback"] == 1).  Synchronises the current stream."""
+    _check_vec(x, n * n, "x")
+    nsv = _lib.saved_size(n) // 8
+    _check_vec(saved_prev, nsv, "saved_prev")
+    so = saved_prev if saved_out is None else saved_out
+    _check_vec(so, nsv, "saved_out")
+    y = torch.empty_like(x) if out is None else out
+    _check_vec(y, n * n, "out")
+    ws = workspace([n], MODES["fp64"], x.device, PSD_FLAG_WARM)
+    inf_t = torch.zeros(INFO_WORDS, dtype=torch.int32, device=x.device) if info else None
+    st = _lib.lib().psd_project_warm(n, _ptr(x), _ptr(y), _ptr(saved_prev), _ptr(so), _ptr(ws), ws.numel(),
+                                     ctypes.c_void_p(_stream_ptr(x.device)), _ptr(inf_t))
+    check(st, "psd_project_warm")
     if info:
         return y, _info_dict(inf_t)
     return y

@@ -16,10 +16,12 @@ STATUS_NAMES = {0: "PSD_OK", 1: "PSD_EINVAL", 2: "PSD_EWORKSPACE", 3: "PSD_ENOME
                 4: "PSD_ENONFINITE", 5: "PSD_ENOCONV", 6: "PSD_EDEVICE", 7: "PSD_EUNSUPPORTED"}
 MODES = {"fp64": 0, "mixed_bf16": 1, "mixed_fp32": 2, "mixed_bf16x3": 3}
 PSD_FLAG_SAVE = 1
+PSD_FLAG_WARM = 2
 NOALLOC_SCRATCH_BYTES = 48 << 20   # PSD_NOALLOC_SCRATCH_BYTES
 
 # Every symbol include/psdproj.h declares.
-EXPORTS = ("psd_workspace_size", "psd_saved_size", "psd_project", "psd_project_noalloc", "psd_project_batched",
+EXPORTS = ("psd_workspace_size", "psd_saved_size", "psd_project", "psd_project_warm", "psd_project_noalloc",
+           "psd_project_batched",
            "psd_project_vjp", "psd_plan_create", "psd_plan_workspace_size", "psd_plan_concurrency",
            "psd_plan_group_size", "psd_plan_ns_tile_threshold",
            "psd_plan_execute", "psd_plan_tune", "psd_plan_destroy", "psd_timing_start", "psd_timing_stop",
@@ -77,6 +79,8 @@ def lib():
     L.psd_saved_size.restype = sz
     L.psd_project.argtypes = [i32, vp, vp, i32, vp, sz, vp, vp, vp]
     L.psd_project.restype = i32
+    L.psd_project_warm.argtypes = [i32, vp, vp, vp, vp, vp, sz, vp, vp]
+    L.psd_project_warm.restype = i32
     L.psd_project_noalloc.argtypes = [i32, vp, vp, i32, vp, vp]
     L.psd_project_noalloc.restype = i32
     L.psd_project_batched.argtypes = [i32, ctypes.POINTER(i32), vp, vp, i32, vp, sz, vp, vp]

@@ -14,6 +14,7 @@
 #include "kernels.h"
 #include "large.h"
 #include "mixed.h"
+#include "warm.h"
 
 using namespace psd;
 
@@ -335,11 +336,15 @@ size_t psd_saved_size(int32_t n) {
 psd_status psd_workspace_size(int32_t nblocks, const int32_t *n, psd_mode mode, int32_t flags,
                               size_t *bytes) {
     if (nblocks < 1 || !n || !bytes || !valid_mode(mode)) return PSD_EINVAL;
+    if ((flags & PSD_FLAG_WARM) && (nblocks != 1 || mode != PSD_FP64_EIG)) return PSD_EINVAL;
     size_t small = 0, large = 0;
     for (int b = 0; b < nblocks; ++b) {
         if (n[b] < 1) return PSD_EINVAL;
-        if (n[b] <= 64 && !(flags & PSD_FLAG_SAVE)) ++small;
-        else large = std::max(large, large_ws_bytes(n[b], mode, flags));
+        if (n[b] <= 64 && !(flags & (PSD_FLAG_SAVE | PSD_FLAG_WARM))) ++small;
+        else large = std::max(large, large_ws_bytes(n[b], mode, flags | (flags & PSD_FLAG_WARM ? PSD_FLAG_SAVE : 0)));
+        // the refinement and, when it is not accepted, the cold path with
+        // the saved pair share the workspace one after the other
+        if (flags & PSD_FLAG_WARM) large = std::max(large, warm_layout(n[b], nullptr, nullptr));
     }
     size_t tables = 0;
     if (nblocks > 1 && !(flags & PSD_FLAG_SAVE)) {
@@ -370,6 +375,47 @@ psd_status psd_project(int32_t n, const double *x, double *y, psd_mode mode, voi
         return status_of(launch_small_one(job, x, y, dinfo, saved, s));
     }
     return status_of(project_block(n, x, y, mode, ws, s, dinfo, saved, true));
+}
+
+psd_status psd_project_warm(int32_t n, const double *x, double *y, const double *saved_prev,
+                            double *saved_out, void *ws, size_t ws_bytes, void *stream, psd_info *info) {
+    if (n < 1 || !x || !y || !saved_prev || !saved_out) return PSD_EINVAL;
+    if (!aligned8(x) || !aligned8(y) || !aligned8(saved_prev) || !aligned8(saved_out)) return PSD_EINVAL;
+    const size_t nb = sizeof(double) * (size_t)n * (size_t)n;
+    const size_t sb = psd_saved_size(n);
+    if (partial_overlap(x, nb, y, nb) || partial_overlap(saved_prev, sb, saved_out, sb)) return PSD_EINVAL;
+    if (partial_overlap(x, nb, saved_out, sb) || partial_overlap(x, nb, saved_prev, sb) ||
+        partial_overlap(y, nb, saved_out, sb) || partial_overlap(y, nb, saved_prev, sb))
+        return PSD_EINVAL;
+    size_t need = 0;
+    psd_status st = psd_workspace_size(1, &n, PSD_FP64_EIG, PSD_FLAG_WARM, &need);
+    if (st != PSD_OK) return st;
+    if (ws_bytes < need || !ws) return PSD_EWORKSPACE;
+    if (reinterpret_cast<uintptr_t>(ws) % kAlign) return PSD_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess) return PSD_EDEVICE;
+    if (cs != hipStreamCaptureStatusNone) return PSD_EUNSUPPORTED;  // the host reads the outcome
+    psd_dev_info *dinfo = reinterpret_cast<psd_dev_info *>(info);
+    WarmWs w;
+    warm_layout(n, ws, &w);
+    if (warm_refine(w, x, saved_prev, y, saved_out, dinfo, s) != hipSuccess) return PSD_EDEVICE;
+    int reject = 1;
+    if (hipMemcpyAsync(&reject, w.flags + WF_REJECT, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return PSD_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return PSD_EDEVICE;
+    if (!reject) return PSD_OK;
+    // not accepted: the cold FP64 path (x is intact: y and saved_out were not written)
+    hipError_t e;
+    if (n <= 64) {
+        SmallJob job{0, 0, n, 0};
+        e = launch_small_one(job, x, y, dinfo, saved_out, s);
+    } else {
+        e = large_project(n, x, y, ws, s, dinfo, saved_out);
+    }
+    if (e != hipSuccess) return PSD_EDEVICE;
+    if (dinfo) hipLaunchKernelGGL(mark_fallback_kernel, dim3(1), dim3(1), 0, s, dinfo);
+    return status_of(hipGetLastError());
 }
 
 psd_status psd_project_noalloc(int32_t n, const double *x, double *y, psd_mode mode, void *stream,

@@ -69,6 +69,9 @@ struct GemmDesc {
     int nmem;
     int64_t zs;
     const int64_t *ioff;
+    // Nullable device flag read by every workgroup first: nonzero skips the
+    // whole product (a step whose outcome the device decided to drop).
+    const int *skip;
 };
 
 // Launch one GEMM described by `d` (grid sized from d) on stream st.

@@ -23,6 +23,7 @@ using namespace gemmdev;
 template <typename T, int OPA, int OPB, int EPI>
 __global__ void __launch_bounds__(NT, 3) gemm_kernel(GemmDesc d) {
     __shared__ GemmLds<T> L;
+    if (d.skip && *d.skip) return;
     int tz = blockIdx.z, b = 0;
     if (d.nmem > 1) {
         const int ks = gemm_kslices(d);

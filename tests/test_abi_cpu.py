@@ -175,3 +175,26 @@ def test_scs_settings_validation():
     assert L.psd_scs_solve(ctypes.byref(st()), ctypes.c_void_p(256), ctypes.c_void_p(1 << 40),
                            ctypes.c_void_p(2 << 40), ctypes.c_void_p(3 << 40), None, ctypes.c_void_p(4 << 40),
                            16, None, ctypes.byref(info)) == 2          # workspace too small
+
+
+def test_warm_rejects_bad_arguments_on_host(L):
+    lib = L.lib()
+    x = ctypes.c_void_p(0x10000)
+    y = ctypes.c_void_p(0x10000 + 8 * 256)
+    sp, so = ctypes.c_void_p(0x200000), ctypes.c_void_p(0x400000)
+    ws = ctypes.c_void_p(0x1000000)
+    big = 1 << 34
+    assert lib.psd_project_warm(0, x, y, sp, so, ws, big, None, None) == 1
+    assert lib.psd_project_warm(16, x, y, None, so, ws, big, None, None) == 1
+    assert lib.psd_project_warm(16, x, y, sp, None, ws, big, None, None) == 1
+    assert lib.psd_project_warm(16, x, y, sp, ctypes.c_void_p(0x200000 + 8), ws, big, None, None) == 1
+    assert lib.psd_project_warm(16, x, ctypes.c_void_p(0x200000), sp, so, ws, big, None, None) == 1
+    assert lib.psd_project_warm(16, x, y, ctypes.c_void_p(0x200004), so, ws, big, None, None) == 1
+    assert lib.psd_project_warm(16, x, y, sp, so, ws, 0, None, None) == 2      # workspace too small
+    out = ctypes.c_size_t(0)
+    assert lib.psd_workspace_size(1, L.int_array([100]), 0, L.PSD_FLAG_WARM, ctypes.byref(out)) == 0
+    warm = out.value
+    assert lib.psd_workspace_size(1, L.int_array([100]), 0, L.PSD_FLAG_SAVE, ctypes.byref(out)) == 0
+    assert warm >= out.value                      # the cold fallback fits in it too
+    assert lib.psd_workspace_size(1, L.int_array([100]), 2, L.PSD_FLAG_WARM, ctypes.byref(out)) == 1
+    assert lib.psd_workspace_size(2, L.int_array([9, 9]), 0, L.PSD_FLAG_WARM, ctypes.byref(out)) == 1
