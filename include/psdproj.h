@@ -349,6 +349,12 @@ typedef struct {
     double mixed_switch;   /* >= 0; > 0: leave mixed_mode for FP64 for good once a
                               residual check finds every termination ratio
                               (||p||/bound_p, ||r||/bound_r, |g|/bound_g) below it */
+    int32_t warm_proj;     /* 0 or 1 (one instance only: psd_scs_solve, or nbatch = 1):
+                              FP64 cone steps by psd_project_warm from the eigen-pair
+                              the previous FP64 step left (successive cone inputs are
+                              close); after an attempt falls back to the cold path the
+                              next 1, 2, 4 .. 16 steps (doubling while attempts keep
+                              failing) are cold, the last of them saving its pair */
 } psd_scs_settings;
 
 /* Result record (host memory, complete when psd_scs_solve returns). */
@@ -368,6 +374,9 @@ typedef struct {
     double sigma;          /* normalisation scale */
     double post_lambda;    /* post-processing mixing weight (0: W was PSD) */
     double post_lambda_min;/* lambda_min of W = b - A x before mixing */
+    int32_t warm_refined;  /* warm_proj: cone steps the refinement served */
+    int32_t warm_fallbacks;/* warm_proj: refinement attempts that fell back to the cold
+                              path (the other FP64 cone steps were cold) */
 } psd_scs_info;
 
 /* Device workspace bytes of psd_scs_solve for these settings (EINVAL for

@@ -249,27 +249,30 @@ def affine_step(ax: torch.Tensor, ay: torch.Tensor, d: int, zx: torch.Tensor = N
 def scs_solve(g: torch.Tensor, d: int, eps: float = 1e-5, alpha: float = 1.5, max_iters: int = 5000,
               check_every: int = 1, normalize: bool = True, mixed_iters: int = 0, mixed_mode="mixed_fp32",
               warm=None, post: bool = True, anderson: int = 0, mixed_switch: float = 0.0,
-              ws: torch.Tensor = None) -> dict:
+              ws: torch.Tensor = None, warm_proj: bool = False) -> dict:
     """Solve max tr[W G] over process matrices by the SCS iteration on the
     GPU (App. D; psd_scs_solve).  g: svec of G (d^8 float64 on the device).
     warm: optional (x, y, s) start.  anderson: memory of the type-I
     Anderson acceleration (0: off).  mixed_iters / mixed_mode: cone steps in
     a mixed mode first; mixed_switch > 0 moves to FP64 as soon as the
-    residuals are within that factor of the tolerance.  Returns the unscaled
+    residuals are within that factor of the tolerance.  warm_proj: the FP64
+    cone steps after the first by psd_project_warm from the previous step's
+    eigen-pair (counts in warm_refined / warm_fallbacks).  Returns the unscaled
     x, y, s, the post-processed process matrix w (if `post`), and the info
     record as a dict (status, iters, pobj, dobj, residuals, tau, kappa,
     sigma, ...)."""
     out = scs_solve_batched(g.reshape(1, -1), d, eps=eps, alpha=alpha, max_iters=max_iters,
                             check_every=check_every, normalize=normalize, mixed_iters=mixed_iters,
                             mixed_mode=mixed_mode, warm=None if warm is None else tuple(t.reshape(1, -1) for t in warm),
-                            post=post, anderson=anderson, mixed_switch=mixed_switch, ws=ws, _single=True)
+                            post=post, anderson=anderson, mixed_switch=mixed_switch, ws=ws, _single=True,
+                            warm_proj=warm_proj)
     return out[0]
 
 
 def scs_solve_batched(g: torch.Tensor, d: int, eps: float = 1e-5, alpha: float = 1.5, max_iters: int = 5000,
                       check_every: int = 1, normalize: bool = True, mixed_iters: int = 0, mixed_mode="mixed_fp32",
                       warm=None, post: bool = True, anderson: int = 0, mixed_switch: float = 0.0,
-                      ws: torch.Tensor = None, _single: bool = False) -> list:
+                      ws: torch.Tensor = None, _single: bool = False, warm_proj: bool = False) -> list:
     """A batch of independent solves in lockstep (psd_scs_solve_batched):
     g is (B, d^8); warm an optional (x, y, s) of shapes (B, n_x), (B, d^8),
     (B, d^8).  Returns one dict per instance, as scs_solve."""
@@ -281,7 +284,7 @@ def scs_solve_batched(g: torch.Tensor, d: int, eps: float = 1e-5, alpha: float =
     st = _lib.ScsSettings(d=d, max_iters=max_iters, check_every=check_every, mixed_iters=mixed_iters,
                           mixed_mode=_mode(mixed_mode), normalize=int(bool(normalize)),
                           warm_start=int(warm is not None), anderson=anderson, eps=eps, alpha=alpha,
-                          mixed_switch=mixed_switch)
+                          mixed_switch=mixed_switch, warm_proj=int(bool(warm_proj)))
     nbytes = _lib.scs_workspace_size(st, B)
     if ws is None or ws.numel() < nbytes:
         ws = torch.empty(nbytes, dtype=torch.uint8, device=g.device)

@@ -48,7 +48,7 @@ class ScsSettings(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("mixed_iters", ctypes.c_int32), ("mixed_mode", ctypes.c_int32), ("normalize", ctypes.c_int32),
                 ("warm_start", ctypes.c_int32), ("anderson", ctypes.c_int32), ("eps", ctypes.c_double),
-                ("alpha", ctypes.c_double), ("mixed_switch", ctypes.c_double)]
+                ("alpha", ctypes.c_double), ("mixed_switch", ctypes.c_double), ("warm_proj", ctypes.c_int32)]
 
 
 class ScsInfo(ctypes.Structure):
@@ -57,7 +57,8 @@ class ScsInfo(ctypes.Structure):
                 ("switch_iter", ctypes.c_int32), ("pobj", ctypes.c_double), ("dobj", ctypes.c_double),
                 ("res_pri", ctypes.c_double), ("res_dual", ctypes.c_double), ("gap", ctypes.c_double),
                 ("tau", ctypes.c_double), ("kappa", ctypes.c_double), ("sigma", ctypes.c_double),
-                ("post_lambda", ctypes.c_double), ("post_lambda_min", ctypes.c_double)]
+                ("post_lambda", ctypes.c_double), ("post_lambda_min", ctypes.c_double),
+                ("warm_refined", ctypes.c_int32), ("warm_fallbacks", ctypes.c_int32)]
 
 
 _lib = None

@@ -57,8 +57,8 @@ namespace psd {
 
 namespace {
 
-static_assert(sizeof(psd_scs_settings) == 56, "psd_scs_settings layout");
-static_assert(sizeof(psd_scs_info) == 104, "psd_scs_info layout");
+static_assert(sizeof(psd_scs_settings) == 64, "psd_scs_settings layout");
+static_assert(sizeof(psd_scs_info) == 112, "psd_scs_info layout");
 
 constexpr int SCS_BLOCK = 256;
 constexpr int SCS_PARTS = 512;   // blocks of the first reduction level
@@ -537,6 +537,7 @@ struct ScsLayout {
     size_t proj, proj_bytes;
     size_t aapart;
     size_t UY, ZY, PINFO, RED, AAOUT, STICKY, ACTIVE;   // batched, instance b at b * (its size)
+    size_t WSAVED;                                        // warm cone steps: the eigen-pair
     size_t slot0, inst;                                   // instance slots
     // offsets inside a slot (the affine workspace and the reduction partials too)
     size_t ux, cv, mhx, zx, tx, vy, mhy, ty, sc, part, aff;
@@ -570,7 +571,14 @@ bool scs_layout(const psd_scs_settings &s, int B, ScsLayout &L) {
     if (s.mixed_iters > 0 && psd_workspace_size(B, sizes.data(), (psd_mode)s.mixed_mode, 0, &pm) != PSD_OK)
         return false;
     L.proj_bytes = std::max(pb, std::max(pg, pm));
+    if (s.warm_proj) {
+        // warm cone steps: one instance only (the pair is that instance's)
+        size_t pw = 0;
+        if (B != 1 || psd_workspace_size(1, &n, PSD_FP64_EIG, PSD_FLAG_WARM, &pw) != PSD_OK) return false;
+        L.proj_bytes = std::max(L.proj_bytes, pw);
+    }
     L.proj = take(L.proj_bytes);
+    L.WSAVED = s.warm_proj ? take(psd_saved_size(n)) : 0;
     L.aapart = take(sizeof(double) * SCS_PARTS * AA_VALS);
     const size_t by = sizeof(double) * (size_t)ny, bx = sizeof(double) * (size_t)nx;
     L.UY = take(by * B);
@@ -614,7 +622,8 @@ bool settings_ok(const psd_scs_settings *s) {
             s->mixed_mode == PSD_MIXED_BF16X3) &&
            (s->normalize == 0 || s->normalize == 1) && (s->warm_start == 0 || s->warm_start == 1) &&
            s->anderson >= 0 && s->anderson <= AA_MAX && s->eps >= 0.0 && std::isfinite(s->eps) && s->alpha > 0.0 &&
-           s->alpha < 2.0 && s->mixed_switch >= 0.0 && std::isfinite(s->mixed_switch);
+           s->alpha < 2.0 && s->mixed_switch >= 0.0 && std::isfinite(s->mixed_switch) &&
+           (s->warm_proj == 0 || s->warm_proj == 1);
 }
 
 int grid_of(int64_t n) { return (int)((n + SCS_BLOCK - 1) / SCS_BLOCK); }
@@ -708,6 +717,9 @@ psd_status scs_solve_batch(const psd_scs_settings *s, int B, const double *g, do
     psd_info *PINFO = reinterpret_cast<psd_info *>(base + L.PINFO);
     int *STICKY = reinterpret_cast<int *>(base + L.STICKY);
     int *ACTIVE = reinterpret_cast<int *>(base + L.ACTIVE);
+    double *WSAVED = s->warm_proj ? D(L.WSAVED) : nullptr;
+    bool have_pair = false;   // WSAVED holds the pair of the previous FP64 cone step
+    int warm_wait = 0, warm_backoff = 0, warm_refined = 0, warm_fallbacks = 0;
     const int d = L.d, n = L.n;
     const int64_t nx = L.nx, ny = L.ny, nq = L.nq;
     const double gamma = 1.0 / (double)(d * d);
@@ -964,7 +976,34 @@ psd_status scs_solve_batch(const psd_scs_settings *s, int B, const double *g, do
         // projected again, its outputs already written), then v_s = u_y - q_y,
         // tau, kappa for the running ones
         const psd_mode mode = (k <= s->mixed_iters && !switched) ? (psd_mode)s->mixed_mode : PSD_FP64_EIG;
-        SCS_TRY(psd_project_batched(B, sizes.data(), ZY, UY, mode, proj, L.proj_bytes, st, PINFO));
+        if (WSAVED && mode == PSD_FP64_EIG) {
+            // warm cone steps: from the eigen-pair the previous FP64 step left
+            // (psd_project_warm falls back to the cold path by itself).  After
+            // a fallback the next 1, 2, 4 .. 16 steps (doubling while attempts
+            // keep failing) go cold, the last of them saving its pair: inputs
+            // that jump (early iterations, accelerated steps) then cost no
+            // refinement attempt each.
+            if (have_pair && warm_wait == 0) {
+                SCS_TRY(psd_project_warm(n, ZY, UY, WSAVED, WSAVED, proj, L.proj_bytes, st, PINFO));
+                psd_info pi{};
+                SCS_READ(&pi, PINFO, sizeof pi);
+                if (pi.fallback) {
+                    ++warm_fallbacks;
+                    warm_backoff = std::min(16, std::max(1, 2 * warm_backoff));
+                    warm_wait = warm_backoff;
+                } else {
+                    ++warm_refined;
+                    warm_backoff = 0;
+                }
+            } else {
+                const bool save = warm_wait <= 1;
+                SCS_TRY(psd_project(n, ZY, UY, PSD_FP64_EIG, proj, L.proj_bytes, st, PINFO, save ? WSAVED : nullptr));
+                have_pair = save;
+                if (warm_wait > 0) --warm_wait;
+            }
+        } else {
+            SCS_TRY(psd_project_batched(B, sizes.data(), ZY, UY, mode, proj, L.proj_bytes, st, PINFO));
+        }
         hipLaunchKernelGGL(scs_fold_kernel, dim3(1, 1, B), dim3(64), 0, st, PINFO, STICKY, zb);
         hipLaunchKernelGGL(scs_dual_kernel, dim3(grid_of(ny), 1, B), dim3(SCS_BLOCK), 0, st, I0.vy, ZY, UY, I0.sc, ny,
                            zb);
@@ -1093,6 +1132,10 @@ psd_status scs_solve_batch(const psd_scs_settings *s, int B, const double *g, do
         I.info->post_lambda_min = lmin;
     }
     for (int b = 0; b < B; ++b) inst[b].info->status = inst[b].status;
+    if (WSAVED) {
+        inst[0].info->warm_refined = warm_refined;
+        inst[0].info->warm_fallbacks = warm_fallbacks;
+    }
 #undef SCS_TRY
 #undef SCS_LAUNCHED
 #undef SCS_READ

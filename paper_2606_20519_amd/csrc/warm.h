@@ -12,6 +12,7 @@ namespace psd {
 constexpr int WARM_STEPS = 5;          // refinement steps at most
 constexpr double WARM_STOP = 1e-7;     // max |E_ij| after which the next step is skipped
 constexpr double WARM_ACCEPT = 1e-6;   // max |E_ij| of the last step for the result to stand
+constexpr double WARM_GIVE_UP = 0.5;   // a step above this (or above half the previous) ends the attempt
 
 // device flags (ints) and scalars (doubles) of one refinement
 enum : int { WF_STATUS = 0, WF_ITERS = 1, WF_REJECT = 2, WF_SKIP = 3, WF_COUNT = WF_SKIP + WARM_STEPS + 1 };

@@ -25,7 +25,9 @@
 // |E_ij| of a step is <= 1e-7 (the next would change X by ~1e-14) and is
 // accepted when the last step's is <= 1e-6; anything else (a step limit of
 // five, a basis that was not close, a non-finite input) leaves the decision
-// to the host, which then runs the cold FP64 path instead.
+// to the host, which then runs the cold FP64 path instead.  A refinement
+// that is not converging is cut short: a step above 1/2, or above half the
+// previous step, skips the rest.
 //
 // Products run as split-K GEMMs (partials summed by the passes that read
 // them) so that a block of a few hundred rows still fills the chip; every
@@ -210,7 +212,7 @@ __global__ void __launch_bounds__(256) wm_correction_kernel(const double2 *__res
 }
 
 // After step k: e = max |E_ij| over the pairs; step k + 1 is skipped once
-// e <= 1e-7 (or when step k was).
+// e <= 1e-7, when the refinement stalls (or when step k was).
 __global__ void __launch_bounds__(256) wm_step_kernel(const double *__restrict__ epart, int np, double *scal,
                                                       int *flags, int k) {
     if (flags[WF_SKIP + k]) {
@@ -227,9 +229,14 @@ __global__ void __launch_bounds__(256) wm_step_kernel(const double *__restrict__
         double e2 = red[0];
         for (int w = 1; w < 4; ++w) e2 = nanmax(e2, red[w]);
         const double e = sqrt(e2);
+        // stop once converged, and give up early (the host then runs the
+        // cold path) when a step is not even half the previous one or
+        // rotates by more than half a radian: a refinement that converges
+        // squares its step
+        const bool stall = e > WARM_GIVE_UP || (k > 0 && e > 0.5 * scal[WS_ELAST]);
         scal[WS_ELAST] = e;
         flags[WF_ITERS] += 1;
-        flags[WF_SKIP + k + 1] = (e <= WARM_STOP) ? 1 : 0;
+        flags[WF_SKIP + k + 1] = (e <= WARM_STOP || stall) ? 1 : 0;
     }
 }
 

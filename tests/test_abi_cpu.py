@@ -163,7 +163,11 @@ def test_scs_settings_validation():
     assert L.psd_scs_workspace_size_batched(ctypes.byref(st()), 0, ctypes.byref(out)) == 1
     assert L.psd_scs_workspace_size_batched(ctypes.byref(st()), 65535, ctypes.byref(out)) == 0  # the bound
     assert L.psd_scs_workspace_size_batched(ctypes.byref(st()), 65536, ctypes.byref(out)) == 1  # beyond it
-    for bad in (dict(d=1), dict(d=9), dict(max_iters=0), dict(check_every=0), dict(alpha=2.0), dict(alpha=0.0),
+    assert ctypes.sizeof(_lib.ScsSettings) == 64 and ctypes.sizeof(_lib.ScsInfo) == 112
+    assert L.psd_scs_workspace_size_batched(ctypes.byref(st(warm_proj=1)), 1, ctypes.byref(out)) == 0
+    assert out.value >= plain + _lib.saved_size(256)        # the warm cone steps' eigen-pair
+    assert L.psd_scs_workspace_size_batched(ctypes.byref(st(warm_proj=1)), 2, ctypes.byref(out)) == 1
+    for bad in (dict(warm_proj=2), dict(warm_proj=-1), dict(d=1), dict(d=9), dict(max_iters=0), dict(check_every=0), dict(alpha=2.0), dict(alpha=0.0),
                 dict(eps=-1.0), dict(eps=float("nan")), dict(mixed_iters=5, mixed_mode=0), dict(anderson=17),
                 dict(anderson=-1), dict(mixed_switch=-1.0), dict(mixed_switch=float("inf")),
                 dict(normalize=2), dict(mixed_iters=-1)):

@@ -165,6 +165,27 @@ def test_certificate(P, d, aa):
     _certificate(d, r, gmat, 10 * eps)
 
 
+@pytest.mark.parametrize("d, aa", [(3, 0), (4, 0), (5, 5)])
+def test_warm_cone_steps(P, d, aa):
+    """warm_proj: every FP64 cone step after the first refines the eigen-pair
+    the previous one left (psd_project_warm); the solve reaches the same
+    certificate, in about as many iterations as the cold solve (the
+    projections agree to rounding)."""
+    g, _ = gyni(d)
+    gmat = oracle.unpack(g, d ** 4)
+    eps = 1e-6 if d < 5 else 1e-5
+    cold = P.scs_solve(dev(g), d, eps=eps, max_iters=10000, anderson=aa)
+    r = P.scs_solve(dev(g), d, eps=eps, max_iters=10000, anderson=aa, warm_proj=True)
+    print(f"d={d} anderson={aa}: cold {cold['iters']} iterations, warm cone steps {r['iters']} "
+          f"({r['warm_refined']} refined, {r['warm_fallbacks']} cold fallbacks), value {r['pobj']:.9f} "
+          f"(cold {cold['pobj']:.9f})", flush=True)
+    assert r["status"] == 0 and r["proj_status"] == 0
+    assert r["warm_refined"] + r["warm_fallbacks"] <= r["iters"] - 1
+    assert r["warm_refined"] > 0
+    assert abs(r["iters"] - cold["iters"]) <= max(3, cold["iters"] // 50)
+    _certificate(d, r, gmat, 10 * eps)
+
+
 @pytest.mark.parametrize("d, which, value", [(2, 0, 1.0), (2, 86, 1.0), (2, "forbidden", 0.0),
                                              (2, "identity", 4.0), (3, "identity", 9.0),
                                              (3, "forbidden", 0.0)])
