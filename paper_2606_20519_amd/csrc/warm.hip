@@ -107,26 +107,12 @@ __global__ void __launch_bounds__(256) wm_sum_kernel(const double2 *__restrict__
     out[idx] = acc;
 }
 
-// Rayleigh quotients lambda_i = Re S_ii / Re G_ii from the partials, and
-// max |lambda| (one workgroup).
-__global__ void __launch_bounds__(1024) wm_lambda_kernel(const double2 *__restrict__ pS,
-                                                         const double2 *__restrict__ pG, int ks, int64_t zs,
-                                                         int64_t ld, int n, double *lam, double *scal,
-                                                         const int *skip) {
-    if (*skip) return;
+// max |lambda| of the previous pair (one workgroup, once per call): the scale
+// of the cluster threshold.
+__global__ void __launch_bounds__(1024) wm_scale_kernel(const double *__restrict__ saved, int n, double *scal) {
     __shared__ double red[16];
     double m = 0.0;
-    for (int i = threadIdx.x; i < n; i += 1024) {
-        const int64_t idx = i + (int64_t)i * ld;
-        double s = 0.0, g = 0.0;
-        for (int z = 0; z < ks; ++z) {
-            s += pS[idx + z * zs].x;
-            g += pG[idx + z * zs].x;
-        }
-        const double l = s / g;
-        lam[i] = l;
-        m = nanmax(m, fabs(l));
-    }
+    for (int i = threadIdx.x; i < n; i += 1024) m = nanmax(m, fabs(saved[i]));
     for (int o = 32; o > 0; o >>= 1) m = nanmax(m, __shfl_xor(m, o, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     __syncthreads();
@@ -137,18 +123,34 @@ __global__ void __launch_bounds__(1024) wm_lambda_kernel(const double2 *__restri
     }
 }
 
+// Rayleigh quotient Re S_kk / Re G_kk from the partials (every workgroup
+// that needs index k forms it the same way, so the values agree bitwise).
+__device__ __forceinline__ double wm_rayleigh(const double2 *__restrict__ pS, const double2 *__restrict__ pG, int ks,
+                                              int64_t zs, int64_t ld, int k) {
+    const int64_t idx = k + (int64_t)k * ld;
+    double sv = 0.0, gv = 0.0;
+    for (int z = 0; z < ks; ++z) {
+        sv += pS[idx + z * zs].x;
+        gv += pG[idx + z * zs].x;
+    }
+    return sv / gv;
+}
+
 // The correction E on a lower tile pair: workgroup b handles the WT x WT
 // tile (I, J), I >= J, from the lower partials of S and G, and writes both
 // E(I, J) and E(J, I) (the latter through LDS, so both stores run along
-// columns).  Also the largest off-diagonal |E_ij| of the pair, to epart[b].
+// columns).  The Rayleigh quotients of its rows and columns come from the
+// partials' diagonals; the diagonal pairs store those of their rows in lam.
+// Also the largest off-diagonal |E_ij|^2 of the pair, to epart[b].
 __global__ void __launch_bounds__(256) wm_correction_kernel(const double2 *__restrict__ pS,
                                                             const double2 *__restrict__ pG, int ks, int64_t zs,
-                                                            int64_t ld, int n, const double *__restrict__ lam,
+                                                            int64_t ld, int n, double *lam,
                                                             const double *__restrict__ scal, double2 *E,
                                                             double *epart, const int *skip) {
     if (*skip) return;
     __shared__ double2 U[WT][WT + 1];
     __shared__ double red[4];
+    __shared__ double lr[WT], lc[WT];  // Rayleigh quotients of the pair's rows and columns
     // lower tile pair b -> (I, J), column by column
     const int nt = (n + WT - 1) / WT;
     int b = blockIdx.x, J = 0;
@@ -158,6 +160,14 @@ __global__ void __launch_bounds__(256) wm_correction_kernel(const double2 *__res
     }
     const int I = J + b;
     const int t = threadIdx.x, r = t % WT, c0 = t / WT;
+    if (t < 2 * WT) {
+        const int k = (t < WT ? I : J) * WT + (t % WT);
+        const double l = k < n ? wm_rayleigh(pS, pG, ks, zs, ld, k) : 0.0;
+        if (t < WT) lr[t] = l;
+        else lc[t - WT] = l;
+        if (t < WT && I == J && k < n) lam[k] = l;
+    }
+    __syncthreads();
     const double tau = 0x1p-40 * scal[WS_LMAX];
     double emax = 0.0;
     const int i = I * WT + r;
@@ -176,7 +186,7 @@ __global__ void __launch_bounds__(256) wm_correction_kernel(const double2 *__res
             E[idx] = cmk(0.5 * (1.0 - g.x), 0.0);
             continue;
         }
-        const double li = lam[i], lj = lam[j];
+        const double li = lr[r], lj = lc[c];
         // E(i, j): R_ij = -G_ij
         double2 eij, eji;
         const double d = lj - li;
@@ -289,11 +299,14 @@ __global__ void __launch_bounds__(256) wm_save_kernel(const double *__restrict__
 }  // namespace
 
 // Split-K slices: enough workgroups on the lower-tile products (about 512),
-// at most 8 slices, each a multiple of the 16-deep k-step.
+// at most 8 slices and one round of workgroups on the full products, each
+// slice a multiple of the 16-deep k-step.
 static void warm_split(int n, int *ks, int *kchunk) {
     const int t = (n + 63) / 64;
     const int lower = t * (t + 1) / 2;
     int s = std::min(8, std::max(1, (512 + lower - 1) / lower));
+    // and at most one round of workgroups (three per CU) on the full products
+    s = std::max(1, std::min(s, 768 / (t * t)));
     int kc = ((n + s - 1) / s + 15) / 16 * 16;
     *kchunk = kc;
     *ks = (n + kc - 1) / kc;
@@ -338,6 +351,7 @@ hipError_t warm_refine(const WarmWs &w, const double *x, const double *saved_pre
     hipLaunchKernelGGL(wm_init_kernel, dim3(1), dim3(64), 0, st, w.flags, (int)WF_COUNT);
     hipLaunchKernelGGL(wm_unpack_kernel, gcol, dim3(256), 0, st, x, w.A, ld, n, w.flags);
     hipLaunchKernelGGL(wm_load_kernel, gcol, dim3(256), 0, st, saved_prev, n, w.X[0], ld);
+    hipLaunchKernelGGL(wm_scale_kernel, dim3(1), dim3(1024), 0, st, saved_prev, n, w.scal);
     // a non-finite input skips every step (the host then runs the cold path)
     hipLaunchKernelGGL(wm_gate_kernel, dim3(1), dim3(64), 0, st, w.flags);
     auto product = [&](const double2 *a, int opa, const double2 *bm, int opb, int lower, const int *skip) {
@@ -371,8 +385,6 @@ hipError_t warm_refine(const WarmWs &w, const double *x, const double *saved_pre
         g = product(X, OP_C, X, OP_N, 1, skip);
         g.C = w.P2;
         if ((e = gemm_launch(g, true, EPI_STORE, st)) != hipSuccess) return e;
-        hipLaunchKernelGGL(wm_lambda_kernel, dim3(1), dim3(1024), 0, st, w.P1, w.P2, w.ks, zs, ld, n, w.lam, w.scal,
-                           skip);
         hipLaunchKernelGGL(wm_correction_kernel, dim3(w.npairs), dim3(256), 0, st, w.P1, w.P2, w.ks, zs, ld, n,
                            w.lam, w.scal, w.E, w.epart, skip);
         hipLaunchKernelGGL(wm_step_kernel, dim3(1), dim3(256), 0, st, w.epart, w.npairs, w.scal, w.flags, k);
