@@ -21,7 +21,8 @@ enum : int { WS_LMAX = 0, WS_ELAST = 1 };
 struct WarmWs {
     int n;
     int64_t ld;        // leading dimension of every matrix (= n)
-    int ks, kchunk;    // split-K slices of the products and rows per slice
+    int ksf, kcf;      // split-K slices of the full products (A X, X E) and rows per slice
+    int ksl, kcl;      // the same for the lower-tile products (X^H B, X^H X)
     double2 *A;        // the input, full Hermitian (M = conj X)
     double2 *X[2];     // eigenvector estimates, ping-pong
     double2 *B;        // A X

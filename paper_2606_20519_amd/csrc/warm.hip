@@ -298,16 +298,13 @@ __global__ void __launch_bounds__(256) wm_save_kernel(const double *__restrict__
 
 }  // namespace
 
-// Split-K slices: enough workgroups on the lower-tile products (about 512),
-// at most 8 slices and one round of workgroups on the full products, each
-// slice a multiple of the 16-deep k-step.
-static void warm_split(int n, int *ks, int *kchunk) {
-    const int t = (n + 63) / 64;
-    const int lower = t * (t + 1) / 2;
-    int s = std::min(8, std::max(1, (512 + lower - 1) / lower));
-    // and at most one round of workgroups (three per CU) on the full products
-    s = std::max(1, std::min(s, 768 / (t * t)));
-    int kc = ((n + s - 1) / s + 15) / 16 * 16;
+// Split-K slices of a product over `tiles` output tiles: enough workgroups
+// (about 512) but at most one round of them (three per CU), at most 8
+// slices, each a multiple of the 16-deep k-step.
+static void warm_split(int n, int tiles, int *ks, int *kchunk) {
+    int s = std::min(8, std::max(1, (512 + tiles - 1) / tiles));
+    s = std::max(1, std::min(s, 768 / tiles));
+    const int kc = ((n + s - 1) / s + 15) / 16 * 16;
     *kchunk = kc;
     *ks = (n + kc - 1) / kc;
 }
@@ -323,15 +320,18 @@ size_t warm_layout(int n, void *base, WarmWs *w) {
     WarmWs W{};
     W.n = n;
     W.ld = n;
-    warm_split(n, &W.ks, &W.kchunk);
+    const int t = (n + 63) / 64;
+    warm_split(n, t * t, &W.ksf, &W.kcf);
+    warm_split(n, t * (t + 1) / 2, &W.ksl, &W.kcl);
+    const int ksmax = std::max(W.ksf, W.ksl);
     const size_t mat = sizeof(double2) * (size_t)n * (size_t)n;
     W.A = static_cast<double2 *>(take(mat));
     W.X[0] = static_cast<double2 *>(take(mat));
     W.X[1] = static_cast<double2 *>(take(mat));
     W.B = static_cast<double2 *>(take(mat));
     W.E = static_cast<double2 *>(take(mat));
-    W.P1 = static_cast<double2 *>(take(mat * W.ks));
-    W.P2 = static_cast<double2 *>(take(mat * W.ks));
+    W.P1 = static_cast<double2 *>(take(mat * ksmax));
+    W.P2 = static_cast<double2 *>(take(mat * W.ksl));
     W.lam = static_cast<double *>(take(sizeof(double) * n));
     W.lamp = static_cast<double *>(take(sizeof(double) * n));
     const int nt = (n + WT - 1) / WT;
@@ -356,6 +356,7 @@ hipError_t warm_refine(const WarmWs &w, const double *x, const double *saved_pre
     hipLaunchKernelGGL(wm_gate_kernel, dim3(1), dim3(64), 0, st, w.flags);
     auto product = [&](const double2 *a, int opa, const double2 *bm, int opb, int lower, const int *skip) {
         GemmDesc g{};
+        g.kchunk = lower ? w.kcl : w.kcf;
         g.M = g.N = g.K = n;
         g.lower_only = lower;
         g.A = GemmOperand{a, a, ld, ld, n, opa, nullptr};
@@ -363,7 +364,6 @@ hipError_t warm_refine(const WarmWs &w, const double *x, const double *saved_pre
         g.ldc = ld;
         g.alpha = 1.0;
         g.beta = 0.0;
-        g.kchunk = w.kchunk;
         g.c_zstride = zs;
         g.skip = skip;
         return g;
@@ -377,7 +377,7 @@ hipError_t warm_refine(const WarmWs &w, const double *x, const double *saved_pre
         GemmDesc g = product(w.A, OP_N, X, OP_N, 0, skip);
         g.C = w.P1;
         if ((e = gemm_launch(g, true, EPI_STORE, st)) != hipSuccess) return e;
-        hipLaunchKernelGGL(wm_sum_kernel, gcol, dim3(256), 0, st, w.P1, w.ks, zs, nullptr, w.B, ld, n, skip);
+        hipLaunchKernelGGL(wm_sum_kernel, gcol, dim3(256), 0, st, w.P1, w.ksf, zs, nullptr, w.B, ld, n, skip);
         // S = X^H B and G = X^H X, lower tiles (summed by the passes below)
         g = product(X, OP_C, w.B, OP_N, 1, skip);
         g.C = w.P1;
@@ -385,14 +385,14 @@ hipError_t warm_refine(const WarmWs &w, const double *x, const double *saved_pre
         g = product(X, OP_C, X, OP_N, 1, skip);
         g.C = w.P2;
         if ((e = gemm_launch(g, true, EPI_STORE, st)) != hipSuccess) return e;
-        hipLaunchKernelGGL(wm_correction_kernel, dim3(w.npairs), dim3(256), 0, st, w.P1, w.P2, w.ks, zs, ld, n,
+        hipLaunchKernelGGL(wm_correction_kernel, dim3(w.npairs), dim3(256), 0, st, w.P1, w.P2, w.ksl, zs, ld, n,
                            w.lam, w.scal, w.E, w.epart, skip);
         hipLaunchKernelGGL(wm_step_kernel, dim3(1), dim3(256), 0, st, w.epart, w.npairs, w.scal, w.flags, k);
         // X_next = X + X E (a copy of X when the step is skipped)
         g = product(X, OP_N, w.E, OP_N, 0, skip);
         g.C = w.P1;
         if ((e = gemm_launch(g, true, EPI_STORE, st)) != hipSuccess) return e;
-        hipLaunchKernelGGL(wm_sum_kernel, gcol, dim3(256), 0, st, w.P1, w.ks, zs, X, Xn, ld, n, skip);
+        hipLaunchKernelGGL(wm_sum_kernel, gcol, dim3(256), 0, st, w.P1, w.ksf, zs, X, Xn, ld, n, skip);
     }
     const double2 *Xf = w.X[WARM_STEPS & 1];
     hipLaunchKernelGGL(wm_final_kernel, dim3(1), dim3(1024), 0, st, w.lam, w.lamp, n, w.scal, w.flags, info);

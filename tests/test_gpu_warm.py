@@ -17,7 +17,9 @@ relative Frobenius) against the oracle or the closed form.
 * in place: y == x and saved_out == saved_prev;
 * the refined pair serves psd_project_vjp: against the oracle's derivative;
 * a non-finite input: NaN output and PSD_ENONFINITE, through the cold path;
-* host-side refusals: mixed workspace flags and overlapping buffers."""
+* host-side refusals: mixed workspace flags and overlapping buffers;
+* two steps at the d = 6 order (three split-K slices on the lower products,
+  one on the full ones) against the cold path."""
 import numpy as np
 import pytest
 
@@ -176,3 +178,19 @@ def test_host_refusals(P):
     sv = saved_buf(P, 100)
     with pytest.raises(_lib.PsdError):
         P.project_warm(x, 100, sv, saved_out=sv, out=sv[: 100 * 100])   # y inside the saved pair
+
+
+@pytest.mark.parametrize("n", [1296])
+def test_warm_step_full_size_d6(P, n):
+    """d = 6 order (three split-K slices on the lower products, one on the
+    full ones): two 1e-3 steps of the sequence,
+    against the cold GPU path (itself held to the oracle at this order by
+    the closed-form tests)."""
+    xs = W.warm_sequence(n, 9000 + n, 3)
+    _, saved = cold_with_saved(P, xs[0], n)
+    for k in (1, 2):
+        print(f"warm n={n} iterate {k}", flush=True)
+        y, info = P.project_warm(dev(xs[k]), n, saved, info=True)
+        assert info["status"] == 0 and info["fallback"] == 0, info
+        yc = P.project(dev(xs[k]), n)
+        assert rel(y.cpu().numpy(), yc.cpu().numpy()) <= TOL
