@@ -160,6 +160,24 @@ def mfma_roofline(fp64_gemm, mode, n, timed, warm=False):
     return out
 
 
+def oracle_single_thread(n: int) -> dict:
+    """The oracle on one thread (a child process with OMP_NUM_THREADS=1, no
+    GPU use): one projection of the first iterate of the n-order sequence."""
+    import subprocess
+    code = ("import sys, time; sys.path.insert(0, sys.argv[1]); import oracle; "
+            "from paper_2606_20519_amd import workloads as W; x = W.warm_sequence(int(sys.argv[2]), 1002, 1)[0]; "
+            "oracle.project(x[:16], 4); t = time.perf_counter(); oracle.project(x, int(sys.argv[2])); "
+            "print(time.perf_counter() - t)")
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code, ROOT, str(n)], env=env, capture_output=True, text=True,
+                       timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr.strip()[-200:]}
+    dt = float(r.stdout.strip().splitlines()[-1])
+    return {"value": round(1.0 / dt, 6), "unit": "projections/s", "cores": 1, "seconds": round(dt, 2),
+            "sample": f"one oracle projection of the first iterate (n={n}), one thread"}
+
+
 def c5_closed_form_errors(P, oracle, W, n, g_np, dev, extra):
     """Errors of the FP64, FP32-, BF16- and BF16x3-mixed projections and of the
     derivative against the closed forms on a constructed spectrum of order n
@@ -734,6 +752,8 @@ def main():
         model, sockets = host_cpu()
         cpu = {"value": round(value_cpu, 6) if value_cpu else None, "unit": unit, "cores": oracle.num_threads(),
                "kind": "oracle", "sample": sample, "cpu_model": model, "sockets": sockets}
+        if wl == "c2":
+            cpu["single_thread"] = oracle_single_thread(n)
 
     metric = {"c4": "PSD cone projections/sec (one graph launch per cone)"}.get(wl, "PSD projections/sec")
     out = {
