@@ -7,7 +7,7 @@ relative Frobenius) against the oracle or the closed form.
   of warm calls, each from the pair the previous call left; sampled iterates
   against the oracle, every iterate against the cold GPU path; no fallback,
   at most five refinement steps;
-* small and tile-ragged orders (16, 40, 65, 130, 257) along sequences of
+* small and tile-ragged orders (1, 2, 16, 40, 65, 130, 257) along sequences of
   their own, against the oracle;
 * a pair that is not close (another matrix's): the cold path runs
   (fallback = 1) and y and the saved pair are bitwise those of psd_project;
@@ -80,7 +80,7 @@ def test_warm_sequence_625(P):
     print("refinement steps per iterate:", steps, flush=True)
 
 
-@pytest.mark.parametrize("n", [16, 40, 65, 130, 257])
+@pytest.mark.parametrize("n", [1, 2, 16, 40, 65, 130, 257])
 def test_warm_sequence_small_and_ragged(P, n):
     xs = W.warm_sequence(n, 2000 + n, 4)
     _, saved = cold_with_saved(P, xs[0], n)
