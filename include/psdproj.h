@@ -128,8 +128,9 @@ psd_status psd_project(int32_t n, const double *x, double *y, psd_mode mode,
  * starting, App. D.2 of the paper; the warm-started refinement, Sec. IV).
  * The eigenvectors are refined by matrix products (the iteration of Ogita
  * and Aishima, 2018: X <- X + X E from G = X^H X and S = X^H A X, at most 5
- * steps, stopping once the largest rotation |E_ij| of a step is <= 1e-7),
- * and Pi = X diag(max(lambda, 0)) X^H.  The refined pair goes to saved_out
+ * steps, stopping once the largest rotation |E_ij| of a step is <= 1e-7 and
+ * giving up when a step is above 1/2 or above half the previous one), and
+ * Pi = X diag(max(lambda, 0)) X^H.  The refined pair goes to saved_out
  * (may equal saved_prev), ready for the next call or psd_project_vjp.
  * When the last step's largest rotation is above 1e-6 (the pair was not
  * close, the spectrum moved too far) or x is not finite, the block is
