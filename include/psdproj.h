@@ -34,7 +34,9 @@
  * non-convergence) are written to `info` asynchronously; synchronise the
  * stream before reading it.  No call prints, throws or allocates, and none
  * synchronises the stream except a mixed-mode psd_project while the FP64
- * fallback is enabled (psd_set_mixed_fallback).  Calls on different streams
+ * fallback is enabled (psd_set_mixed_fallback), psd_project_warm (it reads
+ * whether its refinement was accepted) and the SCS solver (it reads its
+ * residuals back).  Calls on different streams
  * with different workspaces may run concurrently.
  *
  * Failure policy: a block whose input holds a NaN or an infinity gets

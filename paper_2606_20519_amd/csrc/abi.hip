@@ -1,7 +1,8 @@
 // Host runtime behind the C ABI declared in include/psdproj.h: argument
 // validation, workspace layout and kernel dispatch.  No call allocates or
 // prints; all device work goes on the caller's stream, and only a mixed
-// psd_project with the FP64 fallback enabled synchronises it.
+// psd_project with the FP64 fallback enabled and psd_project_warm (which
+// reads whether its refinement was accepted) synchronise it.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
