@@ -41,6 +41,13 @@ namespace {
 
 constexpr int kMaxConcurrency = 32;
 constexpr int kMaxGraphs = 8;  // captured (x, y, ws, infos) sets kept per plan
+// Longest run of captured launches one stream of a plan may carry.  The
+// largest captures that ran are about 27 000 launches per stream (an FP64
+// d = 8 cone at concurrency 4: three groups of order 4096 a stream); a tune
+// of that cone that also tried concurrency 1 (all eleven groups, about
+// 97 000 launches, on one stream) ended the process with a segmentation
+// fault whose cause was not established, so longer chains are not captured.
+constexpr long kMaxChain = 30000;
 
 struct GraphEntry {
     const double *x;
@@ -186,6 +193,23 @@ bool set_jobs(psd_plan_s *p, int group) {
            hipMemcpy(p->didx, hidx.data(), hidx.size() * sizeof(int), hipMemcpyHostToDevice) == hipSuccess;
 }
 
+// Launches of one lockstep group of order n (captured graph nodes): the FP64
+// path launches two kernels per column of the reduction, one GEMM and one
+// norm per panel, and a few hundred for the rest; the mixed forms a few
+// hundred in all.
+long group_launches(int n, int mode) {
+    if (n <= 64) return 0;
+    return mode == PSD_FP64_EIG ? 2L * n + n / 8 + 300 : 400;
+}
+
+// Launches on the busiest stream when the jobs go round-robin over K streams.
+long longest_chain(const psd_plan_s *p, int K) {
+    std::vector<long> per(std::max(1, K), 0);
+    for (size_t ci = 0; ci < p->chunks.size(); ++ci)
+        per[ci % per.size()] += group_launches(p->chunks[ci].n, p->mode);
+    return *std::max_element(per.begin(), per.end());
+}
+
 // Largest group of the current split.
 int max_members(const psd_plan_s *p) {
     size_t m = 0;
@@ -230,6 +254,8 @@ psd_status psd_plan_create(int32_t nblocks, const int32_t *n, psd_mode mode, int
     if (K == 0) K = 4;
     bool ok = set_jobs(p, group);
     p->K = std::max(1, std::min(K, std::max(1, p->nlarge)));
+    // enough streams that no stream carries more than kMaxChain launches
+    while (p->K < std::min(kMaxConcurrency, p->nlarge) && longest_chain(p, p->K) > kMaxChain) ++p->K;
     ok = ok && prepare_kernel_attributes() == hipSuccess &&
               hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) == hipSuccess &&
               hipEventCreateWithFlags(&p->fork, hipEventDisableTiming) == hipSuccess;
@@ -270,6 +296,7 @@ psd_status psd_plan_execute(psd_plan p, const double *x, double *y, void *ws, si
     if (p->nlarge && (!ws || ws_bytes < need)) return PSD_EWORKSPACE;
     if (ws && (reinterpret_cast<uintptr_t>(ws) % 256)) return PSD_EINVAL;
     hipGraphExec_t ex = find_graph(p, x, y, ws, infos, p->K);
+    if (!ex && longest_chain(p, p->K) > kMaxChain) return PSD_EUNSUPPORTED;
     if (!ex) {
         // at most kMaxGraphs captured buffer sets; the oldest is dropped once
         // the work already queued on the stream (which may replay it) is done
@@ -325,6 +352,7 @@ psd_status psd_plan_tune(psd_plan p, const double *x, double *y, void *ws, size_
         cand.push_back(maxK);
         for (int K : cand) {
             if ((size_t)K * p->slot_bytes > ws_bytes) break;
+            if (longest_chain(p, K) > kMaxChain) continue;   // not captured (kMaxChain)
             p->K = K;
             psd_status st = psd_plan_execute(p, x, y, ws, ws_bytes, stream, nullptr);  // capture + warm up
             if (st != PSD_OK) continue;
@@ -352,6 +380,7 @@ psd_status psd_plan_tune(psd_plan p, const double *x, double *y, void *ws, size_
     if (!set_jobs(p, bestG)) return PSD_EDEVICE;
     p->ns_big = bestB;
     p->K = std::max(1, std::min(bestK, std::max(1, p->nlarge)));
+    while (p->K < std::min(kMaxConcurrency, p->nlarge) && longest_chain(p, p->K) > kMaxChain) ++p->K;
     tune_record(tune_key(p->n, p->mode), p->K, bestG, bestB, best_ms);
     if (best_out) *best_out = p->K;
     return PSD_OK;
