@@ -213,3 +213,17 @@ def test_plan_bf16_tile_form(P, tmp_path):
         plan.close()
     finally:
         del os.environ["PSD_TUNE_CACHE"]
+
+
+def test_plan_long_chains_get_more_streams(P):
+    """No stream of a plan's graph carries more than 30 000 launches: the FP64
+    d = 8 cone (eleven lockstep groups of order 4096, about 8 900 launches
+    each) asked for one stream is created with enough streams.  Creation
+    only: nothing is captured or run."""
+    sizes = ([4096] + [64] * 8) * 32
+    plan = P.Plan(sizes, "fp64", concurrency=1)
+    try:
+        assert plan.group_size * plan.concurrency >= 9
+        assert plan.concurrency >= 4
+    finally:
+        plan.close()
