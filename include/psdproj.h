@@ -200,7 +200,7 @@ psd_status psd_project_vjp(int32_t n, const double *x, const double *saved,
  * cache (file PSD_TUNE_CACHE, default ./psdproj_tune.jsonl), else 4; the
  * group size recorded there is used as well.  Concurrency is clamped to
  * [1, number of jobs], and raised until no stream of the graph carries more
- * than 30 000 launches (an FP64 job of order n launches about 2.1 n
+ * than 20 000 launches (an FP64 job of order n launches about 2.1 n
  * kernels): the tuner skips concurrencies below that, and an execution
  * that would capture a longer chain returns PSD_EUNSUPPORTED.  Mixed modes use the
  * Newton-Schulz settings current at capture time.  A plan is not

@@ -42,12 +42,13 @@ namespace {
 constexpr int kMaxConcurrency = 32;
 constexpr int kMaxGraphs = 8;  // captured (x, y, ws, infos) sets kept per plan
 // Longest run of captured launches one stream of a plan may carry.  The
-// largest captures that ran are about 27 000 launches per stream (an FP64
-// d = 8 cone at concurrency 4: three groups of order 4096 a stream); a tune
-// of that cone that also tried concurrency 1 (all eleven groups, about
-// 97 000 launches, on one stream) ended the process with a segmentation
-// fault whose cause was not established, so longer chains are not captured.
-constexpr long kMaxChain = 30000;
+// longest captures known to run carry about 18 000 launches per stream (the
+// FP64 d = 8 cone at concurrency 4: two lockstep groups of order 4096 a
+// stream; the d = 7 cone at concurrency 1: 16 000); a tune of the d = 8 cone
+// that also tried concurrency 2 and 1 (36 000 and 72 000 launches on one
+// stream) ended the process with a segmentation fault whose cause was not
+// established, so longer chains are not captured.
+constexpr long kMaxChain = 20000;
 
 struct GraphEntry {
     const double *x;
