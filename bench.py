@@ -305,6 +305,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=10, help="blocks projected by the CPU oracle (bounded sample)")
     ap.add_argument("--no-context", action="store_true",
                     help="skip the context measurements after the timed region (counter runs)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="c4: run the plan at its default concurrency and group size (no autotuning)")
     ap.add_argument("--warm", action="store_true",
                     help="c2: iterates 1.. by psd_project_warm from the pair the previous one left")
     ap.add_argument("--blocks", type=int, default=50, help="blocks per step for c1 / c2 (counter runs use fewer)")
@@ -467,7 +469,8 @@ def main():
         if not os.environ.get("PSD_TUNE_CACHE"):
             import tempfile
             os.environ["PSD_TUNE_CACHE"] = os.path.join(tempfile.gettempdir(), "psdproj_bench_tune.jsonl")
-        plan.tune(X, Y, reps=3 if args.d <= 6 else 2, max_concurrency=8)
+        if not args.no_tune:
+            plan.tune(X, Y, reps=3 if args.d <= 6 else 2, max_concurrency=8)
         plan.execute(X, out=Y)   # capture outside timing
     log("warm-up")
     for _ in range(args.warmup):
