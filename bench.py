@@ -23,7 +23,8 @@ Other workloads (one JSON line each, selected with --workload):
   c3  orders 1296 and 2401 (d = 6, 7), spectra in [-1,-1e-6] u [1e-6,1],
       --mode mixed_bf16 | mixed_bf16x3 | mixed_fp32 | fp64 (--n picks the order)
   c4  one cone of 32 instances x [W (d^4) + 8 Choi (d^2)] by one graph
-      launch per step (--d picks d, --mode the precision)
+      launch per step (--d picks d, --mode the precision; the plan is
+      autotuned first unless --no-tune)
   c5  (default) order 4096, --mode fp64 | mixed_*
 
 The JSON line carries the roofline of the dominant kernel, timed live with
