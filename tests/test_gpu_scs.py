@@ -63,10 +63,14 @@ def gyni(d, seed=7):
     return _PROBS[key]
 
 
-@pytest.mark.parametrize("d, k", [(2, 1), (2, 3), (2, 40), (3, 1), (3, 12)])
-def test_iterates_match_oracle(P, d, k):
+@pytest.mark.parametrize("d, k, warm", [(2, 1, False), (2, 3, False), (2, 40, False), (3, 1, False),
+                                        (3, 12, False), (2, 40, True), (3, 40, True)])
+def test_iterates_match_oracle(P, d, k, warm):
+    """warm: the FP64 cone steps after the first by psd_project_warm (the
+    oracle projects every step by Jacobi from scratch); early steps move too
+    far and fall back to the cold path, later ones are refined."""
     g, prob = gyni(d)
-    print(f"SCS iterates d={d} k={k}", flush=True)
+    print(f"SCS iterates d={d} k={k} warm cone steps {warm}", flush=True)
     sv = scs.Solver(prob)
     sv.start()
     for _ in range(k):
@@ -77,8 +81,13 @@ def test_iterates_match_oracle(P, d, k):
     else:        # tau = 0 (the first step from the cold start): the raw u_x, u_y, v_s
         x, y, s = sv.u[: sv.nx], sv.u[sv.nx:], sv.v[sv.nx:]
     print(f"  oracle tau {tau:.6e} kappa {kappa:.6e}", flush=True)
-    r = P.scs_solve(dev(g), d, eps=0.0, max_iters=k, post=False)
+    r = P.scs_solve(dev(g), d, eps=0.0, max_iters=k, post=False, warm_proj=warm)
     assert r["status"] == 5 and r["iters"] == k      # PSD_ENOCONV: eps = 0 runs max_iters
+    if warm:
+        print(f"  warm cone steps: {r['warm_refined']} refined, {r['warm_fallbacks']} fell back", flush=True)
+        assert r["warm_refined"] + r["warm_fallbacks"] > 0
+        if d == 2:
+            assert r["warm_refined"] > 0
     assert abs(r["tau"] - tau) <= 1e-12 * max(1.0, abs(tau))
     assert abs(r["kappa"] - kappa) <= 1e-12 * max(1.0, abs(kappa))
     ex, ey, es = rel(host(r["x"]), x), rel(host(r["y"]), y), rel(host(r["s"]), s)
