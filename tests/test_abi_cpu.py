@@ -124,6 +124,10 @@ def test_affine_host_validation(L):
         assert lib.psd_affine_dims(d, ctypes.byref(nx), ctypes.byref(ny)) == 0
         D = d * d
         assert nx.value == d ** 8 - (1 + D * (D - 1)) ** 2 and ny.value == d ** 8
+    # Table II's m column: the number of free parameters x of the process matrix
+    table2_m = {2: 87, 3: 1232, 4: 7455, 5: 29424, 6: 89495, 7: 228192, 8: 512127}
+    for d, m in table2_m.items():
+        assert lib.psd_affine_dims(d, ctypes.byref(nx), ctypes.byref(ny)) == 0 and nx.value == m, d
     assert lib.psd_affine_dims(1, ctypes.byref(nx), ctypes.byref(ny)) == 1
     assert lib.psd_affine_dims(9, ctypes.byref(nx), ctypes.byref(ny)) == 1
     out = ctypes.c_size_t(0)
