@@ -206,3 +206,22 @@ def test_warm_rejects_bad_arguments_on_host(L):
     assert warm >= out.value                      # the cold fallback fits in it too
     assert lib.psd_workspace_size(1, L.int_array([100]), 2, L.PSD_FLAG_WARM, ctypes.byref(out)) == 1
     assert lib.psd_workspace_size(2, L.int_array([9, 9]), 0, L.PSD_FLAG_WARM, ctypes.byref(out)) == 1
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/psdproj.h compiles as strict C99 and as C++11 (a C ABI with no
+    HIP or C++ types in its declarations)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if not gcc:
+        import pytest
+        pytest.skip("gcc not found")
+    src = tmp_path / "use.c"
+    src.write_text('#include "psdproj.h"\n'
+                   "int main(void) { size_t b; int n = 16; return (int)psd_workspace_size(1, &n, PSD_FP64_EIG, 0, &b); }\n")
+    inc = "-I" + os.path.join(ROOT, "include")
+    for cmd in ([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only", inc, str(src)],
+                ["g++", "-std=c++11", "-Wall", "-Werror", "-fsyntax-only", "-x", "c++", inc, str(src)]):
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
