@@ -326,7 +326,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1 "
+        print(json.dumps({"error": "bench.py measures one GPU only; --gpus must be 1 "
                                    "(each cone block is projected on one GPU here)"}))
         sys.exit(2)
 

@@ -62,7 +62,7 @@ typedef enum {
     PSD_ENONFINITE = 4,   /* device: the input held a NaN or an infinity */
     PSD_ENOCONV = 5,      /* device: an iteration did not converge */
     PSD_EDEVICE = 6,      /* a HIP runtime call failed (launch, no device) */
-    PSD_EUNSUPPORTED = 7  /* valid request this build does not serve */
+    PSD_EUNSUPPORTED = 7  /* valid request the library does not serve */
 } psd_status;
 
 typedef enum {
