@@ -225,3 +225,19 @@ def test_header_is_plain_c(tmp_path):
                 ["g++", "-std=c++11", "-Wall", "-Werror", "-fsyntax-only", "-x", "c++", inc, str(src)]):
         r = subprocess.run(cmd, capture_output=True, text=True)
         assert r.returncode == 0, r.stderr
+
+
+def test_warm_workspace_layout(L):
+    """psd_project_warm's workspace: five n x n complex matrices (the input,
+    two bases, A X, the correction) and the split-K partials of the
+    products (8 + 8 slices at n = 625, 3 + 3 at 1296, one each from 2048 on:
+    about 512 workgroups, at most one round of them), and never less than
+    the cold path with the saved pair needs."""
+    out = ctypes.c_size_t(0)
+    lib = L.lib()
+    for n, mats in ((625, 21), (1296, 11), (4096, 7)):
+        assert lib.psd_workspace_size(1, L.int_array([n]), 0, L.PSD_FLAG_WARM, ctypes.byref(out)) == 0
+        warm = out.value
+        assert mats * 16 * n * n <= warm <= mats * 16 * n * n + (1 << 16), (n, warm)
+        assert lib.psd_workspace_size(1, L.int_array([n]), 0, L.PSD_FLAG_SAVE, ctypes.byref(out)) == 0
+        assert warm >= out.value
